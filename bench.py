@@ -1,0 +1,169 @@
+"""Throughput of the DG right-hand side + low-storage RK stage on one MI355X.
+
+Workload (default): flow past a unit-diameter cylinder, O-grid of 80 x 128
+cells (radial ratio 1.05, wall r = 0.5, far field r = 30) split into
+K = 20480 triangles, p = 4 (Np = 15), Re = 100, M = 0.2, SIPG, paper penalty,
+free stream plus seeded 1e-3 uniform noise per node and field, FP64.
+
+A step is one five-stage LSERK step (five fused RHS + stage launches).
+value = DOF-updates/s = 4 Np K x 5 x steps / wall time of the timed steps,
+inputs resident in HBM.  Also reported: the average duration of the stage
+kernel (HIP events on the launch stream) against its algorithmic HBM bytes,
+and the FP64 NumPy oracle timed on the host on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--p P] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DG RHS DOF-updates/s at p=4–6, chosen form vs plain FP64 at stated L2 err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_element(Np):
+    # K0 read, K1 read, K1 write, K0 write (4 x 4 Np doubles) + geometry
+    # (16 doubles) + packed connectivity (3 int32)
+    return 4 * 4 * Np * 8 + 16 * 8 + 3 * 4
+
+
+def cpu_baseline(w, p, budget_s=20.0):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import meshgen as mg
+    from oracle.dg import DGOracle, Physics
+    from oracle.mesh import Mesh
+    from oracle.nodes import RefElement
+
+    ref = RefElement(p)
+    m = w["mesh"]
+    mesh = Mesh(ref, m["VX"], m["VY"], m["EToV"], m["face_tag"], m["period"])
+    dg = DGOracle(mesh, Physics(gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+                                penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"]))
+    U = mg.noisy_free_stream((4, ref.Np, mesh.K), w["U_inf"], mg.rng_for(1))
+    n = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while True:
+            dg.rhs(U)
+            n += 1
+            el = time.perf_counter() - t0
+            if el > budget_s or n >= 5 or el * (n + 1) / n > 1.5 * budget_s:
+                break
+    dofs = 4 * ref.Np * mesh.K
+    return {"value": dofs * n / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d weak-form RHS evaluations of the full K=%d p=%d workload (NumPy FP64, "
+                      "1 BLAS thread, %.1f s)" % (n, mesh.K, p, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the element partition would shard by domain decomposition)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import meshgen as mg
+    from paper_2508_17917_amd import Solver
+
+    w = mg.workload("cylinder20k", args.p)
+    p = w["p"]
+    log("building solver: cylinder20k p=%d" % p)
+    s = Solver(p, w["mesh"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+               penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"])
+    K, Np = s.K, s.Np
+    rng = mg.rng_for(1)
+    U0 = mg.noisy_free_stream((4, Np, K), w["U_inf"], rng)
+    U = torch.from_numpy(np.ascontiguousarray(np.transpose(U0, (2, 0, 1)))).cuda()
+    K1 = torch.zeros_like(U)
+    dt = 2e-6
+    stream = torch.cuda.current_stream()
+
+    log("warmup %d steps" % args.warmup)
+    for _ in range(args.warmup):
+        s.rk_step(U, K1, dt, stream=stream)
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s.rk_step(U, K1, dt, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_steps = ev0.elapsed_time(ev1) / 1e3
+    finite = bool(torch.isfinite(U).all().item())
+
+    # average duration of the stage kernel alone (same stream, HIP events)
+    Ub = torch.empty_like(U)
+    nl = 100
+    for _ in range(5):
+        s.rk_stage(U, Ub, K1, -0.4, 0.3, dt, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(nl):
+        s.rk_stage(U, Ub, K1, -0.4, 0.3, dt, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_launch = e0.elapsed_time(e1) / 1e3 / nl
+    bytes_launch = algorithmic_bytes_per_element(Np) * K
+    achieved = bytes_launch / t_launch / 1e9
+
+    dofs = 4 * Np * K
+    value = dofs * 5 * args.steps / t_steps
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_steps * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cylinder20k: O-grid 80x128 cells (ratio 1.05, r 0.5..30) -> "
+                               "K=%d triangles, p=%d (Np=%d), Re=100, M=0.2, SIPG, free stream + "
+                               "1e-3 seeded noise, plain FP64" % (K, p, Np),
+                   "K": K, "p": p, "dofs": dofs, "form": "fp64", "finite": finite,
+                   "wall_s": wall},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage_kernel<%d>" % p, "avg_launch_us": t_launch * 1e6,
+                     "bytes_per_launch": bytes_launch},
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

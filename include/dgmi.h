@@ -1,0 +1,162 @@
+/*
+ * dgmi -- nodal interior-penalty DG right-hand side for the 2D compressible
+ * Navier-Stokes equations on triangles, hand-written for MI355X (gfx950).
+ *
+ * Method: Zafeiris, Georgoulis & Papadakis, "Parallel nodal interior-penalty
+ * discontinuous Galerkin methods for the subsonic compressible Navier-Stokes
+ * equations" (arXiv 2508.17917).  Section/equation references below are to
+ * that paper.
+ *
+ * Conventions shared by every call
+ *   - State U = [rho, rho v1, rho v2, eps] (Sec. 2.1, eq. cnp), eps = total
+ *     energy per unit volume, p = (gamma-1)(eps - rho|v|^2/2).
+ *   - Nodal layout at the boundary: U[K][4][Np], row-major, element-major:
+ *     one element's 4 x Np block is contiguous.  Np = (p+1)(p+2)/2.
+ *   - Nodes on the reference triangle {(-1,-1),(1,-1),(-1,1)} are Warburton's
+ *     warp & blend nodes, numbered row by row from the edge s = -1 upward,
+ *     by increasing r inside a row; dg_get_nodes returns their physical
+ *     coordinates.
+ *   - Face f of element k joins local vertices f and (f+1)%3 (vertices
+ *     counter-clockwise); face tags: 0 interior or periodic, 1 moving
+ *     adiabatic wall, 2 far field (Sec. 2.1 boundary split).
+ *   - Device pointers are plain HIP device addresses (e.g. a torch tensor's
+ *     data_ptr()); `stream` is a hipStream_t (NULL = default stream).  The
+ *     caller owns U, K1 and R; the library owns its operator, geometry and
+ *     connectivity tables from dg_setup until dg_destroy, plus one state-
+ *     sized scratch buffer used by dg_rk_step.
+ *   - Every call returns a dg_status; none aborts or throws across the ABI.
+ *     dg_last_error gives the message of the last failing call on a context.
+ *   - Calls on one context are not thread-safe; different contexts are
+ *     independent.
+ */
+#ifndef DGMI_H
+#define DGMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+typedef enum dg_status {
+  DG_OK = 0,
+  DG_EINVAL = -1,        /* bad argument (NULL pointer, size, range)            */
+  DG_ENOMEM = -2,        /* host or device allocation failed                    */
+  DG_EHIP = -3,          /* a HIP runtime call failed (message has the reason)  */
+  DG_EMESH = -4,         /* non-conforming face, J <= 0 (clockwise element),    *
+                          * unmatched periodic face, or bad face tag            */
+  DG_EUNSUPPORTED = -5,  /* polynomial order or precision not built             */
+  DG_ENONFINITE = -6,    /* non-finite value found by a health check            */
+  DG_ESTATE = -7         /* call out of order (e.g. dg_rhs before dg_setup)     */
+} dg_status;
+
+typedef enum dg_precision {
+  DG_FP64 = 0            /* every step in IEEE binary64                         */
+} dg_precision;
+
+typedef enum dg_penalty_mode {
+  /* sigma_e = C1 (1+theta)^2 (d+1) Gbar_e max_{+-} C_inv(e,K+-,p),
+   * C_inv = (p+1)(p+2)|e|/(2|K|)                        (eq. penalty_final) */
+  DG_PENALTY_PAPER = 0,
+  /* sigma_e = C (p+1)^2 Gbar_e / min_{+-} h_e, h_e = 2|K|/|e|  (literature
+   * form of Sec. 2.2.3 with the diffusion scale Gbar_e supplying the units) */
+  DG_PENALTY_STANDARD = 1
+} dg_penalty_mode;
+
+/* Create a context for polynomial order p (1 <= p <= 8).  *out receives the
+ * context (owned by the caller, released with dg_destroy).  No GPU work. */
+int dg_create(int p, int precision, dg_ctx** out);
+
+/* Physics of eq. cnp and the IP flux (eq. ip_flux): gamma, Prandtl number,
+ * constant dynamic viscosity mu, theta in [-1,1] (1 SIPG, 0 IIPG, -1 NIPG),
+ * penalty mode and its constant, far-field state U_inf[4] (Sec. 2.2.4,
+ * ghost state on far-field faces).  Host only. */
+int dg_set_physics(dg_ctx* ctx, double gamma, double Pr, double mu, double theta,
+                   int penalty_mode, double C_pen, const double U_inf[4]);
+
+/* Mesh T of straight-sided triangles (Sec. 2.2): Nv vertices (VX, VY host
+ * arrays of length Nv), K triangles (EToV host array K*3, counter-clockwise
+ * vertex indices), face_tag host array K*3 (see conventions), period[2] the
+ * periods in x and y of a periodic mesh (0 = not periodic; interior faces on
+ * opposite sides are then matched by translation).  The arrays are copied.
+ * Host only; connectivity is built here (DG_EMESH on failure). */
+int dg_set_mesh(dg_ctx* ctx, int64_t Nv, const double* VX, const double* VY,
+                int64_t K, const int32_t* EToV, const int8_t* face_tag,
+                const double period[2]);
+
+/* Host part of the set-up, in FP64: warp & blend nodes, PKD Vandermonde V,
+ * Dr = Vr V^-1, Ds = Vs V^-1, M^-1 = V V^T, face mass E, LIFT = M^-1 E and
+ * the theta-term lifts M^-1 Dr^T E, M^-1 Ds^T E (Sec. 2.2, eq.
+ * weak_matrices_calc, built once on the reference element), geometric
+ * factors of the affine maps, face normals, and the penalty's geometric
+ * factors.  Needs dg_set_physics and dg_set_mesh.  No GPU work. */
+int dg_setup_host(dg_ctx* ctx);
+
+/* dg_setup_host (if not done) followed by the upload of every table to the
+ * current HIP device and allocation of the scratch state buffer. */
+int dg_setup(dg_ctx* ctx);
+
+/* Sizes: number of elements K, nodes per element Np, nodes per face Nfp. */
+int64_t dg_num_elements(const dg_ctx* ctx);
+int dg_num_nodes(const dg_ctx* ctx);
+int dg_num_face_nodes(const dg_ctx* ctx);
+
+/* Host copy of a set-up table for inspection (after dg_setup_host).  name:
+ * "r", "s" (Np), "Dr", "Ds" (Np*Np, row-major), "LIFT", "LIFTr", "LIFTs"
+ * (Np*3Nfp), "Fmask" (3*Nfp, as doubles), "wface" (3*Nfp face quadrature
+ * weights), "geo" (K*16: rx ry sx sy, then per face nx ny Fscale sigma_geo),
+ * "nbr" (K*3 neighbour element, as doubles), "nbr_face" (K*3).  count must
+ * equal the table size; out is a host array of that many doubles. */
+int dg_get_host_table(const dg_ctx* ctx, const char* name, double* out, int64_t count);
+
+/* Physical node coordinates, host arrays x[K*Np], y[K*Np] (element-major). */
+int dg_get_nodes(const dg_ctx* ctx, double* x, double* y);
+
+/* Right-hand side R = dU/dt = (M^K)^-1 R_K of eq. dg_on_K for every element,
+ * in strong form (algebraically equal to the weak form): volume divergence
+ * through Dr/Ds, face gather with Roe flux (eq. roe_flux), SIPG/IIPG viscous
+ * flux with penalty (eq. ip_flux, eq. penalty_final), boundary ghosts
+ * (Sec. 2.2.4), LIFT.  U, R: device arrays [K][4][Np] of doubles (must not
+ * alias).  v_w: host pointer to the rigid-frame velocity (Sec. 2.1, eq. cnp).
+ * Asynchronous on `stream`. */
+int dg_rhs(dg_ctx* ctx, const double* U, double* R, const double v_w[2], void* stream);
+
+/* One five-stage low-storage RK step (Alg. 1, coefficients of Carpenter &
+ * Kennedy's 2N-storage (5,4) scheme), in place: U <- U(t + dt); K1 is the
+ * second 2N register (device [K][4][Np], overwritten; need not be
+ * initialised since A_1 = 0).  v_w fixed over the step (Alg. 3).  Uses the
+ * library's scratch state buffer; asynchronous on `stream`. */
+int dg_rk_step(dg_ctx* ctx, double* U, double* K1, double dt, const double v_w[2],
+               void* stream);
+
+/* One RK stage: K1 <- a K1 + dt R(U_in); U_out <- U_in + b K1.  U_in and
+ * U_out must not alias (neighbours read U_in).  Asynchronous. */
+int dg_rk_stage(dg_ctx* ctx, const double* U_in, double* U_out, double* K1,
+                double a, double b, double dt, const double v_w[2], void* stream);
+
+/* Force and moment exerted by the fluid on the wall faces (Alg. 3, "Calculate
+ * Aerodynamic Forces"): out[0..2] = (Fx, Fy, Mz) about the origin, the face-
+ * quadrature integral of p+ n - tau(U^b, grad U+) n with n the fluid's
+ * outward normal.  FP64, deterministic order.  Synchronises `stream`; out is
+ * a host array of 3 doubles. */
+int dg_force(dg_ctx* ctx, const double* U, const double v_w[2], double out[3], void* stream);
+
+/* Host Newmark-beta step (beta 1/4, gamma 1/2) of M y'' + C y' + K y = F
+ * (eq. 1dof_oscillator): state[3] = (y, y', y'') at t, updated to t + dt
+ * with the load F_new. */
+int dg_newmark_step(double state[3], double F_new, double dt, double M, double C, double K);
+
+/* Message of the last failing call on ctx ("" if none).  Valid until the next
+ * call on ctx.  ctx may be NULL (then a message about creation failures). */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* Release every host and device resource of ctx.  NULL is a no-op. */
+void dg_destroy(dg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGMI_H */

@@ -165,9 +165,9 @@ def workload(name, p=None):
     if name == "cylinder20k":
         mesh = ogrid(80, 128, 0.5, 30.0, 1.05)
         phys = physics_params(Re=100.0, M=0.2, L=1.0)
-        return dict(mesh=mesh, p=4 if p is None else p, penalty_mode=0, C_pen=0.01, theta=1.0, **phys)
+        return dict(mesh=mesh, p=4 if p is None else p, penalty_mode=0, C_pen=1.0, theta=1.0, **phys)
     if name == "periodic51k":
         mesh = periodic_square(160, 160, 10.0, 10.0)
         phys = physics_params(Re=100.0, M=0.3, L=1.0)
-        return dict(mesh=mesh, p=6 if p is None else p, penalty_mode=0, C_pen=0.01, theta=1.0, **phys)
+        return dict(mesh=mesh, p=6 if p is None else p, penalty_mode=0, C_pen=1.0, theta=1.0, **phys)
     raise KeyError(name)

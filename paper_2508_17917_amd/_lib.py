@@ -1,0 +1,215 @@
+"""ctypes binding of libdgmi.so: the C-ABI calls under the same names.
+
+Argument marshalling only -- every step of the right-hand side, the RK stage
+and the force integral runs in the library's HIP kernels.  torch is imported
+first so that the library binds to the HIP runtime torch already loaded (one
+runtime per process); device arrays are passed as torch tensors and their
+data pointers, streams as torch streams or raw hipStream_t integers.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgmi.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EMESH, DG_EUNSUPPORTED, DG_ENONFINITE, DG_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+DG_FP64 = 0
+DG_PENALTY_PAPER, DG_PENALTY_STANDARD = 0, 1
+
+STATUS_NAMES = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_EMESH",
+                -5: "DG_EUNSUPPORTED", -6: "DG_ENONFINITE", -7: "DG_ESTATE"}
+
+# exported symbol -> (restype, argtypes)
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_L = ctypes.c_int64
+_DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "dg_create": (_I, [_I, _I, ctypes.POINTER(_P)]),
+    "dg_set_physics": (_I, [_P, _D, _D, _D, _D, _I, _D, _DP]),
+    "dg_set_mesh": (_I, [_P, _L, _DP, _DP, _L, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int8), _DP]),
+    "dg_setup_host": (_I, [_P]),
+    "dg_setup": (_I, [_P]),
+    "dg_num_elements": (_L, [_P]),
+    "dg_num_nodes": (_I, [_P]),
+    "dg_num_face_nodes": (_I, [_P]),
+    "dg_get_host_table": (_I, [_P, ctypes.c_char_p, _DP, _L]),
+    "dg_get_nodes": (_I, [_P, _DP, _DP]),
+    "dg_rhs": (_I, [_P, _P, _P, _DP, _P]),
+    "dg_rk_step": (_I, [_P, _P, _P, _D, _DP, _P]),
+    "dg_rk_stage": (_I, [_P, _P, _P, _P, _D, _D, _D, _DP, _P]),
+    "dg_force": (_I, [_P, _P, _DP, _DP, _P]),
+    "dg_newmark_step": (_I, [_DP, _D, _D, _D, _D, _D]),
+    "dg_last_error": (ctypes.c_char_p, [_P]),
+    "dg_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+def load():
+    """Load the library (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (binds the library to torch's HIP runtime)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdgmi.so is not built; run `python -m paper_2508_17917_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    _check_single_hip_runtime()
+    return lib
+
+
+def _check_single_hip_runtime():
+    try:
+        with open("/proc/self/maps") as fh:
+            paths = {line.split()[-1] for line in fh if "libamdhip64" in line}
+    except OSError:
+        return
+    real = {os.path.realpath(p) for p in paths}
+    if len(real) > 1:
+        raise RuntimeError("two HIP runtimes are mapped in this process: %s" % sorted(real))
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _check(code, handle=None):
+    if code != DG_OK:
+        msg = load().dg_last_error(handle)
+        raise DGError(code, msg.decode() if msg else "")
+    return code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _vw(v_w):
+    return np.ascontiguousarray(np.asarray(v_w if v_w is not None else (0.0, 0.0), dtype=np.float64))
+
+
+# ---- the C-ABI calls ------------------------------------------------------
+def dg_create(p, precision=DG_FP64):
+    h = ctypes.c_void_p()
+    _check(load().dg_create(int(p), int(precision), ctypes.byref(h)))
+    return h
+
+
+def dg_set_physics(h, gamma, Pr, mu, theta, penalty_mode, C_pen, U_inf):
+    u = np.ascontiguousarray(np.asarray(U_inf, dtype=np.float64))
+    return _check(load().dg_set_physics(h, gamma, Pr, mu, theta, int(penalty_mode), C_pen, _dp(u)), h)
+
+
+def dg_set_mesh(h, VX, VY, EToV, face_tag=None, period=(0.0, 0.0)):
+    VX = np.ascontiguousarray(np.asarray(VX, dtype=np.float64))
+    VY = np.ascontiguousarray(np.asarray(VY, dtype=np.float64))
+    E = np.ascontiguousarray(np.asarray(EToV, dtype=np.int32))
+    K = E.shape[0]
+    ft = None if face_tag is None else np.ascontiguousarray(np.asarray(face_tag, dtype=np.int8))
+    per = np.ascontiguousarray(np.asarray(period, dtype=np.float64))
+    return _check(load().dg_set_mesh(
+        h, VX.size, _dp(VX), _dp(VY), K, E.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        None if ft is None else ft.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _dp(per)), h)
+
+
+def dg_setup_host(h):
+    return _check(load().dg_setup_host(h), h)
+
+
+def dg_setup(h):
+    return _check(load().dg_setup(h), h)
+
+
+def dg_num_elements(h):
+    return int(load().dg_num_elements(h))
+
+
+def dg_num_nodes(h):
+    return int(load().dg_num_nodes(h))
+
+
+def dg_num_face_nodes(h):
+    return int(load().dg_num_face_nodes(h))
+
+
+def dg_get_host_table(h, name, count):
+    out = np.zeros(int(count))
+    _check(load().dg_get_host_table(h, name.encode(), _dp(out), int(count)), h)
+    return out
+
+
+def dg_get_nodes(h):
+    n = dg_num_elements(h) * dg_num_nodes(h)
+    x, y = np.zeros(n), np.zeros(n)
+    _check(load().dg_get_nodes(h, _dp(x), _dp(y)), h)
+    return x, y
+
+
+def dg_rhs(h, U, R, v_w=(0.0, 0.0), stream=None):
+    vw = _vw(v_w)
+    return _check(load().dg_rhs(h, _ptr(U), _ptr(R), _dp(vw), _stream(stream)), h)
+
+
+def dg_rk_step(h, U, K1, dt, v_w=(0.0, 0.0), stream=None):
+    vw = _vw(v_w)
+    return _check(load().dg_rk_step(h, _ptr(U), _ptr(K1), float(dt), _dp(vw), _stream(stream)), h)
+
+
+def dg_rk_stage(h, U_in, U_out, K1, a, b, dt, v_w=(0.0, 0.0), stream=None):
+    vw = _vw(v_w)
+    return _check(load().dg_rk_stage(h, _ptr(U_in), _ptr(U_out), _ptr(K1), float(a), float(b),
+                                     float(dt), _dp(vw), _stream(stream)), h)
+
+
+def dg_force(h, U, v_w=(0.0, 0.0), stream=None):
+    vw = _vw(v_w)
+    out = np.zeros(3)
+    _check(load().dg_force(h, _ptr(U), _dp(vw), _dp(out), _stream(stream)), h)
+    return out
+
+
+def dg_newmark_step(state, F_new, dt, M, C, K):
+    st = np.ascontiguousarray(np.asarray(state, dtype=np.float64).copy())
+    code = load().dg_newmark_step(_dp(st), float(F_new), float(dt), float(M), float(C), float(K))
+    if code != DG_OK:
+        raise DGError(code, "invalid Newmark arguments")
+    return st
+
+
+def dg_last_error(h):
+    msg = load().dg_last_error(h)
+    return msg.decode() if msg else ""
+
+
+def dg_destroy(h):
+    if h is not None and h.value:
+        load().dg_destroy(h)

@@ -1,0 +1,77 @@
+// Internal declarations shared by the host set-up, the C-ABI and the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dgmi {
+
+constexpr int kMaxOrder = 8;
+constexpr int kGeoStride = 16;   // doubles per element in the geometry table
+
+// Reference-element operators, row-major, FP64 (built once on K^).
+struct RefOps {
+  int N = 0, Np = 0, Nfp = 0;
+  std::vector<double> r, s;            // Np
+  std::vector<double> Dr, Ds;          // Np x Np
+  std::vector<double> LIFT;            // Np x 3Nfp, M^-1 E
+  std::vector<double> LIFTr, LIFTs;    // Np x 3Nfp, M^-1 Dr^T E, M^-1 Ds^T E
+  std::vector<int> Fmask;              // 3 x Nfp, counter-clockwise per face
+  std::vector<double> wface;           // 3 x Nfp face quadrature weights in xi
+};
+
+struct Physics {
+  double gamma = 1.4, Pr = 0.72, mu = 0.0, theta = 1.0;
+  int penalty_mode = 0;
+  double C_pen = 0.01;
+  double U_inf[4] = {1.0, 0.0, 0.0, 1.0};
+};
+
+// Mesh tables built on the host.
+struct MeshTables {
+  int64_t K = 0;
+  std::vector<double> geo;        // K x 16: rx ry sx sy | (nx ny Fscale sigma_geo) x 3
+  std::vector<int32_t> conn;      // K x 3 packed: nbr << 4 | nbr_face << 2 | tag
+  std::vector<int32_t> nbr;       // K x 3 neighbour element (self on boundary)
+  std::vector<int32_t> nbr_face;  // K x 3
+  std::vector<int8_t> tag;        // K x 3
+  std::vector<double> x, y;       // K x Np node coordinates
+  std::vector<int32_t> wall_faces;  // list of k*3+f with tag wall
+  std::vector<double> wall_xy;      // (x, y) of each wall face node, face-major
+};
+
+// host_setup.cpp
+bool build_ref_ops(int N, RefOps& out, std::string& err);
+bool build_mesh_tables(const RefOps& ref, const Physics& phys, int64_t Nv, const double* VX,
+                       const double* VY, int64_t K, const int32_t* EToV, const int8_t* face_tag,
+                       const double period[2], MeshTables& out, std::string& err);
+
+// Device-side view handed to the kernels.
+struct DeviceTables {
+  const double* geo = nullptr;     // K x 16
+  const int32_t* conn = nullptr;   // K x 3
+  const double* ops = nullptr;     // packed operators, see ops_offsets
+  const int32_t* wall = nullptr;   // wall face list (k*3 + f)
+  const double* wall_xy = nullptr; // node coordinates of the wall faces, (x, y) per face node
+  int64_t K = 0;
+  int nwall = 0;
+};
+
+struct KernelPhysics {
+  double gamma, Pr, mu, theta;
+  double U_inf[4];
+  double vw[2];
+};
+
+// kernels.hip
+int launch_stage(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U_in,
+                 double* U_out, double* K1, double a, double b, double dt, int rhs_only,
+                 void* stream, std::string& err);
+int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
+                 double* out_dev, void* stream, std::string& err);
+// operator packing: Dr | Ds | LIFT | LIFTr | LIFTs | Fmask (as doubles) | wface
+size_t ops_packed_size(int N);
+void pack_ops(const RefOps& ref, std::vector<double>& out);
+
+}  // namespace dgmi

@@ -1,0 +1,346 @@
+// C-ABI of the library: context lifetime, host set-up, device tables and
+// launches.  Every entry point returns a dg_status and records a message;
+// nothing throws across the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dgmi.h"
+#include "dg_internal.h"
+
+// Carpenter & Kennedy (1994) five-stage, fourth-order 2N-storage coefficients
+// (NASA TM-109112): K1 <- A_i K1 + dt R(K0), K0 <- K0 + B_i K1 (Alg. 1).
+static const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                               -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0,
+                               -1275806237668.0 / 842570457699.0};
+static const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+struct dg_ctx {
+  int N = 0;
+  int precision = 0;
+  dgmi::Physics phys;
+  bool have_phys = false;
+  std::vector<double> VX, VY;
+  std::vector<int32_t> EToV;
+  std::vector<int8_t> tag;
+  double period[2] = {0.0, 0.0};
+  int64_t Nv = 0, K = 0;
+  bool have_mesh = false;
+  dgmi::RefOps ref;
+  dgmi::MeshTables mesh;
+  bool host_ready = false;
+  int device = -1;
+  double* d_geo = nullptr;
+  int32_t* d_conn = nullptr;
+  double* d_ops = nullptr;
+  int32_t* d_wall = nullptr;
+  double* d_wall_xy = nullptr;
+  double* d_scratch = nullptr;
+  double* d_force = nullptr;
+  bool dev_ready = false;
+  std::string err;
+};
+
+namespace {
+
+std::string g_create_error;
+
+int fail(dg_ctx* c, int code, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_error = msg;
+  return code;
+}
+
+int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
+  return fail(c, DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void free_device(dg_ctx* c) {
+  void* ptrs[] = {c->d_geo, c->d_conn, c->d_ops, c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  c->d_geo = nullptr;
+  c->d_conn = nullptr;
+  c->d_ops = nullptr;
+  c->d_wall = nullptr;
+  c->d_wall_xy = nullptr;
+  c->d_scratch = nullptr;
+  c->d_force = nullptr;
+  c->dev_ready = false;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  size_t bytes = src.size() * sizeof(T);
+  if (bytes == 0) bytes = sizeof(T);
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+dgmi::DeviceTables tables(const dg_ctx* c) {
+  dgmi::DeviceTables t;
+  t.geo = c->d_geo;
+  t.conn = c->d_conn;
+  t.ops = c->d_ops;
+  t.wall = c->d_wall;
+  t.wall_xy = c->d_wall_xy;
+  t.K = c->K;
+  t.nwall = (int)c->mesh.wall_faces.size();
+  return t;
+}
+
+dgmi::KernelPhysics kphys(const dg_ctx* c, const double vw[2]) {
+  dgmi::KernelPhysics k;
+  k.gamma = c->phys.gamma;
+  k.Pr = c->phys.Pr;
+  k.mu = c->phys.mu;
+  k.theta = c->phys.theta;
+  for (int i = 0; i < 4; ++i) k.U_inf[i] = c->phys.U_inf[i];
+  k.vw[0] = vw ? vw[0] : 0.0;
+  k.vw[1] = vw ? vw[1] : 0.0;
+  return k;
+}
+
+int check_ready(dg_ctx* c) {
+  if (!c) return fail(c, DG_EINVAL, "null context");
+  if (!c->dev_ready) return fail(c, DG_ESTATE, "dg_setup has not completed on this context");
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_create(int p, int precision, dg_ctx** out) {
+  if (!out) return fail(nullptr, DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (p < 1 || p > 6) return fail(nullptr, DG_EUNSUPPORTED, "polynomial order must be in 1..6");
+  if (precision != DG_FP64) return fail(nullptr, DG_EUNSUPPORTED, "unsupported precision mode");
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return fail(nullptr, DG_ENOMEM, "out of host memory");
+  c->N = p;
+  c->precision = precision;
+  *out = c;
+  return DG_OK;
+}
+
+int dg_set_physics(dg_ctx* c, double gamma, double Pr, double mu, double theta, int penalty_mode,
+                   double C_pen, const double U_inf[4]) {
+  if (!c) return fail(c, DG_EINVAL, "null context");
+  if (!U_inf) return fail(c, DG_EINVAL, "U_inf is NULL");
+  if (!(gamma > 1.0) || !(Pr > 0.0) || !(mu >= 0.0) || !(theta >= -1.0 && theta <= 1.0) ||
+      (penalty_mode != DG_PENALTY_PAPER && penalty_mode != DG_PENALTY_STANDARD) || !(C_pen >= 0.0))
+    return fail(c, DG_EINVAL, "physics parameter out of range");
+  if (!(U_inf[0] > 0.0)) return fail(c, DG_EINVAL, "far-field density must be positive");
+  c->phys.gamma = gamma;
+  c->phys.Pr = Pr;
+  c->phys.mu = mu;
+  c->phys.theta = theta;
+  c->phys.penalty_mode = penalty_mode;
+  c->phys.C_pen = C_pen;
+  for (int i = 0; i < 4; ++i) c->phys.U_inf[i] = U_inf[i];
+  c->have_phys = true;
+  c->host_ready = false;
+  return DG_OK;
+}
+
+int dg_set_mesh(dg_ctx* c, int64_t Nv, const double* VX, const double* VY, int64_t K,
+                const int32_t* EToV, const int8_t* face_tag, const double period[2]) {
+  if (!c) return fail(c, DG_EINVAL, "null context");
+  if (Nv < 3 || K < 1 || !VX || !VY || !EToV) return fail(c, DG_EINVAL, "empty or NULL mesh arrays");
+  c->VX.assign(VX, VX + Nv);
+  c->VY.assign(VY, VY + Nv);
+  c->EToV.assign(EToV, EToV + 3 * K);
+  if (face_tag)
+    c->tag.assign(face_tag, face_tag + 3 * K);
+  else
+    c->tag.assign(3 * K, 0);
+  c->period[0] = period ? period[0] : 0.0;
+  c->period[1] = period ? period[1] : 0.0;
+  c->Nv = Nv;
+  c->K = K;
+  c->have_mesh = true;
+  c->host_ready = false;
+  return DG_OK;
+}
+
+int dg_setup_host(dg_ctx* c) {
+  if (!c) return fail(c, DG_EINVAL, "null context");
+  if (!c->have_phys || !c->have_mesh)
+    return fail(c, DG_ESTATE, "dg_set_physics and dg_set_mesh must precede set-up");
+  std::string err;
+  if (!dgmi::build_ref_ops(c->N, c->ref, err)) return fail(c, DG_EUNSUPPORTED, err);
+  if (!dgmi::build_mesh_tables(c->ref, c->phys, c->Nv, c->VX.data(), c->VY.data(), c->K,
+                               c->EToV.data(), c->tag.data(), c->period, c->mesh, err))
+    return fail(c, DG_EMESH, err);
+  c->host_ready = true;
+  return DG_OK;
+}
+
+int dg_setup(dg_ctx* c) {
+  if (!c) return fail(c, DG_EINVAL, "null context");
+  if (!c->host_ready) {
+    int rc = dg_setup_host(c);
+    if (rc != DG_OK) return rc;
+  }
+  free_device(c);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  std::vector<double> ops;
+  dgmi::pack_ops(c->ref, ops);
+  if ((e = upload(&c->d_geo, c->mesh.geo)) != hipSuccess ||
+      (e = upload(&c->d_conn, c->mesh.conn)) != hipSuccess ||
+      (e = upload(&c->d_ops, ops)) != hipSuccess ||
+      (e = upload(&c->d_wall, c->mesh.wall_faces)) != hipSuccess ||
+      (e = upload(&c->d_wall_xy, c->mesh.wall_xy)) != hipSuccess) {
+    free_device(c);
+    return hip_fail(c, e, "uploading set-up tables");
+  }
+  size_t state = (size_t)c->K * 4 * c->ref.Np * sizeof(double);
+  if ((e = hipMalloc((void**)&c->d_scratch, state)) != hipSuccess ||
+      (e = hipMalloc((void**)&c->d_force, 4 * sizeof(double))) != hipSuccess) {
+    free_device(c);
+    return e == hipErrorOutOfMemory ? fail(c, DG_ENOMEM, "device allocation failed")
+                                    : hip_fail(c, e, "hipMalloc");
+  }
+  c->dev_ready = true;
+  return DG_OK;
+}
+
+int64_t dg_num_elements(const dg_ctx* c) { return c ? c->K : 0; }
+int dg_num_nodes(const dg_ctx* c) { return c ? (c->N + 1) * (c->N + 2) / 2 : 0; }
+int dg_num_face_nodes(const dg_ctx* c) { return c ? c->N + 1 : 0; }
+
+int dg_get_host_table(const dg_ctx* cc, const char* name, double* out, int64_t count) {
+  dg_ctx* c = const_cast<dg_ctx*>(cc);
+  if (!c || !name || !out) return fail(c, DG_EINVAL, "NULL argument");
+  if (!c->host_ready) return fail(c, DG_ESTATE, "host set-up not done");
+  std::vector<double> v;
+  const dgmi::RefOps& r = c->ref;
+  const dgmi::MeshTables& m = c->mesh;
+  std::string n(name);
+  if (n == "r") v = r.r;
+  else if (n == "s") v = r.s;
+  else if (n == "Dr") v = r.Dr;
+  else if (n == "Ds") v = r.Ds;
+  else if (n == "LIFT") v = r.LIFT;
+  else if (n == "LIFTr") v = r.LIFTr;
+  else if (n == "LIFTs") v = r.LIFTs;
+  else if (n == "wface") v = r.wface;
+  else if (n == "Fmask") v.assign(r.Fmask.begin(), r.Fmask.end());
+  else if (n == "geo") v = m.geo;
+  else if (n == "nbr") v.assign(m.nbr.begin(), m.nbr.end());
+  else if (n == "nbr_face") v.assign(m.nbr_face.begin(), m.nbr_face.end());
+  else return fail(c, DG_EINVAL, "unknown table " + n);
+  if ((int64_t)v.size() != count)
+    return fail(c, DG_EINVAL, "table " + n + " has " + std::to_string(v.size()) + " entries");
+  std::memcpy(out, v.data(), v.size() * sizeof(double));
+  return DG_OK;
+}
+
+int dg_get_nodes(const dg_ctx* cc, double* x, double* y) {
+  dg_ctx* c = const_cast<dg_ctx*>(cc);
+  if (!c || !x || !y) return fail(c, DG_EINVAL, "NULL argument");
+  if (!c->host_ready) return fail(c, DG_ESTATE, "host set-up not done");
+  std::memcpy(x, c->mesh.x.data(), c->mesh.x.size() * sizeof(double));
+  std::memcpy(y, c->mesh.y.data(), c->mesh.y.size() * sizeof(double));
+  return DG_OK;
+}
+
+int dg_rhs(dg_ctx* c, const double* U, double* R, const double v_w[2], void* stream) {
+  int rc = check_ready(c);
+  if (rc != DG_OK) return rc;
+  if (!U || !R || U == R) return fail(c, DG_EINVAL, "U and R must be distinct device arrays");
+  std::string err;
+  rc = dgmi::launch_stage(c->N, tables(c), kphys(c, v_w), U, nullptr, R, 0.0, 0.0, 1.0, 1, stream,
+                          err);
+  return rc == 0 ? DG_OK : fail(c, rc, err);
+}
+
+int dg_rk_stage(dg_ctx* c, const double* Uin, double* Uout, double* K1, double a, double b,
+                double dt, const double v_w[2], void* stream) {
+  int rc = check_ready(c);
+  if (rc != DG_OK) return rc;
+  if (!Uin || !Uout || !K1 || Uin == Uout || K1 == Uin || K1 == Uout)
+    return fail(c, DG_EINVAL, "U_in, U_out and K1 must be distinct device arrays");
+  std::string err;
+  rc = dgmi::launch_stage(c->N, tables(c), kphys(c, v_w), Uin, Uout, K1, a, b, dt, 0, stream, err);
+  return rc == 0 ? DG_OK : fail(c, rc, err);
+}
+
+int dg_rk_step(dg_ctx* c, double* U, double* K1, double dt, const double v_w[2], void* stream) {
+  int rc = check_ready(c);
+  if (rc != DG_OK) return rc;
+  if (!U || !K1 || U == K1) return fail(c, DG_EINVAL, "U and K1 must be distinct device arrays");
+  if (!std::isfinite(dt)) return fail(c, DG_EINVAL, "dt is not finite");
+  std::string err;
+  dgmi::DeviceTables t = tables(c);
+  dgmi::KernelPhysics k = kphys(c, v_w);
+  double* bufs[2] = {U, c->d_scratch};
+  for (int i = 0; i < 5; ++i) {
+    rc = dgmi::launch_stage(c->N, t, k, bufs[i & 1], bufs[(i + 1) & 1], K1, kRkA[i], kRkB[i], dt, 0,
+                            stream, err);
+    if (rc != 0) return fail(c, rc, err);
+  }
+  size_t bytes = (size_t)c->K * 4 * c->ref.Np * sizeof(double);
+  hipError_t e = hipMemcpyAsync(U, c->d_scratch, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  return DG_OK;
+}
+
+int dg_force(dg_ctx* c, const double* U, const double v_w[2], double out[3], void* stream) {
+  int rc = check_ready(c);
+  if (rc != DG_OK) return rc;
+  if (!U || !out) return fail(c, DG_EINVAL, "NULL argument");
+  if (c->mesh.wall_faces.empty()) {
+    out[0] = out[1] = out[2] = 0.0;
+    return DG_OK;
+  }
+  std::string err;
+  rc = dgmi::launch_force(c->N, tables(c), kphys(c, v_w), U, c->d_force, stream, err);
+  if (rc != 0) return fail(c, rc, err);
+  double h[3];
+  hipError_t e = hipMemcpyAsync(h, c->d_force, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "force read-back");
+  out[0] = h[0];
+  out[1] = h[1];
+  out[2] = h[2];
+  return DG_OK;
+}
+
+int dg_newmark_step(double st[3], double F_new, double dt, double M, double C, double K) {
+  if (!st || !(dt > 0.0)) return DG_EINVAL;
+  const double beta = 0.25, gam = 0.5;
+  double lhs = M + gam * dt * C + beta * dt * dt * K;
+  if (lhs == 0.0) return DG_EINVAL;
+  double y = st[0], yd = st[1], ydd = st[2];
+  double rhs = F_new - C * (yd + (1.0 - gam) * dt * ydd) - K * (y + dt * yd + (0.5 - beta) * dt * dt * ydd);
+  double ydd_n = rhs / lhs;
+  st[0] = y + dt * yd + 0.5 * dt * dt * ((1.0 - 2.0 * beta) * ydd + 2.0 * beta * ydd_n);
+  st[1] = yd + dt * ((1.0 - gam) * ydd + gam * ydd_n);
+  st[2] = ydd_n;
+  return DG_OK;
+}
+
+const char* dg_last_error(const dg_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+void dg_destroy(dg_ctx* c) {
+  if (!c) return;
+  if (c->dev_ready || c->d_geo) free_device(c);
+  delete c;
+}
+
+}  // extern "C"

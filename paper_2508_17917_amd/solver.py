@@ -1,0 +1,83 @@
+"""Convenience wrapper over the C-ABI: one context, state in torch device tensors.
+
+Layout of every nodal tensor: (K, 4, Np) float64, contiguous, on a HIP
+device -- the boundary layout of the library.
+"""
+import numpy as np
+
+from . import _lib as L
+
+
+class Solver:
+    def __init__(self, p, mesh, gamma=1.4, Pr=0.72, mu=0.0, theta=1.0, penalty_mode=0, C_pen=0.01,
+                 U_inf=(1.0, 0.0, 0.0, 1.0), device=True):
+        self.p = int(p)
+        self.h = L.dg_create(self.p, L.DG_FP64)
+        try:
+            L.dg_set_physics(self.h, gamma, Pr, mu, theta, penalty_mode, C_pen, U_inf)
+            L.dg_set_mesh(self.h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh.get("face_tag"),
+                          mesh.get("period", (0.0, 0.0)))
+            if device:
+                L.dg_setup(self.h)
+            else:
+                L.dg_setup_host(self.h)
+        except Exception:
+            L.dg_destroy(self.h)
+            self.h = None
+            raise
+        self.K = L.dg_num_elements(self.h)
+        self.Np = L.dg_num_nodes(self.h)
+        self.Nfp = L.dg_num_face_nodes(self.h)
+
+    # -- host-side helpers
+    def nodes(self):
+        x, y = L.dg_get_nodes(self.h)
+        return x.reshape(self.K, self.Np), y.reshape(self.K, self.Np)
+
+    def table(self, name):
+        sizes = {"r": self.Np, "s": self.Np, "Dr": self.Np ** 2, "Ds": self.Np ** 2,
+                 "LIFT": self.Np * 3 * self.Nfp, "LIFTr": self.Np * 3 * self.Nfp,
+                 "LIFTs": self.Np * 3 * self.Nfp, "Fmask": 3 * self.Nfp, "wface": 3 * self.Nfp,
+                 "geo": self.K * 16, "nbr": self.K * 3, "nbr_face": self.K * 3}
+        return L.dg_get_host_table(self.h, name, sizes[name])
+
+    # -- device calls
+    def empty_state(self):
+        import torch
+        return torch.empty((self.K, 4, self.Np), dtype=torch.float64, device="cuda")
+
+    def rhs(self, U, R=None, v_w=(0.0, 0.0), stream=None):
+        if R is None:
+            R = self.empty_state()
+        L.dg_rhs(self.h, U, R, v_w, stream)
+        return R
+
+    def rk_step(self, U, K1, dt, v_w=(0.0, 0.0), stream=None):
+        L.dg_rk_step(self.h, U, K1, dt, v_w, stream)
+        return U
+
+    def rk_stage(self, U_in, U_out, K1, a, b, dt, v_w=(0.0, 0.0), stream=None):
+        L.dg_rk_stage(self.h, U_in, U_out, K1, a, b, dt, v_w, stream)
+
+    def force(self, U, v_w=(0.0, 0.0), stream=None):
+        return L.dg_force(self.h, U, v_w, stream)
+
+    def close(self):
+        if self.h is not None:
+            L.dg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device_layout(U_oracle):
+    """(4, Np, K) oracle layout -> (K, 4, Np) contiguous numpy array."""
+    return np.ascontiguousarray(np.transpose(U_oracle, (2, 0, 1)))
+
+
+def from_device_layout(U_dev):
+    return np.ascontiguousarray(np.transpose(np.asarray(U_dev), (1, 2, 0)))

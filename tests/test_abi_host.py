@@ -1,0 +1,153 @@
+"""C-ABI library checks that need no GPU (CPU).
+
+* libdgmi.so loads and exports every function include/dgmi.h declares;
+* the C++ host set-up (operators, nodes, geometry, connectivity, penalty
+  geometry) equals the oracle's independent NumPy construction;
+* documented error codes for bad meshes, orders, arguments and call order.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+from tests.oracle_helpers import build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2508_17917_amd", "libdgmi.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdgmi.so not built")
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "dgmi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2508_17917_amd import _lib
+    lib = _lib.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+
+
+def _host_solver(mesh, p, **kw):
+    from paper_2508_17917_amd import Solver
+    return Solver(p, mesh, device=False, **kw)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_host_operators_match_oracle(p):
+    mesh = mg.periodic_square(3, 2, 2.0, 1.5)
+    s = _host_solver(mesh, p)
+    dg = build(mesh, p)
+    ref = dg.ref
+    Np, NF = ref.Np, 3 * ref.Nfp
+    assert np.abs(s.table("r") - ref.r).max() < 1e-14
+    assert np.abs(s.table("s") - ref.s).max() < 1e-14
+    assert np.array_equal(s.table("Fmask").astype(int), ref.Fmask.ravel())
+    tol = 1e-12 * p * p
+    assert np.abs(s.table("Dr").reshape(Np, Np) - ref.Dr).max() < tol
+    assert np.abs(s.table("Ds").reshape(Np, Np) - ref.Ds).max() < tol
+    assert np.abs(s.table("LIFT").reshape(Np, NF) - ref.LIFT).max() < tol
+    assert np.abs(s.table("LIFTr").reshape(Np, NF) - ref.LIFTr).max() < tol
+    assert np.abs(s.table("LIFTs").reshape(Np, NF) - ref.LIFTs).max() < tol
+    assert np.abs(s.table("wface") - ref.wface.ravel()).max() < 1e-14
+    s.close()
+
+
+@pytest.mark.parametrize("which", ["periodic", "ogrid"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_host_geometry_and_connectivity_match_oracle(which, mode):
+    p = 3
+    mesh = mg.periodic_square(4, 3, 2.0, 1.5) if which == "periodic" else mg.ogrid(12, 4, 0.5, 4.0, 1.2)
+    kw = dict(theta=1.0, penalty_mode=mode, C_pen=0.7)
+    s = _host_solver(mesh, p, **kw)
+    dg = build(mesh, p, **kw)
+    m = dg.mesh
+    geo = s.table("geo").reshape(m.K, 16)
+    assert np.abs(geo[:, 0] - m.rx).max() < 1e-13 * np.abs(m.rx).max()
+    assert np.abs(geo[:, 3] - m.sy).max() < 1e-13 * np.abs(m.sy).max()
+    for f in range(3):
+        assert np.abs(geo[:, 4 + 4 * f] - m.nx[f]).max() < 1e-14
+        assert np.abs(geo[:, 5 + 4 * f] - m.ny[f]).max() < 1e-14
+        assert np.abs(geo[:, 6 + 4 * f] - m.Fscale[f]).max() < 1e-13 * m.Fscale.max()
+    # sigma_geo * G-bar equals the oracle's sigma for any G-bar
+    sig = dg.penalty(np.ones((3, m.K)))
+    for f in range(3):
+        assert np.abs(geo[:, 7 + 4 * f] - sig[f]).max() < 1e-12 * sig.max()
+    nbr = s.table("nbr").reshape(m.K, 3).astype(int)
+    want = np.where(m.EToE >= 0, m.EToE, np.arange(m.K)[:, None])
+    assert np.array_equal(nbr, want)
+    x, y = s.nodes()
+    assert np.abs(x - m.x.T).max() < 1e-13 and np.abs(y - m.y.T).max() < 1e-13
+    s.close()
+
+
+def test_error_codes():
+    from paper_2508_17917_amd import _lib as L
+    with pytest.raises(L.DGError) as e:
+        L.dg_create(0)
+    assert e.value.code == L.DG_EUNSUPPORTED
+    with pytest.raises(L.DGError) as e:
+        L.dg_create(3, precision=7)
+    assert e.value.code == L.DG_EUNSUPPORTED
+    h = L.dg_create(2)
+    try:
+        # set-up before physics/mesh -> out of order
+        with pytest.raises(L.DGError) as e:
+            L.dg_setup_host(h)
+        assert e.value.code == L.DG_ESTATE
+        with pytest.raises(L.DGError) as e:
+            L.dg_set_physics(h, 0.9, 0.72, 1e-3, 1.0, 0, 0.01, [1, 0, 0, 1])
+        assert e.value.code == L.DG_EINVAL
+        L.dg_set_physics(h, 1.4, 0.72, 1e-3, 1.0, 0, 0.01, [1, 0, 0, 1.8])
+        mesh = mg.periodic_square(3, 3, 1.0, 1.0)
+        # clockwise element
+        E = mesh["EToV"].copy()
+        E[4] = E[4][::-1]
+        L.dg_set_mesh(h, mesh["VX"], mesh["VY"], E, mesh["face_tag"], mesh["period"])
+        with pytest.raises(L.DGError) as e:
+            L.dg_setup_host(h)
+        assert e.value.code == L.DG_EMESH and "J <= 0" in str(e.value)
+        # not periodic: the outer faces tagged interior have no partner
+        L.dg_set_mesh(h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh["face_tag"], (0.0, 0.0))
+        with pytest.raises(L.DGError) as e:
+            L.dg_setup_host(h)
+        assert e.value.code == L.DG_EMESH
+        # a boundary tag on a shared face
+        ft = mesh["face_tag"].copy()
+        ft[0, 2] = 1
+        L.dg_set_mesh(h, mesh["VX"], mesh["VY"], mesh["EToV"], ft, mesh["period"])
+        with pytest.raises(L.DGError) as e:
+            L.dg_setup_host(h)
+        assert e.value.code == L.DG_EMESH
+        L.dg_set_mesh(h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh["face_tag"], mesh["period"])
+        L.dg_setup_host(h)
+        # device calls before dg_setup -> out of order, no GPU touched
+        import torch
+        U = torch.zeros(1, dtype=torch.float64)
+        R = torch.zeros(1, dtype=torch.float64)
+        with pytest.raises(L.DGError) as e:
+            L.dg_rhs(h, U, R, stream=0)
+        assert e.value.code == L.DG_ESTATE
+        with pytest.raises(L.DGError) as e:
+            L.dg_rk_step(h, U, R, 1e-3, stream=0)
+        assert e.value.code == L.DG_ESTATE
+        assert "dg_setup" in L.dg_last_error(h)
+    finally:
+        L.dg_destroy(h)
+
+
+def test_newmark_matches_oracle():
+    from paper_2508_17917_amd import _lib as L
+    from oracle import fsi
+    st = np.array([0.1, -0.2, 0.3])
+    got = L.dg_newmark_step(st, 0.7, 0.05, 1.0, 0.1, 2.3)
+    want = fsi.newmark_step(0.1, -0.2, 0.3, 0.7, 0.05, 1.0, 0.1, 2.3)
+    assert np.abs(got - np.array(want)).max() < 1e-15

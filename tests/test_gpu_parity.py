@@ -1,0 +1,164 @@
+"""GPU parity of the HIP path against the FP64 oracle (needs an MI355X).
+
+Tolerance (FP64): per field, max |R_gpu - R_oracle| <= 1e-12 * max |R_oracle|.
+The GPU evaluates the strong form and the oracle the weak form; they are
+equal in exact arithmetic and differ here only by rounding, which on the
+cancellation-heavy near-free-stream cases is a few 1e-14 of the largest
+individual term.  Inputs are seeded synthetic states of the workloads'
+shapes (meshgen), identical on both sides.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from oracle import fsi
+from oracle.dg import LSERK_A, LSERK_B
+from tests.oracle_helpers import build
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print("[gpu-case] " + msg, flush=True)
+
+
+def _solver(mesh, p, phys):
+    from paper_2508_17917_amd import Solver
+    return Solver(p, mesh, gamma=phys.gamma, Pr=phys.Pr, mu=phys.mu, theta=phys.theta,
+                  penalty_mode=phys.penalty_mode, C_pen=phys.C_pen, U_inf=phys.U_inf)
+
+
+def _to_dev(torch, U):
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(U, (2, 0, 1)))).cuda()
+
+
+def _from_dev(T):
+    return np.transpose(T.cpu().numpy(), (1, 2, 0))
+
+
+def _check(got, want, tol=TOL, what=""):
+    for f in range(4):
+        scale = np.abs(want[f]).max()
+        err = np.abs(got[f] - want[f]).max()
+        assert err <= tol * scale, "%s field %d: err %.3e scale %.3e ratio %.3e" % (
+            what, f, err, scale, err / scale)
+
+
+CASES = [
+    # name, mesh builder, p, physics overrides, state recipe, v_w
+    ("vortex-periodic-p3", lambda: mg.periodic_square(5, 4, 10.0, 8.0), 3,
+     dict(mu=3e-3, penalty_mode=1, C_pen=1.0, U_inf=mg.free_stream(0.3)), "vortex", (0.0, 0.0)),
+    ("cylinder-p4", lambda: mg.ogrid(12, 5, 0.5, 6.0, 1.3), 4,
+     dict(mu=2e-3, penalty_mode=0, C_pen=1.0), "noise", (0.0, 0.0)),
+    ("cylinder-moving-p4", lambda: mg.ogrid(10, 4, 0.5, 5.0, 1.3), 4,
+     dict(mu=2e-3, penalty_mode=0, C_pen=1.0), "noise", (0.013, -0.021)),
+    ("cylinder-p5-iipg", lambda: mg.ogrid(9, 4, 0.5, 5.0, 1.3), 5,
+     dict(mu=2e-3, penalty_mode=0, C_pen=0.01, theta=0.0), "noise", (0.0, 0.0)),
+    ("periodic-p6", lambda: mg.periodic_square(4, 4, 10.0, 10.0), 6,
+     dict(mu=3e-3, penalty_mode=0, C_pen=1.0, U_inf=mg.free_stream(0.3)), "fourier", (0.0, 0.0)),
+    ("two-elements-p2", lambda: mg.periodic_square(1, 1, 1.0, 1.0), 2,
+     dict(mu=1e-2, penalty_mode=1, C_pen=1.0), "fourier", (0.0, 0.0)),
+    ("periodic-p1-nipg", lambda: mg.periodic_square(7, 3, 2.0, 1.0), 1,
+     dict(mu=1e-2, penalty_mode=1, C_pen=2.0, theta=-1.0), "fourier", (0.05, 0.0)),
+]
+
+
+def _state(dg, recipe, seed):
+    m = dg.mesh
+    rng = np.random.default_rng(seed)
+    if recipe == "vortex":
+        return mg.isentropic_vortex(m.x, m.y, M=0.3, xc=5.0, yc=4.0, Lper=None)
+    if recipe == "noise":
+        return mg.noisy_free_stream((4,) + m.x.shape, dg.phys.U_inf, rng)
+    L = max(np.ptp(m.x), np.ptp(m.y))
+    return mg.fourier_modes(m.x, m.y, rng, L=L, amp=0.05, q0=(1.0, 0.3, 0.0, 1.0 / 1.4))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_rhs_parity(case):
+    torch = _torch()
+    name, mk, p, over, recipe, vw = case
+    mesh = mk()
+    dg = build(mesh, p, **over)
+    U = _state(dg, recipe, 7)
+    want = dg.rhs(U, vw)
+    _say("rhs %s K=%d p=%d" % (name, dg.mesh.K, p))
+    s = _solver(mesh, p, dg.phys)
+    Ud = _to_dev(torch, U)
+    R = s.rhs(Ud, v_w=vw)
+    torch.cuda.synchronize()
+    _check(_from_dev(R), want, what=name)
+    # bitwise reproducible
+    R2 = s.rhs(Ud, v_w=vw)
+    torch.cuda.synchronize()
+    assert torch.equal(R, R2)
+    s.close()
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_rk_step_parity(case):
+    torch = _torch()
+    name, mk, p, over, recipe, vw = case
+    mesh = mk()
+    dg = build(mesh, p, **over)
+    U = _state(dg, recipe, 11)
+    dt = 1e-4
+    want, _ = dg.lserk_step(U, dt, vw)
+    _say("rk_step %s K=%d p=%d" % (name, dg.mesh.K, p))
+    s = _solver(mesh, p, dg.phys)
+    Ud = _to_dev(torch, U)
+    K1 = torch.full_like(Ud, float("nan"))  # A_1 = 0: K1 is never read
+    s.rk_step(Ud, K1, dt, v_w=vw)
+    torch.cuda.synchronize()
+    got = _from_dev(Ud)
+    # compare increments (U changes by O(dt |R|))
+    _check(got - U, want - U, tol=1e-11, what=name)
+    # the stage entry point chained by hand gives the same bits
+    Ua = _to_dev(torch, U)
+    Ub = torch.empty_like(Ua)
+    K1b = torch.zeros_like(Ua)
+    for i, (a, b) in enumerate(zip(LSERK_A, LSERK_B)):
+        src, dst = (Ua, Ub) if i % 2 == 0 else (Ub, Ua)
+        s.rk_stage(src, dst, K1b, a, b, dt, v_w=vw)
+    torch.cuda.synchronize()
+    assert torch.equal(Ub, Ud)
+    s.close()
+
+
+def test_force_parity():
+    torch = _torch()
+    mesh = mg.ogrid(16, 4, 0.5, 5.0, 1.3)
+    for p, vw in [(3, (0.0, 0.0)), (4, (0.01, -0.02))]:
+        dg = build(mesh, p, mu=5e-3, penalty_mode=0, C_pen=1.0)
+        U = _state(dg, "noise", 5)
+        want = fsi.wall_force(dg, U, vw)
+        _say("force p=%d" % p)
+        s = _solver(mesh, p, dg.phys)
+        got = s.force(_to_dev(torch, U), v_w=vw)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+        s.close()
+
+
+def test_rhs_parity_cylinder20k_full_size():
+    """The benchmark workload at full size (80 x 128 O-grid, K = 20480, p = 4)."""
+    torch = _torch()
+    w = mg.workload("cylinder20k")
+    dg = build(w["mesh"], w["p"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+               penalty_mode=w["penalty_mode"], C_pen=1.0, U_inf=w["U_inf"])
+    U = mg.noisy_free_stream((4,) + dg.mesh.x.shape, dg.phys.U_inf, mg.rng_for(1))
+    want = dg.rhs(U)
+    _say("rhs cylinder20k K=%d" % dg.mesh.K)
+    s = _solver(w["mesh"], w["p"], dg.phys)
+    R = s.rhs(_to_dev(torch, U))
+    torch.cuda.synchronize()
+    _check(_from_dev(R), want, what="cylinder20k")
+    s.close()
