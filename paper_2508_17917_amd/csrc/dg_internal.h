@@ -51,7 +51,8 @@ bool build_mesh_tables(const RefOps& ref, const Physics& phys, int64_t Nv, const
 struct DeviceTables {
   const double* geo = nullptr;     // K x 16
   const int32_t* conn = nullptr;   // K x 3
-  const double* ops = nullptr;     // packed operators, see ops_offsets
+  const double* ops = nullptr;     // packed operators (pack_ops)
+  const double* frag = nullptr;    // operator fragments in matrix-core lane order (pack_frags)
   const int32_t* wall = nullptr;   // wall face list (k*3 + f)
   const double* wall_xy = nullptr; // node coordinates of the wall faces, (x, y) per face node
   int64_t K = 0;
@@ -73,5 +74,9 @@ int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const do
 // operator packing: Dr | Ds | LIFT | LIFTr | LIFTs | Fmask (as doubles) | wface
 size_t ops_packed_size(int N);
 void pack_ops(const RefOps& ref, std::vector<double>& out);
+// Dr | Ds | LIFT | LIFTr | LIFTs as B-operand fragments of the 16x16x4 FP64
+// matrix instruction: for output tile t (nodes 16t..16t+15) and k-step s,
+// lane l holds Op[16t + l%16][4s + l/16] (zero outside the matrix).
+void pack_frags(const RefOps& ref, std::vector<double>& out);
 
 }  // namespace dgmi

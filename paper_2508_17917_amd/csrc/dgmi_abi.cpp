@@ -40,6 +40,7 @@ struct dg_ctx {
   double* d_geo = nullptr;
   int32_t* d_conn = nullptr;
   double* d_ops = nullptr;
+  double* d_frag = nullptr;
   int32_t* d_wall = nullptr;
   double* d_wall_xy = nullptr;
   double* d_scratch = nullptr;
@@ -65,12 +66,14 @@ int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 void free_device(dg_ctx* c) {
-  void* ptrs[] = {c->d_geo, c->d_conn, c->d_ops, c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force};
+  void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,
+                  c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   c->d_geo = nullptr;
   c->d_conn = nullptr;
   c->d_ops = nullptr;
+  c->d_frag = nullptr;
   c->d_wall = nullptr;
   c->d_wall_xy = nullptr;
   c->d_scratch = nullptr;
@@ -93,6 +96,7 @@ dgmi::DeviceTables tables(const dg_ctx* c) {
   t.geo = c->d_geo;
   t.conn = c->d_conn;
   t.ops = c->d_ops;
+  t.frag = c->d_frag;
   t.wall = c->d_wall;
   t.wall_xy = c->d_wall_xy;
   t.K = c->K;
@@ -197,11 +201,13 @@ int dg_setup(dg_ctx* c) {
   free_device(c);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
-  std::vector<double> ops;
+  std::vector<double> ops, frag;
   dgmi::pack_ops(c->ref, ops);
+  dgmi::pack_frags(c->ref, frag);
   if ((e = upload(&c->d_geo, c->mesh.geo)) != hipSuccess ||
       (e = upload(&c->d_conn, c->mesh.conn)) != hipSuccess ||
       (e = upload(&c->d_ops, ops)) != hipSuccess ||
+      (e = upload(&c->d_frag, frag)) != hipSuccess ||
       (e = upload(&c->d_wall, c->mesh.wall_faces)) != hipSuccess ||
       (e = upload(&c->d_wall_xy, c->mesh.wall_xy)) != hipSuccess) {
     free_device(c);

@@ -442,6 +442,25 @@ void pack_ops(const RefOps& ref, std::vector<double>& out) {
   out.insert(out.end(), ref.wface.begin(), ref.wface.end());
 }
 
+void pack_frags(const RefOps& ref, std::vector<double>& out) {
+  const int Np = ref.Np, NF = 3 * ref.Nfp;
+  const int NT = (Np + 15) / 16, KS = (Np + 3) / 4, KF = (NF + 3) / 4;
+  out.clear();
+  auto emit = [&](const std::vector<double>& M, int cols, int ksteps) {
+    for (int t = 0; t < NT; ++t)
+      for (int s = 0; s < ksteps; ++s)
+        for (int l = 0; l < 64; ++l) {
+          int row = 16 * t + l % 16, col = 4 * s + l / 16;
+          out.push_back((row < Np && col < cols) ? M[row * cols + col] : 0.0);
+        }
+  };
+  emit(ref.Dr, Np, KS);
+  emit(ref.Ds, Np, KS);
+  emit(ref.LIFT, NF, KF);
+  emit(ref.LIFTr, NF, KF);
+  emit(ref.LIFTs, NF, KF);
+}
+
 size_t ops_packed_size(int N) {
   size_t Np = (N + 1) * (N + 2) / 2, NF = 3 * (N + 1);
   return 2 * Np * Np + 3 * Np * NF + NF;

@@ -1,22 +1,24 @@
 // HIP kernels for gfx950: the fused right-hand side + low-storage RK stage,
 // and the wall-force reduction.
 //
-// One workgroup owns a tile of EPB elements at a time (grid-stride over
-// tiles, operators staged in LDS once per workgroup).  Per tile, in the
-// order of Alg. 2 (with the neighbour exchange replaced by reads of the
-// neighbours' nodal states, which on one GPU are resident in HBM/L2):
-//   A  own states, neighbour states and geometry -> LDS
-//   B  volume nodes: broken gradient grad U = (rx Dr + sx Ds, ry Dr + sy Ds) U,
-//      total flux F = F_c - v_w (x) U - G grad U, contravariant (Fr, Fs)
-//   C  face nodes: neighbour trace and gradient (reversed face node order),
-//      boundary ghosts (Sec. 2.2.4), G-bar_e (max over the face of
-//      ||n^T G n||_2 on both sides), sigma_e, Roe flux, viscous average,
-//      penalty, theta term
-//   D  volume nodes: R = -(Dr Fr + Ds Fs) + LIFT h + LIFTr qr + LIFTs qs
-//      (strong form; M^-1 and 1/J folded into the operators and Fscale),
-//      then K1 <- a K1 + dt R, U_out <- U_in + b K1 (Alg. 1).
-// Every element writes only its own nodes; faces are evaluated once from
-// each side, so there are no atomics and results are bitwise reproducible.
+// Stage kernel, per wavefront and tile of four elements, in the order of
+// Alg. 2 (the neighbour exchange becomes reads of the neighbours' nodal
+// states, resident in HBM / L2 on one GPU):
+//   1  own states, neighbour states and geometry -> LDS
+//   2  broken gradient on the FP64 matrix cores: rows (element, field),
+//      columns nodes, [dU/dr, dU/ds] = U [Dr^T, Ds^T]; the output lane owns one
+//      node of one element with all four fields -> total flux
+//      F = F_c - v_w (x) U - G grad U and its contravariant components
+//   3  face nodes (one lane each): neighbour trace and gradient (reversed face
+//      node order), boundary ghosts (Sec. 2.2.4), G-bar_e = max over the face of
+//      ||n^T G n||_2 on both sides, sigma_e, Roe flux, viscous average,
+//      penalty and theta term
+//   4  strong-form residual on the matrix cores,
+//      R = -(Dr Fr + Ds Fs) + LIFT h + LIFTr qr + LIFTs qs
+//      (M^-1 and 1/J folded into the operators and Fscale), then
+//      K1 <- a K1 + dt R, U_out <- U_in + b K1 (Alg. 1).
+// Every element writes only its own nodes and each face is evaluated from both
+// sides, so there are no atomics and results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -31,10 +33,27 @@ struct Order {
   static constexpr int Np = (N + 1) * (N + 2) / 2;
   static constexpr int Nfp = N + 1;
   static constexpr int NF = 3 * (N + 1);
-  static constexpr int ITEMS = Np > NF ? Np : NF;
-  static constexpr int THREADS = 128;
-  static constexpr int EPB = THREADS / ITEMS;
-  static constexpr int HSZ = (12 * NF > 12 * Np) ? 12 * NF : 12 * Np;  // per element, sN | sH
+  static constexpr int S = 4 * Np;               // doubles per element state
+  static constexpr int NT = (Np + 15) / 16;      // 16-node output tiles
+  static constexpr int KS = (Np + 3) / 4;        // k-steps over volume nodes
+  static constexpr int KF = (NF + 3) / 4;        // k-steps over face nodes
+  static constexpr int RS = 4 * KS + 1;          // padded LDS row (odd: no bank aliasing)
+  static constexpr int HRS = 4 * KF + 1;
+  static constexpr int FIT = (4 * NF + 63) / 64; // face items per lane
+  static constexpr int WAVES = (N <= 4) ? 4 : 2;
+  static constexpr int THREADS = 64 * WAVES;
+  // per-wave LDS (doubles)
+  static constexpr int U_SZ = 16 * RS;           // own state, row 4c + e
+  static constexpr int F_SZ = 32 * RS;           // contravariant flux Fr rows | Fs rows
+  static constexpr int N_SZ = 12 * S;            // neighbour states [e][f][c][n]
+  static constexpr int H_SZ = 48 * HRS;          // face terms h | qr | qs, row 4c + e
+  static constexpr int X_SZ = N_SZ > H_SZ ? N_SZ : H_SZ;
+  static constexpr int NORM_SZ = 4 * NF;
+  static constexpr int WAVE_SZ = U_SZ + F_SZ + X_SZ + NORM_SZ + 64 + 48;
+  // operator fragments (per workgroup)
+  static constexpr int FD = NT * KS * 64;        // one Dr-type fragment set
+  static constexpr int FL = NT * KF * 64;        // one LIFT-type fragment set
+  static constexpr int FRAG_SZ = 2 * FD + 3 * FL;
 };
 
 // Node index of face node j (counter-clockwise) on face f; rows of the node
@@ -47,40 +66,63 @@ __device__ __forceinline__ int face_node(int f, int j) {
   return i * (N + 1) - i * (i - 1) / 2;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D += A B for A 16x4, B 4x16, D 16x16 (FP64 matrix core).  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4v][l%16], v = 0..3.
+// With rows ordered (field c, element e) -> 4c + e, lane l therefore ends up
+// with node l%16 of element l/16, all four fields in v = c.
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// LDS ordering among the lanes of one wavefront (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double lane_read(double v, int src) {
+  int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+  int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// The fused right-hand side + LSERK stage.  Each wavefront owns tiles of four
+// elements (16 MFMA rows = 4 fields x 4 elements); the workgroup only shares
+// the operator fragments.  Tiles are handed out in contiguous ranges per XCD
+// (workgroup b runs on XCD b % 8) so neighbour reads stay in that XCD's L2.
 template <int N>
-__global__ __launch_bounds__(128) void stage_kernel(DeviceTables t, KernelPhysics ph,
-                                                    const double* __restrict__ Uin,
-                                                    double* __restrict__ Uout,
-                                                    double* __restrict__ K1, double a, double b,
-                                                    double dt, int rhs_only) {
+__global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(
+    DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin, double* __restrict__ Uout,
+    double* __restrict__ K1, double a, double b, double dt, int rhs_only) {
   using O = Order<N>;
-  constexpr int Np = O::Np, Nfp = O::Nfp, NF = O::NF, EPB = O::EPB, T = O::THREADS;
-  constexpr int S = 4 * Np;  // doubles per element state
+  constexpr int Np = O::Np, Nfp = O::Nfp, NF = O::NF, S = O::S, NT = O::NT, KS = O::KS,
+                KF = O::KF, RS = O::RS, HRS = O::HRS, FIT = O::FIT;
+  constexpr int OFF_DR = 0, OFF_DS = O::FD, OFF_L = 2 * O::FD, OFF_LR = 2 * O::FD + O::FL,
+                OFF_LS = 2 * O::FD + 2 * O::FL;
+  __shared__ double sFrag[O::FRAG_SZ];
+  __shared__ double sWave[O::WAVES][O::WAVE_SZ];
+  __shared__ int sConnW[O::WAVES][12];
 
-  __shared__ double sDr[Np * Np], sDs[Np * Np];
-  __shared__ double sL[Np * NF], sLr[Np * NF], sLs[Np * NF];
-  __shared__ double sU[EPB][4][Np];
-  __shared__ double sG[EPB][8][Np];   // grad U: x-derivatives 0..3, y 4..7
-  __shared__ double sF[EPB][8][Np];   // contravariant flux: Fr 0..3, Fs 4..7
-  __shared__ double sX[EPB][O::HSZ];  // phase A/C: neighbour states; C/D: face terms
-  __shared__ double sNorm[EPB][NF];
-  __shared__ double sGeo[EPB][kGeoStride];
-  __shared__ double sNGeo[EPB][3][4];
-  __shared__ int sConn[EPB][3];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < O::FRAG_SZ; i += O::THREADS) sFrag[i] = t.frag[i];
+  for (int i = lane; i < O::WAVE_SZ; i += 64) sWave[wid][i] = 0.0;  // zero pads once
+  __syncthreads();
 
-  const int tid = threadIdx.x;
-  const int64_t K = t.K;
-  const int64_t ntiles = (K + EPB - 1) / EPB;
-
-  for (int i = tid; i < Np * Np; i += T) {
-    sDr[i] = t.ops[i];
-    sDs[i] = t.ops[Np * Np + i];
-  }
-  for (int i = tid; i < Np * NF; i += T) {
-    sL[i] = t.ops[2 * Np * Np + i];
-    sLr[i] = t.ops[2 * Np * Np + Np * NF + i];
-    sLs[i] = t.ops[2 * Np * Np + 2 * Np * NF + i];
-  }
+  double* sU = &sWave[wid][0];
+  double* sFr = sU + O::U_SZ;
+  double* sFs = sFr + 16 * RS;
+  double* sX = sU + O::U_SZ + O::F_SZ;   // neighbour states, later face terms
+  double* sH = sX;
+  double* sQr = sX + 16 * HRS;
+  double* sQs = sX + 32 * HRS;
+  double* sNorm = sX + O::X_SZ;
+  double* sGeo = sNorm + O::NORM_SZ;     // [4][16]
+  double* sNGeo = sGeo + 64;             // [4][3][4]
+  int* sConn = sConnW[wid];              // [4][3]
 
   Gas gas;
   gas.gamma = ph.gamma;
@@ -88,223 +130,260 @@ __global__ __launch_bounds__(128) void stage_kernel(DeviceTables t, KernelPhysic
   gas.mu = ph.mu;
   gas.k = ph.gamma / ph.Pr;
   const double theta = ph.theta;
+  const double vwx = ph.vw[0], vwy = ph.vw[1];
 
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t e0 = tile * EPB;
-    const int nel = (int)((K - e0) < EPB ? (K - e0) : EPB);
-    __syncthreads();  // previous tile done with LDS (and operators staged)
-    // ---- A: own states, geometry, connectivity
-    for (int i = tid; i < nel * S; i += T) (&sU[0][0][0])[i] = Uin[e0 * S + i];
-    for (int i = tid; i < nel * kGeoStride; i += T) (&sGeo[0][0])[i] = t.geo[e0 * kGeoStride + i];
-    for (int i = tid; i < nel * 3; i += T) (&sConn[0][0])[i] = t.conn[e0 * 3 + i];
-    __syncthreads();
-    // neighbour states (boundary faces point at the element itself) and metrics
-    for (int i = tid; i < nel * 3 * S; i += T) {
+  const int64_t K = t.K;
+  const int64_t ntiles = (K + 3) / 4;
+  const int xcd = blockIdx.x & 7;
+  const int nbx = gridDim.x >> 3;
+  const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
+  const int64_t w0 = (int64_t)(blockIdx.x >> 3) * O::WAVES + wid;
+  const int64_t wstride = (int64_t)nbx * O::WAVES;
+
+  const int arow = lane & 15, acol = lane >> 4;  // A-operand row (4c + e), k offset
+  const int re = lane >> 4, rn = lane & 15;      // output: element re, node 16 t + rn
+
+  for (int64_t tile = tb + w0; tile < te; tile += wstride) {
+    const int64_t e0 = tile * 4;
+    const int nel = (int)((K - e0) < 4 ? (K - e0) : 4);
+    wave_sync();
+    // ---- own states, geometry, connectivity
+    for (int i = lane; i < nel * S; i += 64) {
+      int e = i / S, r = i - e * S, c = r / Np, n = r - c * Np;
+      sU[(4 * c + e) * RS + n] = Uin[e0 * S + i];
+    }
+    for (int i = lane; i < nel * kGeoStride; i += 64) sGeo[i] = t.geo[e0 * kGeoStride + i];
+    for (int i = lane; i < nel * 3; i += 64) sConn[i] = t.conn[e0 * 3 + i];
+    wave_sync();
+    // ---- neighbour states (a boundary face points at the element itself) and metrics
+    for (int i = lane; i < nel * 3 * S; i += 64) {
       int ef = i / S, r = i - ef * S;
-      int nb = sConn[ef / 3][ef % 3] >> 4;
-      sX[ef / 3][(ef % 3) * S + r] = Uin[(int64_t)nb * S + r];
+      sX[i] = Uin[(int64_t)(sConn[ef] >> 4) * S + r];
     }
-    for (int i = tid; i < nel * 12; i += T) {
-      int ef = i / 4, c = i - ef * 4;
-      int nb = sConn[ef / 3][ef % 3] >> 4;
-      sNGeo[ef / 3][ef % 3][c] = t.geo[(int64_t)nb * kGeoStride + c];
+    for (int i = lane; i < nel * 12; i += 64) {
+      int ef = i >> 2;
+      sNGeo[i] = t.geo[(int64_t)(sConn[ef] >> 4) * kGeoStride + (i & 3)];
     }
-    __syncthreads();
+    wave_sync();
 
-    // ---- B: gradient and contravariant flux at volume nodes
-    {
-      const int e = tid / Np, n = tid - (tid / Np) * Np;
-      if (e < nel) {
-        double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
-#pragma unroll 4
-        for (int m = 0; m < Np; ++m) {
-          double dr = sDr[n * Np + m], ds = sDs[n * Np + m];
+    // ---- gradient on the matrix cores, then the volume flux per node
+    double gxk[NT][4], gyk[NT][4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            double u = sU[e][c][m];
-            ur[c] += dr * u;
-            us[c] += ds * u;
-          }
-        }
-        const double rx = sGeo[e][0], ry = sGeo[e][1], sx = sGeo[e][2], sy = sGeo[e][3];
-        double U[4], dx[4], dy[4];
+    for (int tt = 0; tt < NT; ++tt) {
+      d4 aR = {0.0, 0.0, 0.0, 0.0}, aS = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          U[c] = sU[e][c][n];
-          dx[c] = rx * ur[c] + sx * us[c];
-          dy[c] = ry * ur[c] + sy * us[c];
-          sG[e][c][n] = dx[c];
-          sG[e][4 + c][n] = dy[c];
-        }
+      for (int s = 0; s < KS; ++s) {
+        const double av = sU[arow * RS + 4 * s + acol];
+        aR = mfma(av, sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aR);
+        aS = mfma(av, sFrag[OFF_DS + (tt * KS + s) * 64 + lane], aS);
+      }
+      const int n = 16 * tt + rn;
+      const bool ok = (re < nel) && (n < Np);
+      const double* g = sGeo + re * kGeoStride;
+      const double rx = ok ? g[0] : 0.0, ry = ok ? g[1] : 0.0;
+      const double sx = ok ? g[2] : 0.0, sy = ok ? g[3] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        gxk[tt][c] = rx * aR[c] + sx * aS[c];
+        gyk[tt][c] = ry * aR[c] + sy * aS[c];
+      }
+      if (ok) {
+        double U[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) U[c] = sU[(4 * c + re) * RS + n];
         double fvx[4], fvy[4];
-        viscous_flux(gas, U, dx, dy, fvx, fvy);
-        double ir = 1.0 / U[0];
-        double u = U[1] * ir, v = U[2] * ir;
-        double p = gas.gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
-        double Fx[4], Fy[4];
-        Fx[0] = U[0] * (u - ph.vw[0]);
-        Fx[1] = U[1] * (u - ph.vw[0]) + p;
-        Fx[2] = U[2] * (u - ph.vw[0]);
-        Fx[3] = U[3] * (u - ph.vw[0]) + p * u;
-        Fy[0] = U[0] * (v - ph.vw[1]);
-        Fy[1] = U[1] * (v - ph.vw[1]);
-        Fy[2] = U[2] * (v - ph.vw[1]) + p;
-        Fy[3] = U[3] * (v - ph.vw[1]) + p * v;
+        viscous_flux(gas, U, gxk[tt], gyk[tt], fvx, fvy);
+        const double ir = 1.0 / U[0];
+        const double u = U[1] * ir, v = U[2] * ir;
+        const double p = gas.gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
+        const double qu = u - vwx, qv = v - vwy;
+        double Fx[4] = {U[0] * qu, U[1] * qu + p, U[2] * qu, U[3] * qu + p * u};
+        double Fy[4] = {U[0] * qv, U[1] * qv, U[2] * qv + p, U[3] * qv + p * v};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          double fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
-          sF[e][c][n] = rx * fx + ry * fy;
-          sF[e][4 + c][n] = sx * fx + sy * fy;
+          const double fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
+          sFr[(4 * c + re) * RS + n] = rx * fx + ry * fy;
+          sFs[(4 * c + re) * RS + n] = sx * fx + sy * fy;
         }
       }
     }
-    __syncthreads();
+    wave_sync();
 
-    // ---- C: face nodes
-    const int fe = tid / NF, fn = tid - (tid / NF) * NF;
-    const bool fvalid = fe < nel;
-    const int f = fn / Nfp, j = fn - (fn / Nfp) * Nfp;
-    double Up[4], Uo[4], gxp[4], gyp[4], gxm[4], gym[4];
-    double nx = 0, ny = 0, fsc = 0, sgeo = 0;
-    int tag = 0;
-    if (fvalid) {
+    // ---- face nodes: traces, ghosts, G-bar, fluxes
+    double Up[FIT][4], Uo[FIT][4], Vp[FIT][4], Vm[FIT][4];
+#pragma unroll
+    for (int q = 0; q < FIT; ++q) {
+      const int it = lane + 64 * q;
+      int e = it / NF;
+      const int fn = it - e * NF;
+      const bool ok = (it < 4 * NF) && (e < nel);
+      e = e < 4 ? e : 3;
+      const int f = fn / Nfp, j = fn - f * Nfp;
       const int n = face_node<N>(f, j);
-      const int conn = sConn[fe][f];
-      tag = conn & 3;
-      const int nf = (conn >> 2) & 3;
-      nx = sGeo[fe][4 + 4 * f];
-      ny = sGeo[fe][5 + 4 * f];
-      fsc = sGeo[fe][6 + 4 * f];
-      sgeo = sGeo[fe][7 + 4 * f];
+      // own gradient at the face node from the lane that computed it
+      double gxp[4], gyp[4];
+      const int src = 16 * e + (n & 15);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        Up[c] = sU[fe][c][n];
-        gxp[c] = sG[fe][c][n];
-        gyp[c] = sG[fe][4 + c][n];
-      }
-      if (tag == 0) {
-        const int n2 = face_node<N>(nf, Nfp - 1 - j);
-        const double* nbU = &sX[fe][f * S];
-        double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
-#pragma unroll 4
-        for (int m = 0; m < Np; ++m) {
-          double dr = sDr[n2 * Np + m], ds = sDs[n2 * Np + m];
+      for (int tt = 0; tt < NT; ++tt) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            double u = nbU[c * Np + m];
-            ur[c] += dr * u;
-            us[c] += ds * u;
+        for (int c = 0; c < 4; ++c) {
+          const double vx = lane_read(gxk[tt][c], src), vy = lane_read(gyk[tt][c], src);
+          if ((n >> 4) == tt) {
+            gxp[c] = vx;
+            gyp[c] = vy;
           }
         }
-        const double rx = sNGeo[fe][f][0], ry = sNGeo[fe][f][1];
-        const double sx = sNGeo[fe][f][2], sy = sNGeo[fe][f][3];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          Uo[c] = nbU[c * Np + n2];
-          gxm[c] = rx * ur[c] + sx * us[c];
-          gym[c] = ry * ur[c] + sy * us[c];
-        }
-      } else if (tag == 1) {
-        // moving adiabatic wall: Q^b = [rho+, v_w, p+]
-        double p = pressure(Up, gas.gm1);
-        Uo[0] = Up[0];
-        Uo[1] = Up[0] * ph.vw[0];
-        Uo[2] = Up[0] * ph.vw[1];
-        Uo[3] = p / gas.gm1 + 0.5 * Up[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1]);
-      } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) Uo[c] = ph.U_inf[c];
       }
-      double a1 = normal_diffusion_norm(gas, Up, nx, ny);
-      double a2 = normal_diffusion_norm(gas, Uo, nx, ny);
-      sNorm[fe][fn] = a1 > a2 ? a1 : a2;
-    }
-    __syncthreads();
-    if (fvalid) {
-      double gbar = 0.0;
+      if (ok) {
+        const int conn = sConn[e * 3 + f];
+        const int tag = conn & 3, nf = (conn >> 2) & 3;
+        const double* g = sGeo + e * kGeoStride;
+        const double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
 #pragma unroll
-      for (int jj = 0; jj < Nfp; ++jj) {
-        double v = sNorm[fe][f * Nfp + jj];
-        gbar = v > gbar ? v : gbar;
-      }
-      const double sigma = sgeo * gbar;
-      const double vwn = ph.vw[0] * nx + ph.vw[1] * ny;
-      double Fc[4];
-      if (tag == 1) {
-        double p = pressure(Up, gas.gm1);
-        Fc[0] = 0.0;
-        Fc[1] = p * nx;
-        Fc[2] = p * ny;
-        Fc[3] = p * vwn;
-      } else {
-        roe_flux(Up, Uo, nx, ny, vwn, gas.gm1, Fc);
-      }
-      double vxa[4], vya[4], vn[4];
-      if (tag == 0) {
-        double vxb[4], vyb[4];
-        viscous_flux(gas, Up, gxp, gyp, vxa, vya);
-        viscous_flux(gas, Uo, gxm, gym, vxb, vyb);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) vn[c] = 0.5 * ((vxa[c] + vxb[c]) * nx + (vya[c] + vyb[c]) * ny);
-      } else {
-        viscous_flux(gas, tag == 1 ? Uo : Up, gxp, gyp, vxa, vya);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) vn[c] = vxa[c] * nx + vya[c] * ny;
-      }
-      // Fscale * (own total normal flux): -Fs (face 0), Fr + Fs (face 1), -Fr (face 2)
-      const int n = face_node<N>(f, j);
-      double w[4], h[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        double fr = sF[fe][c][n], fs = sF[fe][4 + c][n];
-        double own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
-        w[c] = Up[c] - Uo[c];
-        double Hm = Fc[c] - vn[c] + sigma * w[c];
-        h[c] = own - fsc * Hm;
-      }
-      double qx[4], qy[4];
-      viscous_transpose(gas, tag == 1 ? Uo : Up, nx, ny, w, qx, qy);
-      const double ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
-      const double rx = sGeo[fe][0], ry = sGeo[fe][1], sx = sGeo[fe][2], sy = sGeo[fe][3];
-      // sX is re-used for the face terms: every neighbour read preceded the barrier above
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        sX[fe][c * NF + fn] = h[c];
-        sX[fe][(4 + c) * NF + fn] = ce * (rx * qx[c] + ry * qy[c]);
-        sX[fe][(8 + c) * NF + fn] = ce * (sx * qx[c] + sy * qy[c]);
-      }
-    }
-    __syncthreads();
-
-    // ---- D: volume divergence + lift + RK update
-    {
-      const int e = tid / Np, n = tid - (tid / Np) * Np;
-      if (e < nel) {
-        double R[4] = {0, 0, 0, 0};
+        for (int c = 0; c < 4; ++c) Up[q][c] = sU[(4 * c + e) * RS + n];
+        // "other side" gradient from the staged neighbour (wall: the element itself)
+        const int n2 = (tag == 0) ? face_node<N>(nf, Nfp - 1 - j) : n;
+        const double* nbU = sX + (e * 3 + f) * S;
+        double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
+        const int dbase = ((n2 >> 4) * KS) * 64 + (n2 & 15);
 #pragma unroll 4
         for (int m = 0; m < Np; ++m) {
-          double dr = sDr[n * Np + m], ds = sDs[n * Np + m];
+          const int fi = dbase + (m >> 2) * 64 + (m & 3) * 16;
+          const double dr = sFrag[OFF_DR + fi], ds = sFrag[OFF_DS + fi];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) R[c] -= dr * sF[e][c][m] + ds * sF[e][4 + c][m];
+          for (int c = 0; c < 4; ++c) {
+            const double uu = nbU[c * Np + m];
+            ur[c] += dr * uu;
+            us[c] += ds * uu;
+          }
         }
-#pragma unroll 4
-        for (int m = 0; m < NF; ++m) {
-          double l = sL[n * NF + m], lr = sLr[n * NF + m], ls = sLs[n * NF + m];
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            R[c] += l * sX[e][c * NF + m] + lr * sX[e][(4 + c) * NF + m] +
-                    ls * sX[e][(8 + c) * NF + m];
-        }
-        const int64_t base = (e0 + e) * S + n;
+        const double* ng = sNGeo + (e * 3 + f) * 4;
+        double gxm[4], gym[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
+          gxm[c] = ng[0] * ur[c] + ng[2] * us[c];
+          gym[c] = ng[1] * ur[c] + ng[3] * us[c];
+        }
+        if (tag == 0) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Uo[q][c] = nbU[c * Np + n2];
+        } else if (tag == 1) {
+          const double p = pressure(Up[q], gas.gm1);
+          Uo[q][0] = Up[q][0];
+          Uo[q][1] = Up[q][0] * vwx;
+          Uo[q][2] = Up[q][0] * vwy;
+          Uo[q][3] = p / gas.gm1 + 0.5 * Up[q][0] * (vwx * vwx + vwy * vwy);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Uo[q][c] = ph.U_inf[c];
+        }
+        // viscous normal fluxes: own side G(U+) grad U+, other side G(U-) grad U-
+        // (wall: G(U^b) grad U+, far field: the own side on both)
+        double vx[4], vy[4];
+        viscous_flux(gas, tag == 1 ? Uo[q] : Up[q], gxp, gyp, vx, vy);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Vp[q][c] = vx[c] * nx + vy[c] * ny;
+        if (tag == 0) {
+          viscous_flux(gas, Uo[q], gxm, gym, vx, vy);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Vm[q][c] = vx[c] * nx + vy[c] * ny;
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Vm[q][c] = Vp[q][c];
+        }
+        const double a1 = normal_diffusion_norm(gas, Up[q], nx, ny);
+        const double a2 = normal_diffusion_norm(gas, Uo[q], nx, ny);
+        sNorm[e * NF + fn] = a1 > a2 ? a1 : a2;
+      }
+    }
+    wave_sync();
+    // the face-term rows reuse the neighbour area: clear their padding columns
+    for (int i = lane; i < 48 * (HRS - NF); i += 64) {
+      const int row = i / (HRS - NF);
+      sX[row * HRS + NF + (i - row * (HRS - NF))] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < FIT; ++q) {
+      const int it = lane + 64 * q;
+      const int e = it / NF;
+      const int fn = it - e * NF;
+      if ((it < 4 * NF) && (e < nel)) {
+        const int f = fn / Nfp, j = fn - f * Nfp;
+        const int n = face_node<N>(f, j);
+        const int tag = sConn[e * 3 + f] & 3;
+        const double* g = sGeo + e * kGeoStride;
+        const double nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f], sgeo = g[7 + 4 * f];
+        double gbar = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < Nfp; ++jj) {
+          const double v = sNorm[e * NF + f * Nfp + jj];
+          gbar = v > gbar ? v : gbar;
+        }
+        const double sigma = sgeo * gbar;
+        const double vwn = vwx * nx + vwy * ny;
+        double Fc[4];
+        if (tag == 1) {
+          const double p = pressure(Up[q], gas.gm1);
+          Fc[0] = 0.0;
+          Fc[1] = p * nx;
+          Fc[2] = p * ny;
+          Fc[3] = p * vwn;
+        } else {
+          roe_flux(Up[q], Uo[q], nx, ny, vwn, gas.gm1, Fc);
+        }
+        double w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          // Fscale * own total normal flux from the contravariant flux:
+          // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
+          const double fr = sFr[(4 * c + e) * RS + n], fs = sFs[(4 * c + e) * RS + n];
+          const double own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
+          w[c] = Up[q][c] - Uo[q][c];
+          const double Hm = Fc[c] - 0.5 * (Vp[q][c] + Vm[q][c]) + sigma * w[c];
+          sH[(4 * c + e) * HRS + fn] = own - fsc * Hm;
+        }
+        double qx[4], qy[4];
+        viscous_transpose(gas, tag == 1 ? Uo[q] : Up[q], nx, ny, w, qx, qy);
+        const double ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
+        const double rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          sQr[(4 * c + e) * HRS + fn] = ce * (rx * qx[c] + ry * qy[c]);
+          sQs[(4 * c + e) * HRS + fn] = ce * (sx * qx[c] + sy * qy[c]);
+        }
+      }
+    }
+    wave_sync();
+
+    // ---- divergence and lifts on the matrix cores, then the RK stage
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      d4 aD = {0.0, 0.0, 0.0, 0.0}, aL = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        aD = mfma(sFr[arow * RS + 4 * s + acol], sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aD);
+        aD = mfma(sFs[arow * RS + 4 * s + acol], sFrag[OFF_DS + (tt * KS + s) * 64 + lane], aD);
+      }
+#pragma unroll
+      for (int s = 0; s < KF; ++s) {
+        const int fi = (tt * KF + s) * 64 + lane;
+        aL = mfma(sH[arow * HRS + 4 * s + acol], sFrag[OFF_L + fi], aL);
+        aL = mfma(sQr[arow * HRS + 4 * s + acol], sFrag[OFF_LR + fi], aL);
+        aL = mfma(sQs[arow * HRS + 4 * s + acol], sFrag[OFF_LS + fi], aL);
+      }
+      const int n = 16 * tt + rn;
+      if (re < nel && n < Np) {
+        const int64_t base = (e0 + re) * S + n;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double R = aL[c] - aD[c];
           const int64_t idx = base + c * Np;
           if (rhs_only) {
-            K1[idx] = R[c];
+            K1[idx] = R;
           } else {
-            double k = (a == 0.0) ? dt * R[c] : a * K1[idx] + dt * R[c];
+            const double k = (a == 0.0) ? dt * R : a * K1[idx] + dt * R;
             K1[idx] = k;
-            Uout[idx] = sU[e][c][n] + b * k;
+            Uout[idx] = sU[(4 * c + re) * RS + n] + b * k;
           }
         }
       }
@@ -387,9 +466,11 @@ int launch_stage_n(const DeviceTables& t, const KernelPhysics& ph, const double*
                    double* K1, double a, double b, double dt, int rhs_only, hipStream_t s,
                    std::string& err) {
   using O = Order<N>;
-  int64_t ntiles = (t.K + O::EPB - 1) / O::EPB;
-  int grid = (int)(ntiles < 8192 ? ntiles : 8192);
-  if (grid < 1) return 0;
+  const int64_t ntiles = (t.K + 3) / 4;
+  // persistent: about two workgroups per CU, a multiple of 8 (one range per XCD)
+  int64_t want = (ntiles + O::WAVES - 1) / O::WAVES;
+  int grid = (int)(want < 512 ? want : 512);
+  grid = ((grid + 7) / 8) * 8;
   hipLaunchKernelGGL(stage_kernel<N>, dim3(grid), dim3(O::THREADS), 0, s, t, ph, Uin, Uout, K1, a,
                      b, dt, rhs_only);
   hipError_t e = hipGetLastError();

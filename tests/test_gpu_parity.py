@@ -1,11 +1,14 @@
 """GPU parity of the HIP path against the FP64 oracle (needs an MI355X).
 
-Tolerance (FP64): per field, max |R_gpu - R_oracle| <= 1e-12 * max |R_oracle|.
-The GPU evaluates the strong form and the oracle the weak form; they are
-equal in exact arithmetic and differ here only by rounding, which on the
-cancellation-heavy near-free-stream cases is a few 1e-14 of the largest
-individual term.  Inputs are seeded synthetic states of the workloads'
-shapes (meshgen), identical on both sides.
+Tolerance (FP64), per conserved field f:
+    max |R_gpu - R_oracle| <= max(1e-12 max|R_oracle,f|, 1e-13 T_f)
+with T_f the largest magnitude of the oracle's separate volume, surface and
+theta contributions to field f.  The GPU evaluates the strong form and the
+oracle the weak form; they agree in exact arithmetic, so the difference is
+rounding of the individual terms.  Where a field's right-hand side is a small
+remainder of large terms (near free stream, or the transverse momentum of a
+flow along x) that rounding is set by T_f, not by R_f.  Inputs are seeded
+synthetic states of the workloads' shapes (meshgen), identical on both sides.
 """
 import numpy as np
 import pytest
@@ -45,11 +48,19 @@ def _from_dev(T):
     return np.transpose(T.cpu().numpy(), (1, 2, 0))
 
 
-def _check(got, want, tol=TOL, what=""):
+def term_scale(parts):
+    return np.array([max(np.abs(parts[k][f]).max() for k in ("vol", "surf", "theta"))
+                     for f in range(4)])
+
+
+def _check(got, want, tol=TOL, what="", terms=None):
     for f in range(4):
         scale = np.abs(want[f]).max()
         err = np.abs(got[f] - want[f]).max()
-        assert err <= tol * scale, "%s field %d: err %.3e scale %.3e ratio %.3e" % (
+        bound = tol * scale
+        if terms is not None:
+            bound = max(bound, 0.1 * tol * terms[f])
+        assert err <= bound, "%s field %d: err %.3e scale %.3e ratio %.3e" % (
             what, f, err, scale, err / scale)
 
 
@@ -90,13 +101,13 @@ def test_rhs_parity(case):
     mesh = mk()
     dg = build(mesh, p, **over)
     U = _state(dg, recipe, 7)
-    want = dg.rhs(U, vw)
+    want, parts = dg.rhs(U, vw, return_parts=True)
     _say("rhs %s K=%d p=%d" % (name, dg.mesh.K, p))
     s = _solver(mesh, p, dg.phys)
     Ud = _to_dev(torch, U)
     R = s.rhs(Ud, v_w=vw)
     torch.cuda.synchronize()
-    _check(_from_dev(R), want, what=name)
+    _check(_from_dev(R), want, what=name, terms=term_scale(parts))
     # bitwise reproducible
     R2 = s.rhs(Ud, v_w=vw)
     torch.cuda.synchronize()
@@ -113,6 +124,7 @@ def test_rk_step_parity(case):
     U = _state(dg, recipe, 11)
     dt = 1e-4
     want, _ = dg.lserk_step(U, dt, vw)
+    terms = dt * term_scale(dg.rhs(U, vw, return_parts=True)[1])
     _say("rk_step %s K=%d p=%d" % (name, dg.mesh.K, p))
     s = _solver(mesh, p, dg.phys)
     Ud = _to_dev(torch, U)
@@ -121,7 +133,7 @@ def test_rk_step_parity(case):
     torch.cuda.synchronize()
     got = _from_dev(Ud)
     # compare increments (U changes by O(dt |R|))
-    _check(got - U, want - U, tol=1e-11, what=name)
+    _check(got - U, want - U, tol=1e-11, what=name, terms=10 * terms)
     # the stage entry point chained by hand gives the same bits
     Ua = _to_dev(torch, U)
     Ub = torch.empty_like(Ua)
@@ -144,7 +156,10 @@ def test_force_parity():
         _say("force p=%d" % p)
         s = _solver(mesh, p, dg.phys)
         got = s.force(_to_dev(torch, U), v_w=vw)
-        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+        # the net force is a small remainder of the pressure integral around the
+        # closed wall: compare against that integral's size, p_inf x perimeter
+        scale = (1.0 / 1.4) * np.pi
+        assert np.abs(got - want).max() <= 1e-12 * scale, (got, want)
         s.close()
 
 
@@ -155,10 +170,10 @@ def test_rhs_parity_cylinder20k_full_size():
     dg = build(w["mesh"], w["p"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
                penalty_mode=w["penalty_mode"], C_pen=1.0, U_inf=w["U_inf"])
     U = mg.noisy_free_stream((4,) + dg.mesh.x.shape, dg.phys.U_inf, mg.rng_for(1))
-    want = dg.rhs(U)
+    want, parts = dg.rhs(U, return_parts=True)
     _say("rhs cylinder20k K=%d" % dg.mesh.K)
     s = _solver(w["mesh"], w["p"], dg.phys)
     R = s.rhs(_to_dev(torch, U))
     torch.cuda.synchronize()
-    _check(_from_dev(R), want, what="cylinder20k")
+    _check(_from_dev(R), want, what="cylinder20k", terms=term_scale(parts))
     s.close()
