@@ -96,10 +96,35 @@ __device__ __forceinline__ void viscous_transpose(const Gas& g, const double U[4
   qy[3] = m * (ny * d3);
 }
 
+// Largest eigenvalue of a symmetric 3x3 matrix by the closed-form
+// trigonometric solution of its characteristic cubic.
+__device__ __noinline__ double sym3_lambda_max_trig(double s00, double s11, double s22,
+                                                       double s01, double s02, double s12) {
+  double q = (s00 + s11 + s22) * (1.0 / 3.0);
+  double p1 = s01 * s01 + s02 * s02 + s12 * s12;
+  double d0 = s00 - q, d1 = s11 - q, d2 = s22 - q;
+  double p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1;
+  if (p2 <= 0.0) return q;
+  double pp = sqrt(p2 * (1.0 / 6.0));
+  double ip = 1.0 / pp;
+  double b00 = d0 * ip, b11 = d1 * ip, b22 = d2 * ip;
+  double b01 = s01 * ip, b02 = s02 * ip, b12 = s12 * ip;
+  double det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) +
+               b02 * (b01 * b12 - b11 * b02);
+  double r = 0.5 * det;
+  r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+  return q + 2.0 * pp * cos(acos(r) * (1.0 / 3.0));
+}
+
 // ||A||_2 for A = nx^2 G11 + nx ny (G12 + G21) + ny^2 G22.  The first row of
 // A is zero, so ||A||_2 = (mu/rho) sqrt(lambda_max(B B^T)) for the 3x4 block B
-// of its lower rows; lambda_max of the symmetric 3x3 B B^T by the closed-form
-// trigonometric solution of its characteristic cubic.
+// of its lower rows.  lambda_max of the symmetric positive semi-definite
+// S = B B^T: Newton on its characteristic cubic from the Frobenius norm of S,
+// an upper bound within a few per cent of lambda_max when the top eigenvalue
+// is well separated (iterates decrease monotonically to the largest root).
+// If the last step is not negligible -- a near-double top eigenvalue, where
+// Newton converges only linearly -- the closed-form trigonometric solution is
+// used instead.
 __device__ __forceinline__ double normal_diffusion_norm(const Gas& g, const double U[4], double nx,
                                                         double ny) {
   double ir = 1.0 / U[0];
@@ -111,45 +136,35 @@ __device__ __forceinline__ double normal_diffusion_norm(const Gas& g, const doub
   double g41b = -v2 * v2 * (1.0 / 3.0) - vv - k * ek;
   const double c43 = 4.0 / 3.0, c23 = 2.0 / 3.0, c13 = 1.0 / 3.0;
   double xx = nx * nx, xy = nx * ny, yy = ny * ny;
-  double B[3][4];
-  B[0][0] = -(c43 * xx + yy) * v1 - c13 * xy * v2;
-  B[0][1] = c43 * xx + yy;
-  B[0][2] = c13 * xy;
-  B[0][3] = 0.0;
-  B[1][0] = -(xx + c43 * yy) * v2 - c13 * xy * v1;
-  B[1][1] = c13 * xy;
-  B[1][2] = xx + c43 * yy;
-  B[1][3] = 0.0;
-  B[2][0] = xx * g41a + yy * g41b - c23 * xy * v1 * v2;
-  B[2][1] = (c43 - k) * v1 * xx + c13 * v2 * xy + (1.0 - k) * v1 * yy;
-  B[2][2] = (1.0 - k) * v2 * xx + c13 * v1 * xy + (c43 - k) * v2 * yy;
-  B[2][3] = k * (xx + yy);
-  double S[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = i; j < 3; ++j) {
-      double acc = 0.0;
-      for (int c = 0; c < 4; ++c) acc += B[i][c] * B[j][c];
-      S[i][j] = acc;
-      S[j][i] = acc;
-    }
-  double q = (S[0][0] + S[1][1] + S[2][2]) * (1.0 / 3.0);
-  double p1 = S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[1][2] * S[1][2];
-  double d0 = S[0][0] - q, d1 = S[1][1] - q, d2 = S[2][2] - q;
-  double p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1;
-  double lam;
-  if (p2 <= 0.0) {
-    lam = q;
-  } else {
-    double pp = sqrt(p2 * (1.0 / 6.0));
-    double ip = 1.0 / pp;
-    double b00 = d0 * ip, b11 = d1 * ip, b22 = d2 * ip;
-    double b01 = S[0][1] * ip, b02 = S[0][2] * ip, b12 = S[1][2] * ip;
-    double det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) +
-                 b02 * (b01 * b12 - b11 * b02);
-    double r = 0.5 * det;
-    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
-    lam = q + 2.0 * pp * cos(acos(r) * (1.0 / 3.0));
+  // rows of B (the fourth column of the momentum rows is zero)
+  double a0 = -(c43 * xx + yy) * v1 - c13 * xy * v2, a1 = c43 * xx + yy, a2 = c13 * xy;
+  double b0 = -(xx + c43 * yy) * v2 - c13 * xy * v1, b1 = c13 * xy, b2 = xx + c43 * yy;
+  double e0 = xx * g41a + yy * g41b - c23 * xy * v1 * v2;
+  double e1 = (c43 - k) * v1 * xx + c13 * v2 * xy + (1.0 - k) * v1 * yy;
+  double e2 = (1.0 - k) * v2 * xx + c13 * v1 * xy + (c43 - k) * v2 * yy;
+  double e3 = k * (xx + yy);
+  double s00 = a0 * a0 + a1 * a1 + a2 * a2;
+  double s11 = b0 * b0 + b1 * b1 + b2 * b2;
+  double s22 = e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+  double s01 = a0 * b0 + a1 * b1 + a2 * b2;
+  double s02 = a0 * e0 + a1 * e1 + a2 * e2;
+  double s12 = b0 * e0 + b1 * e1 + b2 * e2;
+  // characteristic polynomial lambda^3 - c2 lambda^2 + c1 lambda - c0
+  double c2 = s00 + s11 + s22;
+  double c1 = s00 * s11 + s00 * s22 + s11 * s22 - s01 * s01 - s02 * s02 - s12 * s12;
+  double c0 = s00 * (s11 * s22 - s12 * s12) - s01 * (s01 * s22 - s12 * s02) +
+              s02 * (s01 * s12 - s11 * s02);
+  double lam = sqrt(s00 * s00 + s11 * s11 + s22 * s22 +
+                    2.0 * (s01 * s01 + s02 * s02 + s12 * s12));
+  double step = 0.0;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    double f = ((lam - c2) * lam + c1) * lam - c0;
+    double df = (3.0 * lam - 2.0 * c2) * lam + c1;
+    step = (df > 0.0) ? f / df : 0.0;
+    lam -= step;
   }
+  if (!(fabs(step) <= 1e-15 * lam)) lam = sym3_lambda_max_trig(s00, s11, s22, s01, s02, s12);
   return g.mu * ir * sqrt(lam > 0.0 ? lam : 0.0);
 }
 

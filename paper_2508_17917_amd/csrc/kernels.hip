@@ -49,7 +49,8 @@ struct Order {
   static constexpr int H_SZ = 48 * HRS;          // face terms h | qr | qs, row 4c + e
   static constexpr int X_SZ = N_SZ > H_SZ ? N_SZ : H_SZ;
   static constexpr int NORM_SZ = 4 * NF;
-  static constexpr int WAVE_SZ = U_SZ + F_SZ + X_SZ + NORM_SZ + 64 + 48;
+  static constexpr int VN_SZ = 16 * NF;          // mean viscous normal flux per face node
+  static constexpr int WAVE_SZ = U_SZ + F_SZ + X_SZ + NORM_SZ + VN_SZ + 64 + 48;
   // operator fragments (per workgroup)
   static constexpr int FD = NT * KS * 64;        // one Dr-type fragment set
   static constexpr int FL = NT * KF * 64;        // one LIFT-type fragment set
@@ -89,6 +90,27 @@ __device__ __forceinline__ double lane_read(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// State on the other side of a face node: the neighbour's trace (interior,
+// periodic), the moving adiabatic wall's ghost Q^b = [rho+, v_w, p+], or the
+// far-field state (Sec. 2.2.4).  nb points at the neighbour's node, stride Np.
+__device__ __forceinline__ void ghost_state(int tag, const double up[4], const double* nb, int Np,
+                                            double vwx, double vwy, const double* Uinf, double gm1,
+                                            double uo[4]) {
+  if (tag == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) uo[c] = nb[c * Np];
+  } else if (tag == 1) {
+    const double p = pressure(up, gm1);
+    uo[0] = up[0];
+    uo[1] = up[0] * vwx;
+    uo[2] = up[0] * vwy;
+    uo[3] = p / gm1 + 0.5 * up[0] * (vwx * vwx + vwy * vwy);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) uo[c] = Uinf[c];
+  }
+}
+
 // The fused right-hand side + LSERK stage.  Each wavefront owns tiles of four
 // elements (16 MFMA rows = 4 fields x 4 elements); the workgroup only shares
 // the operator fragments.  Tiles are handed out in contiguous ranges per XCD
@@ -120,7 +142,8 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
   double* sQr = sX + 16 * HRS;
   double* sQs = sX + 32 * HRS;
   double* sNorm = sX + O::X_SZ;
-  double* sGeo = sNorm + O::NORM_SZ;     // [4][16]
+  double* sVn = sNorm + O::NORM_SZ;      // [4 NF][4]
+  double* sGeo = sVn + O::VN_SZ;         // [4][16]
   double* sNGeo = sGeo + 64;             // [4][3][4]
   int* sConn = sConnW[wid];              // [4][3]
 
@@ -147,23 +170,47 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
     const int64_t e0 = tile * 4;
     const int nel = (int)((K - e0) < 4 ? (K - e0) : 4);
     wave_sync();
-    // ---- own states, geometry, connectivity
-    for (int i = lane; i < nel * S; i += 64) {
-      int e = i / S, r = i - e * S, c = r / Np, n = r - c * Np;
-      sU[(4 * c + e) * RS + n] = Uin[e0 * S + i];
+    // ---- own states, geometry, connectivity: every load issued before the first use
+    constexpr int NLU = (4 * S + 63) / 64, NLN = (12 * S + 63) / 64;
+    double ru[NLU];
+#pragma unroll
+    for (int q = 0; q < NLU; ++q) {
+      const int i = lane + 64 * q;
+      ru[q] = (i < nel * S) ? Uin[e0 * S + i] : 0.0;
     }
-    for (int i = lane; i < nel * kGeoStride; i += 64) sGeo[i] = t.geo[e0 * kGeoStride + i];
-    for (int i = lane; i < nel * 3; i += 64) sConn[i] = t.conn[e0 * 3 + i];
+    const double rg = (lane < nel * kGeoStride) ? t.geo[e0 * kGeoStride + lane] : 0.0;
+    const int rc = (lane < nel * 3) ? t.conn[e0 * 3 + lane] : 0;
+    if (lane < nel * 3) sConn[lane] = rc;
     wave_sync();
-    // ---- neighbour states (a boundary face points at the element itself) and metrics
-    for (int i = lane; i < nel * 3 * S; i += 64) {
-      int ef = i / S, r = i - ef * S;
-      sX[i] = Uin[(int64_t)(sConn[ef] >> 4) * S + r];
+    // ---- neighbour states (a boundary face points at the element itself) and
+    // metrics, in two batches of independent loads (bounded register use)
+    const double rng = (lane < nel * 12) ? t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NLU; ++q) {
+      const int i = lane + 64 * q;
+      if (i < nel * S) {
+        const int e = i / S, r = i - e * S, c = r / Np, n = r - c * Np;
+        sU[(4 * c + e) * RS + n] = ru[q];
+      }
     }
-    for (int i = lane; i < nel * 12; i += 64) {
-      int ef = i >> 2;
-      sNGeo[i] = t.geo[(int64_t)(sConn[ef] >> 4) * kGeoStride + (i & 3)];
+    if (lane < nel * kGeoStride) sGeo[lane] = rg;
+    constexpr int NLH = (NLN + 1) / 2;
+#pragma nounroll
+    for (int h = 0; h < 2; ++h) {
+      double rnb[NLH];
+#pragma unroll
+      for (int q = 0; q < NLH; ++q) {
+        const int i = lane + 64 * (h * NLH + q);
+        const int ef = i / S;
+        rnb[q] = (i < nel * 3 * S) ? Uin[(int64_t)(sConn[ef < 12 ? ef : 11] >> 4) * S + (i - ef * S)] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < NLH; ++q) {
+        const int i = lane + 64 * (h * NLH + q);
+        if (i < nel * 3 * S) sX[i] = rnb[q];
+      }
     }
+    if (lane < nel * 12) sNGeo[lane] = rng;
     wave_sync();
 
     // ---- gradient on the matrix cores, then the volume flux per node
@@ -209,8 +256,8 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
     }
     wave_sync();
 
-    // ---- face nodes: traces, ghosts, G-bar, fluxes
-    double Up[FIT][4], Uo[FIT][4], Vp[FIT][4], Vm[FIT][4];
+    // ---- face nodes, pass 1: traces, ghosts, ||n^T G n||_2 on both sides and the
+    // mean viscous normal flux (one lane per face node)
 #pragma unroll
     for (int q = 0; q < FIT; ++q) {
       const int it = lane + 64 * q;
@@ -220,7 +267,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
       e = e < 4 ? e : 3;
       const int f = fn / Nfp, j = fn - f * Nfp;
       const int n = face_node<N>(f, j);
-      // own gradient at the face node from the lane that computed it
+      // own gradient at the face node, from the lane that computed it
       double gxp[4], gyp[4];
       const int src = 16 * e + (n & 15);
 #pragma unroll
@@ -239,11 +286,21 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         const int tag = conn & 3, nf = (conn >> 2) & 3;
         const double* g = sGeo + e * kGeoStride;
         const double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
+        double up[4], uo[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Up[q][c] = sU[(4 * c + e) * RS + n];
-        // "other side" gradient from the staged neighbour (wall: the element itself)
+        for (int c = 0; c < 4; ++c) up[c] = sU[(4 * c + e) * RS + n];
         const int n2 = (tag == 0) ? face_node<N>(nf, Nfp - 1 - j) : n;
         const double* nbU = sX + (e * 3 + f) * S;
+        ghost_state(tag, up, nbU + n2, Np, vwx, vwy, ph.U_inf, gas.gm1, uo);
+        // one side at a time: the two evaluations need not be live together
+        double nrm = 0.0;
+#pragma nounroll
+        for (int side = 0; side < 2; ++side) {
+          const double a1 = normal_diffusion_norm(gas, side == 0 ? up : uo, nx, ny);
+          nrm = a1 > nrm ? a1 : nrm;
+        }
+        sNorm[e * NF + fn] = nrm;
+        // "other side" gradient from the staged neighbour (wall: the element itself)
         double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
         const int dbase = ((n2 >> 4) * KS) * 64 + (n2 & 15);
 #pragma unroll 4
@@ -264,44 +321,59 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
           gxm[c] = ng[0] * ur[c] + ng[2] * us[c];
           gym[c] = ng[1] * ur[c] + ng[3] * us[c];
         }
-        if (tag == 0) {
+        // mean of G(U+) grad U+ and G(U-) grad U- inside; G(U^b) grad U+ on the
+        // wall (grad U+ from the staged copy of the element itself); G(U+) grad U+
+        // on the far field
+        double vx[4], vy[4], vn[4];
+        if (tag == 1) {
+          viscous_flux(gas, uo, gxm, gym, vx, vy);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) Uo[q][c] = nbU[c * Np + n2];
-        } else if (tag == 1) {
-          const double p = pressure(Up[q], gas.gm1);
-          Uo[q][0] = Up[q][0];
-          Uo[q][1] = Up[q][0] * vwx;
-          Uo[q][2] = Up[q][0] * vwy;
-          Uo[q][3] = p / gas.gm1 + 0.5 * Up[q][0] * (vwx * vwx + vwy * vwy);
+          for (int c = 0; c < 4; ++c) vn[c] = vx[c] * nx + vy[c] * ny;
         } else {
+          viscous_flux(gas, up, gxp, gyp, vx, vy);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) Uo[q][c] = ph.U_inf[c];
+          for (int c = 0; c < 4; ++c) vn[c] = vx[c] * nx + vy[c] * ny;
+          if (tag == 0) {
+            viscous_flux(gas, uo, gxm, gym, vx, vy);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) vn[c] = 0.5 * (vn[c] + vx[c] * nx + vy[c] * ny);
+          }
         }
-        // viscous normal fluxes: own side G(U+) grad U+, other side G(U-) grad U-
-        // (wall: G(U^b) grad U+, far field: the own side on both)
-        double vx[4], vy[4];
-        viscous_flux(gas, tag == 1 ? Uo[q] : Up[q], gxp, gyp, vx, vy);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Vp[q][c] = vx[c] * nx + vy[c] * ny;
-        if (tag == 0) {
-          viscous_flux(gas, Uo[q], gxm, gym, vx, vy);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) Vm[q][c] = vx[c] * nx + vy[c] * ny;
-        } else {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) Vm[q][c] = Vp[q][c];
-        }
-        const double a1 = normal_diffusion_norm(gas, Up[q], nx, ny);
-        const double a2 = normal_diffusion_norm(gas, Uo[q], nx, ny);
-        sNorm[e * NF + fn] = a1 > a2 ? a1 : a2;
+        for (int c = 0; c < 4; ++c) sVn[(e * NF + fn) * 4 + c] = vn[c];
       }
     }
     wave_sync();
-    // the face-term rows reuse the neighbour area: clear their padding columns
-    for (int i = lane; i < 48 * (HRS - NF); i += 64) {
-      const int row = i / (HRS - NF);
-      sX[row * HRS + NF + (i - row * (HRS - NF))] = 0.0;
+    // ---- face nodes, pass 2: gather what the Roe flux, penalty and theta term
+    // need, then (after every read of the neighbour area) write the face terms
+    double fup[FIT][4], fuo[FIT][4], fvn[FIT][4], fgb[FIT];
+#pragma unroll
+    for (int q = 0; q < FIT; ++q) {
+      const int it = lane + 64 * q;
+      const int e = it / NF;
+      const int fn = it - e * NF;
+      if ((it < 4 * NF) && (e < nel)) {
+        const int f = fn / Nfp, j = fn - f * Nfp;
+        const int n = face_node<N>(f, j);
+        const int conn = sConn[e * 3 + f];
+        const int tag = conn & 3, nf = (conn >> 2) & 3;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fup[q][c] = sU[(4 * c + e) * RS + n];
+        const int n2 = face_node<N>(nf, Nfp - 1 - j);
+        ghost_state(tag, fup[q], sX + (e * 3 + f) * S + n2, Np, vwx, vwy, ph.U_inf, gas.gm1,
+                    fuo[q]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fvn[q][c] = sVn[(e * NF + fn) * 4 + c];
+        double gbar = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < Nfp; ++jj) {
+          const double v = sNorm[e * NF + f * Nfp + jj];
+          gbar = v > gbar ? v : gbar;
+        }
+        fgb[q] = gbar;
+      }
     }
+    wave_sync();
 #pragma unroll
     for (int q = 0; q < FIT; ++q) {
       const int it = lane + 64 * q;
@@ -312,24 +384,18 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         const int n = face_node<N>(f, j);
         const int tag = sConn[e * 3 + f] & 3;
         const double* g = sGeo + e * kGeoStride;
-        const double nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f], sgeo = g[7 + 4 * f];
-        double gbar = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < Nfp; ++jj) {
-          const double v = sNorm[e * NF + f * Nfp + jj];
-          gbar = v > gbar ? v : gbar;
-        }
-        const double sigma = sgeo * gbar;
+        const double nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f];
+        const double sigma = g[7 + 4 * f] * fgb[q];
         const double vwn = vwx * nx + vwy * ny;
         double Fc[4];
         if (tag == 1) {
-          const double p = pressure(Up[q], gas.gm1);
+          const double p = pressure(fup[q], gas.gm1);
           Fc[0] = 0.0;
           Fc[1] = p * nx;
           Fc[2] = p * ny;
           Fc[3] = p * vwn;
         } else {
-          roe_flux(Up[q], Uo[q], nx, ny, vwn, gas.gm1, Fc);
+          roe_flux(fup[q], fuo[q], nx, ny, vwn, gas.gm1, Fc);
         }
         double w[4];
 #pragma unroll
@@ -338,12 +404,11 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
           // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
           const double fr = sFr[(4 * c + e) * RS + n], fs = sFs[(4 * c + e) * RS + n];
           const double own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
-          w[c] = Up[q][c] - Uo[q][c];
-          const double Hm = Fc[c] - 0.5 * (Vp[q][c] + Vm[q][c]) + sigma * w[c];
-          sH[(4 * c + e) * HRS + fn] = own - fsc * Hm;
+          w[c] = fup[q][c] - fuo[q][c];
+          sH[(4 * c + e) * HRS + fn] = own - fsc * (Fc[c] - fvn[q][c] + sigma * w[c]);
         }
         double qx[4], qy[4];
-        viscous_transpose(gas, tag == 1 ? Uo[q] : Up[q], nx, ny, w, qx, qy);
+        viscous_transpose(gas, tag == 1 ? fuo[q] : fup[q], nx, ny, w, qx, qy);
         const double ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
         const double rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll
@@ -353,9 +418,22 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         }
       }
     }
+    for (int i = lane; i < 48 * (HRS - NF); i += 64) {
+      const int row = i / (HRS - NF);
+      sX[row * HRS + NF + (i - row * (HRS - NF))] = 0.0;
+    }
     wave_sync();
 
-    // ---- divergence and lifts on the matrix cores, then the RK stage
+    // ---- divergence and lifts on the matrix cores, then the RK stage; the
+    // K1 loads are issued first so the matrix work covers their latency
+    double rk[NT][4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int n = 16 * tt + rn;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        rk[tt][c] = (!rhs_only && a != 0.0 && re < nel && n < Np) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
+    }
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       d4 aD = {0.0, 0.0, 0.0, 0.0}, aL = {0.0, 0.0, 0.0, 0.0};
@@ -381,7 +459,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
           if (rhs_only) {
             K1[idx] = R;
           } else {
-            const double k = (a == 0.0) ? dt * R : a * K1[idx] + dt * R;
+            const double k = (a == 0.0) ? dt * R : a * rk[tt][c] + dt * R;
             K1[idx] = k;
             Uout[idx] = sU[(4 * c + re) * RS + n] + b * k;
           }
