@@ -5,8 +5,9 @@
 // is garbled, this form is the one the printed (4,1) entries of the viscous
 // blocks require).  The viscous flux is applied through the paper's four
 // 4x4 blocks G11, G12, G21, G22 (Sec. 2.1), written out with their zero
-// pattern; the theta term needs their transposes, and the penalty's
-// diffusion scale needs ||n^T G n||_2 (Sec. 2.2.3).
+// pattern through a factorisation (below); the theta term needs their
+// transposes, and the penalty's diffusion scale needs ||n^T G n||_2
+// (Sec. 2.2.3).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,18 +15,36 @@
 namespace dgmi {
 
 struct Gas {
-  double gamma, gm1, mu, k;  // k = gamma / Pr
+  double gamma, gm1, igm1, mu, k;  // igm1 = 1/(gamma-1), k = gamma / Pr
 };
 
-__device__ __forceinline__ double pressure(const double U[4], double gm1) {
-  return gm1 * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / U[0]);
+__device__ __forceinline__ double pressure(const double U[4], double ir, double gm1) {
+  return gm1 * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) * ir);
+}
+
+// Per-state quantities shared by the viscous operators: 1/rho, velocity,
+// mu/rho, eps/rho - |v|^2 and the (4,1) entries of G11 and G22.
+struct VState {
+  double ir, v1, v2, m, ek, g41a, g41b;
+};
+
+__device__ __forceinline__ VState vstate(const Gas& g, const double U[4]) {
+  VState s;
+  s.ir = 1.0 / U[0];
+  s.v1 = U[1] * s.ir;
+  s.v2 = U[2] * s.ir;
+  s.m = g.mu * s.ir;
+  const double vv = s.v1 * s.v1 + s.v2 * s.v2;
+  s.ek = U[3] * s.ir - vv;  // eps/rho - |v|^2, as in the printed (4,1) entries
+  s.g41a = -s.v1 * s.v1 * (1.0 / 3.0) - vv - g.k * s.ek;
+  s.g41b = -s.v2 * s.v2 * (1.0 / 3.0) - vv - g.k * s.ek;
+  return s;
 }
 
 // F_c,x, F_c,y minus the moving-frame term v_w (x) U, dotted with n:
 // the advective flux through a face of normal n.
-__device__ __forceinline__ void normal_adv_flux(const double U[4], double nx, double ny, double vwn,
-                                                double gm1, double F[4]) {
-  double ir = 1.0 / U[0];
+__device__ __forceinline__ void normal_adv_flux(const double U[4], double ir, double nx, double ny,
+                                                double vwn, double gm1, double F[4]) {
   double u = U[1] * ir, v = U[2] * ir;
   double p = gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
   double qn = u * nx + v * ny - vwn;
@@ -35,65 +54,53 @@ __device__ __forceinline__ void normal_adv_flux(const double U[4], double nx, do
   F[3] = U[3] * qn + p * (u * nx + v * ny);
 }
 
-// F_v = G(U) grad U via the printed blocks: Fx = G11 dUx + G12 dUy,
-// Fy = G21 dUx + G22 dUy (first rows of every block are zero).
-__device__ __forceinline__ void viscous_flux(const Gas& g, const double U[4], const double dx[4],
+// The printed blocks factor as G_ab = (mu/rho) C_ab T with the same 3x4 map
+// T = [[-v1, 1, 0, 0], [-v2, 0, 1, 0], [-ek, -v1, -v2, 1]] in both directions:
+// T d_a U = rho (d_a v1, d_a v2, d_a e) (ek = eps/rho - |v|^2), and C_ab the
+// constant-coefficient stress / heat-flux weights.  Both operators below use
+// that factorisation; expanding it reproduces every printed entry.
+//
+// F_v = G(U) grad U: Fx = G11 dUx + G12 dUy, Fy = G21 dUx + G22 dUy.
+__device__ __forceinline__ void viscous_flux(const Gas& g, const VState& st, const double dx[4],
                                              const double dy[4], double Fx[4], double Fy[4]) {
-  double ir = 1.0 / U[0];
-  double v1 = U[1] * ir, v2 = U[2] * ir;
-  double m = g.mu * ir, k = g.k;
-  double vv = v1 * v1 + v2 * v2;
-  double ek = U[3] * ir - vv;  // eps/rho - |v|^2, as in the printed (4,1) entries
-  double g41a = -v1 * v1 * (1.0 / 3.0) - vv - k * ek;
-  double g41b = -v2 * v2 * (1.0 / 3.0) - vv - k * ek;
-  const double c43 = 4.0 / 3.0, c23 = 2.0 / 3.0, c13 = 1.0 / 3.0;
-  double txx = -c43 * v1 * dx[0] + c43 * dx[1] + c23 * v2 * dy[0] - c23 * dy[2];
-  double txy = -v2 * dx[0] + dx[2] - v1 * dy[0] + dy[1];
-  double tyy = c23 * v1 * dx[0] - c23 * dx[1] - c43 * v2 * dy[0] + c43 * dy[2];
-  double ex = g41a * dx[0] + (c43 - k) * v1 * dx[1] + (1.0 - k) * v2 * dx[2] + k * dx[3] -
-              c13 * v1 * v2 * dy[0] + v2 * dy[1] - c23 * v1 * dy[2];
-  double ey = -c13 * v1 * v2 * dx[0] - c23 * v2 * dx[1] + v1 * dx[2] + g41b * dy[0] +
-              (1.0 - k) * v1 * dy[1] + (c43 - k) * v2 * dy[2] + k * dy[3];
+  const double v1 = st.v1, v2 = st.v2, m = st.m, k = g.k;
+  const double c43 = 4.0 / 3.0, c23 = 2.0 / 3.0;
+  // rho-scaled primitive gradients T dU
+  const double ux = dx[1] - v1 * dx[0], vx = dx[2] - v2 * dx[0];
+  const double uy = dy[1] - v1 * dy[0], vy = dy[2] - v2 * dy[0];
+  const double ex = dx[3] - st.ek * dx[0] - v1 * dx[1] - v2 * dx[2];
+  const double ey = dy[3] - st.ek * dy[0] - v1 * dy[1] - v2 * dy[2];
+  const double txx = c43 * ux - c23 * vy, tyy = c43 * vy - c23 * ux, txy = uy + vx;
   Fx[0] = 0.0;
   Fx[1] = m * txx;
   Fx[2] = m * txy;
-  Fx[3] = m * ex;
+  Fx[3] = m * (v1 * txx + v2 * txy + k * ex);
   Fy[0] = 0.0;
   Fy[1] = m * txy;
   Fy[2] = m * tyy;
-  Fy[3] = m * ey;
+  Fy[3] = m * (v1 * txy + v2 * tyy + k * ey);
 }
 
-// q = G(U)^T (n (x) w): qx = nx G11^T w + ny G21^T w, qy = nx G12^T w + ny G22^T w.
-__device__ __forceinline__ void viscous_transpose(const Gas& g, const double U[4], double nx,
+// q = G(U)^T (n (x) w) = (mu/rho) (T^T z_x, T^T z_y) with z = C^T (n (x) w):
+// qx = nx G11^T w + ny G21^T w, qy = nx G12^T w + ny G22^T w.
+__device__ __forceinline__ void viscous_transpose(const Gas& g, const VState& st, double nx,
                                                   double ny, const double w[4], double qx[4],
                                                   double qy[4]) {
-  double ir = 1.0 / U[0];
-  double v1 = U[1] * ir, v2 = U[2] * ir;
-  double m = g.mu * ir, k = g.k;
-  double vv = v1 * v1 + v2 * v2;
-  double ek = U[3] * ir - vv;  // eps/rho - |v|^2, as in the printed (4,1) entries
-  double g41a = -v1 * v1 * (1.0 / 3.0) - vv - k * ek;
-  double g41b = -v2 * v2 * (1.0 / 3.0) - vv - k * ek;
-  const double c43 = 4.0 / 3.0, c23 = 2.0 / 3.0, c13 = 1.0 / 3.0;
-  double w1 = w[1], w2 = w[2], w3 = w[3];
-  // G11^T w, G21^T w, G12^T w, G22^T w (component 3 of G21^T, G12^T is zero)
-  double a0 = -c43 * v1 * w1 - v2 * w2 + g41a * w3, a1 = c43 * w1 + (c43 - k) * v1 * w3,
-         a2 = w2 + (1.0 - k) * v2 * w3, a3 = k * w3;
-  double b0 = -v2 * w1 + c23 * v1 * w2 - c13 * v1 * v2 * w3, b1 = -c23 * w2 - c23 * v2 * w3,
-         b2 = w1 + v1 * w3;
-  double c0 = c23 * v2 * w1 - v1 * w2 - c13 * v1 * v2 * w3, c1 = w2 + v2 * w3,
-         c2 = -c23 * w1 - c23 * v1 * w3;
-  double d0 = -v1 * w1 - c43 * v2 * w2 + g41b * w3, d1 = w1 + (1.0 - k) * v1 * w3,
-         d2 = c43 * w2 + (c43 - k) * v2 * w3, d3 = k * w3;
-  qx[0] = m * (nx * a0 + ny * b0);
-  qx[1] = m * (nx * a1 + ny * b1);
-  qx[2] = m * (nx * a2 + ny * b2);
-  qx[3] = m * (nx * a3);
-  qy[0] = m * (nx * c0 + ny * d0);
-  qy[1] = m * (nx * c1 + ny * d1);
-  qy[2] = m * (nx * c2 + ny * d2);
-  qy[3] = m * (ny * d3);
+  const double v1 = st.v1, v2 = st.v2, m = st.m, k = g.k;
+  const double c43 = 4.0 / 3.0, c23 = 2.0 / 3.0;
+  const double W1 = w[1] + v1 * w[3], W2 = w[2] + v2 * w[3];
+  const double sxy = nx * W2 + ny * W1;
+  // weights of the rho-scaled primitive gradients (u, v, e) in x and in y
+  const double zux = c43 * nx * W1 - c23 * ny * W2, zvx = sxy, zex = k * nx * w[3];
+  const double zuy = sxy, zvy = c43 * ny * W2 - c23 * nx * W1, zey = k * ny * w[3];
+  qx[0] = m * (-v1 * zux - v2 * zvx - st.ek * zex);
+  qx[1] = m * (zux - v1 * zex);
+  qx[2] = m * (zvx - v2 * zex);
+  qx[3] = m * zex;
+  qy[0] = m * (-v1 * zuy - v2 * zvy - st.ek * zey);
+  qy[1] = m * (zuy - v1 * zey);
+  qy[2] = m * (zvy - v2 * zey);
+  qy[3] = m * zey;
 }
 
 // Largest eigenvalue of a symmetric 3x3 matrix by the closed-form
@@ -125,21 +132,15 @@ __device__ __noinline__ double sym3_lambda_max_trig(double s00, double s11, doub
 // If the last step is not negligible -- a near-double top eigenvalue, where
 // Newton converges only linearly -- the closed-form trigonometric solution is
 // used instead.
-__device__ __forceinline__ double normal_diffusion_norm(const Gas& g, const double U[4], double nx,
+__device__ __forceinline__ double normal_diffusion_norm(const Gas& g, const VState& st, double nx,
                                                         double ny) {
-  double ir = 1.0 / U[0];
-  double v1 = U[1] * ir, v2 = U[2] * ir;
-  double k = g.k;
-  double vv = v1 * v1 + v2 * v2;
-  double ek = U[3] * ir - vv;  // eps/rho - |v|^2, as in the printed (4,1) entries
-  double g41a = -v1 * v1 * (1.0 / 3.0) - vv - k * ek;
-  double g41b = -v2 * v2 * (1.0 / 3.0) - vv - k * ek;
+  const double v1 = st.v1, v2 = st.v2, k = g.k;
   const double c43 = 4.0 / 3.0, c23 = 2.0 / 3.0, c13 = 1.0 / 3.0;
   double xx = nx * nx, xy = nx * ny, yy = ny * ny;
   // rows of B (the fourth column of the momentum rows is zero)
   double a0 = -(c43 * xx + yy) * v1 - c13 * xy * v2, a1 = c43 * xx + yy, a2 = c13 * xy;
   double b0 = -(xx + c43 * yy) * v2 - c13 * xy * v1, b1 = c13 * xy, b2 = xx + c43 * yy;
-  double e0 = xx * g41a + yy * g41b - c23 * xy * v1 * v2;
+  double e0 = xx * st.g41a + yy * st.g41b - c23 * xy * v1 * v2;
   double e1 = (c43 - k) * v1 * xx + c13 * v2 * xy + (1.0 - k) * v1 * yy;
   double e2 = (1.0 - k) * v2 * xx + c13 * v1 * xy + (c43 - k) * v2 * yy;
   double e3 = k * (xx + yy);
@@ -158,26 +159,29 @@ __device__ __forceinline__ double normal_diffusion_norm(const Gas& g, const doub
                     2.0 * (s01 * s01 + s02 * s02 + s12 * s12));
   double step = 0.0;
 #pragma unroll
-  for (int it = 0; it < 6; ++it) {
+  for (int it = 0; it < 5; ++it) {
     double f = ((lam - c2) * lam + c1) * lam - c0;
     double df = (3.0 * lam - 2.0 * c2) * lam + c1;
-    step = (df > 0.0) ? f / df : 0.0;
+    // the step only needs an approximate reciprocal: Newton corrects the rest
+    double r = __builtin_amdgcn_rcp(df);
+    r = r * (2.0 - df * r);
+    step = (df > 0.0) ? f * r : 0.0;
     lam -= step;
   }
   if (!(fabs(step) <= 1e-15 * lam)) lam = sym3_lambda_max_trig(s00, s11, s22, s01, s02, s12);
-  return g.mu * ir * sqrt(lam > 0.0 ? lam : 0.0);
+  return st.m * sqrt(lam > 0.0 ? lam : 0.0);
 }
 
 // Roe flux, own state Ul ("+"), other state Ur ("-"), own outward normal n,
 // moving frame: mean normal flux + (1/2)|A~ - (v_w.n) I|(Ul - Ur), with the
 // dissipation in wave-strength form (Roe averages of velocity and total
 // enthalpy; eigenvalues (v~.n - v_w.n) and (v~.n - v_w.n) +- c~).
-__device__ __forceinline__ void roe_flux(const double Ul[4], const double Ur[4], double nx,
-                                         double ny, double vwn, double gm1, double F[4]) {
+__device__ __forceinline__ void roe_flux(const double Ul[4], double irl, const double Ur[4],
+                                         double irr, double nx, double ny, double vwn, double gm1,
+                                         double F[4]) {
   double fl[4], fr[4];
-  normal_adv_flux(Ul, nx, ny, vwn, gm1, fl);
-  normal_adv_flux(Ur, nx, ny, vwn, gm1, fr);
-  double irl = 1.0 / Ul[0], irr = 1.0 / Ur[0];
+  normal_adv_flux(Ul, irl, nx, ny, vwn, gm1, fl);
+  normal_adv_flux(Ur, irr, nx, ny, vwn, gm1, fr);
   double ul = Ul[1] * irl, vl = Ul[2] * irl, ur = Ur[1] * irr, vr = Ur[2] * irr;
   double pl = gm1 * (Ul[3] - 0.5 * (Ul[1] * ul + Ul[2] * vl));
   double pr = gm1 * (Ur[3] - 0.5 * (Ur[1] * ur + Ur[2] * vr));

@@ -94,17 +94,17 @@ __device__ __forceinline__ double lane_read(double v, int src) {
 // periodic), the moving adiabatic wall's ghost Q^b = [rho+, v_w, p+], or the
 // far-field state (Sec. 2.2.4).  nb points at the neighbour's node, stride Np.
 __device__ __forceinline__ void ghost_state(int tag, const double up[4], const double* nb, int Np,
-                                            double vwx, double vwy, const double* Uinf, double gm1,
-                                            double uo[4]) {
+                                            double vwx, double vwy, const double* Uinf,
+                                            const Gas& gas, double uo[4]) {
   if (tag == 0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) uo[c] = nb[c * Np];
   } else if (tag == 1) {
-    const double p = pressure(up, gm1);
+    const double p = pressure(up, 1.0 / up[0], gas.gm1);
     uo[0] = up[0];
     uo[1] = up[0] * vwx;
     uo[2] = up[0] * vwy;
-    uo[3] = p / gm1 + 0.5 * up[0] * (vwx * vwx + vwy * vwy);
+    uo[3] = p * gas.igm1 + 0.5 * up[0] * (vwx * vwx + vwy * vwy);
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) uo[c] = Uinf[c];
@@ -150,6 +150,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
   Gas gas;
   gas.gamma = ph.gamma;
   gas.gm1 = ph.gamma - 1.0;
+  gas.igm1 = 1.0 / (ph.gamma - 1.0);
   gas.mu = ph.mu;
   gas.k = ph.gamma / ph.Pr;
   const double theta = ph.theta;
@@ -165,49 +166,61 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
 
   const int arow = lane & 15, acol = lane >> 4;  // A-operand row (4c + e), k offset
   const int re = lane >> 4, rn = lane & 15;      // output: element re, node 16 t + rn
+  // state loads: value r = lane + 64 q of an element block is field r / Np,
+  // node r % Np
+  constexpr int NQ = (S + 63) / 64;
+  bool lr_ok[NQ];
+  int lds_u[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int r = lane + 64 * q;
+    lr_ok[q] = r < S;
+    lds_u[q] = lr_ok[q] ? (4 * (r / Np)) * RS + (r - (r / Np) * Np) : 0;
+  }
 
   for (int64_t tile = tb + w0; tile < te; tile += wstride) {
     const int64_t e0 = tile * 4;
     const int nel = (int)((K - e0) < 4 ? (K - e0) : 4);
     wave_sync();
-    // ---- own states, geometry, connectivity: every load issued before the first use
-    constexpr int NLU = (4 * S + 63) / 64, NLN = (12 * S + 63) / 64;
-    double ru[NLU];
+    // ---- own states, geometry, connectivity.  Lane l owns values r = l + 64 q
+    // of every element block, so addresses are a per-lane constant plus a
+    // wave-uniform base, and every load is issued before the first use.
+    double ru[4][NQ];
 #pragma unroll
-    for (int q = 0; q < NLU; ++q) {
-      const int i = lane + 64 * q;
-      ru[q] = (i < nel * S) ? Uin[e0 * S + i] : 0.0;
-    }
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        ru[e][q] = (lr_ok[q] && e < nel) ? Uin[(e0 + e) * S + lane + 64 * q] : 0.0;
     const double rg = (lane < nel * kGeoStride) ? t.geo[e0 * kGeoStride + lane] : 0.0;
     const int rc = (lane < nel * 3) ? t.conn[e0 * 3 + lane] : 0;
     if (lane < nel * 3) sConn[lane] = rc;
     wave_sync();
     // ---- neighbour states (a boundary face points at the element itself) and
-    // metrics, in two batches of independent loads (bounded register use)
+    // metrics, in two batches of six blocks (bounded register use)
     const double rng = (lane < nel * 12) ? t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)] : 0.0;
 #pragma unroll
-    for (int q = 0; q < NLU; ++q) {
-      const int i = lane + 64 * q;
-      if (i < nel * S) {
-        const int e = i / S, r = i - e * S, c = r / Np, n = r - c * Np;
-        sU[(4 * c + e) * RS + n] = ru[q];
-      }
-    }
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (lr_ok[q] && e < nel) sU[lds_u[q] + e * RS] = ru[e][q];
     if (lane < nel * kGeoStride) sGeo[lane] = rg;
-    constexpr int NLH = (NLN + 1) / 2;
 #pragma nounroll
     for (int h = 0; h < 2; ++h) {
-      double rnb[NLH];
+      double rnb[6][NQ];
 #pragma unroll
-      for (int q = 0; q < NLH; ++q) {
-        const int i = lane + 64 * (h * NLH + q);
-        const int ef = i / S;
-        rnb[q] = (i < nel * 3 * S) ? Uin[(int64_t)(sConn[ef < 12 ? ef : 11] >> 4) * S + (i - ef * S)] : 0.0;
+      for (int b = 0; b < 6; ++b) {
+        const int ef = 6 * h + b;  // uniform across the wave
+        const int64_t nb = (int64_t)(sConn[ef] >> 4) * S;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          rnb[b][q] = (lr_ok[q] && ef < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < NLH; ++q) {
-        const int i = lane + 64 * (h * NLH + q);
-        if (i < nel * 3 * S) sX[i] = rnb[q];
+      for (int b = 0; b < 6; ++b) {
+        const int ef = 6 * h + b;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (lr_ok[q] && ef < 3 * nel) sX[ef * S + lane + 64 * q] = rnb[b][q];
       }
     }
     if (lane < nel * 12) sNGeo[lane] = rng;
@@ -239,9 +252,9 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int c = 0; c < 4; ++c) U[c] = sU[(4 * c + re) * RS + n];
         double fvx[4], fvy[4];
-        viscous_flux(gas, U, gxk[tt], gyk[tt], fvx, fvy);
-        const double ir = 1.0 / U[0];
-        const double u = U[1] * ir, v = U[2] * ir;
+        const VState st = vstate(gas, U);
+        viscous_flux(gas, st, gxk[tt], gyk[tt], fvx, fvy);
+        const double u = st.v1, v = st.v2;
         const double p = gas.gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
         const double qu = u - vwx, qv = v - vwy;
         double Fx[4] = {U[0] * qu, U[1] * qu + p, U[2] * qu, U[3] * qu + p * u};
@@ -291,12 +304,13 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         for (int c = 0; c < 4; ++c) up[c] = sU[(4 * c + e) * RS + n];
         const int n2 = (tag == 0) ? face_node<N>(nf, Nfp - 1 - j) : n;
         const double* nbU = sX + (e * 3 + f) * S;
-        ghost_state(tag, up, nbU + n2, Np, vwx, vwy, ph.U_inf, gas.gm1, uo);
+        ghost_state(tag, up, nbU + n2, Np, vwx, vwy, ph.U_inf, gas, uo);
+        const VState sp = vstate(gas, up), so = vstate(gas, uo);
         // one side at a time: the two evaluations need not be live together
         double nrm = 0.0;
 #pragma nounroll
         for (int side = 0; side < 2; ++side) {
-          const double a1 = normal_diffusion_norm(gas, side == 0 ? up : uo, nx, ny);
+          const double a1 = normal_diffusion_norm(gas, side == 0 ? sp : so, nx, ny);
           nrm = a1 > nrm ? a1 : nrm;
         }
         sNorm[e * NF + fn] = nrm;
@@ -326,15 +340,15 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         // on the far field
         double vx[4], vy[4], vn[4];
         if (tag == 1) {
-          viscous_flux(gas, uo, gxm, gym, vx, vy);
+          viscous_flux(gas, so, gxm, gym, vx, vy);
 #pragma unroll
           for (int c = 0; c < 4; ++c) vn[c] = vx[c] * nx + vy[c] * ny;
         } else {
-          viscous_flux(gas, up, gxp, gyp, vx, vy);
+          viscous_flux(gas, sp, gxp, gyp, vx, vy);
 #pragma unroll
           for (int c = 0; c < 4; ++c) vn[c] = vx[c] * nx + vy[c] * ny;
           if (tag == 0) {
-            viscous_flux(gas, uo, gxm, gym, vx, vy);
+            viscous_flux(gas, so, gxm, gym, vx, vy);
 #pragma unroll
             for (int c = 0; c < 4; ++c) vn[c] = 0.5 * (vn[c] + vx[c] * nx + vy[c] * ny);
           }
@@ -360,8 +374,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int c = 0; c < 4; ++c) fup[q][c] = sU[(4 * c + e) * RS + n];
         const int n2 = face_node<N>(nf, Nfp - 1 - j);
-        ghost_state(tag, fup[q], sX + (e * 3 + f) * S + n2, Np, vwx, vwy, ph.U_inf, gas.gm1,
-                    fuo[q]);
+        ghost_state(tag, fup[q], sX + (e * 3 + f) * S + n2, Np, vwx, vwy, ph.U_inf, gas, fuo[q]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) fvn[q][c] = sVn[(e * NF + fn) * 4 + c];
         double gbar = 0.0;
@@ -387,15 +400,17 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         const double nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f];
         const double sigma = g[7 + 4 * f] * fgb[q];
         const double vwn = vwx * nx + vwy * ny;
+        const VState sp = vstate(gas, fup[q]);
+        const VState so = vstate(gas, fuo[q]);
         double Fc[4];
         if (tag == 1) {
-          const double p = pressure(fup[q], gas.gm1);
+          const double p = pressure(fup[q], sp.ir, gas.gm1);
           Fc[0] = 0.0;
           Fc[1] = p * nx;
           Fc[2] = p * ny;
           Fc[3] = p * vwn;
         } else {
-          roe_flux(fup[q], fuo[q], nx, ny, vwn, gas.gm1, Fc);
+          roe_flux(fup[q], sp.ir, fuo[q], so.ir, nx, ny, vwn, gas.gm1, Fc);
         }
         double w[4];
 #pragma unroll
@@ -408,7 +423,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
           sH[(4 * c + e) * HRS + fn] = own - fsc * (Fc[c] - fvn[q][c] + sigma * w[c]);
         }
         double qx[4], qy[4];
-        viscous_transpose(gas, tag == 1 ? fuo[q] : fup[q], nx, ny, w, qx, qy);
+        viscous_transpose(gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
         const double ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
         const double rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll
@@ -481,6 +496,7 @@ __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysic
   Gas gas;
   gas.gamma = ph.gamma;
   gas.gm1 = ph.gamma - 1.0;
+  gas.igm1 = 1.0 / (ph.gamma - 1.0);
   gas.mu = ph.mu;
   gas.k = ph.gamma / ph.Pr;
   const double* Dr = t.ops;
@@ -510,11 +526,11 @@ __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysic
       dx[c] = g[0] * ur[c] + g[2] * us[c];
       dy[c] = g[1] * ur[c] + g[3] * us[c];
     }
-    double p = pressure(Up, gas.gm1);
+    double p = pressure(Up, 1.0 / Up[0], gas.gm1);
     double Ub[4] = {Up[0], Up[0] * ph.vw[0], Up[0] * ph.vw[1],
-                    p / gas.gm1 + 0.5 * Up[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1])};
+                    p * gas.igm1 + 0.5 * Up[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1])};
     double vx[4], vy[4];
-    viscous_flux(gas, Ub, dx, dy, vx, vy);
+    viscous_flux(gas, vstate(gas, Ub), dx, dy, vx, vy);
     const double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
     const double sJ = g[6 + 4 * f] / (g[0] * g[3] - g[1] * g[2]);  // Fscale * J
     const double w = wface[f * Nfp + j] * sJ;
