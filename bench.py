@@ -25,6 +25,14 @@ if ROOT not in sys.path:
 
 METRIC = "DG RHS DOF-updates/s at p=4–6, chosen form vs plain FP64 at stated L2 err"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# HBM bytes per stage launch measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (cylinder20k, p = 4), each scaled by the counter's reading for a
+# plain 512 MiB device copy (FETCH x 2.000, WRITE x 1.000); valid only for the
+# kernel sources they were taken on (hash of kernels.hip + dg_physics.h).
+MEASURED_TRAFFIC = {"sources": "9a940f7d70753cd2", "p": 4,
+                    "fetch_bytes": 11410.0 * 2.0 * 1024, "write_bytes": 19200.0 * 1.0 * 1024}
 
 
 def log(msg):
@@ -35,6 +43,35 @@ def algorithmic_bytes_per_element(Np):
     # K0 read, K1 read, K1 write, K0 write (4 x 4 Np doubles) + geometry
     # (16 doubles) + packed connectivity (3 int32)
     return 4 * 4 * Np * 8 + 16 * 8 + 3 * 4
+
+
+def algorithmic_flops_per_element(Np, Nfp):
+    """FP64 flops of one RHS + stage per element, counted from the method.
+
+    gradient and divergence 2 x 16 Np^2 (Dr, Ds on 4 fields), three lifts
+    24 Np (3 Nfp), volume-node flux 75 Np, face nodes (16 Np + 460) per
+    node of the 3 Nfp (neighbour gradient at the node 16 Np; two
+    ||n^T G n||_2 ~200, two viscous normal fluxes ~80, Roe ~110, penalty and
+    residual ~20, theta term ~50), stage update 16 Np.
+    """
+    NF = 3 * Nfp
+    return 32 * Np * Np + 24 * Np * NF + 75 * Np + (16 * Np + 460) * NF + 16 * Np
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "dg_physics.h"):
+        with open(os.path.join(ROOT, "paper_2508_17917_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(p):
+    t = MEASURED_TRAFFIC
+    if t["sources"] != kernel_sources_hash() or t["p"] != p:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
 def cpu_baseline(w, p, budget_s=20.0):
@@ -74,6 +111,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -133,7 +172,8 @@ def main():
     torch.cuda.synchronize()
     t_launch = e0.elapsed_time(e1) / 1e3 / nl
     bytes_launch = algorithmic_bytes_per_element(Np) * K
-    achieved = bytes_launch / t_launch / 1e9
+    flops_launch = algorithmic_flops_per_element(Np, p + 1) * K
+    achieved = flops_launch / t_launch / 1e12
 
     dofs = 4 * Np * K
     value = dofs * 5 * args.steps / t_steps
@@ -155,12 +195,25 @@ def main():
                                "1e-3 seeded noise, plain FP64" % (K, p, Np),
                    "K": K, "p": p, "dofs": dofs, "form": "fp64", "finite": finite,
                    "wall_s": wall},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(p),
                      "kernel": "stage_kernel<%d>" % p, "avg_launch_us": t_launch * 1e6,
-                     "bytes_per_launch": bytes_launch},
+                     "flops_per_launch": flops_launch, "bytes_per_launch": bytes_launch,
+                     "hbm_achieved_GBs": bytes_launch / t_launch / 1e9,
+                     "hbm_frac": bytes_launch / t_launch / 1e9 / HBM_PEAK_GBS},
     }
     s.close()
+    if args.copy_probe:
+        # a plain copy kernel of known size: 512 MiB read + 512 MiB written per copy,
+        # out of any cache, for scaling the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel() * 8
+        del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, p)
