@@ -11,7 +11,16 @@ inputs resident in HBM.  Also reported: the average duration of the stage
 kernel (HIP events on the launch stream) against its algorithmic HBM bytes,
 and the FP64 NumPy oracle timed on the host on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--p P] [--no-cpu-baseline]
+Forms (--form): fp64 (plain, every step binary64), fp64-pert and fp32-pert
+(the right-hand side on U - U_inf with cancellation-free flux differences, in
+binary64 or binary32; the RK registers stay binary64).  Whatever the form,
+plain FP64 is run beside it from the same initial state for the same number
+of steps, and the relative L2 difference of the two final states, measured
+on the change of the state over the run and on its deviation from U_inf, is
+reported with the number.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--p P] [--form F]
+                       [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -26,12 +35,14 @@ if ROOT not in sys.path:
 METRIC = "DG RHS DOF-updates/s at p=4–6, chosen form vs plain FP64 at stated L2 err"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+FORMS = {"fp64": 0, "fp64-pert": 1, "fp32-pert": 2}
 
 # HBM bytes per stage launch measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (cylinder20k, p = 4), each scaled by the counter's reading for a
 # plain 512 MiB device copy (FETCH x 2.000, WRITE x 1.000); valid only for the
 # kernel sources they were taken on (hash of kernels.hip + dg_physics.h).
-MEASURED_TRAFFIC = {"sources": "9a940f7d70753cd2", "p": 4,
+MEASURED_TRAFFIC = {"sources": "9a940f7d70753cd2", "p": 4, "form": "fp64",
                     "fetch_bytes": 11410.0 * 2.0 * 1024, "write_bytes": 19200.0 * 1.0 * 1024}
 
 
@@ -67,9 +78,9 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(p):
+def measured_traffic(p, form):
     t = MEASURED_TRAFFIC
-    if t["sources"] != kernel_sources_hash() or t["p"] != p:
+    if t["sources"] != kernel_sources_hash() or t["p"] != p or t["form"] != form:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
 
@@ -104,12 +115,58 @@ def cpu_baseline(w, p, budget_s=20.0):
                       "1 BLAS thread, %.1f s)" % (n, mesh.K, p, el)}
 
 
+def run_form(Solver, w, U0, precision, steps, warmup, dt):
+    """Advance U0 by warmup + steps LSERK steps in one form; return the final
+    state, the time of the timed steps and the average stage-kernel duration."""
+    import torch
+
+    s = Solver(w["p"], w["mesh"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+               penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"],
+               precision=precision)
+    U = U0.clone()
+    K1 = torch.zeros_like(U)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        s.rk_step(U, K1, dt, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        s.rk_step(U, K1, dt, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_steps = ev0.elapsed_time(ev1) / 1e3
+
+    # average duration of the stage kernel alone (same stream, HIP events), on
+    # scratch copies so the state above is left as the steps made it
+    Ua = U.clone()
+    Ub = torch.empty_like(U)
+    Kb = K1.clone()
+    nl = 100
+    for _ in range(5):
+        s.rk_stage(Ua, Ub, Kb, -0.4, 0.3, dt, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(nl):
+        s.rk_stage(Ua, Ub, Kb, -0.4, 0.3, dt, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_launch = e0.elapsed_time(e1) / 1e3 / nl
+    s.close()
+    return U, t_steps, wall, t_launch
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--form", choices=sorted(FORMS), default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
@@ -127,54 +184,33 @@ def main():
 
     w = mg.workload("cylinder20k", args.p)
     p = w["p"]
-    log("building solver: cylinder20k p=%d" % p)
-    s = Solver(p, w["mesh"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
-               penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"])
-    K, Np = s.K, s.Np
+    Np = (p + 1) * (p + 2) // 2
+    K = len(w["mesh"]["EToV"])
     rng = mg.rng_for(1)
-    U0 = mg.noisy_free_stream((4, Np, K), w["U_inf"], rng)
-    U = torch.from_numpy(np.ascontiguousarray(np.transpose(U0, (2, 0, 1)))).cuda()
-    K1 = torch.zeros_like(U)
+    U0n = mg.noisy_free_stream((4, Np, K), w["U_inf"], rng)
+    U0 = torch.from_numpy(np.ascontiguousarray(np.transpose(U0n, (2, 0, 1)))).cuda()
     # SIPG with C1 = 1 on the 2.9e-3 wall layer at p = 4 is penalty-limited
     # near 3e-7; 1e-7 keeps the impulsively started state bounded
     dt = 1e-7
-    stream = torch.cuda.current_stream()
 
-    log("warmup %d steps" % args.warmup)
-    for _ in range(args.warmup):
-        s.rk_step(U, K1, dt, stream=stream)
-    torch.cuda.synchronize()
-    log("timing %d steps" % args.steps)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        s.rk_step(U, K1, dt, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    t_steps = ev0.elapsed_time(ev1) / 1e3
+    log("form %s: cylinder20k p=%d, warmup %d, steps %d" % (args.form, p, args.warmup, args.steps))
+    U, t_steps, wall, t_launch = run_form(Solver, w, U0, FORMS[args.form], args.steps,
+                                          args.warmup, dt)
     finite = bool(torch.isfinite(U).all().item())
+    if args.form != "fp64":
+        log("plain fp64 beside it")
+        U64, t64, _, tl64 = run_form(Solver, w, U0, FORMS["fp64"], args.steps, args.warmup, dt)
+    else:
+        U64, t64, tl64 = U, t_steps, t_launch
+    uinf = torch.tensor(w["U_inf"], dtype=torch.float64, device=U.device).view(1, 4, 1)
+    diff = (U - U64).norm().item()
+    l2_change = diff / max((U64 - U0).norm().item(), 1e-300)
+    l2_pert = diff / max((U64 - uinf).norm().item(), 1e-300)
 
-    # average duration of the stage kernel alone (same stream, HIP events)
-    Ub = torch.empty_like(U)
-    nl = 100
-    for _ in range(5):
-        s.rk_stage(U, Ub, K1, -0.4, 0.3, dt, stream=stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(nl):
-        s.rk_stage(U, Ub, K1, -0.4, 0.3, dt, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_launch = e0.elapsed_time(e1) / 1e3 / nl
     bytes_launch = algorithmic_bytes_per_element(Np) * K
     flops_launch = algorithmic_flops_per_element(Np, p + 1) * K
     achieved = flops_launch / t_launch / 1e12
-
+    peak = FP32_PEAK_TFLOPS if args.form == "fp32-pert" else FP64_PEAK_TFLOPS
     dofs = 4 * Np * K
     value = dofs * 5 * args.steps / t_steps
     out = {
@@ -188,22 +224,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if args.form == "fp32-pert" else "f64",
         "data": "synthetic",
         "config": {"workload": "cylinder20k: O-grid 80x128 cells (ratio 1.05, r 0.5..30) -> "
                                "K=%d triangles, p=%d (Np=%d), Re=100, M=0.2, SIPG, free stream + "
-                               "1e-3 seeded noise, plain FP64" % (K, p, Np),
-                   "K": K, "p": p, "dofs": dofs, "form": "fp64", "finite": finite,
+                               "1e-3 seeded noise, %s form" % (K, p, Np, args.form),
+                   "K": K, "p": p, "dofs": dofs, "form": args.form, "dt": dt, "finite": finite,
                    "wall_s": wall},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(p),
-                     "kernel": "stage_kernel<%d>" % p, "avg_launch_us": t_launch * 1e6,
+        "vs_plain_fp64": {"value": dofs * 5 * args.steps / t64, "avg_launch_us": tl64 * 1e6,
+                          "speedup": t64 / t_steps,
+                          "l2_rel_err_of_change": l2_change, "l2_rel_err_of_perturbation": l2_pert,
+                          "steps_compared": args.warmup + args.steps},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(p, args.form),
+                     "kernel": "stage_kernel<%d, %s>" % (p, args.form),
+                     "avg_launch_us": t_launch * 1e6,
                      "flops_per_launch": flops_launch, "bytes_per_launch": bytes_launch,
                      "hbm_achieved_GBs": bytes_launch / t_launch / 1e9,
                      "hbm_frac": bytes_launch / t_launch / 1e9 / HBM_PEAK_GBS},
     }
-    s.close()
     if args.copy_probe:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per copy,
         # out of any cache, for scaling the FETCH_SIZE / WRITE_SIZE counters

@@ -52,8 +52,19 @@ typedef enum dg_status {
   DG_ESTATE = -7         /* call out of order (e.g. dg_rhs before dg_setup)     */
 } dg_status;
 
+/* Arithmetic of the right-hand side.  The RK registers (the state U and
+ * K1 of Alg. 1) are binary64 in every mode; in the perturbation modes the
+ * kernel works on U' = U - U_inf (U_inf the far-field state of
+ * dg_set_physics), writing every flux as F(U_inf + U') - F(U_inf) without
+ * cancellation (the constant F(U_inf) has no divergence and cancels from
+ * every face term), so that the small deviations of a low-Mach flow from
+ * the free stream keep their relative precision in binary32. */
 typedef enum dg_precision {
-  DG_FP64 = 0            /* every step in IEEE binary64                         */
+  DG_FP64 = 0,           /* every step in IEEE binary64                         */
+  DG_FP64_PERT = 1,      /* perturbation form, binary64 (equal to DG_FP64 up    *
+                          * to rounding; a check on the perturbation algebra)   */
+  DG_FP32_PERT = 2       /* perturbation form, binary32 right-hand side,        *
+                          * binary32 matrix-core products, binary64 RK update   */
 } dg_precision;
 
 typedef enum dg_penalty_mode {
@@ -65,7 +76,7 @@ typedef enum dg_penalty_mode {
   DG_PENALTY_STANDARD = 1
 } dg_penalty_mode;
 
-/* Create a context for polynomial order p (1 <= p <= 8).  *out receives the
+/* Create a context for polynomial order p (1 <= p <= 6) and a dg_precision mode.  *out receives the
  * context (owned by the caller, released with dg_destroy).  No GPU work. */
 int dg_create(int p, int precision, dg_ctx** out);
 

@@ -53,6 +53,7 @@ struct DeviceTables {
   const int32_t* conn = nullptr;   // K x 3
   const double* ops = nullptr;     // packed operators (pack_ops)
   const double* frag = nullptr;    // operator fragments in matrix-core lane order (pack_frags)
+  const float* frag32 = nullptr;   // the same fragments rounded to FP32 (FP32 form)
   const int32_t* wall = nullptr;   // wall face list (k*3 + f)
   const double* wall_xy = nullptr; // node coordinates of the wall faces, (x, y) per face node
   int64_t K = 0;
@@ -65,8 +66,9 @@ struct KernelPhysics {
   double vw[2];
 };
 
-// kernels.hip
-int launch_stage(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U_in,
+// kernels.hip.  form: 0 plain FP64, 1 perturbation FP64, 2 perturbation FP32
+// (the dg_precision values).
+int launch_stage(int N, int form, const DeviceTables& t, const KernelPhysics& ph, const double* U_in,
                  double* U_out, double* K1, double a, double b, double dt, int rhs_only,
                  void* stream, std::string& err);
 int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
@@ -78,5 +80,8 @@ void pack_ops(const RefOps& ref, std::vector<double>& out);
 // matrix instruction: for output tile t (nodes 16t..16t+15) and k-step s,
 // lane l holds Op[16t + l%16][4s + l/16] (zero outside the matrix).
 void pack_frags(const RefOps& ref, std::vector<double>& out);
+// The FP32 matrix instruction (16x16x4 f32) takes its B operand in the same
+// lane order, so the FP32 fragments are the FP64 ones rounded.
+void pack_frags32(const RefOps& ref, std::vector<float>& out);
 
 }  // namespace dgmi

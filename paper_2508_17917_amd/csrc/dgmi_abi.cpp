@@ -41,6 +41,7 @@ struct dg_ctx {
   int32_t* d_conn = nullptr;
   double* d_ops = nullptr;
   double* d_frag = nullptr;
+  float* d_frag32 = nullptr;
   int32_t* d_wall = nullptr;
   double* d_wall_xy = nullptr;
   double* d_scratch = nullptr;
@@ -66,7 +67,7 @@ int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 void free_device(dg_ctx* c) {
-  void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,
+  void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,  c->d_frag32,
                   c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -74,6 +75,7 @@ void free_device(dg_ctx* c) {
   c->d_conn = nullptr;
   c->d_ops = nullptr;
   c->d_frag = nullptr;
+  c->d_frag32 = nullptr;
   c->d_wall = nullptr;
   c->d_wall_xy = nullptr;
   c->d_scratch = nullptr;
@@ -97,6 +99,7 @@ dgmi::DeviceTables tables(const dg_ctx* c) {
   t.conn = c->d_conn;
   t.ops = c->d_ops;
   t.frag = c->d_frag;
+  t.frag32 = c->d_frag32;
   t.wall = c->d_wall;
   t.wall_xy = c->d_wall_xy;
   t.K = c->K;
@@ -130,7 +133,8 @@ int dg_create(int p, int precision, dg_ctx** out) {
   if (!out) return fail(nullptr, DG_EINVAL, "out is NULL");
   *out = nullptr;
   if (p < 1 || p > 6) return fail(nullptr, DG_EUNSUPPORTED, "polynomial order must be in 1..6");
-  if (precision != DG_FP64) return fail(nullptr, DG_EUNSUPPORTED, "unsupported precision mode");
+  if (precision != DG_FP64 && precision != DG_FP64_PERT && precision != DG_FP32_PERT)
+    return fail(nullptr, DG_EUNSUPPORTED, "unsupported precision mode");
   dg_ctx* c = new (std::nothrow) dg_ctx();
   if (!c) return fail(nullptr, DG_ENOMEM, "out of host memory");
   c->N = p;
@@ -202,12 +206,15 @@ int dg_setup(dg_ctx* c) {
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
   std::vector<double> ops, frag;
+  std::vector<float> frag32;
   dgmi::pack_ops(c->ref, ops);
   dgmi::pack_frags(c->ref, frag);
+  dgmi::pack_frags32(c->ref, frag32);
   if ((e = upload(&c->d_geo, c->mesh.geo)) != hipSuccess ||
       (e = upload(&c->d_conn, c->mesh.conn)) != hipSuccess ||
       (e = upload(&c->d_ops, ops)) != hipSuccess ||
       (e = upload(&c->d_frag, frag)) != hipSuccess ||
+      (e = upload(&c->d_frag32, frag32)) != hipSuccess ||
       (e = upload(&c->d_wall, c->mesh.wall_faces)) != hipSuccess ||
       (e = upload(&c->d_wall_xy, c->mesh.wall_xy)) != hipSuccess) {
     free_device(c);
@@ -269,7 +276,7 @@ int dg_rhs(dg_ctx* c, const double* U, double* R, const double v_w[2], void* str
   if (rc != DG_OK) return rc;
   if (!U || !R || U == R) return fail(c, DG_EINVAL, "U and R must be distinct device arrays");
   std::string err;
-  rc = dgmi::launch_stage(c->N, tables(c), kphys(c, v_w), U, nullptr, R, 0.0, 0.0, 1.0, 1, stream,
+  rc = dgmi::launch_stage(c->N, c->precision, tables(c), kphys(c, v_w), U, nullptr, R, 0.0, 0.0, 1.0, 1, stream,
                           err);
   return rc == 0 ? DG_OK : fail(c, rc, err);
 }
@@ -281,7 +288,7 @@ int dg_rk_stage(dg_ctx* c, const double* Uin, double* Uout, double* K1, double a
   if (!Uin || !Uout || !K1 || Uin == Uout || K1 == Uin || K1 == Uout)
     return fail(c, DG_EINVAL, "U_in, U_out and K1 must be distinct device arrays");
   std::string err;
-  rc = dgmi::launch_stage(c->N, tables(c), kphys(c, v_w), Uin, Uout, K1, a, b, dt, 0, stream, err);
+  rc = dgmi::launch_stage(c->N, c->precision, tables(c), kphys(c, v_w), Uin, Uout, K1, a, b, dt, 0, stream, err);
   return rc == 0 ? DG_OK : fail(c, rc, err);
 }
 
@@ -295,7 +302,7 @@ int dg_rk_step(dg_ctx* c, double* U, double* K1, double dt, const double v_w[2],
   dgmi::KernelPhysics k = kphys(c, v_w);
   double* bufs[2] = {U, c->d_scratch};
   for (int i = 0; i < 5; ++i) {
-    rc = dgmi::launch_stage(c->N, t, k, bufs[i & 1], bufs[(i + 1) & 1], K1, kRkA[i], kRkB[i], dt, 0,
+    rc = dgmi::launch_stage(c->N, c->precision, t, k, bufs[i & 1], bufs[(i + 1) & 1], K1, kRkA[i], kRkB[i], dt, 0,
                             stream, err);
     if (rc != 0) return fail(c, rc, err);
   }

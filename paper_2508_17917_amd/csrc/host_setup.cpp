@@ -461,6 +461,12 @@ void pack_frags(const RefOps& ref, std::vector<double>& out) {
   emit(ref.LIFTs, NF, KF);
 }
 
+void pack_frags32(const RefOps& ref, std::vector<float>& out) {
+  std::vector<double> d;
+  pack_frags(ref, d);
+  out.assign(d.begin(), d.end());
+}
+
 size_t ops_packed_size(int N) {
   size_t Np = (N + 1) * (N + 2) / 2, NF = 3 * (N + 1);
   return 2 * Np * Np + 3 * Np * NF + NF;

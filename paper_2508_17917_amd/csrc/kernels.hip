@@ -5,9 +5,9 @@
 // Alg. 2 (the neighbour exchange becomes reads of the neighbours' nodal
 // states, resident in HBM / L2 on one GPU):
 //   1  own states, neighbour states and geometry -> LDS
-//   2  broken gradient on the FP64 matrix cores: rows (element, field),
-//      columns nodes, [dU/dr, dU/ds] = U [Dr^T, Ds^T]; the output lane owns one
-//      node of one element with all four fields -> total flux
+//   2  broken gradient on the matrix cores: rows (element, field), columns
+//      nodes, [dU/dr, dU/ds] = U [Dr^T, Ds^T]; the output lane owns one node
+//      of one element with all four fields -> total flux
 //      F = F_c - v_w (x) U - G grad U and its contravariant components
 //   3  face nodes (one lane each): neighbour trace and gradient (reversed face
 //      node order), boundary ghosts (Sec. 2.2.4), G-bar_e = max over the face of
@@ -16,9 +16,14 @@
 //   4  strong-form residual on the matrix cores,
 //      R = -(Dr Fr + Ds Fs) + LIFT h + LIFTr qr + LIFTs qs
 //      (M^-1 and 1/J folded into the operators and Fscale), then
-//      K1 <- a K1 + dt R, U_out <- U_in + b K1 (Alg. 1).
+//      K1 <- a K1 + dt R, U_out <- U_in + b K1 (Alg. 1) in FP64.
 // Every element writes only its own nodes and each face is evaluated from both
 // sides, so there are no atomics and results are bitwise reproducible.
+//
+// Variants (template parameters): the real type T of the right-hand side
+// (double, float) and the form (plain: the state itself; perturbation: the
+// state minus the free stream, fluxes as cancellation-free differences).  The
+// RK registers K0 = U and K1 are FP64 in every variant.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -28,25 +33,25 @@
 
 namespace dgmi {
 
-template <int N>
+template <int N, typename T>
 struct Order {
   static constexpr int Np = (N + 1) * (N + 2) / 2;
   static constexpr int Nfp = N + 1;
   static constexpr int NF = 3 * (N + 1);
-  static constexpr int S = 4 * Np;               // doubles per element state
+  static constexpr int S = 4 * Np;               // values per element state
   static constexpr int NT = (Np + 15) / 16;      // 16-node output tiles
   static constexpr int KS = (Np + 3) / 4;        // k-steps over volume nodes
   static constexpr int KF = (NF + 3) / 4;        // k-steps over face nodes
   static constexpr int RS = 4 * KS + 1;          // padded LDS row (odd: no bank aliasing)
   static constexpr int HRS = 4 * KF + 1;
   static constexpr int FIT = (4 * NF + 63) / 64; // face items per lane
-  static constexpr int WAVES = (N <= 4) ? 4 : 2;
+  static constexpr int WAVES = (N <= 4 || sizeof(T) == 4) ? 4 : 2;
   static constexpr int THREADS = 64 * WAVES;
-  // per-wave LDS (doubles)
-  static constexpr int U_SZ = 16 * RS;           // own state, row 4c + e
+  // per-wave LDS (elements of T)
+  static constexpr int U_SZ = 16 * RS;           // own state
   static constexpr int F_SZ = 32 * RS;           // contravariant flux Fr rows | Fs rows
   static constexpr int N_SZ = 12 * S;            // neighbour states [e][f][c][n]
-  static constexpr int H_SZ = 48 * HRS;          // face terms h | qr | qs, row 4c + e
+  static constexpr int H_SZ = 48 * HRS;          // face terms h | qr | qs
   static constexpr int X_SZ = N_SZ > H_SZ ? N_SZ : H_SZ;
   static constexpr int NORM_SZ = 4 * NF;
   static constexpr int VN_SZ = 16 * NF;          // mean viscous normal flux per face node
@@ -55,6 +60,11 @@ struct Order {
   static constexpr int FD = NT * KS * 64;        // one Dr-type fragment set
   static constexpr int FL = NT * KF * 64;        // one LIFT-type fragment set
   static constexpr int FRAG_SZ = 2 * FD + 3 * FL;
+  // matrix-core row of (field c, element e): the FP64 instruction returns rows
+  // l/16 + 4v to lane l, the FP32 one rows 4(l/16) + v; either way lane l ends
+  // up with element l/16 and field v
+  static constexpr int ROWC = sizeof(T) == 8 ? 4 : 1;
+  static constexpr int ROWE = sizeof(T) == 8 ? 1 : 4;
 };
 
 // Node index of face node j (counter-clockwise) on face f; rows of the node
@@ -67,14 +77,19 @@ __device__ __forceinline__ int face_node(int f, int j) {
   return i * (N + 1) - i * (i - 1) / 2;
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Vec4 {
+  typedef T type __attribute__((ext_vector_type(4)));
+};
 
-// D += A B for A 16x4, B 4x16, D 16x16 (FP64 matrix core).  Lane l supplies
-// A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4v][l%16], v = 0..3.
-// With rows ordered (field c, element e) -> 4c + e, lane l therefore ends up
-// with node l%16 of element l/16, all four fields in v = c.
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+// D += A B for A 16x4, B 4x16, D 16x16 on the matrix cores.  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; it holds D[l/16 + 4v][l%16] (FP64) or
+// D[4(l/16) + v][l%16] (FP32), v = 0..3.
+__device__ __forceinline__ Vec4<double>::type mfma(double a, double b, Vec4<double>::type c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ Vec4<float>::type mfma(float a, float b, Vec4<float>::type c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 // LDS ordering among the lanes of one wavefront (no workgroup barrier).
@@ -89,72 +104,149 @@ __device__ __forceinline__ double lane_read(double v, int src) {
   int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float lane_read(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
 
-// State on the other side of a face node: the neighbour's trace (interior,
-// periodic), the moving adiabatic wall's ghost Q^b = [rho+, v_w, p+], or the
-// far-field state (Sec. 2.2.4).  nb points at the neighbour's node, stride Np.
-__device__ __forceinline__ void ghost_state(int tag, const double up[4], const double* nb, int Np,
-                                            double vwx, double vwy, const double* Uinf,
-                                            const Gas& gas, double uo[4]) {
+template <typename T, bool PERT>
+__device__ __forceinline__ void full_state(const T u[4], const Base<T>& b, T uf[4]) {
+  if (PERT) {
+    uf[0] = b.rho + u[0];
+    uf[1] = b.mx + u[1];
+    uf[2] = b.my + u[2];
+    uf[3] = b.E + u[3];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) uf[c] = u[c];
+  }
+}
+
+template <typename T, bool PERT>
+__device__ __forceinline__ Prim<T> prim_of(const T uf[4], const T u[4], const Base<T>& b, T gm1) {
+  return PERT ? prim_pert(uf, u, b, gm1) : prim_plain(uf, gm1);
+}
+
+template <typename T, bool PERT>
+__device__ __forceinline__ void normal_flux(const T uf[4], const T u[4], const Prim<T>& s,
+                                            const Base<T>& b, T nx, T ny, T vwn, T F[4]) {
+  if (PERT)
+    normal_flux_pert(u, s, b, nx, ny, vwn, F);
+  else
+    normal_flux_plain(uf, s, nx, ny, vwn, F);
+}
+
+// Value of the state on the other side of a face node (in what the kernel
+// stores: the state, or its perturbation from U_inf): the neighbour's trace
+// (interior, periodic), the moving adiabatic wall's ghost Q^b = [rho+, v_w,
+// p+], or the far field U_inf (Sec. 2.2.4).  nb points at the neighbour's
+// node, stride Np; up is the own value, upf the own full state.
+template <typename T, bool PERT>
+__device__ __forceinline__ void ghost_state(int tag, const T up[4], const T upf[4], const T* nb,
+                                            int Np, T vwx, T vwy, const Gas<T>& gas,
+                                            const Base<T>& b, T uo[4]) {
   if (tag == 0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) uo[c] = nb[c * Np];
   } else if (tag == 1) {
-    const double p = pressure(up, 1.0 / up[0], gas.gm1);
-    uo[0] = up[0];
-    uo[1] = up[0] * vwx;
-    uo[2] = up[0] * vwy;
-    uo[3] = p * gas.igm1 + 0.5 * up[0] * (vwx * vwx + vwy * vwy);
+    const T rho = upf[0];
+    const T kw = T(0.5) * rho * (vwx * vwx + vwy * vwy);
+    const Prim<T> s = prim_of<T, PERT>(upf, up, b, gas.gm1);
+    if (!PERT) {
+      uo[0] = rho;
+      uo[1] = rho * vwx;
+      uo[2] = rho * vwy;
+      uo[3] = s.p * gas.igm1 + kw;
+    } else {
+      uo[0] = up[0];
+      uo[1] = rho * vwx - b.mx;
+      uo[2] = rho * vwy - b.my;
+      // eps_b - eps_inf = p'/(gamma-1) + rho |v_w|^2/2 - rho_inf |u_inf|^2/2
+      uo[3] = s.jp * gas.igm1 + kw - T(0.5) * (b.mx * b.ux + b.my * b.uy);
+    }
   } else {
+    if (PERT) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) uo[c] = Uinf[c];
+      for (int c = 0; c < 4; ++c) uo[c] = T(0);
+    } else {
+      uo[0] = b.rho;
+      uo[1] = b.mx;
+      uo[2] = b.my;
+      uo[3] = b.E;
+    }
   }
 }
 
+template <typename T>
+__device__ __forceinline__ const T* frag_of(const DeviceTables& t);
+template <>
+__device__ __forceinline__ const double* frag_of<double>(const DeviceTables& t) {
+  return t.frag;
+}
+template <>
+__device__ __forceinline__ const float* frag_of<float>(const DeviceTables& t) {
+  return t.frag32;
+}
+
 // The fused right-hand side + LSERK stage.  Each wavefront owns tiles of four
-// elements (16 MFMA rows = 4 fields x 4 elements); the workgroup only shares
-// the operator fragments.  Tiles are handed out in contiguous ranges per XCD
-// (workgroup b runs on XCD b % 8) so neighbour reads stay in that XCD's L2.
-template <int N>
-__global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(
-    DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin, double* __restrict__ Uout,
-    double* __restrict__ K1, double a, double b, double dt, int rhs_only) {
-  using O = Order<N>;
+// elements (16 matrix-core rows = 4 fields x 4 elements); the workgroup only
+// shares the operator fragments.  Tiles are handed out in contiguous ranges
+// per XCD (workgroup b runs on XCD b % 8) so neighbour reads stay in that
+// XCD's L2.
+template <int N, typename T, bool PERT>
+__global__ __launch_bounds__((Order<N, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(2))) void
+stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
+             double* __restrict__ Uout, double* __restrict__ K1, double a, double b, double dt,
+             int rhs_only) {
+  using O = Order<N, T>;
+  typedef typename Vec4<T>::type V4;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF = O::NF, S = O::S, NT = O::NT, KS = O::KS,
-                KF = O::KF, RS = O::RS, HRS = O::HRS, FIT = O::FIT;
+                KF = O::KF, RS = O::RS, HRS = O::HRS, FIT = O::FIT, ROWC = O::ROWC,
+                ROWE = O::ROWE;
   constexpr int OFF_DR = 0, OFF_DS = O::FD, OFF_L = 2 * O::FD, OFF_LR = 2 * O::FD + O::FL,
                 OFF_LS = 2 * O::FD + 2 * O::FL;
-  __shared__ double sFrag[O::FRAG_SZ];
-  __shared__ double sWave[O::WAVES][O::WAVE_SZ];
+  __shared__ T sFrag[O::FRAG_SZ];
+  __shared__ T sWave[O::WAVES][O::WAVE_SZ];
   __shared__ int sConnW[O::WAVES][12];
 
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < O::FRAG_SZ; i += O::THREADS) sFrag[i] = t.frag[i];
-  for (int i = lane; i < O::WAVE_SZ; i += 64) sWave[wid][i] = 0.0;  // zero pads once
+  const T* frag = frag_of<T>(t);
+  for (int i = threadIdx.x; i < O::FRAG_SZ; i += O::THREADS) sFrag[i] = frag[i];
+  for (int i = lane; i < O::WAVE_SZ; i += 64) sWave[wid][i] = T(0);  // zero pads once
   __syncthreads();
 
-  double* sU = &sWave[wid][0];
-  double* sFr = sU + O::U_SZ;
-  double* sFs = sFr + 16 * RS;
-  double* sX = sU + O::U_SZ + O::F_SZ;   // neighbour states, later face terms
-  double* sH = sX;
-  double* sQr = sX + 16 * HRS;
-  double* sQs = sX + 32 * HRS;
-  double* sNorm = sX + O::X_SZ;
-  double* sVn = sNorm + O::NORM_SZ;      // [4 NF][4]
-  double* sGeo = sVn + O::VN_SZ;         // [4][16]
-  double* sNGeo = sGeo + 64;             // [4][3][4]
-  int* sConn = sConnW[wid];              // [4][3]
+  T* sU = &sWave[wid][0];
+  T* sFr = sU + O::U_SZ;
+  T* sFs = sFr + 16 * RS;
+  T* sX = sU + O::U_SZ + O::F_SZ;   // neighbour states, later face terms
+  T* sH = sX;
+  T* sQr = sX + 16 * HRS;
+  T* sQs = sX + 32 * HRS;
+  T* sNorm = sX + O::X_SZ;
+  T* sVn = sNorm + O::NORM_SZ;      // [4 NF][4]
+  T* sGeo = sVn + O::VN_SZ;         // [4][16]
+  T* sNGeo = sGeo + 64;             // [4][3][4]
+  int* sConn = sConnW[wid];         // [4][3]
 
-  Gas gas;
-  gas.gamma = ph.gamma;
-  gas.gm1 = ph.gamma - 1.0;
-  gas.igm1 = 1.0 / (ph.gamma - 1.0);
-  gas.mu = ph.mu;
-  gas.k = ph.gamma / ph.Pr;
-  const double theta = ph.theta;
-  const double vwx = ph.vw[0], vwy = ph.vw[1];
+  Gas<T> gas;
+  gas.gamma = (T)ph.gamma;
+  gas.gm1 = (T)(ph.gamma - 1.0);
+  gas.igm1 = (T)(1.0 / (ph.gamma - 1.0));
+  gas.mu = (T)ph.mu;
+  gas.k = (T)(ph.gamma / ph.Pr);
+  const T theta = (T)ph.theta;
+  const T vwx = (T)ph.vw[0], vwy = (T)ph.vw[1];
+  Base<T> base;
+  {
+    const double r0 = ph.U_inf[0], ux0 = ph.U_inf[1] / r0, uy0 = ph.U_inf[2] / r0;
+    base.rho = (T)r0;
+    base.mx = (T)ph.U_inf[1];
+    base.my = (T)ph.U_inf[2];
+    base.E = (T)ph.U_inf[3];
+    base.p = (T)((ph.gamma - 1.0) * (ph.U_inf[3] - 0.5 * (ph.U_inf[1] * ux0 + ph.U_inf[2] * uy0)));
+    base.ux = (T)ux0;
+    base.uy = (T)uy0;
+  }
 
   const int64_t K = t.K;
   const int64_t ntiles = (K + 3) / 4;
@@ -164,18 +256,20 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
   const int64_t w0 = (int64_t)(blockIdx.x >> 3) * O::WAVES + wid;
   const int64_t wstride = (int64_t)nbx * O::WAVES;
 
-  const int arow = lane & 15, acol = lane >> 4;  // A-operand row (4c + e), k offset
+  const int arow = lane & 15, acol = lane >> 4;  // A-operand row, k offset
   const int re = lane >> 4, rn = lane & 15;      // output: element re, node 16 t + rn
   // state loads: value r = lane + 64 q of an element block is field r / Np,
   // node r % Np
   constexpr int NQ = (S + 63) / 64;
   bool lr_ok[NQ];
   int lds_u[NQ];
+  double uinf_q[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int r = lane + 64 * q;
     lr_ok[q] = r < S;
-    lds_u[q] = lr_ok[q] ? (4 * (r / Np)) * RS + (r - (r / Np) * Np) : 0;
+    lds_u[q] = lr_ok[q] ? ROWC * (r / Np) * RS + (r - (r / Np) * Np) : 0;
+    uinf_q[q] = (PERT && lr_ok[q]) ? ph.U_inf[r / Np] : 0.0;
   }
 
   for (int64_t tile = tb + w0; tile < te; tile += wstride) {
@@ -197,73 +291,74 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
     wave_sync();
     // ---- neighbour states (a boundary face points at the element itself) and
     // metrics, in two batches of six blocks (bounded register use)
-    const double rng = (lane < nel * 12) ? t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)] : 0.0;
+    const double rng =
+        (lane < nel * 12) ? t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)] : 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        if (lr_ok[q] && e < nel) sU[lds_u[q] + e * RS] = ru[e][q];
-    if (lane < nel * kGeoStride) sGeo[lane] = rg;
+        if (lr_ok[q] && e < nel) sU[lds_u[q] + ROWE * e * RS] = (T)(ru[e][q] - uinf_q[q]);
+    if (lane < nel * kGeoStride) sGeo[lane] = (T)rg;
 #pragma nounroll
     for (int h = 0; h < 2; ++h) {
       double rnb[6][NQ];
 #pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        const int ef = 6 * h + b;  // uniform across the wave
+      for (int bb = 0; bb < 6; ++bb) {
+        const int ef = 6 * h + bb;  // uniform across the wave
         const int64_t nb = (int64_t)(sConn[ef] >> 4) * S;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-          rnb[b][q] = (lr_ok[q] && ef < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
+          rnb[bb][q] = (lr_ok[q] && ef < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
       }
 #pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        const int ef = 6 * h + b;
+      for (int bb = 0; bb < 6; ++bb) {
+        const int ef = 6 * h + bb;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-          if (lr_ok[q] && ef < 3 * nel) sX[ef * S + lane + 64 * q] = rnb[b][q];
+          if (lr_ok[q] && ef < 3 * nel) sX[ef * S + lane + 64 * q] = (T)(rnb[bb][q] - uinf_q[q]);
       }
     }
-    if (lane < nel * 12) sNGeo[lane] = rng;
+    if (lane < nel * 12) sNGeo[lane] = (T)rng;
     wave_sync();
 
     // ---- gradient on the matrix cores, then the volume flux per node
-    double gxk[NT][4], gyk[NT][4];
+    T gxk[NT][4], gyk[NT][4];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
-      d4 aR = {0.0, 0.0, 0.0, 0.0}, aS = {0.0, 0.0, 0.0, 0.0};
+      V4 aR = {T(0), T(0), T(0), T(0)}, aS = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const double av = sU[arow * RS + 4 * s + acol];
+        const T av = sU[arow * RS + 4 * s + acol];
         aR = mfma(av, sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aR);
         aS = mfma(av, sFrag[OFF_DS + (tt * KS + s) * 64 + lane], aS);
       }
       const int n = 16 * tt + rn;
       const bool ok = (re < nel) && (n < Np);
-      const double* g = sGeo + re * kGeoStride;
-      const double rx = ok ? g[0] : 0.0, ry = ok ? g[1] : 0.0;
-      const double sx = ok ? g[2] : 0.0, sy = ok ? g[3] : 0.0;
+      const T* g = sGeo + re * kGeoStride;
+      const T rx = ok ? g[0] : T(0), ry = ok ? g[1] : T(0);
+      const T sx = ok ? g[2] : T(0), sy = ok ? g[3] : T(0);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         gxk[tt][c] = rx * aR[c] + sx * aS[c];
         gyk[tt][c] = ry * aR[c] + sy * aS[c];
       }
       if (ok) {
-        double U[4];
+        T u[4], uf[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) U[c] = sU[(4 * c + re) * RS + n];
-        double fvx[4], fvy[4];
-        const VState st = vstate(gas, U);
+        for (int c = 0; c < 4; ++c) u[c] = sU[(ROWC * c + ROWE * re) * RS + n];
+        full_state<T, PERT>(u, base, uf);
+        T fvx[4], fvy[4];
+        const VState<T> st = vstate(gas, uf);
         viscous_flux(gas, st, gxk[tt], gyk[tt], fvx, fvy);
-        const double u = st.v1, v = st.v2;
-        const double p = gas.gm1 * (U[3] - 0.5 * (U[1] * u + U[2] * v));
-        const double qu = u - vwx, qv = v - vwy;
-        double Fx[4] = {U[0] * qu, U[1] * qu + p, U[2] * qu, U[3] * qu + p * u};
-        double Fy[4] = {U[0] * qv, U[1] * qv, U[2] * qv + p, U[3] * qv + p * v};
+        const Prim<T> pr = prim_of<T, PERT>(uf, u, base, gas.gm1);
+        T Fx[4], Fy[4];
+        normal_flux<T, PERT>(uf, u, pr, base, T(1), T(0), vwx, Fx);
+        normal_flux<T, PERT>(uf, u, pr, base, T(0), T(1), vwy, Fy);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const double fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
-          sFr[(4 * c + re) * RS + n] = rx * fx + ry * fy;
-          sFs[(4 * c + re) * RS + n] = sx * fx + sy * fy;
+          const T fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
+          sFr[(ROWC * c + ROWE * re) * RS + n] = rx * fx + ry * fy;
+          sFs[(ROWC * c + ROWE * re) * RS + n] = sx * fx + sy * fy;
         }
       }
     }
@@ -281,13 +376,13 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
       const int f = fn / Nfp, j = fn - f * Nfp;
       const int n = face_node<N>(f, j);
       // own gradient at the face node, from the lane that computed it
-      double gxp[4], gyp[4];
+      T gxp[4], gyp[4];
       const int src = 16 * e + (n & 15);
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const double vx = lane_read(gxk[tt][c], src), vy = lane_read(gyk[tt][c], src);
+          const T vx = lane_read(gxk[tt][c], src), vy = lane_read(gyk[tt][c], src);
           if ((n >> 4) == tt) {
             gxp[c] = vx;
             gyp[c] = vy;
@@ -297,39 +392,41 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
       if (ok) {
         const int conn = sConn[e * 3 + f];
         const int tag = conn & 3, nf = (conn >> 2) & 3;
-        const double* g = sGeo + e * kGeoStride;
-        const double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
-        double up[4], uo[4];
+        const T* g = sGeo + e * kGeoStride;
+        const T nx = g[4 + 4 * f], ny = g[5 + 4 * f];
+        T up[4], uo[4], upf[4], uof[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) up[c] = sU[(4 * c + e) * RS + n];
+        for (int c = 0; c < 4; ++c) up[c] = sU[(ROWC * c + ROWE * e) * RS + n];
+        full_state<T, PERT>(up, base, upf);
         const int n2 = (tag == 0) ? face_node<N>(nf, Nfp - 1 - j) : n;
-        const double* nbU = sX + (e * 3 + f) * S;
-        ghost_state(tag, up, nbU + n2, Np, vwx, vwy, ph.U_inf, gas, uo);
-        const VState sp = vstate(gas, up), so = vstate(gas, uo);
+        const T* nbU = sX + (e * 3 + f) * S;
+        ghost_state<T, PERT>(tag, up, upf, nbU + n2, Np, vwx, vwy, gas, base, uo);
+        full_state<T, PERT>(uo, base, uof);
+        const VState<T> sp = vstate(gas, upf), so = vstate(gas, uof);
         // one side at a time: the two evaluations need not be live together
-        double nrm = 0.0;
+        T nrm = T(0);
 #pragma nounroll
         for (int side = 0; side < 2; ++side) {
-          const double a1 = normal_diffusion_norm(gas, side == 0 ? sp : so, nx, ny);
+          const T a1 = normal_diffusion_norm(gas, side == 0 ? sp : so, nx, ny);
           nrm = a1 > nrm ? a1 : nrm;
         }
         sNorm[e * NF + fn] = nrm;
         // "other side" gradient from the staged neighbour (wall: the element itself)
-        double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
+        T ur[4] = {T(0), T(0), T(0), T(0)}, us[4] = {T(0), T(0), T(0), T(0)};
         const int dbase = ((n2 >> 4) * KS) * 64 + (n2 & 15);
 #pragma unroll 4
         for (int m = 0; m < Np; ++m) {
           const int fi = dbase + (m >> 2) * 64 + (m & 3) * 16;
-          const double dr = sFrag[OFF_DR + fi], ds = sFrag[OFF_DS + fi];
+          const T dr = sFrag[OFF_DR + fi], ds = sFrag[OFF_DS + fi];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const double uu = nbU[c * Np + m];
+            const T uu = nbU[c * Np + m];
             ur[c] += dr * uu;
             us[c] += ds * uu;
           }
         }
-        const double* ng = sNGeo + (e * 3 + f) * 4;
-        double gxm[4], gym[4];
+        const T* ng = sNGeo + (e * 3 + f) * 4;
+        T gxm[4], gym[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           gxm[c] = ng[0] * ur[c] + ng[2] * us[c];
@@ -338,7 +435,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         // mean of G(U+) grad U+ and G(U-) grad U- inside; G(U^b) grad U+ on the
         // wall (grad U+ from the staged copy of the element itself); G(U+) grad U+
         // on the far field
-        double vx[4], vy[4], vn[4];
+        T vx[4], vy[4], vn[4];
         if (tag == 1) {
           viscous_flux(gas, so, gxm, gym, vx, vy);
 #pragma unroll
@@ -350,7 +447,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
           if (tag == 0) {
             viscous_flux(gas, so, gxm, gym, vx, vy);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) vn[c] = 0.5 * (vn[c] + vx[c] * nx + vy[c] * ny);
+            for (int c = 0; c < 4; ++c) vn[c] = T(0.5) * (vn[c] + vx[c] * nx + vy[c] * ny);
           }
         }
 #pragma unroll
@@ -360,7 +457,7 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
     wave_sync();
     // ---- face nodes, pass 2: gather what the Roe flux, penalty and theta term
     // need, then (after every read of the neighbour area) write the face terms
-    double fup[FIT][4], fuo[FIT][4], fvn[FIT][4], fgb[FIT];
+    T fup[FIT][4], fuo[FIT][4], fvn[FIT][4], fgb[FIT];
 #pragma unroll
     for (int q = 0; q < FIT; ++q) {
       const int it = lane + 64 * q;
@@ -372,15 +469,18 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         const int conn = sConn[e * 3 + f];
         const int tag = conn & 3, nf = (conn >> 2) & 3;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fup[q][c] = sU[(4 * c + e) * RS + n];
+        for (int c = 0; c < 4; ++c) fup[q][c] = sU[(ROWC * c + ROWE * e) * RS + n];
+        T upf[4];
+        full_state<T, PERT>(fup[q], base, upf);
         const int n2 = face_node<N>(nf, Nfp - 1 - j);
-        ghost_state(tag, fup[q], sX + (e * 3 + f) * S + n2, Np, vwx, vwy, ph.U_inf, gas, fuo[q]);
+        ghost_state<T, PERT>(tag, fup[q], upf, sX + (e * 3 + f) * S + n2, Np, vwx, vwy, gas, base,
+                             fuo[q]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) fvn[q][c] = sVn[(e * NF + fn) * 4 + c];
-        double gbar = 0.0;
+        T gbar = T(0);
 #pragma unroll
         for (int jj = 0; jj < Nfp; ++jj) {
-          const double v = sNorm[e * NF + f * Nfp + jj];
+          const T v = sNorm[e * NF + f * Nfp + jj];
           gbar = v > gbar ? v : gbar;
         }
         fgb[q] = gbar;
@@ -396,62 +496,81 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
         const int f = fn / Nfp, j = fn - f * Nfp;
         const int n = face_node<N>(f, j);
         const int tag = sConn[e * 3 + f] & 3;
-        const double* g = sGeo + e * kGeoStride;
-        const double nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f];
-        const double sigma = g[7 + 4 * f] * fgb[q];
-        const double vwn = vwx * nx + vwy * ny;
-        const VState sp = vstate(gas, fup[q]);
-        const VState so = vstate(gas, fuo[q]);
-        double Fc[4];
+        const T* g = sGeo + e * kGeoStride;
+        const T nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f];
+        const T sigma = g[7 + 4 * f] * fgb[q];
+        const T vwn = vwx * nx + vwy * ny;
+        T upf[4], uof[4];
+        full_state<T, PERT>(fup[q], base, upf);
+        full_state<T, PERT>(fuo[q], base, uof);
+        const Prim<T> pp = prim_of<T, PERT>(upf, fup[q], base, gas.gm1);
+        T Fc[4];
         if (tag == 1) {
-          const double p = pressure(fup[q], sp.ir, gas.gm1);
-          Fc[0] = 0.0;
-          Fc[1] = p * nx;
-          Fc[2] = p * ny;
-          Fc[3] = p * vwn;
+          // pressure through the moving wall (minus the free-stream flux in the
+          // perturbation form)
+          if (!PERT) {
+            Fc[0] = T(0);
+            Fc[1] = pp.p * nx;
+            Fc[2] = pp.p * ny;
+            Fc[3] = pp.p * vwn;
+          } else {
+            const T q0n = base.ux * nx + base.uy * ny - vwn;
+            Fc[0] = -base.rho * q0n;
+            Fc[1] = pp.jp * nx - base.mx * q0n;
+            Fc[2] = pp.jp * ny - base.my * q0n;
+            Fc[3] = pp.jp * vwn - (base.E + base.p) * q0n;
+          }
         } else {
-          roe_flux(fup[q], sp.ir, fuo[q], so.ir, nx, ny, vwn, gas.gm1, Fc);
+          const Prim<T> po = prim_of<T, PERT>(uof, fuo[q], base, gas.gm1);
+          T FL[4], FR[4];
+          normal_flux<T, PERT>(upf, fup[q], pp, base, nx, ny, vwn, FL);
+          normal_flux<T, PERT>(uof, fuo[q], po, base, nx, ny, vwn, FR);
+          roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
         }
-        double w[4];
+        T w[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           // Fscale * own total normal flux from the contravariant flux:
           // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
-          const double fr = sFr[(4 * c + e) * RS + n], fs = sFs[(4 * c + e) * RS + n];
-          const double own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
+          const T fr = sFr[(ROWC * c + ROWE * e) * RS + n], fs = sFs[(ROWC * c + ROWE * e) * RS + n];
+          const T own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
           w[c] = fup[q][c] - fuo[q][c];
-          sH[(4 * c + e) * HRS + fn] = own - fsc * (Fc[c] - fvn[q][c] + sigma * w[c]);
+          sH[(ROWC * c + ROWE * e) * HRS + fn] = own - fsc * (Fc[c] - fvn[q][c] + sigma * w[c]);
         }
-        double qx[4], qy[4];
-        viscous_transpose(gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
-        const double ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
-        const double rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+        T qx[4], qy[4];
+        viscous_transpose(gas, vstate(gas, tag == 1 ? uof : upf), nx, ny, w, qx, qy);
+        const T ce = theta * (tag == 0 ? T(0.5) : T(1)) * fsc;
+        const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          sQr[(4 * c + e) * HRS + fn] = ce * (rx * qx[c] + ry * qy[c]);
-          sQs[(4 * c + e) * HRS + fn] = ce * (sx * qx[c] + sy * qy[c]);
+          sQr[(ROWC * c + ROWE * e) * HRS + fn] = ce * (rx * qx[c] + ry * qy[c]);
+          sQs[(ROWC * c + ROWE * e) * HRS + fn] = ce * (sx * qx[c] + sy * qy[c]);
         }
       }
     }
     for (int i = lane; i < 48 * (HRS - NF); i += 64) {
       const int row = i / (HRS - NF);
-      sX[row * HRS + NF + (i - row * (HRS - NF))] = 0.0;
+      sX[row * HRS + NF + (i - row * (HRS - NF))] = T(0);
     }
     wave_sync();
 
-    // ---- divergence and lifts on the matrix cores, then the RK stage; the
-    // K1 loads are issued first so the matrix work covers their latency
-    double rk[NT][4];
+    // ---- divergence and lifts on the matrix cores, then the RK stage in FP64;
+    // the K1 (and, in the perturbation form, K0) loads are issued first so the
+    // matrix work covers their latency
+    double rk[NT][4], r0[NT][4];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       const int n = 16 * tt + rn;
+      const bool ok = !rhs_only && re < nel && n < Np;
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        rk[tt][c] = (!rhs_only && a != 0.0 && re < nel && n < Np) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
+      for (int c = 0; c < 4; ++c) {
+        rk[tt][c] = (ok && a != 0.0) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
+        r0[tt][c] = (PERT && ok) ? Uin[(e0 + re) * S + c * Np + n] : 0.0;
+      }
     }
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
-      d4 aD = {0.0, 0.0, 0.0, 0.0}, aL = {0.0, 0.0, 0.0, 0.0};
+      V4 aD = {T(0), T(0), T(0), T(0)}, aL = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         aD = mfma(sFr[arow * RS + 4 * s + acol], sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aD);
@@ -466,17 +585,18 @@ __global__ __launch_bounds__(Order<N>::THREADS) __attribute__((amdgpu_waves_per_
       }
       const int n = 16 * tt + rn;
       if (re < nel && n < Np) {
-        const int64_t base = (e0 + re) * S + n;
+        const int64_t base_i = (e0 + re) * S + n;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const double R = aL[c] - aD[c];
-          const int64_t idx = base + c * Np;
+          const double R = (double)(aL[c] - aD[c]);
+          const int64_t idx = base_i + c * Np;
           if (rhs_only) {
             K1[idx] = R;
           } else {
             const double k = (a == 0.0) ? dt * R : a * rk[tt][c] + dt * R;
             K1[idx] = k;
-            Uout[idx] = sU[(4 * c + re) * RS + n] + b * k;
+            const double u0 = PERT ? r0[tt][c] : (double)sU[(ROWC * c + ROWE * re) * RS + n];
+            Uout[idx] = u0 + b * k;
           }
         }
       }
@@ -490,10 +610,10 @@ template <int N>
 __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysics ph,
                                                     const double* __restrict__ U,
                                                     double* __restrict__ out) {
-  using O = Order<N>;
+  using O = Order<N, double>;
   constexpr int Np = O::Np, Nfp = O::Nfp, S = 4 * Np;
   __shared__ double red[3][256];
-  Gas gas;
+  Gas<double> gas;
   gas.gamma = ph.gamma;
   gas.gm1 = ph.gamma - 1.0;
   gas.igm1 = 1.0 / (ph.gamma - 1.0);
@@ -526,7 +646,7 @@ __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysic
       dx[c] = g[0] * ur[c] + g[2] * us[c];
       dy[c] = g[1] * ur[c] + g[3] * us[c];
     }
-    double p = pressure(Up, 1.0 / Up[0], gas.gm1);
+    const double p = gas.gm1 * (Up[3] - 0.5 * (Up[1] * Up[1] + Up[2] * Up[2]) / Up[0]);
     double Ub[4] = {Up[0], Up[0] * ph.vw[0], Up[0] * ph.vw[1],
                     p * gas.igm1 + 0.5 * Up[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1])};
     double vx[4], vy[4];
@@ -555,18 +675,19 @@ __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysic
 }
 
 namespace {
-template <int N>
-int launch_stage_n(const DeviceTables& t, const KernelPhysics& ph, const double* Uin, double* Uout,
+template <int N, typename T, bool PERT>
+int launch_stage_t(const DeviceTables& t, const KernelPhysics& ph, const double* Uin, double* Uout,
                    double* K1, double a, double b, double dt, int rhs_only, hipStream_t s,
                    std::string& err) {
-  using O = Order<N>;
+  using O = Order<N, T>;
   const int64_t ntiles = (t.K + 3) / 4;
-  // persistent: about two workgroups per CU, a multiple of 8 (one range per XCD)
+  // persistent: a few workgroups per CU, a multiple of 8 (one range per XCD)
+  const int64_t cap = sizeof(T) == 8 ? 512 : 1024;
   int64_t want = (ntiles + O::WAVES - 1) / O::WAVES;
-  int grid = (int)(want < 512 ? want : 512);
+  int grid = (int)(want < cap ? want : cap);
   grid = ((grid + 7) / 8) * 8;
-  hipLaunchKernelGGL(stage_kernel<N>, dim3(grid), dim3(O::THREADS), 0, s, t, ph, Uin, Uout, K1, a,
-                     b, dt, rhs_only);
+  hipLaunchKernelGGL((stage_kernel<N, T, PERT>), dim3(grid), dim3(O::THREADS), 0, s, t, ph, Uin,
+                     Uout, K1, a, b, dt, rhs_only);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     err = std::string("stage kernel launch: ") + hipGetErrorString(e);
@@ -574,6 +695,19 @@ int launch_stage_n(const DeviceTables& t, const KernelPhysics& ph, const double*
   }
   return 0;
 }
+
+template <int N>
+int launch_stage_n(int form, const DeviceTables& t, const KernelPhysics& ph, const double* Uin,
+                   double* Uout, double* K1, double a, double b, double dt, int rhs_only,
+                   hipStream_t s, std::string& err) {
+  switch (form) {
+    case 0: return launch_stage_t<N, double, false>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 1: return launch_stage_t<N, double, true>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 2: return launch_stage_t<N, float, true>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    default: err = "precision mode not built"; return -5;
+  }
+}
+
 template <int N>
 int launch_force_n(const DeviceTables& t, const KernelPhysics& ph, const double* U, double* out,
                    hipStream_t s, std::string& err) {
@@ -587,17 +721,17 @@ int launch_force_n(const DeviceTables& t, const KernelPhysics& ph, const double*
 }
 }  // namespace
 
-int launch_stage(int N, const DeviceTables& t, const KernelPhysics& ph, const double* Uin,
+int launch_stage(int N, int form, const DeviceTables& t, const KernelPhysics& ph, const double* Uin,
                  double* Uout, double* K1, double a, double b, double dt, int rhs_only,
                  void* stream, std::string& err) {
   hipStream_t s = (hipStream_t)stream;
   switch (N) {
-    case 1: return launch_stage_n<1>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 2: return launch_stage_n<2>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 3: return launch_stage_n<3>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 4: return launch_stage_n<4>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 5: return launch_stage_n<5>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 6: return launch_stage_n<6>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 1: return launch_stage_n<1>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 2: return launch_stage_n<2>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 3: return launch_stage_n<3>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 4: return launch_stage_n<4>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 5: return launch_stage_n<5>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 6: return launch_stage_n<6>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
     default: err = "polynomial order not built"; return -5;
   }
 }

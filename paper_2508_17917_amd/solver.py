@@ -10,9 +10,10 @@ from . import _lib as L
 
 class Solver:
     def __init__(self, p, mesh, gamma=1.4, Pr=0.72, mu=0.0, theta=1.0, penalty_mode=0, C_pen=0.01,
-                 U_inf=(1.0, 0.0, 0.0, 1.0), device=True):
+                 U_inf=(1.0, 0.0, 0.0, 1.0), device=True, precision=L.DG_FP64):
         self.p = int(p)
-        self.h = L.dg_create(self.p, L.DG_FP64)
+        self.precision = int(precision)
+        self.h = L.dg_create(self.p, self.precision)
         try:
             L.dg_set_physics(self.h, gamma, Pr, mu, theta, penalty_mode, C_pen, U_inf)
             L.dg_set_mesh(self.h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh.get("face_tag"),

@@ -97,6 +97,8 @@ def test_error_codes():
     with pytest.raises(L.DGError) as e:
         L.dg_create(3, precision=7)
     assert e.value.code == L.DG_EUNSUPPORTED
+    for prec in (L.DG_FP64, L.DG_FP64_PERT, L.DG_FP32_PERT):
+        L.dg_destroy(L.dg_create(4, precision=prec))
     h = L.dg_create(2)
     try:
         # set-up before physics/mesh -> out of order
