@@ -47,6 +47,9 @@ struct Order {
   static constexpr int FIT = (4 * NF + 63) / 64; // face items per lane
   static constexpr int WAVES = (N <= 4 || sizeof(T) == 4) ? 4 : 2;
   static constexpr int THREADS = 64 * WAVES;
+  // waves per SIMD the register allocation must allow: 3 for FP32 at p <= 4
+  // (a few spills, measured faster than 2 and than 4), else 2
+  static constexpr int MIN_WAVES_EU = (sizeof(T) == 4 && N <= 4) ? 3 : 2;
   // per-wave LDS (elements of T)
   static constexpr int U_SZ = 16 * RS;           // own state
   static constexpr int F_SZ = 32 * RS;           // contravariant flux Fr rows | Fs rows
@@ -193,7 +196,7 @@ __device__ __forceinline__ const float* frag_of<float>(const DeviceTables& t) {
 // per XCD (workgroup b runs on XCD b % 8) so neighbour reads stay in that
 // XCD's L2.
 template <int N, typename T, bool PERT>
-__global__ __launch_bounds__((Order<N, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(2))) void
+__global__ __launch_bounds__((Order<N, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(Order<N, T>::MIN_WAVES_EU))) void
 stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
              double* __restrict__ Uout, double* __restrict__ K1, double a, double b, double dt,
              int rhs_only) {
@@ -675,19 +678,43 @@ __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysic
 }
 
 namespace {
+// Workgroups of one stage kernel that are resident on the whole device at
+// once (occupancy query, cached per device): the persistent grid is sized to
+// this, so every tile range is worked by waves that run concurrently.
+template <int N, typename T, bool PERT>
+int resident_blocks() {
+  constexpr int kMaxDev = 64;
+  static int cache[kMaxDev] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) dev = 0;
+  if (cache[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<N, T, PERT>,
+                                                     Order<N, T>::THREADS, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per_cu <= 0 || cus <= 0) {
+      per_cu = 1;
+      cus = 256;
+    }
+    cache[dev] = per_cu * cus;
+  }
+  return cache[dev];
+}
+
 template <int N, typename T, bool PERT>
 int launch_stage_t(const DeviceTables& t, const KernelPhysics& ph, const double* Uin, double* Uout,
                    double* K1, double a, double b, double dt, int rhs_only, hipStream_t s,
                    std::string& err) {
   using O = Order<N, T>;
   const int64_t ntiles = (t.K + 3) / 4;
-  // persistent: a few workgroups per CU, a multiple of 8 (one range per XCD)
-  const int64_t cap = sizeof(T) == 8 ? 512 : 1024;
-  int64_t want = (ntiles + O::WAVES - 1) / O::WAVES;
-  int grid = (int)(want < cap ? want : cap);
-  grid = ((grid + 7) / 8) * 8;
-  hipLaunchKernelGGL((stage_kernel<N, T, PERT>), dim3(grid), dim3(O::THREADS), 0, s, t, ph, Uin,
-                     Uout, K1, a, b, dt, rhs_only);
+  // persistent: at most the resident workgroups, a multiple of 8 (one tile
+  // range per XCD)
+  const int64_t cap = resident_blocks<N, T, PERT>();
+  const int64_t want = (ntiles + O::WAVES - 1) / O::WAVES;
+  int64_t grid = want < cap ? want : cap;
+  grid = grid >= 8 ? grid / 8 * 8 : 8;
+  hipLaunchKernelGGL((stage_kernel<N, T, PERT>), dim3((unsigned)grid), dim3(O::THREADS), 0, s, t,
+                     ph, Uin, Uout, K1, a, b, dt, rhs_only);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     err = std::string("stage kernel launch: ") + hipGetErrorString(e);
