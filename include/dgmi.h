@@ -159,6 +159,78 @@ int dg_force(dg_ctx* ctx, const double* U, const double v_w[2], double out[3], v
  * with the load F_new. */
 int dg_newmark_step(double state[3], double F_new, double dt, double M, double C, double K);
 
+/* ---- Launch shape and its autotuner --------------------------------------
+ * The stage kernel's launch shape: waves per workgroup (2 or 4; each wave
+ * owns tiles of 4 elements, the workgroup shares the operator fragments held
+ * in LDS; 0 = the default for the order and precision) and the grid (0 =
+ * persistent: the resident workgroups stride over the tiles, 1 = one tile per
+ * wave).  Results do not depend on the shape (bitwise).  Host only. */
+int dg_set_tuning(dg_ctx* ctx, int waves, int grid);
+int dg_get_tuning(const dg_ctx* ctx, int* waves, int* grid);
+
+/* Time every launch shape on this context's mesh (reps stage launches each,
+ * reading U, a device state [K][4][Np], writing only library scratch) and
+ * keep the fastest.  With cache_path non-NULL, a matching entry of that
+ * JSON-lines file (same device architecture, order, precision and element
+ * count within a factor 2) is used instead of timing, and a new measurement
+ * is appended to it.  Allocates a temporary device register; synchronises
+ * `stream`.  *best_us (may be NULL) receives the chosen shape's time per
+ * launch in microseconds (0 when taken from the cache). */
+int dg_autotune(dg_ctx* ctx, const double* U, int reps, const char* cache_path, void* stream,
+                double* best_us);
+
+/* ---- Batches ---------------------------------------------------------------
+ * A batch advances n set-up contexts (same precision and HIP device; orders,
+ * meshes and physics may differ; e.g. the instances of a parameter sweep)
+ * together: every RK stage of every instance runs in one launch (instances
+ * grouped by order, each group owning a range of workgroups), and the five
+ * stages of a step are captured once as a HIP graph and replayed.  Per-step
+ * dt and v_w of each instance are uploaded into device memory before each
+ * replay, so the graph stays valid.  The batch owns each instance's state
+ * (two ping-pong buffers, the current one alternating from step to step) and
+ * its K1 register; results equal those of dg_rk_step on each context
+ * (bitwise).  The contexts must outlive the batch and must not be set up
+ * again meanwhile. */
+typedef struct dg_batch dg_batch;
+
+/* Create a batch of the n contexts ctxs[0..n-1] (all set up by dg_setup).
+ * Allocates device memory (3 states per instance) and pinned host memory. */
+int dg_batch_create(dg_ctx* const* ctxs, int n, dg_batch** out);
+
+/* Copy instance i's state in from / out to a device array [K_i][4][Np_i]
+ * (asynchronous on `stream`). */
+int dg_batch_set_state(dg_batch* b, int i, const double* U, void* stream);
+int dg_batch_get_state(dg_batch* b, int i, double* U, void* stream);
+
+/* One LSERK step of every instance: dt[i] and v_w[2i], v_w[2i+1] are host
+ * arrays of n and 2n doubles.  Asynchronous on `stream` (the previous step's
+ * parameter upload is waited for before the pinned staging area is
+ * rewritten). */
+int dg_batch_rk_step(dg_batch* b, const double* dt, const double* v_w, void* stream);
+
+/* Force and moment on each instance's wall faces (as dg_force), out a host
+ * array of 3n doubles.  Synchronises `stream`. */
+int dg_batch_force(dg_batch* b, const double* v_w, double* out, void* stream);
+
+/* Launch shape: mode 0 one launch per stage for all instances, 1 one launch
+ * per order group; waves and grid as dg_set_tuning; use_graph 0 launches the
+ * stages directly instead of replaying the captured graph. */
+int dg_batch_configure(dg_batch* b, int mode, int waves, int grid, int use_graph);
+
+/* Time every (mode, waves, grid) on the batch (reps first-stage launches
+ * each; the states are left unchanged, K1 is overwritten) and keep the
+ * fastest.  Synchronises `stream`.  *best_us (may be NULL) receives its time
+ * per stage in microseconds. */
+int dg_batch_autotune(dg_batch* b, int reps, void* stream, double* best_us);
+
+/* Message of the last failing call on b; with b NULL, of the last failed
+ * dg_batch_create (which releases everything it allocated and sets *out to
+ * NULL). */
+const char* dg_batch_last_error(const dg_batch* b);
+
+/* Release the batch (not its contexts).  NULL is a no-op. */
+void dg_batch_destroy(dg_batch* b);
+
 /* Message of the last failing call on ctx ("" if none).  Valid until the next
  * call on ctx.  ctx may be NULL (then a message about creation failures). */
 const char* dg_last_error(const dg_ctx* ctx);

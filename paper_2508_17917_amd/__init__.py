@@ -12,4 +12,4 @@ from ._lib import (DGError, DG_FP32_PERT, DG_FP64, DG_FP64_PERT, DG_PENALTY_PAPE
                    dg_newmark_step, dg_num_elements, dg_num_face_nodes, dg_num_nodes, dg_rhs,
                    dg_rk_stage, dg_rk_step, dg_set_mesh, dg_set_physics, dg_setup, dg_setup_host,
                    load)
-from .solver import Solver  # noqa: F401
+from .solver import Batch, Solver  # noqa: F401

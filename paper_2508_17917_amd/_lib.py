@@ -45,6 +45,18 @@ SIGNATURES = {
     "dg_rk_stage": (_I, [_P, _P, _P, _P, _D, _D, _D, _DP, _P]),
     "dg_force": (_I, [_P, _P, _DP, _DP, _P]),
     "dg_newmark_step": (_I, [_DP, _D, _D, _D, _D, _D]),
+    "dg_set_tuning": (_I, [_P, _I, _I]),
+    "dg_get_tuning": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "dg_autotune": (_I, [_P, _P, _I, ctypes.c_char_p, _P, _DP]),
+    "dg_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_P)]),
+    "dg_batch_set_state": (_I, [_P, _I, _P, _P]),
+    "dg_batch_get_state": (_I, [_P, _I, _P, _P]),
+    "dg_batch_rk_step": (_I, [_P, _DP, _DP, _P]),
+    "dg_batch_force": (_I, [_P, _DP, _DP, _P]),
+    "dg_batch_configure": (_I, [_P, _I, _I, _I, _I]),
+    "dg_batch_autotune": (_I, [_P, _I, _P, _DP]),
+    "dg_batch_last_error": (ctypes.c_char_p, [_P]),
+    "dg_batch_destroy": (None, [_P]),
     "dg_last_error": (ctypes.c_char_p, [_P]),
     "dg_destroy": (None, [_P]),
 }
@@ -213,3 +225,78 @@ def dg_last_error(h):
 def dg_destroy(h):
     if h is not None and h.value:
         load().dg_destroy(h)
+
+
+def dg_set_tuning(h, waves, grid):
+    return _check(load().dg_set_tuning(h, int(waves), int(grid)), h)
+
+
+def dg_get_tuning(h):
+    w, g = ctypes.c_int(), ctypes.c_int()
+    _check(load().dg_get_tuning(h, ctypes.byref(w), ctypes.byref(g)), h)
+    return w.value, g.value
+
+
+def dg_autotune(h, U, reps=20, cache_path=None, stream=None):
+    best = ctypes.c_double()
+    _check(load().dg_autotune(h, _ptr(U), int(reps),
+                              None if cache_path is None else os.fsencode(cache_path),
+                              _stream(stream), ctypes.byref(best)), h)
+    return best.value
+
+
+# ---- batches --------------------------------------------------------------
+def _bcheck(code, b=None):
+    if code != DG_OK:
+        msg = load().dg_batch_last_error(b)
+        raise DGError(code, msg.decode() if msg else "")
+    return code
+
+
+def dg_batch_create(handles):
+    arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
+    b = ctypes.c_void_p()
+    _bcheck(load().dg_batch_create(arr, len(handles), ctypes.byref(b)))
+    return b
+
+
+def dg_batch_set_state(b, i, U, stream=None):
+    return _bcheck(load().dg_batch_set_state(b, int(i), _ptr(U), _stream(stream)), b)
+
+
+def dg_batch_get_state(b, i, U, stream=None):
+    return _bcheck(load().dg_batch_get_state(b, int(i), _ptr(U), _stream(stream)), b)
+
+
+def dg_batch_rk_step(b, dt, v_w, stream=None):
+    dt = np.ascontiguousarray(np.asarray(dt, dtype=np.float64))
+    vw = np.ascontiguousarray(np.asarray(v_w, dtype=np.float64).reshape(-1))
+    return _bcheck(load().dg_batch_rk_step(b, _dp(dt), _dp(vw), _stream(stream)), b)
+
+
+def dg_batch_force(b, n, v_w=None, stream=None):
+    vw = np.zeros(2 * n) if v_w is None else np.ascontiguousarray(
+        np.asarray(v_w, dtype=np.float64).reshape(-1))
+    out = np.zeros(3 * n)
+    _bcheck(load().dg_batch_force(b, _dp(vw), _dp(out), _stream(stream)), b)
+    return out.reshape(n, 3)
+
+
+def dg_batch_configure(b, mode=0, waves=0, grid=0, use_graph=1):
+    return _bcheck(load().dg_batch_configure(b, int(mode), int(waves), int(grid), int(use_graph)), b)
+
+
+def dg_batch_autotune(b, reps=10, stream=None):
+    best = ctypes.c_double()
+    _bcheck(load().dg_batch_autotune(b, int(reps), _stream(stream), ctypes.byref(best)), b)
+    return best.value
+
+
+def dg_batch_last_error(b):
+    msg = load().dg_batch_last_error(b)
+    return msg.decode() if msg else ""
+
+
+def dg_batch_destroy(b):
+    if b is not None and b.value:
+        load().dg_batch_destroy(b)

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgmi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["host_setup.cpp", "dgmi_abi.cpp", "kernels.hip"]
+SOURCES = ["host_setup.cpp", "dgmi_abi.cpp", "batch.cpp", "tune.cpp", "kernels.hip"]
 ARCH = os.environ.get("DGMI_OFFLOAD_ARCH", "gfx950")
 
 
@@ -32,9 +32,12 @@ def common_flags():
 
 
 def device_flags():
-    # packed FP32 instructions are disabled for every device compile
+    # packed FP32 instructions are disabled for every device compile.  Fused
+    # multiply-adds are formed within a source expression only (not across
+    # statements), so an element's rounding is fixed by the source and does
+    # not depend on the kernel (single mesh or batch) that inlines it.
     return ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-ffp-contract=fast"]
+            "-ffp-contract=on"]
 
 
 def build(verbose=False, jobs=None):

@@ -66,11 +66,49 @@ struct KernelPhysics {
   double vw[2];
 };
 
+// Launch shape of the stage kernel: waves (= elements / 4) per workgroup, 0
+// for the default of the order and form; grid 0 persistent (the resident
+// workgroups stride over the tiles), 1 one tile per wave.
+struct StageTuning {
+  int waves = 0;
+  int grid = 0;
+};
+
 // kernels.hip.  form: 0 plain FP64, 1 perturbation FP64, 2 perturbation FP32
 // (the dg_precision values).
-int launch_stage(int N, int form, const DeviceTables& t, const KernelPhysics& ph, const double* U_in,
-                 double* U_out, double* K1, double a, double b, double dt, int rhs_only,
-                 void* stream, std::string& err);
+int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t,
+                 const KernelPhysics& ph, const double* U_in, double* U_out, double* K1, double a,
+                 double b, double dt, int rhs_only, void* stream, std::string& err);
+int default_waves(int N, int form);
+
+// Batched stages over many meshes (one launch per stage).
+struct BatchItem {              // one instance, in device memory
+  DeviceTables t;
+  KernelPhysics ph;             // v_w is taken from the step parameters
+  double* buf[2];               // state ping-pong buffers
+  double* K1;
+  int64_t tile_begin, tile_end; // its tiles in the numbering of its group
+};
+struct BatchStep {              // per instance and step, in device memory
+  double dt;
+  double vw[2];
+  double pad;
+};
+struct BatchGroup {             // instances of one order
+  int p;
+  int first_item, n_items;
+  int block_begin, nblocks;     // multiples of 8
+  int64_t ntiles;
+};
+struct BatchGroups {
+  int ng;
+  BatchGroup g[kMaxOrder];
+};
+int batch_resident_blocks(int form, int waves);
+// stage i of a step reads buf[(parity + i) & 1] and writes the other buffer
+int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchStep* steps,
+                       const int* parity, const BatchGroups& G, int blocks, int stage, double a,
+                       double b, void* stream, std::string& err);
 int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
                  double* out_dev, void* stream, std::string& err);
 // operator packing: Dr | Ds | LIFT | LIFTr | LIFTs | Fmask (as doubles) | wface

@@ -9,46 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dgmi.h"
-#include "dg_internal.h"
-
-// Carpenter & Kennedy (1994) five-stage, fourth-order 2N-storage coefficients
-// (NASA TM-109112): K1 <- A_i K1 + dt R(K0), K0 <- K0 + B_i K1 (Alg. 1).
-static const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0,
-                               -2404267990393.0 / 2016746695238.0,
-                               -3550918686646.0 / 2091501179385.0,
-                               -1275806237668.0 / 842570457699.0};
-static const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
-                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
-                               2277821191437.0 / 14882151754819.0};
-
-struct dg_ctx {
-  int N = 0;
-  int precision = 0;
-  dgmi::Physics phys;
-  bool have_phys = false;
-  std::vector<double> VX, VY;
-  std::vector<int32_t> EToV;
-  std::vector<int8_t> tag;
-  double period[2] = {0.0, 0.0};
-  int64_t Nv = 0, K = 0;
-  bool have_mesh = false;
-  dgmi::RefOps ref;
-  dgmi::MeshTables mesh;
-  bool host_ready = false;
-  int device = -1;
-  double* d_geo = nullptr;
-  int32_t* d_conn = nullptr;
-  double* d_ops = nullptr;
-  double* d_frag = nullptr;
-  float* d_frag32 = nullptr;
-  int32_t* d_wall = nullptr;
-  double* d_wall_xy = nullptr;
-  double* d_scratch = nullptr;
-  double* d_force = nullptr;
-  bool dev_ready = false;
-  std::string err;
-};
+#include "dg_ctx.h"
 
 namespace {
 
@@ -126,6 +87,13 @@ int check_ready(dg_ctx* c) {
 }
 
 }  // namespace
+
+namespace dgmi {
+int ctx_fail(dg_ctx* c, int code, const std::string& msg) { return fail(c, code, msg); }
+int ctx_hip_fail(dg_ctx* c, hipError_t e, const char* what) { return hip_fail(c, e, what); }
+DeviceTables ctx_tables(const dg_ctx* c) { return tables(c); }
+KernelPhysics ctx_phys(const dg_ctx* c, const double vw[2]) { return kphys(c, vw); }
+}  // namespace dgmi
 
 extern "C" {
 
@@ -276,7 +244,7 @@ int dg_rhs(dg_ctx* c, const double* U, double* R, const double v_w[2], void* str
   if (rc != DG_OK) return rc;
   if (!U || !R || U == R) return fail(c, DG_EINVAL, "U and R must be distinct device arrays");
   std::string err;
-  rc = dgmi::launch_stage(c->N, c->precision, tables(c), kphys(c, v_w), U, nullptr, R, 0.0, 0.0, 1.0, 1, stream,
+  rc = dgmi::launch_stage(c->N, c->precision, c->tune, tables(c), kphys(c, v_w), U, nullptr, R, 0.0, 0.0, 1.0, 1, stream,
                           err);
   return rc == 0 ? DG_OK : fail(c, rc, err);
 }
@@ -288,7 +256,7 @@ int dg_rk_stage(dg_ctx* c, const double* Uin, double* Uout, double* K1, double a
   if (!Uin || !Uout || !K1 || Uin == Uout || K1 == Uin || K1 == Uout)
     return fail(c, DG_EINVAL, "U_in, U_out and K1 must be distinct device arrays");
   std::string err;
-  rc = dgmi::launch_stage(c->N, c->precision, tables(c), kphys(c, v_w), Uin, Uout, K1, a, b, dt, 0, stream, err);
+  rc = dgmi::launch_stage(c->N, c->precision, c->tune, tables(c), kphys(c, v_w), Uin, Uout, K1, a, b, dt, 0, stream, err);
   return rc == 0 ? DG_OK : fail(c, rc, err);
 }
 
@@ -302,7 +270,7 @@ int dg_rk_step(dg_ctx* c, double* U, double* K1, double dt, const double v_w[2],
   dgmi::KernelPhysics k = kphys(c, v_w);
   double* bufs[2] = {U, c->d_scratch};
   for (int i = 0; i < 5; ++i) {
-    rc = dgmi::launch_stage(c->N, c->precision, t, k, bufs[i & 1], bufs[(i + 1) & 1], K1, kRkA[i], kRkB[i], dt, 0,
+    rc = dgmi::launch_stage(c->N, c->precision, c->tune, t, k, bufs[i & 1], bufs[(i + 1) & 1], K1, dgmi::kRkA[i], dgmi::kRkB[i], dt, 0,
                             stream, err);
     if (rc != 0) return fail(c, rc, err);
   }

@@ -45,8 +45,9 @@ struct Order {
   static constexpr int RS = 4 * KS + 1;          // padded LDS row (odd: no bank aliasing)
   static constexpr int HRS = 4 * KF + 1;
   static constexpr int FIT = (4 * NF + 63) / 64; // face items per lane
+  // default waves per workgroup (each wave owns its own tiles; the workgroup
+  // shares the operator fragments)
   static constexpr int WAVES = (N <= 4 || sizeof(T) == 4) ? 4 : 2;
-  static constexpr int THREADS = 64 * WAVES;
   // waves per SIMD the register allocation must allow: 3 for FP32 at p <= 4
   // (a few spills, measured faster than 2 and than 4), else 2
   static constexpr int MIN_WAVES_EU = (sizeof(T) == 4 && N <= 4) ? 3 : 2;
@@ -190,16 +191,18 @@ __device__ __forceinline__ const float* frag_of<float>(const DeviceTables& t) {
   return t.frag32;
 }
 
-// The fused right-hand side + LSERK stage.  Each wavefront owns tiles of four
-// elements (16 matrix-core rows = 4 fields x 4 elements); the workgroup only
-// shares the operator fragments.  Tiles are handed out in contiguous ranges
-// per XCD (workgroup b runs on XCD b % 8) so neighbour reads stay in that
-// XCD's L2.
+// The fused right-hand side + LSERK stage for the tiles tile0, tile0 + stride,
+// ... < tile_end of one mesh, run by one wavefront.  A tile is four elements
+// (16 matrix-core rows = 4 fields x 4 elements).  sFrag holds the operator
+// fragments (shared by the workgroup), sU this wave's LDS area (WAVE_SZ
+// elements, pads zeroed once), sConn 12 ints of this wave.
 template <int N, typename T, bool PERT>
-__global__ __launch_bounds__((Order<N, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(Order<N, T>::MIN_WAVES_EU))) void
-stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
-             double* __restrict__ Uout, double* __restrict__ K1, double a, double b, double dt,
-             int rhs_only) {
+__device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelPhysics& ph,
+                                            const double* __restrict__ Uin,
+                                            double* __restrict__ Uout, double* __restrict__ K1,
+                                            double a, double b, double dt, int rhs_only,
+                                            const T* sFrag, T* sU, int* sConn,
+                                            int64_t tile0, int64_t tile_end, int64_t stride) {
   using O = Order<N, T>;
   typedef typename Vec4<T>::type V4;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF = O::NF, S = O::S, NT = O::NT, KS = O::KS,
@@ -207,18 +210,8 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
                 ROWE = O::ROWE;
   constexpr int OFF_DR = 0, OFF_DS = O::FD, OFF_L = 2 * O::FD, OFF_LR = 2 * O::FD + O::FL,
                 OFF_LS = 2 * O::FD + 2 * O::FL;
-  __shared__ T sFrag[O::FRAG_SZ];
-  __shared__ T sWave[O::WAVES][O::WAVE_SZ];
-  __shared__ int sConnW[O::WAVES][12];
-
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const T* frag = frag_of<T>(t);
-  for (int i = threadIdx.x; i < O::FRAG_SZ; i += O::THREADS) sFrag[i] = frag[i];
-  for (int i = lane; i < O::WAVE_SZ; i += 64) sWave[wid][i] = T(0);  // zero pads once
-  __syncthreads();
 
-  T* sU = &sWave[wid][0];
   T* sFr = sU + O::U_SZ;
   T* sFs = sFr + 16 * RS;
   T* sX = sU + O::U_SZ + O::F_SZ;   // neighbour states, later face terms
@@ -229,7 +222,6 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
   T* sVn = sNorm + O::NORM_SZ;      // [4 NF][4]
   T* sGeo = sVn + O::VN_SZ;         // [4][16]
   T* sNGeo = sGeo + 64;             // [4][3][4]
-  int* sConn = sConnW[wid];         // [4][3]
 
   Gas<T> gas;
   gas.gamma = (T)ph.gamma;
@@ -250,14 +242,7 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
     base.ux = (T)ux0;
     base.uy = (T)uy0;
   }
-
   const int64_t K = t.K;
-  const int64_t ntiles = (K + 3) / 4;
-  const int xcd = blockIdx.x & 7;
-  const int nbx = gridDim.x >> 3;
-  const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
-  const int64_t w0 = (int64_t)(blockIdx.x >> 3) * O::WAVES + wid;
-  const int64_t wstride = (int64_t)nbx * O::WAVES;
 
   const int arow = lane & 15, acol = lane >> 4;  // A-operand row, k offset
   const int re = lane >> 4, rn = lane & 15;      // output: element re, node 16 t + rn
@@ -272,10 +257,12 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
     const int r = lane + 64 * q;
     lr_ok[q] = r < S;
     lds_u[q] = lr_ok[q] ? ROWC * (r / Np) * RS + (r - (r / Np) * Np) : 0;
-    uinf_q[q] = (PERT && lr_ok[q]) ? ph.U_inf[r / Np] : 0.0;
+    const int c = r / Np;  // selects, not an indexed load: ph may be a local copy
+    const double u_c = c == 0 ? ph.U_inf[0] : (c == 1 ? ph.U_inf[1] : (c == 2 ? ph.U_inf[2] : ph.U_inf[3]));
+    uinf_q[q] = (PERT && lr_ok[q]) ? u_c : 0.0;
   }
 
-  for (int64_t tile = tb + w0; tile < te; tile += wstride) {
+  for (int64_t tile = tile0; tile < tile_end; tile += stride) {
     const int64_t e0 = tile * 4;
     const int nel = (int)((K - e0) < 4 ? (K - e0) : 4);
     wave_sync();
@@ -607,6 +594,108 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
   }
 }
 
+// Copy the operator fragments of order N into LDS and zero this workgroup's
+// wave areas (their pads are read as zeros by the matrix-core products).
+template <int N, typename T, int W>
+__device__ __forceinline__ void stage_lds_init(const T* __restrict__ frag, T* sFrag, T* sWave) {
+  using O = Order<N, T>;
+  for (int i = threadIdx.x; i < O::FRAG_SZ; i += 64 * W) sFrag[i] = frag[i];
+  for (int i = threadIdx.x; i < W * O::WAVE_SZ; i += 64 * W) sWave[i] = T(0);
+  __syncthreads();
+}
+
+// Single mesh.  Tiles are handed out in contiguous ranges per XCD (workgroup b
+// runs on XCD b % 8, the grid is a multiple of 8) so that neighbour reads stay
+// in that XCD's L2; within a range the waves stride over the tiles (a
+// persistent grid) or take one tile each (a grid of one tile per wave).
+template <int N, typename T, bool PERT, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(Order<N, T>::MIN_WAVES_EU))) void
+stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
+             double* __restrict__ Uout, double* __restrict__ K1, double a, double b, double dt,
+             int rhs_only) {
+  using O = Order<N, T>;
+  __shared__ T sFrag[O::FRAG_SZ];
+  __shared__ T sWave[W * O::WAVE_SZ];
+  __shared__ int sConnW[W * 12];
+  stage_lds_init<N, T, W>(frag_of<T>(t), sFrag, sWave);
+  const int wid = threadIdx.x >> 6;
+  const int64_t ntiles = (t.K + 3) / 4;
+  const int xcd = blockIdx.x & 7;
+  const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
+  const int64_t w0 = (int64_t)(blockIdx.x >> 3) * W + wid;
+  const int64_t wstride = (int64_t)(gridDim.x >> 3) * W;
+  stage_tiles<N, T, PERT>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, sFrag, sWave + wid * O::WAVE_SZ,
+                          sConnW + 12 * wid, tb + w0, te, wstride);
+}
+
+// Many meshes in one launch.  The instances are grouped by order; group g
+// owns the workgroups [block_begin, block_begin + nblocks) (multiples of 8)
+// and numbers the tiles of its instances consecutively.  Per-instance dt and
+// v_w, and the parity of the state buffers, come from device memory, so a
+// captured graph of the five stages stays valid from step to step.
+template <int N, typename T, bool PERT, int W>
+__device__ __forceinline__ void batch_group(const BatchItem* __restrict__ items,
+                                            const BatchStep* __restrict__ steps, int par,
+                                            const BatchGroup& g, int stage, double a, double b,
+                                            unsigned char* smem) {
+  using O = Order<N, T>;
+  T* sFrag = (T*)smem;
+  T* sWave = sFrag + O::FRAG_SZ;
+  int* sConnW = (int*)(sWave + W * O::WAVE_SZ);
+  stage_lds_init<N, T, W>(frag_of<T>(items[g.first_item].t), sFrag, sWave);
+  const int wid = threadIdx.x >> 6;
+  const int local = blockIdx.x - g.block_begin;
+  const int xcd = local & 7;
+  const int64_t tb = g.ntiles * xcd / 8, te = g.ntiles * (xcd + 1) / 8;
+  const int64_t wstride = (int64_t)(g.nblocks >> 3) * W;
+  int i = g.first_item;
+  for (int64_t tile = tb + (int64_t)(local >> 3) * W + wid; tile < te; tile += wstride) {
+    while (tile >= items[i].tile_end) ++i;  // tiles only increase
+    const BatchItem& it = items[i];
+    KernelPhysics ph = it.ph;
+    ph.vw[0] = steps[i].vw[0];
+    ph.vw[1] = steps[i].vw[1];
+    const int src = (par + stage) & 1;
+    stage_tiles<N, T, PERT>(it.t, ph, it.buf[src], it.buf[src ^ 1], it.K1, a, b, steps[i].dt, 0,
+                            sFrag, sWave + wid * O::WAVE_SZ, sConnW + 12 * wid,
+                            tile - it.tile_begin, tile - it.tile_begin + 1, 1);
+  }
+}
+
+template <typename T, int W>
+struct BatchLds {
+  template <int N>
+  static constexpr size_t of() {
+    return (Order<N, T>::FRAG_SZ + W * Order<N, T>::WAVE_SZ) * sizeof(T) + W * 12 * sizeof(int);
+  }
+  static constexpr size_t mx(size_t x, size_t y) { return x > y ? x : y; }
+  static constexpr size_t bytes =
+      mx(mx(mx(of<1>(), of<2>()), mx(of<3>(), of<4>())), mx(of<5>(), of<6>()));
+};
+
+template <typename T, bool PERT, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void
+batch_stage_kernel(const BatchItem* __restrict__ items, const BatchStep* __restrict__ steps,
+                   const int* __restrict__ parity, BatchGroups G, int stage, double a, double b) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[BatchLds<T, W>::bytes];
+  // the group of this workgroup, selected without dynamic indexing of the
+  // by-value argument (which would place a copy of it in scratch memory)
+  BatchGroup g = G.g[0];
+#pragma unroll
+  for (int k = 1; k < kMaxOrder; ++k)
+    if (k < G.ng && (int)blockIdx.x >= G.g[k].block_begin) g = G.g[k];
+  const int par = parity[0];
+  switch (g.p) {
+    case 1: batch_group<1, T, PERT, W>(items, steps, par, g, stage, a, b, smem); break;
+    case 2: batch_group<2, T, PERT, W>(items, steps, par, g, stage, a, b, smem); break;
+    case 3: batch_group<3, T, PERT, W>(items, steps, par, g, stage, a, b, smem); break;
+    case 4: batch_group<4, T, PERT, W>(items, steps, par, g, stage, a, b, smem); break;
+    case 5: batch_group<5, T, PERT, W>(items, steps, par, g, stage, a, b, smem); break;
+    case 6: batch_group<6, T, PERT, W>(items, steps, par, g, stage, a, b, smem); break;
+    default: break;
+  }
+}
+
 // Wall force: one workgroup walks the wall faces in a fixed order; each
 // thread accumulates its share, then a fixed-shape tree reduction in LDS.
 template <int N>
@@ -678,59 +767,101 @@ __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysic
 }
 
 namespace {
-// Workgroups of one stage kernel that are resident on the whole device at
-// once (occupancy query, cached per device): the persistent grid is sized to
-// this, so every tile range is worked by waves that run concurrently.
-template <int N, typename T, bool PERT>
-int resident_blocks() {
-  constexpr int kMaxDev = 64;
+constexpr int kMaxDev = 64;
+
+int device_cus(int dev) {
   static int cache[kMaxDev] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) dev = 0;
+  if (dev < 0 || dev >= kMaxDev) dev = 0;
   if (cache[dev] == 0) {
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<N, T, PERT>,
-                                                     Order<N, T>::THREADS, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        per_cu <= 0 || cus <= 0) {
-      per_cu = 1;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
       cus = 256;
-    }
-    cache[dev] = per_cu * cus;
+    cache[dev] = cus;
   }
   return cache[dev];
 }
 
-template <int N, typename T, bool PERT>
-int launch_stage_t(const DeviceTables& t, const KernelPhysics& ph, const double* Uin, double* Uout,
-                   double* K1, double a, double b, double dt, int rhs_only, hipStream_t s,
-                   std::string& err) {
-  using O = Order<N, T>;
-  const int64_t ntiles = (t.K + 3) / 4;
-  // persistent: at most the resident workgroups, a multiple of 8 (one tile
-  // range per XCD)
-  const int64_t cap = resident_blocks<N, T, PERT>();
-  const int64_t want = (ntiles + O::WAVES - 1) / O::WAVES;
-  int64_t grid = want < cap ? want : cap;
-  grid = grid >= 8 ? grid / 8 * 8 : 8;
-  hipLaunchKernelGGL((stage_kernel<N, T, PERT>), dim3((unsigned)grid), dim3(O::THREADS), 0, s, t,
-                     ph, Uin, Uout, K1, a, b, dt, rhs_only);
+int current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) dev = 0;
+  return dev;
+}
+
+// Workgroups of a kernel that are resident on the whole device at once
+// (occupancy query, cached per device and kernel).
+template <typename F>
+int resident_blocks(F kernel, int threads, int* cache) {
+  const int dev = current_device();
+  if (cache[dev] == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    cache[dev] = per_cu * device_cus(dev);
+  }
+  return cache[dev];
+}
+
+int launch_error(std::string& err, const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
-    err = std::string("stage kernel launch: ") + hipGetErrorString(e);
+    err = std::string(what) + ": " + hipGetErrorString(e);
     return -3;
   }
   return 0;
 }
 
+// Grid of the single-mesh stage kernel: persistent (at most the resident
+// workgroups) or one tile per wave; a multiple of 8 either way.
+int64_t stage_grid(int64_t ntiles, int waves, int resident, int mode) {
+  const int64_t want = (ntiles + waves - 1) / waves;
+  int64_t grid;
+  if (mode == 1) {
+    grid = (want + 7) / 8 * 8;
+  } else {
+    grid = want < resident ? want : resident;
+    grid = grid >= 8 ? grid / 8 * 8 : 8;
+  }
+  return grid < 8 ? 8 : grid;
+}
+
+template <int N, typename T, bool PERT, int W>
+int launch_stage_t(const StageTuning& tune, const DeviceTables& t, const KernelPhysics& ph,
+                   const double* Uin, double* Uout, double* K1, double a, double b, double dt,
+                   int rhs_only, hipStream_t s, std::string& err) {
+  static int cache[kMaxDev] = {0};
+  const int resident = resident_blocks(stage_kernel<N, T, PERT, W>, 64 * W, cache);
+  const int64_t grid = stage_grid((t.K + 3) / 4, W, resident, tune.grid);
+  hipLaunchKernelGGL((stage_kernel<N, T, PERT, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, t,
+                     ph, Uin, Uout, K1, a, b, dt, rhs_only);
+  return launch_error(err, "stage kernel launch");
+}
+
+template <int N, typename T, bool PERT>
+int launch_stage_w(const StageTuning& tune, const DeviceTables& t, const KernelPhysics& ph,
+                   const double* Uin, double* Uout, double* K1, double a, double b, double dt,
+                   int rhs_only, hipStream_t s, std::string& err) {
+  const int w = tune.waves ? tune.waves : Order<N, T>::WAVES;
+  if (w == 2)
+    return launch_stage_t<N, T, PERT, 2>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+  if (w == 4)
+    return launch_stage_t<N, T, PERT, 4>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+  err = "waves per workgroup must be 2 or 4";
+  return -1;
+}
+
 template <int N>
-int launch_stage_n(int form, const DeviceTables& t, const KernelPhysics& ph, const double* Uin,
-                   double* Uout, double* K1, double a, double b, double dt, int rhs_only,
-                   hipStream_t s, std::string& err) {
+int launch_stage_n(int form, const StageTuning& tune, const DeviceTables& t,
+                   const KernelPhysics& ph, const double* Uin, double* Uout, double* K1, double a,
+                   double b, double dt, int rhs_only, hipStream_t s, std::string& err) {
   switch (form) {
-    case 0: return launch_stage_t<N, double, false>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 1: return launch_stage_t<N, double, true>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 2: return launch_stage_t<N, float, true>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 0:
+      return launch_stage_w<N, double, false>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 1:
+      return launch_stage_w<N, double, true>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 2:
+      return launch_stage_w<N, float, true>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
     default: err = "precision mode not built"; return -5;
   }
 }
@@ -739,27 +870,68 @@ template <int N>
 int launch_force_n(const DeviceTables& t, const KernelPhysics& ph, const double* U, double* out,
                    hipStream_t s, std::string& err) {
   hipLaunchKernelGGL(force_kernel<N>, dim3(1), dim3(256), 0, s, t, ph, U, out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    err = std::string("force kernel launch: ") + hipGetErrorString(e);
-    return -3;
-  }
-  return 0;
+  return launch_error(err, "force kernel launch");
+}
+
+template <typename T, bool PERT, int W>
+int launch_batch_t(const BatchItem* items, const BatchStep* steps, const int* parity,
+                   const BatchGroups& G, int blocks, int stage, double a, double b, hipStream_t s,
+                   std::string& err) {
+  hipLaunchKernelGGL((batch_stage_kernel<T, PERT, W>), dim3((unsigned)blocks), dim3(64 * W), 0, s,
+                     items, steps, parity, G, stage, a, b);
+  return launch_error(err, "batched stage kernel launch");
+}
+
+template <typename T, bool PERT, int W>
+int batch_resident_t() {
+  static int cache[kMaxDev] = {0};
+  return resident_blocks(batch_stage_kernel<T, PERT, W>, 64 * W, cache);
 }
 }  // namespace
 
-int launch_stage(int N, int form, const DeviceTables& t, const KernelPhysics& ph, const double* Uin,
-                 double* Uout, double* K1, double a, double b, double dt, int rhs_only,
-                 void* stream, std::string& err) {
+int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t,
+                 const KernelPhysics& ph, const double* Uin, double* Uout, double* K1, double a,
+                 double b, double dt, int rhs_only, void* stream, std::string& err) {
   hipStream_t s = (hipStream_t)stream;
   switch (N) {
-    case 1: return launch_stage_n<1>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 2: return launch_stage_n<2>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 3: return launch_stage_n<3>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 4: return launch_stage_n<4>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 5: return launch_stage_n<5>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 6: return launch_stage_n<6>(form, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 1: return launch_stage_n<1>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 2: return launch_stage_n<2>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 3: return launch_stage_n<3>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 4: return launch_stage_n<4>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 5: return launch_stage_n<5>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 6: return launch_stage_n<6>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
     default: err = "polynomial order not built"; return -5;
+  }
+}
+
+int default_waves(int N, int form) { return (N <= 4 || form == 2) ? 4 : 2; }
+
+int batch_resident_blocks(int form, int waves) {
+  if (form == 0) return waves == 4 ? batch_resident_t<double, false, 4>() : batch_resident_t<double, false, 2>();
+  if (form == 1) return waves == 4 ? batch_resident_t<double, true, 4>() : batch_resident_t<double, true, 2>();
+  return waves == 4 ? batch_resident_t<float, true, 4>() : batch_resident_t<float, true, 2>();
+}
+
+int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchStep* steps,
+                       const int* parity, const BatchGroups& G, int blocks, int stage, double a,
+                       double b, void* stream, std::string& err) {
+  hipStream_t s = (hipStream_t)stream;
+  if (waves != 2 && waves != 4) {
+    err = "waves per workgroup must be 2 or 4";
+    return -1;
+  }
+  const bool w4 = waves == 4;
+  switch (form) {
+    case 0:
+      return w4 ? launch_batch_t<double, false, 4>(items, steps, parity, G, blocks, stage, a, b, s, err)
+                : launch_batch_t<double, false, 2>(items, steps, parity, G, blocks, stage, a, b, s, err);
+    case 1:
+      return w4 ? launch_batch_t<double, true, 4>(items, steps, parity, G, blocks, stage, a, b, s, err)
+                : launch_batch_t<double, true, 2>(items, steps, parity, G, blocks, stage, a, b, s, err);
+    case 2:
+      return w4 ? launch_batch_t<float, true, 4>(items, steps, parity, G, blocks, stage, a, b, s, err)
+                : launch_batch_t<float, true, 2>(items, steps, parity, G, blocks, stage, a, b, s, err);
+    default: err = "precision mode not built"; return -5;
   }
 }
 

@@ -63,10 +63,63 @@ class Solver:
     def force(self, U, v_w=(0.0, 0.0), stream=None):
         return L.dg_force(self.h, U, v_w, stream)
 
+    # -- launch shape
+    def set_tuning(self, waves=0, grid=0):
+        L.dg_set_tuning(self.h, waves, grid)
+
+    def get_tuning(self):
+        return L.dg_get_tuning(self.h)
+
+    def autotune(self, U, reps=20, cache_path=None, stream=None):
+        return L.dg_autotune(self.h, U, reps, cache_path, stream)
+
     def close(self):
         if self.h is not None:
             L.dg_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several solvers advanced together (one launch per RK stage for all of
+    them, the five stages replayed as a captured HIP graph).  The batch owns
+    the states: load them with set_state, read them with get_state."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        self.n = len(self.solvers)
+        self.b = L.dg_batch_create([s.h for s in self.solvers])
+
+    def set_state(self, i, U, stream=None):
+        L.dg_batch_set_state(self.b, i, U, stream)
+
+    def get_state(self, i, out=None, stream=None):
+        if out is None:
+            out = self.solvers[i].empty_state()
+        L.dg_batch_get_state(self.b, i, out, stream)
+        return out
+
+    def rk_step(self, dt, v_w, stream=None):
+        L.dg_batch_rk_step(self.b, dt, v_w, stream)
+
+    def force(self, v_w=None, stream=None):
+        return L.dg_batch_force(self.b, self.n, v_w, stream)
+
+    def configure(self, mode=0, waves=0, grid=0, use_graph=True):
+        L.dg_batch_configure(self.b, mode, waves, grid, 1 if use_graph else 0)
+
+    def autotune(self, reps=10, stream=None):
+        return L.dg_batch_autotune(self.b, reps, stream)
+
+    def close(self):
+        if self.b is not None:
+            L.dg_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -153,3 +153,37 @@ def test_newmark_matches_oracle():
     got = L.dg_newmark_step(st, 0.7, 0.05, 1.0, 0.1, 2.3)
     want = fsi.newmark_step(0.1, -0.2, 0.3, 0.7, 0.05, 1.0, 0.1, 2.3)
     assert np.abs(got - np.array(want)).max() < 1e-15
+
+
+def test_tuning_and_batch_error_paths():
+    """Launch-shape and batch entry points reject bad arguments and contexts
+    that are not set up, without touching a GPU."""
+    from paper_2508_17917_amd import _lib as L
+    mesh = mg.periodic_square(3, 3, 1.0, 1.0)
+    h = L.dg_create(3)
+    try:
+        L.dg_set_physics(h, 1.4, 0.72, 1e-3, 1.0, 0, 0.01, [1, 0.2, 0, 1.8])
+        L.dg_set_mesh(h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh["face_tag"], mesh["period"])
+        L.dg_setup_host(h)
+        assert L.dg_get_tuning(h) == (4, 0)  # defaults at p = 3, FP64
+        L.dg_set_tuning(h, 2, 1)
+        assert L.dg_get_tuning(h) == (2, 1)
+        for bad in ((3, 0), (4, 2), (-1, 0)):
+            with pytest.raises(L.DGError) as e:
+                L.dg_set_tuning(h, *bad)
+            assert e.value.code == L.DG_EINVAL
+        assert L.dg_get_tuning(h) == (2, 1)
+        import torch
+        U = torch.zeros(1, dtype=torch.float64)
+        with pytest.raises(L.DGError) as e:
+            L.dg_autotune(h, U, 5, None, stream=0)
+        assert e.value.code == L.DG_ESTATE
+        with pytest.raises(L.DGError) as e:
+            L.dg_batch_create([h])
+        assert e.value.code == L.DG_ESTATE
+        assert "dg_setup" in L.dg_batch_last_error(None)
+        with pytest.raises(L.DGError) as e:
+            L.dg_batch_create([])
+        assert e.value.code == L.DG_EINVAL
+    finally:
+        L.dg_destroy(h)

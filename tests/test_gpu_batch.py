@@ -1,0 +1,214 @@
+"""GPU tests of batches (one stage launch for many meshes, graph-replayed
+steps), of the launch-shape autotuner and of the coupled VIV sweep.
+
+A batch step must give what dg_rk_step gives on each instance alone: the
+arithmetic of an element does not depend on the launch that runs it.  Each
+graph replay is checked against eager per-instance steps taken between the
+replays.  The coupled sweep is checked against the oracle's coupling loop
+(Alg. 3 order: Newmark under the last force, v_w = dy/dt, RK step, force).
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from oracle import fsi
+from tests.oracle_helpers import build
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print("[gpu-case] " + msg, flush=True)
+
+
+def _to_dev(torch, U):
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(U, (2, 0, 1)))).cuda()
+
+
+def _from_dev(T):
+    return np.transpose(T.cpu().numpy(), (1, 2, 0))
+
+
+# uneven meshes, mixed orders (two instances share p = 4), per-instance physics
+INSTANCES = [
+    (lambda: mg.ogrid(10, 4, 0.5, 5.0, 1.3), 4, 2e-3),
+    (lambda: mg.ogrid(12, 5, 0.5, 6.0, 1.3), 5, 3e-3),
+    (lambda: mg.periodic_square(4, 3, 4.0, 3.0), 3, 2e-3),
+    (lambda: mg.ogrid(9, 3, 0.5, 4.0, 1.3), 6, 4e-3),
+    (lambda: mg.ogrid(8, 6, 0.5, 6.0, 1.2), 4, 2.5e-3),
+]
+
+
+def _make(precision):
+    from paper_2508_17917_amd import Solver
+    U_inf = mg.free_stream(0.2)
+    out = []
+    for k, (mk, p, mu) in enumerate(INSTANCES):
+        mesh = mk()
+        s = Solver(p, mesh, gamma=1.4, Pr=0.72, mu=mu, theta=1.0, penalty_mode=0, C_pen=1.0,
+                   U_inf=U_inf, precision=precision)
+        rng = np.random.default_rng(100 + k)
+        U = mg.noisy_free_stream((4, s.Np, s.K), U_inf, rng)
+        out.append((s, U))
+    return out
+
+
+def _params(step, n):
+    dt = np.array([1e-4 * (1.0 + 0.1 * i) * (1.0 + 0.05 * step) for i in range(n)])
+    vw = np.array([[0.0, 0.01 * np.sin(0.7 * i + step)] for i in range(n)])
+    return dt, vw
+
+
+SHAPES = [  # mode, waves, grid, graph
+    (0, 0, 0, True), (0, 4, 1, True), (1, 2, 0, True), (1, 4, 1, False), (0, 2, 1, False),
+]
+
+
+@pytest.mark.parametrize("precision", [0, 2], ids=["fp64", "fp32-pert"])
+def test_batch_steps_equal_single_instance_steps(precision):
+    torch = _torch()
+    from paper_2508_17917_amd import Batch
+    inst = _make(precision)
+    n = len(inst)
+    for shape in SHAPES:
+        _say("batch precision=%d shape=%s n=%d K=%s" % (precision, shape, n,
+                                                        [s.K for s, _ in inst]))
+        b = Batch([s for s, _ in inst])
+        b.configure(*shape[:3], use_graph=shape[3])
+        ref, K1s = [], []
+        for i, (s, U) in enumerate(inst):
+            Ud = _to_dev(torch, U)
+            b.set_state(i, Ud)
+            ref.append(Ud.clone())
+            K1s.append(torch.zeros_like(Ud))
+        for step in range(3):
+            dt, vw = _params(step, n)
+            b.rk_step(dt, vw)
+            # eager single-instance steps between the replays
+            for i, (s, _) in enumerate(inst):
+                s.rk_step(ref[i], K1s[i], dt[i], v_w=vw[i])
+            torch.cuda.synchronize()
+            for i, (s, _) in enumerate(inst):
+                got = b.get_state(i)
+                torch.cuda.synchronize()
+                diff = float((got - ref[i]).abs().max())
+                assert torch.equal(got, ref[i]), "shape %s step %d instance %d: max diff %.3e" % (
+                    shape, step, i, diff)
+        # forces on the batch states equal the single-instance forces
+        vw = _params(3, n)[1]
+        F = b.force(vw)
+        for i, (s, _) in enumerate(inst):
+            assert np.array_equal(F[i], s.force(ref[i], v_w=vw[i]))
+        b.close()
+    for s, _ in inst:
+        s.close()
+
+
+def test_batch_autotune_keeps_results():
+    torch = _torch()
+    from paper_2508_17917_amd import Batch
+    inst = _make(2)
+    n = len(inst)
+    b = Batch([s for s, _ in inst])
+    ref, K1s = [], []
+    for i, (s, U) in enumerate(inst):
+        Ud = _to_dev(torch, U)
+        b.set_state(i, Ud)
+        ref.append(Ud.clone())
+        K1s.append(torch.zeros_like(Ud))
+    _say("batch autotune")
+    us = b.autotune(reps=5)
+    assert us > 0.0
+    # the timed first-stage launches leave the states alone
+    for i in range(n):
+        assert torch.equal(b.get_state(i), ref[i])
+    dt, vw = _params(0, n)
+    b.rk_step(dt, vw)
+    for i, (s, _) in enumerate(inst):
+        s.rk_step(ref[i], K1s[i], dt[i], v_w=vw[i])
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert torch.equal(b.get_state(i), ref[i])
+    b.close()
+    for s, _ in inst:
+        s.close()
+
+
+def test_single_autotune_and_cache(tmp_path):
+    torch = _torch()
+    from paper_2508_17917_amd import Solver
+    w = mg.workload("cylinder20k")
+    path = str(tmp_path / "tune.jsonl")
+    for precision in (0, 2):
+        s = Solver(4, w["mesh"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+                   penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"],
+                   precision=precision)
+        U = _to_dev(torch, mg.noisy_free_stream((4, s.Np, s.K), w["U_inf"], mg.rng_for(1)))
+        R0 = s.rhs(U)
+        _say("autotune precision=%d" % precision)
+        us = s.autotune(U, reps=10, cache_path=path)
+        assert us > 0.0
+        shape = s.get_tuning()
+        assert shape[0] in (2, 4) and shape[1] in (0, 1)
+        # a second context finds the entry in the cache without timing
+        s2 = Solver(4, w["mesh"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+                    penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"],
+                    precision=precision)
+        assert s2.autotune(U, reps=10, cache_path=path) == 0.0
+        assert s2.get_tuning() == shape
+        # every shape gives the same bits
+        for wv in (2, 4):
+            for grid in (0, 1):
+                s.set_tuning(wv, grid)
+                assert torch.equal(s.rhs(U), R0), (precision, wv, grid)
+        s.close()
+        s2.close()
+    lines = open(path).read().strip().splitlines()
+    assert len(lines) == 2 and all('"p": 4' in ln for ln in lines)
+
+
+def test_viv_sweep_matches_oracle_coupling():
+    torch = _torch()
+    from paper_2508_17917_amd.viv import VIVSweep
+    phys = dict(gamma=1.4, Pr=0.72, mu=1e-2, theta=1.0, penalty_mode=0, C_pen=1.0)
+    U_inf = mg.free_stream(0.2)
+    cases = [dict(mesh=mg.ogrid(10, 4, 0.5, 5.0, 1.3), p=3, U_star=4.0, m_star=10.0, xi=0.0),
+             dict(mesh=mg.ogrid(12, 4, 0.5, 5.0, 1.3), p=4, U_star=6.5, m_star=10.0, xi=0.0)]
+    sweep = VIVSweep(cases, U_inf=U_inf, **phys)
+    oracles, states = [], []
+    for i, c in enumerate(cases):
+        dg = build(c["mesh"], c["p"], U_inf=U_inf, **phys)
+        U = mg.noisy_free_stream((4,) + dg.mesh.x.shape, U_inf, np.random.default_rng(7 + i))
+        oracles.append(dg)
+        states.append(U)
+        sweep.set_state(i, _to_dev(torch, U))
+    sweep.update_forces()
+    body = np.zeros((2, 3))
+    F = np.array([fsi.wall_force(dg, U) for dg, U in zip(oracles, states)])
+    v_inf = np.hypot(U_inf[1], U_inf[2]) / U_inf[0]
+    coef = [fsi.viv_coefficients(c["U_star"], c["m_star"], c["xi"], v_inf) for c in cases]
+    dt = 2e-4
+    _say("viv coupled sweep, 3 steps")
+    for step in range(3):
+        got_F = sweep.step(dt)
+        for i, dg in enumerate(oracles):
+            M, C, K, inv_m = coef[i]
+            y, yd, ydd = fsi.newmark_step(*body[i], F[i, 1] * inv_m, dt, M, C, K)
+            vw = (0.0, (y - body[i, 0]) / dt)
+            body[i] = (y, yd, ydd)
+            states[i], _ = dg.lserk_step(states[i], dt, vw)
+            F[i] = fsi.wall_force(dg, states[i], vw)
+        scale = (1.0 / 1.4) * np.pi
+        assert np.abs(got_F - F).max() <= 1e-11 * scale, (step, got_F, F)
+        assert np.abs(sweep.body - body).max() <= 1e-11 * np.abs(body).max() + 1e-300
+        for i in range(2):
+            U = _from_dev(sweep.get_state(i))
+            assert np.abs(U - states[i]).max() <= 1e-12 * np.abs(states[i]).max()
+    sweep.close()
