@@ -115,7 +115,8 @@ int dg_num_nodes(const dg_ctx* ctx);
 int dg_num_face_nodes(const dg_ctx* ctx);
 
 /* Host copy of a set-up table for inspection (after dg_setup_host).  name:
- * "r", "s" (Np), "Dr", "Ds" (Np*Np, row-major), "LIFT", "LIFTr", "LIFTs"
+ * "r", "s" (Np), "Dr", "Ds", "M" (Np*Np, row-major; M the reference mass
+ * matrix (V V^T)^-1), "LIFT", "LIFTr", "LIFTs"
  * (Np*3Nfp), "Fmask" (3*Nfp, as doubles), "wface" (3*Nfp face quadrature
  * weights), "geo" (K*16: rx ry sx sy, then per face nx ny Fscale sigma_geo),
  * "nbr" (K*3 neighbour element, as doubles), "nbr_face" (K*3).  count must
@@ -153,6 +154,12 @@ int dg_rk_stage(dg_ctx* ctx, const double* U_in, double* U_out, double* K1,
  * outward normal.  FP64, deterministic order.  Synchronises `stream`; out is
  * a host array of 3 doubles. */
 int dg_force(dg_ctx* ctx, const double* U, const double v_w[2], double out[3], void* stream);
+
+/* As dg_force, but asynchronous: the three doubles are written to the device
+ * array out_dev on `stream` (for monitoring the force every step without a
+ * host synchronisation). */
+int dg_force_device(dg_ctx* ctx, const double* U, const double v_w[2], double* out_dev,
+                    void* stream);
 
 /* Host Newmark-beta step (beta 1/4, gamma 1/2) of M y'' + C y' + K y = F
  * (eq. 1dof_oscillator): state[3] = (y, y', y'') at t, updated to t + dt

@@ -166,8 +166,31 @@ def workload(name, p=None):
         mesh = ogrid(80, 128, 0.5, 30.0, 1.05)
         phys = physics_params(Re=100.0, M=0.2, L=1.0)
         return dict(mesh=mesh, p=4 if p is None else p, penalty_mode=0, C_pen=1.0, theta=1.0, **phys)
+    if name == "cylinder327k":
+        # the same O-grid refined 4x in each direction: K = 327,680, FP64 states
+        # well beyond the 256 MB last-level cache
+        mesh = ogrid(320, 512, 0.5, 30.0, 1.0 + 0.05 / 4)
+        phys = physics_params(Re=100.0, M=0.2, L=1.0)
+        return dict(mesh=mesh, p=4 if p is None else p, penalty_mode=0, C_pen=1.0, theta=1.0, **phys)
     if name == "periodic51k":
         mesh = periodic_square(160, 160, 10.0, 10.0)
         phys = physics_params(Re=100.0, M=0.3, L=1.0)
         return dict(mesh=mesh, p=6 if p is None else p, penalty_mode=0, C_pen=1.0, theta=1.0, **phys)
     raise KeyError(name)
+
+
+def viv_sweep_cases(n=16, seed_index=2):
+    """Seeded instances of a transverse-VIV sweep: per instance an O-grid with
+    ntheta in [40, 100] and nr in [64, 160] cells (K = 2 ntheta nr), order p in
+    {4, 5, 6}, reduced velocity U* = linspace(3, 8, n), mass ratio 10, no
+    structural damping.  Returns (cases, physics) for Re = 100, M = 0.2."""
+    rng = rng_for(seed_index)
+    cases = []
+    for i, U_star in enumerate(np.linspace(3.0, 8.0, n)):
+        nt = int(rng.integers(40, 101))
+        nr = int(rng.integers(64, 161))
+        p = int(rng.choice([4, 5, 6]))
+        cases.append(dict(ntheta=nt, nr=nr, p=p, U_star=float(U_star), m_star=10.0, xi=0.0,
+                          mesh=ogrid(nt, nr, 0.5, 30.0, 1.05)))
+    phys = physics_params(Re=100.0, M=0.2, L=1.0)
+    return cases, dict(penalty_mode=0, C_pen=1.0, theta=1.0, **phys)

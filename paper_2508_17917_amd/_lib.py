@@ -44,6 +44,7 @@ SIGNATURES = {
     "dg_rk_step": (_I, [_P, _P, _P, _D, _DP, _P]),
     "dg_rk_stage": (_I, [_P, _P, _P, _P, _D, _D, _D, _DP, _P]),
     "dg_force": (_I, [_P, _P, _DP, _DP, _P]),
+    "dg_force_device": (_I, [_P, _P, _DP, _P, _P]),
     "dg_newmark_step": (_I, [_DP, _D, _D, _D, _D, _D]),
     "dg_set_tuning": (_I, [_P, _I, _I]),
     "dg_get_tuning": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -207,6 +208,11 @@ def dg_force(h, U, v_w=(0.0, 0.0), stream=None):
     out = np.zeros(3)
     _check(load().dg_force(h, _ptr(U), _dp(vw), _dp(out), _stream(stream)), h)
     return out
+
+
+def dg_force_device(h, U, out, v_w=(0.0, 0.0), stream=None):
+    vw = _vw(v_w)
+    return _check(load().dg_force_device(h, _ptr(U), _dp(vw), _ptr(out), _stream(stream)), h)
 
 
 def dg_newmark_step(state, F_new, dt, M, C, K):

@@ -15,6 +15,7 @@ struct RefOps {
   int N = 0, Np = 0, Nfp = 0;
   std::vector<double> r, s;            // Np
   std::vector<double> Dr, Ds;          // Np x Np
+  std::vector<double> M;               // Np x Np reference mass matrix
   std::vector<double> LIFT;            // Np x 3Nfp, M^-1 E
   std::vector<double> LIFTr, LIFTs;    // Np x 3Nfp, M^-1 Dr^T E, M^-1 Ds^T E
   std::vector<int> Fmask;              // 3 x Nfp, counter-clockwise per face

@@ -215,6 +215,7 @@ int dg_get_host_table(const dg_ctx* cc, const char* name, double* out, int64_t c
   else if (n == "s") v = r.s;
   else if (n == "Dr") v = r.Dr;
   else if (n == "Ds") v = r.Ds;
+  else if (n == "M") v = r.M;
   else if (n == "LIFT") v = r.LIFT;
   else if (n == "LIFTr") v = r.LIFTr;
   else if (n == "LIFTs") v = r.LIFTs;
@@ -300,6 +301,20 @@ int dg_force(dg_ctx* c, const double* U, const double v_w[2], double out[3], voi
   out[1] = h[1];
   out[2] = h[2];
   return DG_OK;
+}
+
+int dg_force_device(dg_ctx* c, const double* U, const double v_w[2], double* out_dev,
+                    void* stream) {
+  int rc = check_ready(c);
+  if (rc != DG_OK) return rc;
+  if (!U || !out_dev) return fail(c, DG_EINVAL, "NULL argument");
+  if (c->mesh.wall_faces.empty()) {
+    hipError_t e = hipMemsetAsync(out_dev, 0, 3 * sizeof(double), (hipStream_t)stream);
+    return e == hipSuccess ? DG_OK : hip_fail(c, e, "hipMemsetAsync");
+  }
+  std::string err;
+  rc = dgmi::launch_force(c->N, tables(c), kphys(c, v_w), U, out_dev, stream, err);
+  return rc == 0 ? DG_OK : fail(c, rc, err);
 }
 
 int dg_newmark_step(double st[3], double F_new, double dt, double M, double C, double K) {

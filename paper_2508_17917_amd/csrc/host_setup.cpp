@@ -217,6 +217,8 @@ bool build_ref_ops(int N, RefOps& o, std::string& err) {
   o.Dr = matmul(Vr, Vinv, Np, Np, Np);
   o.Ds = matmul(Vs, Vinv, Np, Np, Np);
   std::vector<double> Minv = matmul(V, transpose(V, Np, Np), Np, Np, Np);
+  // reference mass matrix M = (V V^T)^-1 = V^-T V^-1 (for norms of states)
+  o.M = matmul(transpose(Vinv, Np, Np), Vinv, Np, Np, Np);
   // face node lists from the row structure of the node numbering:
   // row i starts at off(i) = i(N+1) - i(i-1)/2 and holds N+1-i nodes
   o.Fmask.assign(3 * Nfp, 0);

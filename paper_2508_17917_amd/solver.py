@@ -37,6 +37,7 @@ class Solver:
 
     def table(self, name):
         sizes = {"r": self.Np, "s": self.Np, "Dr": self.Np ** 2, "Ds": self.Np ** 2,
+                 "M": self.Np ** 2,
                  "LIFT": self.Np * 3 * self.Nfp, "LIFTr": self.Np * 3 * self.Nfp,
                  "LIFTs": self.Np * 3 * self.Nfp, "Fmask": 3 * self.Nfp, "wface": 3 * self.Nfp,
                  "geo": self.K * 16, "nbr": self.K * 3, "nbr_face": self.K * 3}
@@ -62,6 +63,11 @@ class Solver:
 
     def force(self, U, v_w=(0.0, 0.0), stream=None):
         return L.dg_force(self.h, U, v_w, stream)
+
+    def force_device(self, U, out, v_w=(0.0, 0.0), stream=None):
+        """Force into the device tensor out[0:3] without synchronising."""
+        L.dg_force_device(self.h, U, out, v_w, stream)
+        return out
 
     # -- launch shape
     def set_tuning(self, waves=0, grid=0):

@@ -54,6 +54,7 @@ def test_host_operators_match_oracle(p):
     tol = 1e-12 * p * p
     assert np.abs(s.table("Dr").reshape(Np, Np) - ref.Dr).max() < tol
     assert np.abs(s.table("Ds").reshape(Np, Np) - ref.Ds).max() < tol
+    assert np.abs(s.table("M").reshape(Np, Np) - ref.M).max() < tol * 10
     assert np.abs(s.table("LIFT").reshape(Np, NF) - ref.LIFT).max() < tol
     assert np.abs(s.table("LIFTr").reshape(Np, NF) - ref.LIFTr).max() < tol
     assert np.abs(s.table("LIFTs").reshape(Np, NF) - ref.LIFTs).max() < tol

@@ -155,7 +155,11 @@ def test_force_parity():
         want = fsi.wall_force(dg, U, vw)
         _say("force p=%d" % p)
         s = _solver(mesh, p, dg.phys)
-        got = s.force(_to_dev(torch, U), v_w=vw)
+        Ud = _to_dev(torch, U)
+        got = s.force(Ud, v_w=vw)
+        out = torch.zeros(3, dtype=torch.float64, device="cuda")
+        s.force_device(Ud, out, v_w=vw)
+        assert np.array_equal(out.cpu().numpy(), got)
         # the net force is a small remainder of the pressure integral around the
         # closed wall: compare against that integral's size, p_inf x perimeter
         scale = (1.0 / 1.4) * np.pi
