@@ -238,6 +238,87 @@ const char* dg_batch_last_error(const dg_batch* b);
 /* Release the batch (not its contexts).  NULL is a no-op. */
 void dg_batch_destroy(dg_batch* b);
 
+/* ---- Learned closure --------------------------------------------------------
+ * A per-element network corrects an order-lo solution toward the order-hi
+ * one (a spec extension; the paper has no closure).  A sample of
+ * element k is x = [Pi_lo(U - U_inf) (Np_lo nodes x 4 fields, field-major),
+ * rx, ry, sx, sy]; its target the part of the order-hi state that order lo
+ * cannot represent, t = U_hi - I Pi_lo U_hi (Np_hi x 4, field-major), where
+ * Pi_lo is the L2 projection onto degree <= lo at the order-lo nodes and I
+ * the interpolation back to the order-hi nodes.  The corrected state is
+ * I U_lo + y.  The network is y = W3 g(W2 g(W1 x + b1) + b2) + b3 (g the
+ * exact-erf GELU) on per-column normalised x and t, trained on the mean
+ * squared error with Adam; its products run on the matrix cores with
+ * bfloat16 operands and FP32 accumulation, its parameters are FP32. */
+typedef struct dg_mlp dg_mlp;
+typedef struct dg_closure dg_closure;
+
+/* Network of widths n_in (1..64) -> n_hidden (64 or 128) -> n_hidden ->
+ * n_out (1..64), with buffers for batches of up to max_batch samples.
+ * Parameters start at zero; set them with dg_mlp_set_params. */
+int dg_mlp_create(int n_in, int n_hidden, int n_out, int64_t max_batch, dg_mlp** out);
+int64_t dg_mlp_num_params(const dg_mlp* m);
+
+/* Parameters as one host FP32 vector W1 b1 W2 b2 W3 b3 (W_l row-major
+ * [width out][width in]).  Setting them resets the Adam state.  Both calls
+ * synchronise the device. */
+int dg_mlp_set_params(dg_mlp* m, const float* host, int64_t count);
+int dg_mlp_get_params(dg_mlp* m, float* host, int64_t count);
+/* Gradient of the last dg_mlp_backward, same layout (synchronises). */
+int dg_mlp_get_grad(dg_mlp* m, float* host, int64_t count);
+
+/* Per-column normalisation: inputs (x - in_mean) / in_std, targets
+ * (t - out_mean) / out_std; outputs are returned denormalised.  Host arrays
+ * of n_in and n_out floats (standard deviations positive). */
+int dg_mlp_set_normalization(dg_mlp* m, const float* in_mean, const float* in_std,
+                             const float* out_mean, const float* out_std);
+
+/* Y[b][0..n_out) = network(X[b][0..n_in)) for b < B: X device FP32 with row
+ * stride ldx, Y device FP32 with row stride ldy.  Asynchronous. */
+int dg_mlp_forward(dg_mlp* m, const float* X, int64_t ldx, int64_t B, float* Y, int64_t ldy,
+                   void* stream);
+
+/* Gradient of the mean squared error (over B x n_out normalised entries)
+ * against raw targets T (device FP32, row stride ldt), kept for dg_mlp_adam
+ * (partials per workgroup summed in a fixed order: reproducible).  With loss
+ * non-NULL the loss is returned on the host (synchronises). */
+int dg_mlp_backward(dg_mlp* m, const float* X, int64_t ldx, const float* T, int64_t ldt,
+                    int64_t B, double* loss, void* stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected) with the last gradient;
+ * refreshes the bfloat16 weight copies.  Asynchronous. */
+int dg_mlp_adam(dg_mlp* m, float lr, float beta1, float beta2, float eps, void* stream);
+
+const char* dg_mlp_last_error(const dg_mlp* m);
+void dg_mlp_destroy(dg_mlp* m);
+
+/* Mean and standard deviation (population) of each of the first cols (<= 64)
+ * columns of a device FP32 array of rows x ld; host outputs.  Allocates a
+ * temporary device buffer; synchronises. */
+int dg_column_stats(const float* A, int64_t rows, int64_t ld, int cols, double* mean,
+                    double* stdev, void* stream);
+
+/* Order-change maps between two set-up contexts on the same mesh, lo->N <
+ * hi->N (U_inf of hi).  The contexts must outlive the closure. */
+int dg_closure_create(const dg_ctx* lo, const dg_ctx* hi, dg_closure** out);
+int dg_closure_sizes(const dg_closure* c, int* n_features, int* n_targets);
+/* Samples of every element into X (device FP32, row stride ldx >=
+ * n_features) from an order-hi state (from_hi = 1, restricted) or an
+ * order-lo state (from_hi = 0).  Asynchronous. */
+int dg_closure_features(dg_closure* c, const double* U, int from_hi, float* X, int64_t ldx,
+                        void* stream);
+/* Targets of every element from an order-hi state (T row stride >=
+ * n_targets).  Asynchronous. */
+int dg_closure_targets(dg_closure* c, const double* U_hi, float* T, int64_t ldt, void* stream);
+/* U_lo = Pi_lo U_hi, the order-lo state of an order-hi one (device
+ * [K][4][Np_lo]).  Asynchronous. */
+int dg_closure_restrict(dg_closure* c, const double* U_hi, double* U_lo, void* stream);
+/* U_hi = I U_lo + Y (Y may be NULL: interpolation only).  Asynchronous. */
+int dg_closure_apply(dg_closure* c, const double* U_lo, const float* Y, int64_t ldy,
+                     double* U_hi, void* stream);
+const char* dg_closure_last_error(const dg_closure* c);
+void dg_closure_destroy(dg_closure* c);
+
 /* Message of the last failing call on ctx ("" if none).  Valid until the next
  * call on ctx.  ctx may be NULL (then a message about creation failures). */
 const char* dg_last_error(const dg_ctx* ctx);

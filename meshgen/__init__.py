@@ -194,3 +194,14 @@ def viv_sweep_cases(n=16, seed_index=2):
                           mesh=ogrid(nt, nr, 0.5, 30.0, 1.05)))
     phys = physics_params(Re=100.0, M=0.2, L=1.0)
     return cases, dict(penalty_mode=0, C_pen=1.0, theta=1.0, **phys)
+
+
+def mlp_init(rng, n_in, n_hidden, n_out):
+    """Seeded initial parameters of an n_in -> n_hidden -> n_hidden -> n_out
+    network as one float32 vector W1 b1 W2 b2 W3 b3 (W row-major [out][in]):
+    weights N(0, 2 / fan_in), biases zero."""
+    parts = []
+    for fi, fo in ((n_in, n_hidden), (n_hidden, n_hidden), (n_hidden, n_out)):
+        parts.append(rng.standard_normal((fo, fi)) * math.sqrt(2.0 / fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)

@@ -58,6 +58,26 @@ SIGNATURES = {
     "dg_batch_autotune": (_I, [_P, _I, _P, _DP]),
     "dg_batch_last_error": (ctypes.c_char_p, [_P]),
     "dg_batch_destroy": (None, [_P]),
+    "dg_mlp_create": (_I, [_I, _I, _I, _L, ctypes.POINTER(_P)]),
+    "dg_mlp_num_params": (_L, [_P]),
+    "dg_mlp_set_params": (_I, [_P, ctypes.POINTER(ctypes.c_float), _L]),
+    "dg_mlp_get_params": (_I, [_P, ctypes.POINTER(ctypes.c_float), _L]),
+    "dg_mlp_get_grad": (_I, [_P, ctypes.POINTER(ctypes.c_float), _L]),
+    "dg_mlp_set_normalization": (_I, [_P] + [ctypes.POINTER(ctypes.c_float)] * 4),
+    "dg_mlp_forward": (_I, [_P, _P, _L, _L, _P, _L, _P]),
+    "dg_mlp_backward": (_I, [_P, _P, _L, _P, _L, _L, _DP, _P]),
+    "dg_mlp_adam": (_I, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "dg_mlp_last_error": (ctypes.c_char_p, [_P]),
+    "dg_mlp_destroy": (None, [_P]),
+    "dg_column_stats": (_I, [_P, _L, _L, _I, _DP, _DP, _P]),
+    "dg_closure_create": (_I, [_P, _P, ctypes.POINTER(_P)]),
+    "dg_closure_sizes": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "dg_closure_features": (_I, [_P, _P, _I, _P, _L, _P]),
+    "dg_closure_targets": (_I, [_P, _P, _P, _L, _P]),
+    "dg_closure_apply": (_I, [_P, _P, _P, _L, _P, _P]),
+    "dg_closure_restrict": (_I, [_P, _P, _P, _P]),
+    "dg_closure_last_error": (ctypes.c_char_p, [_P]),
+    "dg_closure_destroy": (None, [_P]),
     "dg_last_error": (ctypes.c_char_p, [_P]),
     "dg_destroy": (None, [_P]),
 }
@@ -306,3 +326,146 @@ def dg_batch_last_error(b):
 def dg_batch_destroy(b):
     if b is not None and b.value:
         load().dg_batch_destroy(b)
+
+
+# ---- learned closure --------------------------------------------------------
+_FP = ctypes.POINTER(ctypes.c_float)
+
+
+def _fp(a):
+    return a.ctypes.data_as(_FP)
+
+
+def _ld(t):
+    """Row stride of a 2-D device array whose rows are contiguous."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("expected a 2-D array with contiguous rows")
+    return t.stride(0)
+
+
+def _mcheck(code, m=None):
+    if code != DG_OK:
+        msg = load().dg_mlp_last_error(m)
+        raise DGError(code, msg.decode() if msg else "")
+    return code
+
+
+def _ccheck(code, c=None):
+    if code != DG_OK:
+        msg = load().dg_closure_last_error(c)
+        raise DGError(code, msg.decode() if msg else "")
+    return code
+
+
+def dg_mlp_create(n_in, n_hidden, n_out, max_batch):
+    m = ctypes.c_void_p()
+    _mcheck(load().dg_mlp_create(int(n_in), int(n_hidden), int(n_out), int(max_batch),
+                                 ctypes.byref(m)))
+    return m
+
+
+def dg_mlp_num_params(m):
+    return int(load().dg_mlp_num_params(m))
+
+
+def dg_mlp_set_params(m, params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    return _mcheck(load().dg_mlp_set_params(m, _fp(p), p.size), m)
+
+
+def dg_mlp_get_params(m):
+    out = np.zeros(dg_mlp_num_params(m), dtype=np.float32)
+    _mcheck(load().dg_mlp_get_params(m, _fp(out), out.size), m)
+    return out
+
+
+def dg_mlp_get_grad(m):
+    out = np.zeros(dg_mlp_num_params(m), dtype=np.float32)
+    _mcheck(load().dg_mlp_get_grad(m, _fp(out), out.size), m)
+    return out
+
+
+def dg_mlp_set_normalization(m, in_mean, in_std, out_mean, out_std):
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+            for a in (in_mean, in_std, out_mean, out_std)]
+    return _mcheck(load().dg_mlp_set_normalization(m, *[_fp(a) for a in arrs]), m)
+
+
+def dg_mlp_forward(m, X, Y, B=None, stream=None):
+    B = X.shape[0] if B is None else B
+    return _mcheck(load().dg_mlp_forward(m, _ptr(X), _ld(X), int(B), _ptr(Y), _ld(Y),
+                                         _stream(stream)), m)
+
+
+def dg_mlp_backward(m, X, T, B=None, want_loss=True, stream=None):
+    B = X.shape[0] if B is None else B
+    loss = ctypes.c_double()
+    _mcheck(load().dg_mlp_backward(m, _ptr(X), _ld(X), _ptr(T), _ld(T), int(B),
+                                   ctypes.byref(loss) if want_loss else None, _stream(stream)), m)
+    return loss.value if want_loss else None
+
+
+def dg_mlp_adam(m, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    return _mcheck(load().dg_mlp_adam(m, float(lr), float(beta1), float(beta2), float(eps),
+                                      _stream(stream)), m)
+
+
+def dg_mlp_last_error(m):
+    msg = load().dg_mlp_last_error(m)
+    return msg.decode() if msg else ""
+
+
+def dg_mlp_destroy(m):
+    if m is not None and m.value:
+        load().dg_mlp_destroy(m)
+
+
+def dg_column_stats(A, cols=None, rows=None, stream=None):
+    rows = A.shape[0] if rows is None else rows
+    cols = A.shape[1] if cols is None else cols
+    mean, std = np.zeros(cols), np.zeros(cols)
+    code = load().dg_column_stats(_ptr(A), int(rows), _ld(A), int(cols), _dp(mean), _dp(std),
+                                  _stream(stream))
+    if code != DG_OK:
+        raise DGError(code, "dg_column_stats failed")
+    return mean, std
+
+
+def dg_closure_create(lo, hi):
+    c = ctypes.c_void_p()
+    _ccheck(load().dg_closure_create(lo, hi, ctypes.byref(c)))
+    return c
+
+
+def dg_closure_sizes(c):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _ccheck(load().dg_closure_sizes(c, ctypes.byref(a), ctypes.byref(b)), c)
+    return a.value, b.value
+
+
+def dg_closure_features(c, U, X, from_hi, stream=None):
+    return _ccheck(load().dg_closure_features(c, _ptr(U), int(bool(from_hi)), _ptr(X), _ld(X),
+                                              _stream(stream)), c)
+
+
+def dg_closure_targets(c, U_hi, T, stream=None):
+    return _ccheck(load().dg_closure_targets(c, _ptr(U_hi), _ptr(T), _ld(T), _stream(stream)), c)
+
+
+def dg_closure_restrict(c, U_hi, U_lo, stream=None):
+    return _ccheck(load().dg_closure_restrict(c, _ptr(U_hi), _ptr(U_lo), _stream(stream)), c)
+
+
+def dg_closure_apply(c, U_lo, Y, U_hi, stream=None):
+    return _ccheck(load().dg_closure_apply(c, _ptr(U_lo), _ptr(Y), 0 if Y is None else _ld(Y),
+                                           _ptr(U_hi), _stream(stream)), c)
+
+
+def dg_closure_last_error(c):
+    msg = load().dg_closure_last_error(c)
+    return msg.decode() if msg else ""
+
+
+def dg_closure_destroy(c):
+    if c is not None and c.value:
+        load().dg_closure_destroy(c)

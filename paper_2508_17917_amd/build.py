@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgmi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["host_setup.cpp", "dgmi_abi.cpp", "batch.cpp", "tune.cpp", "kernels.hip"]
+SOURCES = ["host_setup.cpp", "dgmi_abi.cpp", "batch.cpp", "tune.cpp", "closure.cpp", "kernels.hip",
+           "mlp.hip"]
 ARCH = os.environ.get("DGMI_OFFLOAD_ARCH", "gfx950")
 
 

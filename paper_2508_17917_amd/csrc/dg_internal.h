@@ -48,6 +48,9 @@ bool build_mesh_tables(const RefOps& ref, const Physics& phys, int64_t Nv, const
                        const double* VY, int64_t K, const int32_t* EToV, const int8_t* face_tag,
                        const double period[2], MeshTables& out, std::string& err);
 
+bool build_order_maps(int lo, int hi, std::vector<double>& P, std::vector<double>& I,
+                      std::string& err);
+
 // Device-side view handed to the kernels.
 struct DeviceTables {
   const double* geo = nullptr;     // K x 16

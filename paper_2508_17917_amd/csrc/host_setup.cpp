@@ -474,4 +474,68 @@ size_t ops_packed_size(int N) {
   return 2 * Np * Np + 3 * Np * NF + NF;
 }
 
+// Order-change maps between the nodal bases of orders lo < hi on the
+// reference triangle.  P (Np_lo x Np_hi): the L2 projection onto degree <= lo
+// (the orthonormal modal coefficients V_hi^-1 u truncated to the modes
+// i + j <= lo), evaluated at the order-lo nodes.  I (Np_hi x Np_lo): the
+// order-lo polynomial evaluated at the order-hi nodes.
+bool build_order_maps(int lo, int hi, std::vector<double>& P, std::vector<double>& I,
+                      std::string& err) {
+  if (lo < 1 || hi <= lo || hi > kMaxOrder) {
+    err = "orders must satisfy 1 <= lo < hi <= 8";
+    return false;
+  }
+  const int nl = (lo + 1) * (lo + 2) / 2, nh = (hi + 1) * (hi + 2) / 2;
+  std::vector<double> rl, sl, rh, sh;
+  warp_blend_nodes(lo, rl, sl);
+  warp_blend_nodes(hi, rh, sh);
+  auto vander = [](int N, const std::vector<double>& r, const std::vector<double>& s, int maxdeg,
+                   int& ncol) {
+    std::vector<double> V;
+    const int n = (int)r.size();
+    ncol = 0;
+    for (int i = 0; i <= N; ++i)
+      for (int j = 0; j <= N - i; ++j)
+        if (i + j <= maxdeg) ++ncol;
+    V.assign((size_t)n * ncol, 0.0);
+    for (int m = 0; m < n; ++m) {
+      int col = 0;
+      for (int i = 0; i <= N; ++i)
+        for (int j = 0; j <= N - i; ++j) {
+          if (i + j > maxdeg) continue;
+          double v, dr, ds;
+          pkd(r[m], s[m], i, j, v, dr, ds);
+          V[(size_t)m * ncol + col++] = v;
+        }
+    }
+    return V;
+  };
+  int c;
+  std::vector<double> Vh = vander(hi, rh, sh, hi, c);
+  if (!invert(Vh, nh)) {
+    err = "singular Vandermonde matrix";
+    return false;
+  }
+  // rows of V_hi^-1 of the kept modes, in mode order
+  std::vector<double> keep_rows;
+  {
+    int row = 0;
+    for (int i = 0; i <= hi; ++i)
+      for (int j = 0; j <= hi - i; ++j, ++row)
+        if (i + j <= lo) keep_rows.insert(keep_rows.end(), Vh.begin() + (size_t)row * nh,
+                                          Vh.begin() + (size_t)(row + 1) * nh);
+  }
+  // the kept order-hi modes are the order-lo modes (same (i, j), same order)
+  std::vector<double> Psi_l = vander(hi, rl, sl, lo, c);  // nl x nl
+  P = matmul(Psi_l, keep_rows, nl, nl, nh);
+  std::vector<double> Vl = vander(lo, rl, sl, lo, c);
+  if (!invert(Vl, nl)) {
+    err = "singular Vandermonde matrix";
+    return false;
+  }
+  std::vector<double> Psi_h = vander(lo, rh, sh, lo, c);  // nh x nl
+  I = matmul(Psi_h, Vl, nh, nl, nl);
+  return true;
+}
+
 }  // namespace dgmi

@@ -1,0 +1,600 @@
+// Learned-closure kernels for gfx950: a per-element MLP
+// (n_in -> H -> GELU -> H -> GELU -> n_out) trained and evaluated with
+// bfloat16 operands on the matrix cores (16x16x16, FP32 accumulation) and
+// FP32 master weights, plus the per-element order-change maps that make its
+// samples.
+//
+// Matrix-core operand layout (v_mfma_f32_16x16x16_bf16): lane l supplies
+// A[l%16][4(l/16) + j] and B[4(l/16) + j][l%16], j = 0..3, and receives
+// D[4(l/16) + v][l%16], v = 0..3.
+#include <hip/hip_runtime.h>
+
+#include "mlp_internal.h"
+
+namespace dgmi {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16, round to nearest, ties to even
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ---------------------------------------------------------------- dense layer
+// out[B x N] = epilogue(A[B x K] W^T) with W[N x K] bfloat16 (row stride
+// ldw), staged in LDS.  One wave computes 16 rows x all N = 16 NT columns;
+// waves stride over the 16-row tiles.
+//   A: bfloat16 [B][lda], or (NORM_IN) raw FP32 inputs normalised on the fly,
+//      (x - mean) / std for columns < kvalid, 0 beyond (the normalised
+//      bfloat16 copy is stored to Aout for the weight gradient).
+enum DenseEpi { EPI_GELU = 0, EPI_OUT = 1, EPI_LOSS = 2, EPI_DGELU = 3 };
+
+struct DenseArgs {
+  const void* A;
+  int64_t lda;
+  const float* in_mean;      // NORM_IN
+  const float* in_rstd;
+  unsigned short* Aout;      // NORM_IN: normalised copy, ld = K
+  int kvalid;
+  const unsigned short* W;   // [N][ldw]
+  int K, ldw;
+  const float* bias;         // [N] (EPI_GELU, EPI_OUT, EPI_LOSS)
+  int nvalid;                // valid output columns
+  float* Z;                  // EPI_GELU: pre-activation out [B][N]; EPI_DGELU: pre-activation in
+  unsigned short* H;         // EPI_GELU / EPI_LOSS / EPI_DGELU output bfloat16 [B][N]
+  float* Y;                  // EPI_OUT output [B][ldy]
+  int64_t ldy;
+  const float* T;            // EPI_LOSS raw targets [B][ldt]
+  int64_t ldt;
+  const float* out_mean;     // EPI_OUT / EPI_LOSS
+  const float* out_std;
+  float loss_scale;          // EPI_LOSS: 2 / (B n_out)
+  double* loss_part;         // EPI_LOSS: one per workgroup
+  int64_t B;
+};
+
+template <int NT, int EPI, bool NORM_IN>
+__global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
+  constexpr int N = 16 * NT;
+  extern __shared__ unsigned char smem[];
+  const int K = g.K;
+  const int ldl = K + 4;  // padded LDS row: rows start 2 banks apart
+  unsigned short* sW = (unsigned short*)smem;
+  double* sLoss = (double*)(smem + ((N * ldl * 2 + 15) / 16) * 16);
+  for (int i = threadIdx.x; i < N * K; i += blockDim.x) {
+    const int n = i / K, k = i - n * K;
+    sW[n * ldl + k] = g.W[(int64_t)n * g.ldw + k];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int ar = lane & 15, ak = 4 * (lane >> 4);
+  const int64_t ntiles = (g.B + 15) / 16;
+  double loss = 0.0;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wid; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t row = tile * 16 + ar;
+    const bool rok = row < g.B;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < K / 16; ++ks) {
+      const int k0 = ks * 16 + ak;
+      bf16x4 a;
+      if (NORM_IN) {
+        const float* X = (const float*)g.A;
+        unsigned short h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = k0 + j;
+          const float x = (rok && k < g.kvalid) ? (X[row * g.lda + k] - g.in_mean[k]) * g.in_rstd[k] : 0.f;
+          h[j] = f2bf(x);
+          if (rok) g.Aout[row * K + k] = h[j];
+        }
+        a = bf16x4{(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
+      } else {
+        const unsigned short* A = (const unsigned short*)g.A;
+        if (rok) {
+          const uint2 v = *(const uint2*)(A + row * g.lda + k0);
+          a = bf16x4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
+        } else {
+          a = bf16x4{0, 0, 0, 0};
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const uint2 w = *(const uint2*)(sW + (t * 16 + ar) * ldl + k0);
+        const bf16x4 b{(short)(w.x & 0xffff), (short)(w.x >> 16), (short)(w.y & 0xffff), (short)(w.y >> 16)};
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    // epilogue: lane holds rows 4(l/16) + v, column 16 t + l%16
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = t * 16 + ar;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = tile * 16 + 4 * (lane >> 4) + v;
+        if (r >= g.B) continue;
+        const float s = acc[t][v];
+        if (EPI == EPI_GELU) {
+          const float z = s + g.bias[col];
+          g.Z[r * N + col] = z;
+          g.H[r * N + col] = f2bf(gelu(z));
+        } else if (EPI == EPI_OUT) {
+          if (col < g.nvalid) g.Y[r * g.ldy + col] = g.out_mean[col] + g.out_std[col] * (s + g.bias[col]);
+        } else if (EPI == EPI_LOSS) {
+          float d = 0.f;
+          if (col < g.nvalid) {
+            const float tn = (g.T[r * g.ldt + col] - g.out_mean[col]) / g.out_std[col];
+            const float res = s + g.bias[col] - tn;
+            loss += (double)res * (double)res;
+            d = g.loss_scale * res;
+          }
+          g.H[r * N + col] = f2bf(d);
+        } else {  // EPI_DGELU
+          g.H[r * N + col] = f2bf(s * gelu_grad(g.Z[r * N + col]));
+        }
+      }
+    }
+  }
+  if (EPI == EPI_LOSS) {
+    // fixed-shape reduction of the squared residuals of this workgroup
+    for (int o = 32; o > 0; o >>= 1) loss += __shfl_down(loss, o, 64);
+    if (lane == 0) sLoss[wid] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) g.loss_part[blockIdx.x] = sLoss[0] + sLoss[1] + sLoss[2] + sLoss[3];
+  }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// part[blk] <- (sum over this workgroup's samples of G[b][n] A[b][k]) for
+// n < nvalid, k < kvalid, followed by the bias part sum_b G[b][n].  Samples
+// are staged 64 at a time in LDS (the k-index of the products); wave w owns
+// the 16-row output tiles [w TNW, (w + 1) TNW) against all TK column tiles.
+struct WgradArgs {
+  const unsigned short* G;   // [B][NG]
+  const unsigned short* A;   // [B][KA]
+  int NG, KA, nvalid, kvalid;
+  int64_t B, chunk;          // samples per workgroup (multiple of 64)
+  float* part;               // [gridDim][nvalid * kvalid + nvalid]
+};
+
+template <int TNW, int TK>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
+  extern __shared__ unsigned char smem[];
+  const int NG = g.NG, KA = 16 * TK;
+  const int ldg = NG + 4, lda = KA + 4;
+  unsigned short* sG = (unsigned short*)smem;   // [64][ldg]
+  unsigned short* sA = sG + 64 * ldg;           // [64][lda]
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int tn = NG / 16;
+  f32x4 acc[TNW][TK];
+#pragma unroll
+  for (int i = 0; i < TNW; ++i)
+#pragma unroll
+    for (int t = 0; t < TK; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;  // thread t < NG: bias column t
+  const int64_t b0 = (int64_t)blockIdx.x * g.chunk;
+  const int64_t b1 = b0 + g.chunk < g.B ? b0 + g.chunk : g.B;
+#pragma unroll 1
+  for (int64_t c = b0; c < b1; c += 64) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * NG; i += 256) {
+      const int r = i / NG, n = i - r * NG;
+      sG[r * ldg + n] = (c + r < b1) ? g.G[(c + r) * NG + n] : (unsigned short)0;
+    }
+    for (int i = threadIdx.x; i < 64 * KA; i += 256) {
+      const int r = i / KA, k = i - r * KA;
+      sA[r * lda + k] = (c + r < b1) ? g.A[(c + r) * KA + k] : (unsigned short)0;
+    }
+    __syncthreads();
+    if (threadIdx.x < NG)
+      for (int r = 0; r < 64; ++r) bsum += bf2f(sG[r * ldg + threadIdx.x]);
+#pragma unroll 1
+    for (int ks = 0; ks < 4; ++ks) {
+      // A operand: row n, k-index sample; B operand: k-index sample, column k
+      const int sb = ks * 16 + 4 * (lane >> 4);
+      bf16x4 bfr[TK];
+#pragma unroll
+      for (int t = 0; t < TK; ++t) {
+        const int col = 16 * t + (lane & 15);
+        bfr[t] = bf16x4{(short)sA[(sb + 0) * lda + col], (short)sA[(sb + 1) * lda + col],
+                        (short)sA[(sb + 2) * lda + col], (short)sA[(sb + 3) * lda + col]};
+      }
+#pragma unroll
+      for (int i = 0; i < TNW; ++i) {
+        const int nt = wid * TNW + i;
+        if (nt >= tn) break;
+        const int row = 16 * nt + (lane & 15);
+        const bf16x4 afr{(short)sG[(sb + 0) * ldg + row], (short)sG[(sb + 1) * ldg + row],
+                         (short)sG[(sb + 2) * ldg + row], (short)sG[(sb + 3) * ldg + row]};
+#pragma unroll
+        for (int t = 0; t < TK; ++t)
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(afr, bfr[t], acc[i][t], 0, 0, 0);
+      }
+    }
+  }
+  float* out = g.part + (int64_t)blockIdx.x * ((int64_t)g.nvalid * g.kvalid + g.nvalid);
+#pragma unroll
+  for (int i = 0; i < TNW; ++i) {
+    const int nt = wid * TNW + i;
+    if (nt >= tn) break;
+#pragma unroll
+    for (int t = 0; t < TK; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = 16 * nt + 4 * (lane >> 4) + v, k = 16 * t + (lane & 15);
+        if (n < g.nvalid && k < g.kvalid) out[n * g.kvalid + k] = acc[i][t][v];
+      }
+  }
+  if (threadIdx.x < g.nvalid) out[(int64_t)g.nvalid * g.kvalid + threadIdx.x] = bsum;
+}
+
+// gradient = sum over the workgroup partials, in workgroup order
+__global__ void reduce_parts_kernel(const float* __restrict__ part, int nparts, int64_t stride,
+                                    int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * stride + i];
+  out[i] = s;
+}
+
+// Adam with bias correction on the FP32 master parameters; the bfloat16 copies
+// (row-major W[N][ldw] and transposed WT[K][ldwt]) of every weight entry are
+// refreshed.  Layout of the parameter vector: W1 b1 W2 b2 W3 b3, W row-major
+// [n_out_l][n_in_l] (unpadded).
+__global__ void adam_kernel(MlpDev d, float lr, float beta1, float beta2, float eps, float bc1,
+                            float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nparams) return;
+  const float gr = d.grad[i];
+  const float m = beta1 * d.m[i] + (1.f - beta1) * gr;
+  const float v = beta2 * d.v[i] + (1.f - beta2) * gr * gr;
+  d.m[i] = m;
+  d.v[i] = v;
+  const float p = d.params[i] - lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+  d.params[i] = p;
+  // which weight entry (biases have no bfloat16 copy)
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const int64_t off = d.woff[l];
+    const int rows = d.wrows[l], cols = d.wcols[l];
+    if (i >= off && i < off + (int64_t)rows * cols) {
+      const int r = (int)((i - off) / cols), c = (int)((i - off) % cols);
+      const unsigned short h = f2bf(p);
+      d.wb[l][r * d.ldw[l] + c] = h;
+      d.wt[l][c * d.ldwt[l] + r] = h;
+    }
+  }
+}
+
+// bfloat16 copies of every weight from the master parameters (after a set)
+__global__ void refresh_bf16_kernel(MlpDev d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nparams) return;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const int64_t off = d.woff[l];
+    const int rows = d.wrows[l], cols = d.wcols[l];
+    if (i >= off && i < off + (int64_t)rows * cols) {
+      const int r = (int)((i - off) / cols), c = (int)((i - off) % cols);
+      const unsigned short h = f2bf(d.params[i]);
+      d.wb[l][r * d.ldw[l] + c] = h;
+      d.wt[l][c * d.ldwt[l] + r] = h;
+    }
+  }
+}
+
+// per-column sum and sum of squares (FP64) of rows [blk*chunk, ...): lane =
+// column (cols <= 64), waves stride over rows; one partial per workgroup
+__global__ __launch_bounds__(256) void column_stats_kernel(const float* __restrict__ A, int64_t rows,
+                                                           int64_t ld, int cols, int64_t chunk,
+                                                           double* __restrict__ part) {
+  __shared__ double s1[4][64], s2[4][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
+  double a = 0.0, b = 0.0;
+  if (lane < cols)
+    for (int64_t r = r0 + wid; r < r1; r += 4) {
+      const double x = A[r * ld + lane];
+      a += x;
+      b += x * x;
+    }
+  s1[wid][lane] = a;
+  s2[wid][lane] = b;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    part[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] =
+        s1[0][threadIdx.x] + s1[1][threadIdx.x] + s1[2][threadIdx.x] + s1[3][threadIdx.x];
+    part[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] =
+        s2[0][threadIdx.x] + s2[1][threadIdx.x] + s2[2][threadIdx.x] + s2[3][threadIdx.x];
+  }
+}
+
+// ---------------------------------------------------------------- order maps
+// One thread per element.  Samples x = [P (U - U_inf) field-major, rx ry sx sy]
+// (from_hi) or [(U_lo - U_inf), rx ry sx sy]; targets t = U_hi - I P U_hi;
+// apply: U_hi = I U_lo + Y.
+__global__ void closure_features_kernel(ClosureDev c, const double* __restrict__ U, int from_hi,
+                                        float* __restrict__ X, int64_t ldx) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= c.K) return;
+  const int nl = c.np_lo, nh = c.np_hi;
+  float* x = X + k * ldx;
+  for (int f = 0; f < 4; ++f) {
+    const double u0 = c.U_inf[f];
+    if (from_hi) {
+      const double* u = U + (k * 4 + f) * nh;
+      for (int m = 0; m < nl; ++m) {
+        double s = 0.0;
+        for (int n = 0; n < nh; ++n) s += c.P[m * nh + n] * (u[n] - u0);
+        x[f * nl + m] = (float)s;
+      }
+    } else {
+      const double* u = U + (k * 4 + f) * nl;
+      for (int m = 0; m < nl; ++m) x[f * nl + m] = (float)(u[m] - u0);
+    }
+  }
+  for (int j = 0; j < 4; ++j) x[4 * nl + j] = (float)c.geo[k * kGeoStride + j];
+}
+
+__global__ void closure_targets_kernel(ClosureDev c, const double* __restrict__ U,
+                                       float* __restrict__ T, int64_t ldt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= c.K) return;
+  const int nl = c.np_lo, nh = c.np_hi;
+  for (int f = 0; f < 4; ++f) {
+    const double* u = U + (k * 4 + f) * nh;
+    double lo[kMaxNodes];
+    for (int m = 0; m < nl; ++m) {
+      double s = 0.0;
+      for (int n = 0; n < nh; ++n) s += c.P[m * nh + n] * u[n];
+      lo[m] = s;
+    }
+    for (int n = 0; n < nh; ++n) {
+      double s = 0.0;
+      for (int m = 0; m < nl; ++m) s += c.I[n * nl + m] * lo[m];
+      T[k * ldt + f * nh + n] = (float)(u[n] - s);
+    }
+  }
+}
+
+__global__ void closure_restrict_kernel(ClosureDev c, const double* __restrict__ Uhi,
+                                        double* __restrict__ Ulo) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= c.K) return;
+  const int nl = c.np_lo, nh = c.np_hi;
+  for (int f = 0; f < 4; ++f) {
+    const double* u = Uhi + (k * 4 + f) * nh;
+    for (int m = 0; m < nl; ++m) {
+      double s = 0.0;
+      for (int n = 0; n < nh; ++n) s += c.P[m * nh + n] * u[n];
+      Ulo[(k * 4 + f) * nl + m] = s;
+    }
+  }
+}
+
+__global__ void closure_apply_kernel(ClosureDev c, const double* __restrict__ Ulo,
+                                     const float* __restrict__ Y, int64_t ldy,
+                                     double* __restrict__ Uhi) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= c.K) return;
+  const int nl = c.np_lo, nh = c.np_hi;
+  for (int f = 0; f < 4; ++f) {
+    const double* u = Ulo + (k * 4 + f) * nl;
+    for (int n = 0; n < nh; ++n) {
+      double s = 0.0;
+      for (int m = 0; m < nl; ++m) s += c.I[n * nl + m] * u[m];
+      Uhi[(k * 4 + f) * nh + n] = s + (Y ? (double)Y[k * ldy + f * nh + n] : 0.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+namespace {
+int lerr(std::string& err, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return -3;
+  }
+  return 0;
+}
+
+size_t dense_lds(int N, int K) { return ((size_t)N * (K + 4) * 2 + 15) / 16 * 16 + 4 * sizeof(double); }
+
+template <int NT, int EPI, bool NORM>
+int dense_go(const DenseArgs& a, int blocks, hipStream_t s, std::string& err) {
+  hipLaunchKernelGGL((dense_kernel<NT, EPI, NORM>), dim3(blocks), dim3(256), dense_lds(16 * NT, a.K), s, a);
+  return lerr(err, "dense kernel launch");
+}
+
+int dense(int NT, int epi, bool norm, const DenseArgs& a, int blocks, hipStream_t s, std::string& err) {
+  if (NT == 8) {
+    if (epi == EPI_GELU) return norm ? dense_go<8, EPI_GELU, true>(a, blocks, s, err)
+                                     : dense_go<8, EPI_GELU, false>(a, blocks, s, err);
+    if (epi == EPI_DGELU) return dense_go<8, EPI_DGELU, false>(a, blocks, s, err);
+  } else if (NT == 4) {
+    if (epi == EPI_OUT) return dense_go<4, EPI_OUT, false>(a, blocks, s, err);
+    if (epi == EPI_LOSS) return dense_go<4, EPI_LOSS, false>(a, blocks, s, err);
+    if (epi == EPI_GELU) return norm ? dense_go<4, EPI_GELU, true>(a, blocks, s, err)
+                                     : dense_go<4, EPI_GELU, false>(a, blocks, s, err);
+    if (epi == EPI_DGELU) return dense_go<4, EPI_DGELU, false>(a, blocks, s, err);
+  }
+  err = "dense layer shape not built";
+  return -5;
+}
+
+template <int TNW, int TK>
+int wgrad_go(const WgradArgs& a, int blocks, hipStream_t s, std::string& err) {
+  const size_t lds = (size_t)64 * (a.NG + 4) * 2 + (size_t)64 * (16 * TK + 4) * 2;
+  hipLaunchKernelGGL((wgrad_kernel<TNW, TK>), dim3(blocks), dim3(256), lds, s, a);
+  return lerr(err, "weight-gradient kernel launch");
+}
+
+int wgrad(const WgradArgs& a, int blocks, hipStream_t s, std::string& err) {
+  const int tn = a.NG / 16, tk = a.KA / 16;
+  const int tnw = (tn + 3) / 4;  // n-tiles per wave
+  if (tnw == 1) {
+    if (tk == 1) return wgrad_go<1, 1>(a, blocks, s, err);
+    if (tk == 2) return wgrad_go<1, 2>(a, blocks, s, err);
+    if (tk == 4) return wgrad_go<1, 4>(a, blocks, s, err);
+    if (tk == 8) return wgrad_go<1, 8>(a, blocks, s, err);
+  } else if (tnw == 2) {
+    if (tk == 1) return wgrad_go<2, 1>(a, blocks, s, err);
+    if (tk == 2) return wgrad_go<2, 2>(a, blocks, s, err);
+    if (tk == 4) return wgrad_go<2, 4>(a, blocks, s, err);
+    if (tk == 8) return wgrad_go<2, 8>(a, blocks, s, err);
+  }
+  err = "weight-gradient shape not built";
+  return -5;
+}
+
+int dense_blocks(int64_t B) {
+  const int64_t tiles = (B + 15) / 16;
+  const int64_t b = (tiles + 3) / 4;
+  return (int)(b < 1024 ? (b > 0 ? b : 1) : 1024);
+}
+}  // namespace
+
+int mlp_forward(const MlpDev& d, const float* X, int64_t ldx, int64_t B, float* Y, int64_t ldy,
+                void* stream, std::string& err) {
+  hipStream_t s = (hipStream_t)stream;
+  const int blocks = dense_blocks(B);
+  const int NTH = d.H / 16, NTO = d.out_pad / 16;
+  DenseArgs a{};
+  a.B = B;
+  // layer 1 (normalised inputs)
+  a.A = X; a.lda = ldx; a.in_mean = d.in_mean; a.in_rstd = d.in_rstd; a.Aout = d.Xn;
+  a.kvalid = d.n_in; a.W = d.wb[0]; a.K = d.in_pad; a.ldw = d.ldw[0]; a.bias = d.params + d.boff[0];
+  a.Z = d.Z1; a.H = d.H1;
+  int rc = dense(NTH, EPI_GELU, true, a, blocks, s, err);
+  if (rc) return rc;
+  // layer 2
+  a = DenseArgs{}; a.B = B;
+  a.A = d.H1; a.lda = d.H; a.W = d.wb[1]; a.K = d.H; a.ldw = d.ldw[1]; a.bias = d.params + d.boff[1];
+  a.Z = d.Z2; a.H = d.H2;
+  rc = dense(NTH, EPI_GELU, false, a, blocks, s, err);
+  if (rc) return rc;
+  // layer 3 (denormalised outputs)
+  a = DenseArgs{}; a.B = B;
+  a.A = d.H2; a.lda = d.H; a.W = d.wb[2]; a.K = d.H; a.ldw = d.ldw[2]; a.bias = d.params + d.boff[2];
+  a.nvalid = d.n_out; a.Y = Y; a.ldy = ldy; a.out_mean = d.out_mean; a.out_std = d.out_std;
+  return dense(NTO, EPI_OUT, false, a, blocks, s, err);
+}
+
+int mlp_backward(const MlpDev& d, const float* X, int64_t ldx, const float* T, int64_t ldt,
+                 int64_t B, void* stream, std::string& err) {
+  hipStream_t s = (hipStream_t)stream;
+  const int blocks = dense_blocks(B);
+  const int NTH = d.H / 16, NTO = d.out_pad / 16;
+  DenseArgs a{};
+  a.B = B;
+  a.A = X; a.lda = ldx; a.in_mean = d.in_mean; a.in_rstd = d.in_rstd; a.Aout = d.Xn;
+  a.kvalid = d.n_in; a.W = d.wb[0]; a.K = d.in_pad; a.ldw = d.ldw[0]; a.bias = d.params + d.boff[0];
+  a.Z = d.Z1; a.H = d.H1;
+  int rc = dense(NTH, EPI_GELU, true, a, blocks, s, err);
+  if (rc) return rc;
+  a = DenseArgs{}; a.B = B;
+  a.A = d.H1; a.lda = d.H; a.W = d.wb[1]; a.K = d.H; a.ldw = d.ldw[1]; a.bias = d.params + d.boff[1];
+  a.Z = d.Z2; a.H = d.H2;
+  if ((rc = dense(NTH, EPI_GELU, false, a, blocks, s, err))) return rc;
+  // output layer + loss: dY = 2 (y - t) / (B n_out) in normalised units
+  a = DenseArgs{}; a.B = B;
+  a.A = d.H2; a.lda = d.H; a.W = d.wb[2]; a.K = d.H; a.ldw = d.ldw[2]; a.bias = d.params + d.boff[2];
+  a.nvalid = d.n_out; a.T = T; a.ldt = ldt; a.out_mean = d.out_mean; a.out_std = d.out_std;
+  a.loss_scale = (float)(2.0 / ((double)B * d.n_out)); a.loss_part = d.loss_part; a.H = d.dY;
+  if ((rc = dense(NTO, EPI_LOSS, false, a, blocks, s, err))) return rc;
+  // dZ2 = (dY W3) * gelu'(Z2): W3^T is [H][out_pad]
+  a = DenseArgs{}; a.B = B;
+  a.A = d.dY; a.lda = d.out_pad; a.W = d.wt[2]; a.K = d.out_pad; a.ldw = d.ldwt[2];
+  a.Z = d.Z2; a.H = d.dZ2;
+  if ((rc = dense(NTH, EPI_DGELU, false, a, blocks, s, err))) return rc;
+  // dZ1 = (dZ2 W2) * gelu'(Z1)
+  a = DenseArgs{}; a.B = B;
+  a.A = d.dZ2; a.lda = d.H; a.W = d.wt[1]; a.K = d.H; a.ldw = d.ldwt[1];
+  a.Z = d.Z1; a.H = d.dZ1;
+  if ((rc = dense(NTH, EPI_DGELU, false, a, blocks, s, err))) return rc;
+  // weight gradients: partials per workgroup, then a fixed-order sum
+  const int64_t chunk = ((B + d.nparts - 1) / d.nparts + 63) / 64 * 64;
+  const int parts = (int)((B + chunk - 1) / chunk);
+  struct L { const unsigned short* G; int NG; int nv; const unsigned short* A; int KA; int kv; int64_t off; };
+  const L layers[3] = {{d.dZ1, d.H, d.H, d.Xn, d.in_pad, d.n_in, d.woff[0]},
+                       {d.dZ2, d.H, d.H, d.H1, d.H, d.H, d.woff[1]},
+                       {d.dY, d.out_pad, d.n_out, d.H2, d.H, d.H, d.woff[2]}};
+  for (int l = 0; l < 3; ++l) {
+    WgradArgs w{};
+    w.G = layers[l].G; w.NG = layers[l].NG; w.nvalid = layers[l].nv;
+    w.A = layers[l].A; w.KA = layers[l].KA; w.kvalid = layers[l].kv;
+    w.B = B; w.chunk = chunk; w.part = d.part;
+    if ((rc = wgrad(w, parts, s, err))) return rc;
+    const int64_t n = (int64_t)w.nvalid * w.kvalid + w.nvalid;  // W then b: contiguous
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const float*)d.part, parts, n, n, d.grad + layers[l].off);
+    if ((rc = lerr(err, "reduce kernel launch"))) return rc;
+  }
+  return 0;
+}
+
+int mlp_adam(const MlpDev& d, float lr, float beta1, float beta2, float eps, int step, void* stream,
+             std::string& err) {
+  const float bc1 = 1.f - powf(beta1, (float)step), bc2 = 1.f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((d.nparams + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, d, lr, beta1, beta2, eps, bc1, bc2);
+  return lerr(err, "adam kernel launch");
+}
+
+int mlp_refresh_bf16(const MlpDev& d, void* stream, std::string& err) {
+  hipLaunchKernelGGL(refresh_bf16_kernel, dim3((unsigned)((d.nparams + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, d);
+  return lerr(err, "refresh kernel launch");
+}
+
+int column_stats(const float* A, int64_t rows, int64_t ld, int cols, double* part, int nparts,
+                 void* stream, std::string& err) {
+  const int64_t chunk = (rows + nparts - 1) / nparts;
+  hipLaunchKernelGGL(column_stats_kernel, dim3(nparts), dim3(256), 0, (hipStream_t)stream, A, rows,
+                     ld, cols, chunk > 0 ? chunk : 1, part);
+  return lerr(err, "column statistics kernel launch");
+}
+
+int closure_features(const ClosureDev& c, const double* U, int from_hi, float* X, int64_t ldx,
+                     void* stream, std::string& err) {
+  hipLaunchKernelGGL(closure_features_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+                     (hipStream_t)stream, c, U, from_hi, X, ldx);
+  return lerr(err, "closure features kernel launch");
+}
+
+int closure_targets(const ClosureDev& c, const double* U, float* T, int64_t ldt, void* stream,
+                    std::string& err) {
+  hipLaunchKernelGGL(closure_targets_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+                     (hipStream_t)stream, c, U, T, ldt);
+  return lerr(err, "closure targets kernel launch");
+}
+
+int closure_restrict(const ClosureDev& c, const double* Uhi, double* Ulo, void* stream,
+                     std::string& err) {
+  hipLaunchKernelGGL(closure_restrict_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+                     (hipStream_t)stream, c, Uhi, Ulo);
+  return lerr(err, "closure restrict kernel launch");
+}
+
+int closure_apply(const ClosureDev& c, const double* Ulo, const float* Y, int64_t ldy, double* Uhi,
+                  void* stream, std::string& err) {
+  hipLaunchKernelGGL(closure_apply_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+                     (hipStream_t)stream, c, Ulo, Y, ldy, Uhi);
+  return lerr(err, "closure apply kernel launch");
+}
+
+}  // namespace dgmi

@@ -188,3 +188,19 @@ def test_tuning_and_batch_error_paths():
         assert e.value.code == L.DG_EINVAL
     finally:
         L.dg_destroy(h)
+
+
+def test_mlp_and_closure_argument_checks():
+    from paper_2508_17917_amd import _lib as L
+    for bad in ((0, 128, 60), (65, 128, 60), (28, 96, 60), (28, 128, 65)):
+        with pytest.raises(L.DGError) as e:
+            L.dg_mlp_create(*bad, 16)
+        assert e.value.code == L.DG_EUNSUPPORTED
+    assert "n_hidden" in L.dg_mlp_last_error(None)
+    h = L.dg_create(2)
+    try:
+        with pytest.raises(L.DGError) as e:
+            L.dg_closure_create(h, h)
+        assert e.value.code == L.DG_ESTATE
+    finally:
+        L.dg_destroy(h)

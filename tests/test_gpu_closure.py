@@ -1,0 +1,278 @@
+"""GPU tests of the learned closure: order-change maps and samples against the
+oracle, the bfloat16 network's forward pass, gradients and Adam step against
+the FP64 oracle network, and the gain of a trained closure over plain
+interpolation on a cylinder flow.
+
+Network tolerance.  The GPU rounds every matrix-core operand to bfloat16
+(unit roundoff u = 2^-9) and accumulates in FP32; the oracle is given the same
+bfloat16 weights and normalised inputs and computes everything else in FP64.
+What remains is the rounding of the activations and back-propagated
+quantities fed to the next product: about 2u per product, three products
+forward and five backward, so the normwise relative error is bounded by
+about 6u ~ 1.2e-2 forward and 10u ~ 2e-2 for the gradients; the bounds below
+are 1.5e-2 and 3e-2.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from oracle import closure as OC
+from tests.oracle_helpers import build
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print("[gpu-case] " + msg, flush=True)
+
+
+def _to_dev(torch, U):
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(U, (2, 0, 1)))).cuda()
+
+
+def _from_dev(T):
+    return np.transpose(T.cpu().numpy(), (1, 2, 0))
+
+
+def _solver(mesh, p, phys):
+    from paper_2508_17917_amd import Solver
+    return Solver(p, mesh, gamma=phys.gamma, Pr=phys.Pr, mu=phys.mu, theta=phys.theta,
+                  penalty_mode=phys.penalty_mode, C_pen=phys.C_pen, U_inf=phys.U_inf)
+
+
+def test_order_maps_and_samples_match_oracle():
+    torch = _torch()
+    from paper_2508_17917_amd.closure import Closure
+    mesh = mg.ogrid(10, 5, 0.5, 4.0, 1.3)
+    dg4 = build(mesh, 4, mu=2e-3, penalty_mode=0, C_pen=1.0)
+    lo, hi = _solver(mesh, 2, dg4.phys), _solver(mesh, 4, dg4.phys)
+    _say("closure maps K=%d" % hi.K)
+    cl = Closure(lo, hi, max_batch=4096)
+    U4 = mg.noisy_free_stream((4, 15, hi.K), dg4.phys.U_inf, np.random.default_rng(2), amp=0.05)
+    P, I = OC.restriction(4, 2), OC.interpolation(2, 4)
+    geo = np.stack([dg4.mesh.rx, dg4.mesh.ry, dg4.mesh.sx, dg4.mesh.sy], axis=1)
+    U4d = _to_dev(torch, U4)
+    X = cl.features(U4d, True).cpu().numpy()
+    T = cl.targets(U4d).cpu().numpy()
+    want_X = OC.features(U4, geo, dg4.phys.U_inf, P)
+    want_T = OC.targets(U4, P, I)
+    assert np.abs(X - want_X).max() <= 1e-6 * np.abs(want_X).max()
+    assert np.abs(T - want_T).max() <= 1e-6 * np.abs(U4).max()
+    U2 = cl.restrict(U4d)
+    want_U2 = np.einsum("mn,cnk->cmk", P, U4)
+    assert np.abs(_from_dev(U2) - want_U2).max() <= 1e-13 * np.abs(U4).max()
+    X2 = cl.features(U2, False).cpu().numpy()
+    assert np.abs(X2 - OC.features(want_U2, geo, dg4.phys.U_inf)).max() <= 1e-6 * np.abs(want_X).max()
+    # interpolation, and interpolation plus the exact targets gives back U4
+    Ui = _from_dev(cl.interpolate(U2))
+    assert np.abs(Ui - np.einsum("mn,cnk->cmk", I, want_U2)).max() <= 1e-13 * np.abs(U4).max()
+    Tt = torch.from_numpy(np.ascontiguousarray(want_T, dtype=np.float32)).cuda()
+    out = hi.empty_state()
+    from paper_2508_17917_amd import _lib as L
+    L.dg_closure_apply(cl.c, U2, Tt, out)
+    assert np.abs(_from_dev(out) - U4).max() <= 1e-6 * np.abs(U4).max()
+    cl.close()
+    lo.close()
+    hi.close()
+
+
+def _net_case(seed, B=300):
+    rng = np.random.default_rng(seed)
+    params = mg.mlp_init(rng, 28, 128, 60)
+    X = (rng.standard_normal((B, 28)) * 0.3 + 0.1).astype(np.float32)
+    T = (rng.standard_normal((B, 60)) * 0.02 - 0.01).astype(np.float32)
+    norm = [(0.1 + 0.05 * rng.standard_normal(28)).astype(np.float32),
+            (0.3 * np.exp(0.2 * rng.standard_normal(28))).astype(np.float32),
+            (-0.01 + 0.005 * rng.standard_normal(60)).astype(np.float32),
+            (0.02 * np.exp(0.2 * rng.standard_normal(60))).astype(np.float32)]
+    return params, X, T, norm
+
+
+def _unpack(p, n_in=28, h=128, n_out=60):
+    out, o = {}, 0
+    for name, shape in (("W1", (h, n_in)), ("b1", (h,)), ("W2", (h, h)), ("b2", (h,)),
+                        ("W3", (n_out, h)), ("b3", (n_out,))):
+        n = int(np.prod(shape))
+        out[name] = np.asarray(p[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return out
+
+
+def _oracle_inputs(params, X, T, norm):
+    """Parameters with bfloat16 weights, bfloat16 normalised inputs, and
+    normalised targets, as the GPU sees them."""
+    q = _unpack(params)
+    for k in ("W1", "W2", "W3"):
+        q[k] = OC.round_bf16(q[k].astype(np.float32)).astype(np.float64)
+    rstd = (np.float32(1.0) / norm[1]).astype(np.float32)
+    Xn = OC.round_bf16(((X - norm[0]) * rstd).astype(np.float32)).astype(np.float64)
+    Tn = ((T.astype(np.float64) - norm[2]) / norm[3])
+    return q, Xn, Tn
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_network_forward_backward_adam_match_oracle():
+    torch = _torch()
+    from paper_2508_17917_amd import _lib as L
+    params, X, T, norm = _net_case(1)
+    m = L.dg_mlp_create(28, 128, 60, 512)
+    L.dg_mlp_set_params(m, params)
+    L.dg_mlp_set_normalization(m, *norm)
+    Xd = torch.from_numpy(X).cuda()
+    Td = torch.from_numpy(T).cuda()
+    Y = torch.zeros((X.shape[0], 60), dtype=torch.float32, device="cuda")
+    _say("mlp forward B=%d" % X.shape[0])
+    L.dg_mlp_forward(m, Xd, Y)
+    q, Xn, Tn = _oracle_inputs(params, X, T, norm)
+    Yo, _ = OC.forward(q, Xn)
+    Yn = (Y.cpu().numpy().astype(np.float64) - norm[2]) / norm[3]
+    e = _rel(Yn, Yo)
+    _say("forward rel err %.3e" % e)
+    assert e <= 1.5e-2
+    _say("mlp backward")
+    loss = L.dg_mlp_backward(m, Xd, Td)
+    lo, go = OC.loss_and_grads(q, Xn, Tn)
+    assert abs(loss - lo) <= 1.5e-2 * lo
+    g = _unpack(L.dg_mlp_get_grad(m))
+    for k in go:
+        e = _rel(g[k], go[k])
+        _say("grad %s rel err %.3e" % (k, e))
+        assert e <= 3e-2, k
+    # Adam, two steps, against the oracle's update applied to the GPU's gradients
+    p0 = _unpack(L.dg_mlp_get_params(m))
+    z = {k: np.zeros_like(v) for k, v in p0.items()}
+    L.dg_mlp_adam(m, 1e-3)
+    torch.cuda.synchronize()
+    p1, m1, v1 = OC.adam_step(p0, g, z, z, 1, lr=1e-3)
+    got = _unpack(L.dg_mlp_get_params(m))
+    for k in p1:
+        assert np.abs(got[k] - p1[k]).max() <= 1e-6 * np.abs(p1[k]).max() + 1e-8, k
+    L.dg_mlp_backward(m, Xd, Td, want_loss=False)
+    g2 = _unpack(L.dg_mlp_get_grad(m))
+    L.dg_mlp_adam(m, 1e-3)
+    p2, _, _ = OC.adam_step(got, g2, m1, v1, 2, lr=1e-3)
+    got2 = _unpack(L.dg_mlp_get_params(m))
+    for k in p2:
+        assert np.abs(got2[k] - p2[k]).max() <= 1e-6 * np.abs(p2[k]).max() + 1e-8, k
+    # forward/backward are reproducible
+    L.dg_mlp_backward(m, Xd, Td, want_loss=False)
+    ga = L.dg_mlp_get_grad(m)
+    L.dg_mlp_backward(m, Xd, Td, want_loss=False)
+    assert np.array_equal(ga, L.dg_mlp_get_grad(m))
+    L.dg_mlp_destroy(m)
+
+
+def test_training_fits_a_smooth_map():
+    """Adam on the GPU drives the loss of a smooth regression down."""
+    torch = _torch()
+    from paper_2508_17917_amd import _lib as L
+    rng = np.random.default_rng(4)
+    n = 8192
+    X = rng.uniform(-1, 1, (n, 28)).astype(np.float32)
+    A = rng.standard_normal((28, 60)) / np.sqrt(28)
+    T = np.tanh(X @ A).astype(np.float32) + 0.1 * np.sin(3 * X[:, :1]).astype(np.float32)
+    m = L.dg_mlp_create(28, 128, 60, 1024)
+    L.dg_mlp_set_params(m, mg.mlp_init(rng, 28, 128, 60))
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    xm, xs = L.dg_column_stats(Xd)
+    tm, ts = L.dg_column_stats(Td)
+    assert np.abs(xm - X.mean(0)).max() < 1e-6 and np.abs(xs - X.std(0)).max() < 1e-5
+    L.dg_mlp_set_normalization(m, xm, xs, tm, ts)
+    _say("mlp training, 400 steps")
+    first = L.dg_mlp_backward(m, Xd[:1024], Td[:1024])
+    for it in range(400):
+        b0 = (it % 8) * 1024
+        L.dg_mlp_backward(m, Xd[b0:b0 + 1024], Td[b0:b0 + 1024], want_loss=False)
+        L.dg_mlp_adam(m, 2e-3)
+    last = L.dg_mlp_backward(m, Xd[:1024], Td[:1024])
+    _say("loss %.4e -> %.4e" % (first, last))
+    assert last < 0.05 * first
+    L.dg_mlp_destroy(m)
+
+
+def _run(solver, U, K1, dt, steps):
+    for _ in range(steps):
+        solver.rk_step(U, K1, dt)
+    return U
+
+
+def test_closure_gain_over_interpolation():
+    """Train on order-4 snapshots of impulsively started cylinder flows at
+    Re = 70, 100, 150; at Re = 120, restrict the order-4 state to order 2,
+    advance both, and compare the corrected and the plainly interpolated
+    order-2 states with the order-4 one (mass-matrix L2 norm over the mesh)."""
+    torch = _torch()
+    from paper_2508_17917_amd import Solver
+    from paper_2508_17917_amd.closure import Closure
+    mesh = mg.ogrid(32, 16, 0.5, 8.0, 1.15)
+    dt = 5e-5  # inside the viscous limit of the 0.13 wall cell at p = 4 down to Re = 70
+
+    def pair(Re):
+        ph = mg.physics_params(Re=Re, M=0.2)
+        mk = lambda p: Solver(p, mesh, gamma=ph["gamma"], Pr=ph["Pr"], mu=ph["mu"], theta=1.0,
+                              penalty_mode=0, C_pen=1.0, U_inf=ph["U_inf"])
+        return mk(2), mk(4), ph["U_inf"]
+
+    Xs, Ts = [], []
+    cl = None
+    for Re in (70.0, 100.0, 150.0):
+        lo, hi, U_inf = pair(Re)
+        if cl is None:
+            cl = Closure(lo, hi, max_batch=4096,
+                         params=mg.mlp_init(np.random.default_rng(9), 28, 128, 60))
+        else:
+            cl.rebind(lo, hi)
+        U = _to_dev(torch, np.broadcast_to(U_inf[:, None, None], (4, 15, hi.K)).copy())
+        K1 = torch.zeros_like(U)
+        _say("closure snapshots Re=%g K=%d" % (Re, hi.K))
+        for snap in range(24):
+            _run(hi, U, K1, dt, 40)
+            assert bool(torch.isfinite(U).all())
+            X, T = cl.samples(U)
+            Xs.append(X.clone())
+            Ts.append(T.clone())
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    cl.fit_normalization(X, T)
+    losses = cl.train(X, T, epochs=40, batch=1024, lr=1e-3, seed=1)
+    _say("closure training loss %.4e -> %.4e over %d steps" % (losses[0], losses[-1], len(losses)))
+    assert losses[-1] < 0.5 * losses[0]
+    # evaluation at Re = 120
+    lo, hi, U_inf = pair(120.0)
+    cl.rebind(lo, hi)
+    U4 = _to_dev(torch, np.broadcast_to(U_inf[:, None, None], (4, 15, hi.K)).copy())
+    K14 = torch.zeros_like(U4)
+    _run(hi, U4, K14, dt, 300)
+    U2 = cl.restrict(U4)
+    K12 = torch.zeros_like(U2)
+    M4 = hi.table("M").reshape(15, 15)
+    geo = hi.table("geo").reshape(hi.K, 16)
+    J = 1.0 / (geo[:, 0] * geo[:, 3] - geo[:, 1] * geo[:, 2])
+
+    def norm(D):
+        d = D.cpu().numpy()
+        return float(np.sqrt(np.einsum("kcn,nm,kcm,k->", d, M4, d, J)))
+
+    ratios = []
+    for seg in range(3):
+        base = norm(cl.interpolate(U2) - U4)
+        corr = norm(cl.correct(U2) - U4)
+        ratios.append(corr / base)
+        _say("after %d steps: interpolation err %.4e, closure err %.4e, ratio %.3f, fallback %s"
+             % (10 * seg, base, corr, corr / base, cl.needs_fallback(U2)))
+        _run(hi, U4, K14, dt, 10)
+        _run(lo, U2, K12, dt, 10)
+    assert ratios[0] < 0.7 and max(ratios) < 0.95, ratios
+    cl.close()
+    lo.close()
+    hi.close()
