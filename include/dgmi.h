@@ -143,6 +143,15 @@ int dg_rhs(dg_ctx* ctx, const double* U, double* R, const double v_w[2], void* s
 int dg_rk_step(dg_ctx* ctx, double* U, double* K1, double dt, const double v_w[2],
                void* stream);
 
+/* nsteps RK steps (as dg_rk_step, v_w fixed), with the wall force (as
+ * dg_force_device) after each step written to force_dev[3 n .. 3 n + 2]
+ * when force_dev (device, 3 nsteps doubles) is not NULL.  The state
+ * alternates between U and the scratch buffer from step to step, so it is
+ * copied back into U only when nsteps is odd (dg_rk_step copies every
+ * step).  Asynchronous on `stream`. */
+int dg_rk_steps(dg_ctx* ctx, double* U, double* K1, int nsteps, double dt, const double v_w[2],
+                double* force_dev, void* stream);
+
 /* One RK stage: K1 <- a K1 + dt R(U_in); U_out <- U_in + b K1.  U_in and
  * U_out must not alias (neighbours read U_in).  Asynchronous. */
 int dg_rk_stage(dg_ctx* ctx, const double* U_in, double* U_out, double* K1,

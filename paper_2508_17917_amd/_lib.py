@@ -42,6 +42,7 @@ SIGNATURES = {
     "dg_get_nodes": (_I, [_P, _DP, _DP]),
     "dg_rhs": (_I, [_P, _P, _P, _DP, _P]),
     "dg_rk_step": (_I, [_P, _P, _P, _D, _DP, _P]),
+    "dg_rk_steps": (_I, [_P, _P, _P, _I, _D, _DP, _P, _P]),
     "dg_rk_stage": (_I, [_P, _P, _P, _P, _D, _D, _D, _DP, _P]),
     "dg_force": (_I, [_P, _P, _DP, _DP, _P]),
     "dg_force_device": (_I, [_P, _P, _DP, _P, _P]),
@@ -215,6 +216,12 @@ def dg_rhs(h, U, R, v_w=(0.0, 0.0), stream=None):
 def dg_rk_step(h, U, K1, dt, v_w=(0.0, 0.0), stream=None):
     vw = _vw(v_w)
     return _check(load().dg_rk_step(h, _ptr(U), _ptr(K1), float(dt), _dp(vw), _stream(stream)), h)
+
+
+def dg_rk_steps(h, U, K1, nsteps, dt, v_w=(0.0, 0.0), force=None, stream=None):
+    vw = _vw(v_w)
+    return _check(load().dg_rk_steps(h, _ptr(U), _ptr(K1), int(nsteps), float(dt), _dp(vw),
+                                     _ptr(force), _stream(stream)), h)
 
 
 def dg_rk_stage(h, U_in, U_out, K1, a, b, dt, v_w=(0.0, 0.0), stream=None):

@@ -281,6 +281,48 @@ int dg_rk_step(dg_ctx* c, double* U, double* K1, double dt, const double v_w[2],
   return DG_OK;
 }
 
+int dg_rk_steps(dg_ctx* c, double* U, double* K1, int nsteps, double dt, const double v_w[2],
+                double* force_dev, void* stream) {
+  int rc = check_ready(c);
+  if (rc != DG_OK) return rc;
+  if (!U || !K1 || U == K1) return fail(c, DG_EINVAL, "U and K1 must be distinct device arrays");
+  if (nsteps < 0) return fail(c, DG_EINVAL, "nsteps must be non-negative");
+  if (!std::isfinite(dt)) return fail(c, DG_EINVAL, "dt is not finite");
+  std::string err;
+  const dgmi::DeviceTables t = tables(c);
+  const dgmi::KernelPhysics k = kphys(c, v_w);
+  const bool walls = !c->mesh.wall_faces.empty();
+  // the state alternates between U and the scratch buffer: five stages per
+  // step, so it sits in the other buffer after every step
+  double* bufs[2] = {U, c->d_scratch};
+  int cur = 0;
+  for (int n = 0; n < nsteps; ++n) {
+    for (int i = 0; i < 5; ++i) {
+      rc = dgmi::launch_stage(c->N, c->precision, c->tune, t, k, bufs[(cur + i) & 1],
+                              bufs[(cur + i + 1) & 1], K1, dgmi::kRkA[i], dgmi::kRkB[i], dt, 0,
+                              stream, err);
+      if (rc != 0) return fail(c, rc, err);
+    }
+    cur ^= 1;
+    if (force_dev) {
+      if (walls) {
+        rc = dgmi::launch_force(c->N, t, k, bufs[cur], force_dev + 3 * (int64_t)n, stream, err);
+        if (rc != 0) return fail(c, rc, err);
+      } else {
+        hipError_t e = hipMemsetAsync(force_dev + 3 * (int64_t)n, 0, 3 * sizeof(double),
+                                      (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+      }
+    }
+  }
+  if (cur == 1) {
+    const size_t bytes = (size_t)c->K * 4 * c->ref.Np * sizeof(double);
+    hipError_t e = hipMemcpyAsync(U, c->d_scratch, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  }
+  return DG_OK;
+}
+
 int dg_force(dg_ctx* c, const double* U, const double v_w[2], double out[3], void* stream) {
   int rc = check_ready(c);
   if (rc != DG_OK) return rc;

@@ -696,15 +696,17 @@ batch_stage_kernel(const BatchItem* __restrict__ items, const BatchStep* __restr
   }
 }
 
-// Wall force: one workgroup walks the wall faces in a fixed order; each
-// thread accumulates its share, then a fixed-shape tree reduction in LDS.
+// Wall force: one workgroup of 1024 threads walks the wall face nodes in a
+// fixed order (16 waves on one CU hide the latency of the per-node loads);
+// each thread accumulates its share, then a fixed-shape tree reduction in LDS.
+constexpr int kForceThreads = 1024;
 template <int N>
-__global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysics ph,
+__global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, KernelPhysics ph,
                                                     const double* __restrict__ U,
                                                     double* __restrict__ out) {
   using O = Order<N, double>;
   constexpr int Np = O::Np, Nfp = O::Nfp, S = 4 * Np;
-  __shared__ double red[3][256];
+  __shared__ double red[3][kForceThreads];
   Gas<double> gas;
   gas.gamma = ph.gamma;
   gas.gm1 = ph.gamma - 1.0;
@@ -757,7 +759,7 @@ __global__ __launch_bounds__(256) void force_kernel(DeviceTables t, KernelPhysic
   red[1][threadIdx.x] = fy;
   red[2][threadIdx.x] = mz;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = kForceThreads / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
       for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
     __syncthreads();
@@ -869,7 +871,7 @@ int launch_stage_n(int form, const StageTuning& tune, const DeviceTables& t,
 template <int N>
 int launch_force_n(const DeviceTables& t, const KernelPhysics& ph, const double* U, double* out,
                    hipStream_t s, std::string& err) {
-  hipLaunchKernelGGL(force_kernel<N>, dim3(1), dim3(256), 0, s, t, ph, U, out);
+  hipLaunchKernelGGL(force_kernel<N>, dim3(1), dim3(kForceThreads), 0, s, t, ph, U, out);
   return launch_error(err, "force kernel launch");
 }
 

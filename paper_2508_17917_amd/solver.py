@@ -58,6 +58,12 @@ class Solver:
         L.dg_rk_step(self.h, U, K1, dt, v_w, stream)
         return U
 
+    def rk_steps(self, U, K1, nsteps, dt, v_w=(0.0, 0.0), force=None, stream=None):
+        """nsteps steps; with `force` (device float64, 3 nsteps) the wall force
+        after every step."""
+        L.dg_rk_steps(self.h, U, K1, nsteps, dt, v_w, force, stream)
+        return U
+
     def rk_stage(self, U_in, U_out, K1, a, b, dt, v_w=(0.0, 0.0), stream=None):
         L.dg_rk_stage(self.h, U_in, U_out, K1, a, b, dt, v_w, stream)
 

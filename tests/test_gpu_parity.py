@@ -181,3 +181,28 @@ def test_rhs_parity_cylinder20k_full_size():
     torch.cuda.synchronize()
     _check(_from_dev(R), want, what="cylinder20k", terms=term_scale(parts))
     s.close()
+
+
+def test_rk_steps_equal_repeated_steps():
+    """The multi-step call (state alternating between two buffers, force
+    after every step) gives the bits of repeated single steps, for an even
+    and an odd step count."""
+    torch = _torch()
+    mesh = mg.ogrid(12, 5, 0.5, 6.0, 1.3)
+    dg = build(mesh, 4, mu=2e-3, penalty_mode=0, C_pen=1.0)
+    U = _state(dg, "noise", 3)
+    s = _solver(mesh, 4, dg.phys)
+    vw = (0.0, 0.01)
+    for n in (2, 3):
+        _say("rk_steps n=%d" % n)
+        Ua, Ka = _to_dev(torch, U), torch.zeros(s.K, 4, s.Np, dtype=torch.float64, device="cuda")
+        Fa = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+        s.rk_steps(Ua, Ka, n, 1e-4, v_w=vw, force=Fa)
+        Ub, Kb = _to_dev(torch, U), torch.zeros_like(Ka)
+        Fb = torch.zeros_like(Fa)
+        for i in range(n):
+            s.rk_step(Ub, Kb, 1e-4, v_w=vw)
+            s.force_device(Ub, Fb[i], v_w=vw)
+        torch.cuda.synchronize()
+        assert torch.equal(Ua, Ub) and torch.equal(Fa, Fb)
+    s.close()
