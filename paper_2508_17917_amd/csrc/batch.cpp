@@ -85,7 +85,7 @@ double tile_cost(int p) { return (double)np_of(p) * (np_of(p) + 3 * (p + 1)); }
 // Workgroups for each group and the launches of one stage, for the current
 // shape.  Group block counts are multiples of 8 (one tile range per XCD).
 int plan(dg_batch* b) {
-  const int W = b->waves ? b->waves : (b->form == 2 ? 4 : 2);
+  const int W = b->waves ? b->waves : 4;
   if (W != 2 && W != 4) return bfail(b, DG_EINVAL, "waves per workgroup must be 2 or 4");
   b->plan_waves = W;
   const int resident = dgmi::batch_resident_blocks(b->form, W);

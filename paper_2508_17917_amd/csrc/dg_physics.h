@@ -43,6 +43,34 @@ __device__ __forceinline__ float rcp_approx<float>(float x) {
   return __builtin_amdgcn_rcpf(x);
 }
 
+// Reciprocal and square root at the accuracy each real type needs: binary64
+// from the hardware reciprocal estimate refined by two Newton steps (within
+// about 1 ulp: far inside the FP64 parity bound, and cheaper than the
+// correctly rounded division); binary32 with the single hardware
+// instructions (1 ulp).
+template <typename T>
+__device__ __forceinline__ T rcp(T x);
+template <>
+__device__ __forceinline__ double rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <typename T>
+__device__ __forceinline__ T root(T x);
+template <>
+__device__ __forceinline__ double root<double>(double x) {
+  return sqrt(x);
+}
+template <>
+__device__ __forceinline__ float root<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+
 // Primitive view of one face state.  rho, u, v, p, H are the full state
 // (Roe averages, eigenvalues); jr, ju, jv, jp are what jumps are taken of:
 // the full values in the plain form, the perturbations in the perturbation
@@ -58,7 +86,7 @@ template <typename T>
 __device__ __forceinline__ Prim<T> prim_plain(const T U[4], T gm1) {
   Prim<T> s;
   s.rho = U[0];
-  s.ir = T(1) / U[0];
+  s.ir = rcp(U[0]);
   s.u = U[1] * s.ir;
   s.v = U[2] * s.ir;
   s.p = gm1 * (U[3] - T(0.5) * (U[1] * s.u + U[2] * s.v));
@@ -76,7 +104,7 @@ __device__ __forceinline__ Prim<T> prim_pert(const T Uf[4], const T Ud[4], const
                                              T gm1) {
   Prim<T> s;
   s.rho = Uf[0];
-  s.ir = T(1) / Uf[0];
+  s.ir = rcp(Uf[0]);
   s.u = Uf[1] * s.ir;
   s.v = Uf[2] * s.ir;
   // u' = (m' - rho' u0) / rho; kinetic-energy perturbation from products of
@@ -129,7 +157,7 @@ struct VState {
 template <typename T>
 __device__ __forceinline__ VState<T> vstate(const Gas<T>& g, const T U[4]) {
   VState<T> s;
-  s.ir = T(1) / U[0];
+  s.ir = rcp(U[0]);
   s.v1 = U[1] * s.ir;
   s.v2 = U[2] * s.ir;
   s.m = g.mu * s.ir;
@@ -243,7 +271,7 @@ __device__ __forceinline__ T normal_diffusion_norm(const Gas<T>& g, const VState
   const T c1 = s00 * s11 + s00 * s22 + s11 * s22 - s01 * s01 - s02 * s02 - s12 * s12;
   const T c0 = s00 * (s11 * s22 - s12 * s12) - s01 * (s01 * s22 - s12 * s02) +
                s02 * (s01 * s12 - s11 * s02);
-  T lam = sqrt(s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12));
+  T lam = root(s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12));
   T step = T(0);
 #pragma unroll
   for (int it = 0; it < 5; ++it) {
@@ -259,7 +287,7 @@ __device__ __forceinline__ T normal_diffusion_norm(const Gas<T>& g, const VState
   if (!(fabs(step) <= tol * lam))
     lam = (T)sym3_lambda_max_trig((double)s00, (double)s11, (double)s22, (double)s01, (double)s02,
                                   (double)s12);
-  return st.m * sqrt(lam > T(0) ? lam : T(0));
+  return st.m * root(lam > T(0) ? lam : T(0));
 }
 
 // Roe flux: mean of the two normal fluxes FL (own, "+") and FR (other, "-")
@@ -269,20 +297,20 @@ __device__ __forceinline__ T normal_diffusion_norm(const Gas<T>& g, const VState
 template <typename T>
 __device__ __forceinline__ void roe_flux(const Prim<T>& sl, const Prim<T>& sr, const T FL[4],
                                          const T FR[4], T nx, T ny, T vwn, T gm1, T F[4]) {
-  const T ql = sqrt(sl.rho), qr = sqrt(sr.rho);
-  const T iw = T(1) / (ql + qr);
+  const T ql = root(sl.rho), qr = root(sr.rho);
+  const T iw = rcp(ql + qr);
   const T rt = ql * qr;
   const T ut = (ql * sl.u + qr * sr.u) * iw, vt = (ql * sl.v + qr * sr.v) * iw;
   const T ht = (ql * sl.H + qr * sr.H) * iw;
   const T c2 = gm1 * (ht - T(0.5) * (ut * ut + vt * vt));
-  const T ct = sqrt(c2);
+  const T ct = root(c2);
   const T qn = ut * nx + vt * ny, qt = -ut * ny + vt * nx;
   // jumps taken as (other - own)
   const T dr = sr.jr - sl.jr, dp = sr.jp - sl.jp;
   const T du = sr.ju - sl.ju, dv = sr.jv - sl.jv;
   const T dqn = du * nx + dv * ny;
   const T dqt = -du * ny + dv * nx;
-  const T ic2 = T(1) / c2;
+  const T ic2 = rcp(c2);
   const T a1 = T(0.5) * (dp - rt * ct * dqn) * ic2;
   const T a2 = dr - dp * ic2;
   const T a3 = rt * dqt;

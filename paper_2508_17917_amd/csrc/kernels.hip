@@ -47,7 +47,10 @@ struct Order {
   static constexpr int FIT = (4 * NF + 63) / 64; // face items per lane
   // default waves per workgroup (each wave owns its own tiles; the workgroup
   // shares the operator fragments)
-  static constexpr int WAVES = (N <= 4 || sizeof(T) == 4) ? 4 : 2;
+  // (4 measured fastest for every order and form on MI355X: the fragments
+  // are shared by more waves, and at p >= 5 in FP64 LDS and registers allow
+  // one workgroup per CU either way)
+  static constexpr int WAVES = 4;
   // waves per SIMD the register allocation must allow: 3 for FP32 at p <= 4
   // (a few spills, measured faster than 2 and than 4), else 2
   static constexpr int MIN_WAVES_EU = (sizeof(T) == 4 && N <= 4) ? 3 : 2;
@@ -262,54 +265,55 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     uinf_q[q] = (PERT && lr_ok[q]) ? u_c : 0.0;
   }
 
-  for (int64_t tile = tile0; tile < tile_end; tile += stride) {
-    const int64_t e0 = tile * 4;
-    const int nel = (int)((K - e0) < 4 ? (K - e0) : 4);
-    wave_sync();
-    // ---- own states, geometry, connectivity.  Lane l owns values r = l + 64 q
-    // of every element block, so addresses are a per-lane constant plus a
-    // wave-uniform base, and every load is issued before the first use.
-    double ru[4][NQ];
+  // The global loads of a tile are software-pipelined: a tile's own states,
+  // geometry and connectivity are issued at the end of the previous tile
+  // (before its final matrix-core phase), and its neighbour states before
+  // its volume phase, so that their latency overlaps computation.
+  constexpr int NB1 = NQ == 1 ? 12 : 6;  // neighbour blocks issued before the volume phase
+  double ru[4][NQ];
+  double rg = 0.0;
+  int rc = 0;
+  auto load_own = [&](int64_t tl) {
+    const int64_t b = tl * 4;
+    const int ne = (int)((K - b) < 4 ? (K - b) : 4);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        ru[e][q] = (lr_ok[q] && e < nel) ? Uin[(e0 + e) * S + lane + 64 * q] : 0.0;
-    const double rg = (lane < nel * kGeoStride) ? t.geo[e0 * kGeoStride + lane] : 0.0;
-    const int rc = (lane < nel * 3) ? t.conn[e0 * 3 + lane] : 0;
-    if (lane < nel * 3) sConn[lane] = rc;
+        ru[e][q] = (tl < tile_end && lr_ok[q] && e < ne) ? Uin[(b + e) * S + lane + 64 * q] : 0.0;
+    rg = (tl < tile_end && lane < ne * kGeoStride) ? t.geo[b * kGeoStride + lane] : 0.0;
+    rc = (tl < tile_end && lane < ne * 3) ? t.conn[b * 3 + lane] : 0;
+  };
+  load_own(tile0);
+
+  for (int64_t tile = tile0; tile < tile_end; tile += stride) {
+    const int64_t e0 = tile * 4;
+    const int nel = (int)((K - e0) < 4 ? (K - e0) : 4);
     wave_sync();
-    // ---- neighbour states (a boundary face points at the element itself) and
-    // metrics, in two batches of six blocks (bounded register use)
-    const double rng =
-        (lane < nel * 12) ? t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)] : 0.0;
+    // ---- own states, geometry, connectivity (loaded ahead).  Lane l owns
+    // values r = l + 64 q of every element block, so addresses are a per-lane
+    // constant plus a wave-uniform base.
+    if (lane < nel * 3) sConn[lane] = rc;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
         if (lr_ok[q] && e < nel) sU[lds_u[q] + ROWE * e * RS] = (T)(ru[e][q] - uinf_q[q]);
     if (lane < nel * kGeoStride) sGeo[lane] = (T)rg;
-#pragma nounroll
-    for (int h = 0; h < 2; ++h) {
-      double rnb[6][NQ];
-#pragma unroll
-      for (int bb = 0; bb < 6; ++bb) {
-        const int ef = 6 * h + bb;  // uniform across the wave
-        const int64_t nb = (int64_t)(sConn[ef] >> 4) * S;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          rnb[bb][q] = (lr_ok[q] && ef < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
-      }
-#pragma unroll
-      for (int bb = 0; bb < 6; ++bb) {
-        const int ef = 6 * h + bb;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          if (lr_ok[q] && ef < 3 * nel) sX[ef * S + lane + 64 * q] = (T)(rnb[bb][q] - uinf_q[q]);
-      }
-    }
-    if (lane < nel * 12) sNGeo[lane] = (T)rng;
     wave_sync();
+    // ---- neighbour states (a boundary face points at the element itself) and
+    // metrics: the first NB1 blocks are issued now and stored after the volume
+    // phase, the rest (high orders: bounded register use) after that
+    const double rng =
+        (lane < nel * 12) ? t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)] : 0.0;
+    double rnb[NB1][NQ];
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb) {
+      const int64_t nb = (int64_t)(sConn[bb] >> 4) * S;  // bb uniform across the wave
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        rnb[bb][q] = (lr_ok[q] && bb < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
+    }
 
     // ---- gradient on the matrix cores, then the volume flux per node
     T gxk[NT][4], gyk[NT][4];
@@ -352,6 +356,30 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         }
       }
     }
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (lr_ok[q] && bb < 3 * nel) sX[bb * S + lane + 64 * q] = (T)(rnb[bb][q] - uinf_q[q]);
+    if (NB1 < 12) {
+      double rnb2[12 - NB1 > 0 ? 12 - NB1 : 1][NQ];
+#pragma unroll
+      for (int bb = 0; bb < 12 - NB1; ++bb) {
+        const int ef = NB1 + bb;
+        const int64_t nb = (int64_t)(sConn[ef] >> 4) * S;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          rnb2[bb][q] = (lr_ok[q] && ef < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
+      }
+#pragma unroll
+      for (int bb = 0; bb < 12 - NB1; ++bb) {
+        const int ef = NB1 + bb;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (lr_ok[q] && ef < 3 * nel) sX[ef * S + lane + 64 * q] = (T)(rnb2[bb][q] - uinf_q[q]);
+      }
+    }
+    if (lane < nel * 12) sNGeo[lane] = (T)rng;
     wave_sync();
 
     // ---- face nodes, pass 1: traces, ghosts, ||n^T G n||_2 on both sides and the
@@ -545,8 +573,9 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     wave_sync();
 
     // ---- divergence and lifts on the matrix cores, then the RK stage in FP64;
-    // the K1 (and, in the perturbation form, K0) loads are issued first so the
-    // matrix work covers their latency
+    // the K1 (and, in the perturbation form, K0) loads, and those of the next
+    // tile's own data, are issued first so the matrix work covers their latency
+    load_own(tile + stride);
     double rk[NT][4], r0[NT][4];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
@@ -906,7 +935,7 @@ int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t
   }
 }
 
-int default_waves(int N, int form) { return (N <= 4 || form == 2) ? 4 : 2; }
+int default_waves(int, int) { return 4; }
 
 int batch_resident_blocks(int form, int waves) {
   if (form == 0) return waves == 4 ? batch_resident_t<double, false, 4>() : batch_resident_t<double, false, 2>();
