@@ -48,7 +48,7 @@ HBM_PEAK_GBS = 8000.0
 # (packed FP32 is disabled in the build; 157.3 is the packed FP32 figure)
 ALU_PEAK_TFLOPS = 78.6
 FP32_PACKED_PEAK_TFLOPS = 157.3
-FORMS = {"fp64": 0, "fp64-pert": 1, "fp32-pert": 2}
+FORMS = {"fp64": 0, "fp64-pert": 1, "fp32-pert": 2, "bf16-ops": 3}
 
 # HBM bytes per stage launch measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (cylinder20k, p = 4), each scaled by the counter's reading for a
@@ -280,7 +280,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--form", choices=sorted(FORMS), default="fp32-pert")
-    ap.add_argument("--workload", choices=["cylinder20k", "cylinder327k", "viv16"],
+    ap.add_argument("--compare-forms", action="store_true",
+                    help="also run every other form and report its rate and L2 error")
+    ap.add_argument("--workload", choices=["cylinder20k", "cylinder327k", "periodic51k", "viv16"],
                     default="cylinder20k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -338,11 +340,28 @@ def main():
         p = w["p"]
         Np = (p + 1) * (p + 2) // 2
         K = len(w["mesh"]["EToV"])
-        U0n = mg.noisy_free_stream((4, Np, K), w["U_inf"], mg.rng_for(1))
+        if args.workload == "periodic51k":
+            # smooth field: three seeded Fourier modes of amplitude 1e-2
+            sv = make_solver(w, p, w["mesh"], FORMS["fp64"])
+            x, y = sv.nodes()
+            sv.close()
+            U0n = mg.fourier_modes(x.T, y.T, mg.rng_for(3), L=10.0, amp=1e-2,
+                                   q0=(1.0, 0.3, 0.0, 1.0 / w["gamma"]), gamma=w["gamma"])
+            desc = ("%s: periodic [0,10]^2, 160x160x2 -> K=%d triangles, p=%d (Np=%d), Re=100, "
+                    "M=0.3, 3 seeded Fourier modes (amplitude 1e-2), %s form"
+                    % (args.workload, K, p, Np, args.form))
+        else:
+            U0n = mg.noisy_free_stream((4, Np, K), w["U_inf"], mg.rng_for(1))
+            desc = ("%s: O-grid %s cells (ratio %s, r 0.5..30) -> K=%d triangles, p=%d (Np=%d), "
+                    "Re=100, M=0.2, SIPG, free stream + 1e-3 seeded noise, %s form"
+                    % (args.workload, "80x128" if args.workload == "cylinder20k" else "320x512",
+                       "1.05" if args.workload == "cylinder20k" else "1.0125", K, p, Np,
+                       args.form))
         U0 = torch.from_numpy(np.ascontiguousarray(np.transpose(U0n, (2, 0, 1)))).cuda()
         # SIPG with C1 = 1 on the 2.9e-3 wall layer at p = 4 is penalty-limited
         # near 3e-7; 1e-7 keeps the impulsively started state bounded
-        dt = min(1e-7, stable_dt(w["mesh"], p, w["mu"]) * 1.5)
+        dt = min(1e-7 if args.workload != "periodic51k" else 1.0,
+                 stable_dt(w["mesh"], p, w["mu"]) * 1.5)
         log("%s p=%d form %s, warmup %d, steps %d" % (args.workload, p, args.form, args.warmup,
                                                     args.steps))
         U, t_steps, t_launch, s = run_single(w, U0, prec, args.steps, args.warmup, dt)
@@ -356,20 +375,27 @@ def main():
         flops = algorithmic_flops_per_element(Np, p + 1) * K
         nbytes = algorithmic_bytes_per_element(Np) * K
         dofs = 4 * Np * K
-        config = {"workload": "%s: O-grid %s cells (ratio %s, r 0.5..30) -> K=%d triangles, p=%d "
-                              "(Np=%d), Re=100, M=0.2, SIPG, free stream + 1e-3 seeded noise, %s "
-                              "form" % (args.workload,
-                                        "80x128" if args.workload == "cylinder20k" else "320x512",
-                                        "1.05" if args.workload == "cylinder20k" else "1.0125",
-                                        K, p, Np, args.form),
-                  "K": K, "p": p, "dofs": dofs, "form": args.form, "dt": dt, "finite": finite}
+        config = {"workload": desc, "K": K, "p": p, "dofs": dofs, "form": args.form, "dt": dt,
+                  "finite": finite}
+        if args.compare_forms:
+            forms = {}
+            for name in FORMS:
+                if name in ("fp64", args.form):
+                    continue
+                log("form %s" % name)
+                Uf, tf, tlf, sf = run_single(w, U0, FORMS[name], args.steps, args.warmup, dt)
+                forms[name] = {"value": dofs * 5 * args.steps / tf, "avg_launch_us": tlf * 1e6,
+                               "l2_rel_err": rel_l2([s64], [Uf], [U64], w["U_inf"])}
+                sf.close()
+            config["other_forms"] = forms
         kernel = "stage_kernel<%d, %s>" % (p, args.form)
         cpu = None
         if not args.no_cpu_baseline and args.workload == "cylinder20k":
             log("cpu baseline (oracle)")
             cpu = cpu_baseline(w, p)
         s.close()
-        s64.close()
+        if s64 is not s:
+            s64.close()
 
     achieved = flops / t_launch / 1e12
     value = dofs * 5 * args.steps / t_steps

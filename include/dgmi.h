@@ -63,8 +63,11 @@ typedef enum dg_precision {
   DG_FP64 = 0,           /* every step in IEEE binary64                         */
   DG_FP64_PERT = 1,      /* perturbation form, binary64 (equal to DG_FP64 up    *
                           * to rounding; a check on the perturbation algebra)   */
-  DG_FP32_PERT = 2       /* perturbation form, binary32 right-hand side,        *
+  DG_FP32_PERT = 2,      /* perturbation form, binary32 right-hand side,        *
                           * binary32 matrix-core products, binary64 RK update   */
+  DG_FP32_PERT_BF16OPS = 3 /* as DG_FP32_PERT, but the operator products (Dr, *
+                          * Ds, LIFT, LIFTr, LIFTs) on the bfloat16 matrix      *
+                          * cores with binary32 accumulation                    */
 } dg_precision;
 
 typedef enum dg_penalty_mode {

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdgmi.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EMESH, DG_EUNSUPPORTED, DG_ENONFINITE, DG_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
-DG_FP64, DG_FP64_PERT, DG_FP32_PERT = 0, 1, 2
+DG_FP64, DG_FP64_PERT, DG_FP32_PERT, DG_FP32_PERT_BF16OPS = 0, 1, 2, 3
 DG_PENALTY_PAPER, DG_PENALTY_STANDARD = 0, 1
 
 STATUS_NAMES = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_EMESH",

@@ -43,6 +43,7 @@ struct dg_ctx {
   double* d_ops = nullptr;
   double* d_frag = nullptr;
   float* d_frag32 = nullptr;
+  uint16_t* d_frag16 = nullptr;
   int32_t* d_wall = nullptr;
   double* d_wall_xy = nullptr;
   double* d_scratch = nullptr;

@@ -58,6 +58,7 @@ struct DeviceTables {
   const double* ops = nullptr;     // packed operators (pack_ops)
   const double* frag = nullptr;    // operator fragments in matrix-core lane order (pack_frags)
   const float* frag32 = nullptr;   // the same fragments rounded to FP32 (FP32 form)
+  const unsigned short* frag16 = nullptr;  // bfloat16 fragments of the 16x16x16 instruction
   const int32_t* wall = nullptr;   // wall face list (k*3 + f)
   const double* wall_xy = nullptr; // node coordinates of the wall faces, (x, y) per face node
   int64_t K = 0;
@@ -78,8 +79,8 @@ struct StageTuning {
   int grid = 0;
 };
 
-// kernels.hip.  form: 0 plain FP64, 1 perturbation FP64, 2 perturbation FP32
-// (the dg_precision values).
+// kernels.hip.  form: 0 plain FP64, 1 perturbation FP64, 2 perturbation FP32,
+// 3 perturbation FP32 with bfloat16 operator products (the dg_precision values).
 int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t,
                  const KernelPhysics& ph, const double* U_in, double* U_out, double* K1, double a,
                  double b, double dt, int rhs_only, void* stream, std::string& err);
@@ -125,5 +126,10 @@ void pack_frags(const RefOps& ref, std::vector<double>& out);
 // The FP32 matrix instruction (16x16x4 f32) takes its B operand in the same
 // lane order, so the FP32 fragments are the FP64 ones rounded.
 void pack_frags32(const RefOps& ref, std::vector<float>& out);
+// Dr | Ds | LIFT | LIFTr | LIFTs as bfloat16 B-operand fragments of the
+// 16x16x16 instruction: for output tile t and 16-deep k-step s, lane l holds
+// Op[16t + l%16][16s + 4(l/16) + j], j = 0..3 (round to nearest even, zero
+// outside the matrix).
+void pack_frags_bf16(const RefOps& ref, std::vector<uint16_t>& out);
 
 }  // namespace dgmi

@@ -28,7 +28,7 @@ int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 void free_device(dg_ctx* c) {
-  void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,  c->d_frag32,
+  void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,  c->d_frag32, c->d_frag16,
                   c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -37,6 +37,7 @@ void free_device(dg_ctx* c) {
   c->d_ops = nullptr;
   c->d_frag = nullptr;
   c->d_frag32 = nullptr;
+  c->d_frag16 = nullptr;
   c->d_wall = nullptr;
   c->d_wall_xy = nullptr;
   c->d_scratch = nullptr;
@@ -61,6 +62,7 @@ dgmi::DeviceTables tables(const dg_ctx* c) {
   t.ops = c->d_ops;
   t.frag = c->d_frag;
   t.frag32 = c->d_frag32;
+  t.frag16 = c->d_frag16;
   t.wall = c->d_wall;
   t.wall_xy = c->d_wall_xy;
   t.K = c->K;
@@ -101,7 +103,8 @@ int dg_create(int p, int precision, dg_ctx** out) {
   if (!out) return fail(nullptr, DG_EINVAL, "out is NULL");
   *out = nullptr;
   if (p < 1 || p > 6) return fail(nullptr, DG_EUNSUPPORTED, "polynomial order must be in 1..6");
-  if (precision != DG_FP64 && precision != DG_FP64_PERT && precision != DG_FP32_PERT)
+  if (precision != DG_FP64 && precision != DG_FP64_PERT && precision != DG_FP32_PERT &&
+      precision != DG_FP32_PERT_BF16OPS)
     return fail(nullptr, DG_EUNSUPPORTED, "unsupported precision mode");
   dg_ctx* c = new (std::nothrow) dg_ctx();
   if (!c) return fail(nullptr, DG_ENOMEM, "out of host memory");
@@ -175,14 +178,17 @@ int dg_setup(dg_ctx* c) {
   if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
   std::vector<double> ops, frag;
   std::vector<float> frag32;
+  std::vector<uint16_t> frag16;
   dgmi::pack_ops(c->ref, ops);
   dgmi::pack_frags(c->ref, frag);
   dgmi::pack_frags32(c->ref, frag32);
+  dgmi::pack_frags_bf16(c->ref, frag16);
   if ((e = upload(&c->d_geo, c->mesh.geo)) != hipSuccess ||
       (e = upload(&c->d_conn, c->mesh.conn)) != hipSuccess ||
       (e = upload(&c->d_ops, ops)) != hipSuccess ||
       (e = upload(&c->d_frag, frag)) != hipSuccess ||
       (e = upload(&c->d_frag32, frag32)) != hipSuccess ||
+      (e = upload(&c->d_frag16, frag16)) != hipSuccess ||
       (e = upload(&c->d_wall, c->mesh.wall_faces)) != hipSuccess ||
       (e = upload(&c->d_wall_xy, c->mesh.wall_xy)) != hipSuccess) {
     free_device(c);

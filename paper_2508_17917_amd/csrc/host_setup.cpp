@@ -8,6 +8,7 @@
 // E^e of eq. dg_on_K.  Everything here runs once per mesh on the host.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <cstdio>
 #include <unordered_map>
 
@@ -467,6 +468,33 @@ void pack_frags32(const RefOps& ref, std::vector<float>& out) {
   std::vector<double> d;
   pack_frags(ref, d);
   out.assign(d.begin(), d.end());
+}
+
+void pack_frags_bf16(const RefOps& ref, std::vector<uint16_t>& out) {
+  const int Np = ref.Np, NF = 3 * ref.Nfp;
+  const int NT = (Np + 15) / 16, KS = (Np + 15) / 16, KF = (NF + 15) / 16;
+  out.clear();
+  auto bf16 = [](double v) {
+    float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  };
+  auto emit = [&](const std::vector<double>& M, int cols, int ksteps) {
+    for (int t = 0; t < NT; ++t)
+      for (int s = 0; s < ksteps; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 4; ++j) {
+            const int row = 16 * t + l % 16, col = 16 * s + 4 * (l / 16) + j;
+            out.push_back((row < Np && col < cols) ? bf16(M[row * cols + col]) : (uint16_t)0);
+          }
+  };
+  emit(ref.Dr, Np, KS);
+  emit(ref.Ds, Np, KS);
+  emit(ref.LIFT, NF, KF);
+  emit(ref.LIFTr, NF, KF);
+  emit(ref.LIFTs, NF, KF);
 }
 
 size_t ops_packed_size(int N) {

@@ -33,8 +33,24 @@
 
 namespace dgmi {
 
-template <int N, typename T>
+// Real types of the right-hand side: double, float, or float with the
+// operator products on the bfloat16 matrix cores (FP32 accumulation).
+struct bf16ops {};
+template <typename X>
+struct Real {
+  typedef X type;
+  static constexpr bool bf = false;
+};
+template <>
+struct Real<bf16ops> {
+  typedef float type;
+  static constexpr bool bf = true;
+};
+
+template <int N, typename X>
 struct Order {
+  typedef typename Real<X>::type T;
+  static constexpr bool BF = Real<X>::bf;
   static constexpr int Np = (N + 1) * (N + 2) / 2;
   static constexpr int Nfp = N + 1;
   static constexpr int NF = 3 * (N + 1);
@@ -42,8 +58,11 @@ struct Order {
   static constexpr int NT = (Np + 15) / 16;      // 16-node output tiles
   static constexpr int KS = (Np + 3) / 4;        // k-steps over volume nodes
   static constexpr int KF = (NF + 3) / 4;        // k-steps over face nodes
-  static constexpr int RS = 4 * KS + 1;          // padded LDS row (odd: no bank aliasing)
-  static constexpr int HRS = 4 * KF + 1;
+  static constexpr int KS16 = (Np + 15) / 16;    // bfloat16 k-steps (16 deep)
+  static constexpr int KF16 = (NF + 15) / 16;
+  // padded LDS rows (odd: no bank aliasing), long enough for the k-steps
+  static constexpr int RS = (BF && 16 * KS16 > 4 * KS ? 16 * KS16 : 4 * KS) + 1;
+  static constexpr int HRS = (BF && 16 * KF16 > 4 * KF ? 16 * KF16 : 4 * KF) + 1;
   static constexpr int FIT = (4 * NF + 63) / 64; // face items per lane
   // default waves per workgroup (each wave owns its own tiles; the workgroup
   // shares the operator fragments)
@@ -64,8 +83,10 @@ struct Order {
   static constexpr int VN_SZ = 16 * NF;          // mean viscous normal flux per face node
   static constexpr int WAVE_SZ = U_SZ + F_SZ + X_SZ + NORM_SZ + VN_SZ + 64 + 48;
   // operator fragments (per workgroup)
-  static constexpr int FD = NT * KS * 64;        // one Dr-type fragment set
-  static constexpr int FL = NT * KF * 64;        // one LIFT-type fragment set
+  // one Dr-type / LIFT-type fragment set, in elements of T (bfloat16: four
+  // values per lane, i.e. two floats' worth)
+  static constexpr int FD = BF ? NT * KS16 * 64 * 2 : NT * KS * 64;
+  static constexpr int FL = BF ? NT * KF16 * 64 * 2 : NT * KF * 64;
   static constexpr int FRAG_SZ = 2 * FD + 3 * FL;
   // matrix-core row of (field c, element e): the FP64 instruction returns rows
   // l/16 + 4v to lane l, the FP32 one rows 4(l/16) + v; either way lane l ends
@@ -97,6 +118,29 @@ __device__ __forceinline__ Vec4<double>::type mfma(double a, double b, Vec4<doub
 }
 __device__ __forceinline__ Vec4<float>::type mfma(float a, float b, Vec4<float>::type c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// bfloat16 operands (16x16x16, FP32 accumulation): lane l supplies
+// A[l%16][4(l/16) + j] and B[4(l/16) + j][l%16]; the result layout is that of
+// the FP32 instruction.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ bf16x4_t bf16_row(const float* p) {
+  return bf16x4_t{(short)to_bf16(p[0]), (short)to_bf16(p[1]), (short)to_bf16(p[2]),
+                  (short)to_bf16(p[3])};
+}
+__device__ __forceinline__ bf16x4_t bf16_frag(const float* frag, int lane) {
+  const uint2 w = ((const uint2*)frag)[lane];
+  return bf16x4_t{(short)(w.x & 0xffff), (short)(w.x >> 16), (short)(w.y & 0xffff),
+                  (short)(w.y >> 16)};
+}
+__device__ __forceinline__ Vec4<float>::type mfma_bf16(bf16x4_t a, bf16x4_t b,
+                                                       Vec4<float>::type c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
 // LDS ordering among the lanes of one wavefront (no workgroup barrier).
@@ -183,8 +227,8 @@ __device__ __forceinline__ void ghost_state(int tag, const T up[4], const T upf[
   }
 }
 
-template <typename T>
-__device__ __forceinline__ const T* frag_of(const DeviceTables& t);
+template <typename X>
+__device__ __forceinline__ const typename Real<X>::type* frag_of(const DeviceTables& t);
 template <>
 __device__ __forceinline__ const double* frag_of<double>(const DeviceTables& t) {
   return t.frag;
@@ -193,20 +237,29 @@ template <>
 __device__ __forceinline__ const float* frag_of<float>(const DeviceTables& t) {
   return t.frag32;
 }
+// bfloat16 fragments, moved as 32-bit words (never used as floats)
+template <>
+__device__ __forceinline__ const float* frag_of<bf16ops>(const DeviceTables& t) {
+  return (const float*)t.frag16;
+}
 
 // The fused right-hand side + LSERK stage for the tiles tile0, tile0 + stride,
 // ... < tile_end of one mesh, run by one wavefront.  A tile is four elements
 // (16 matrix-core rows = 4 fields x 4 elements).  sFrag holds the operator
 // fragments (shared by the workgroup), sU this wave's LDS area (WAVE_SZ
 // elements, pads zeroed once), sConn 12 ints of this wave.
-template <int N, typename T, bool PERT>
+template <int N, typename X, bool PERT>
 __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelPhysics& ph,
                                             const double* __restrict__ Uin,
                                             double* __restrict__ Uout, double* __restrict__ K1,
                                             double a, double b, double dt, int rhs_only,
-                                            const T* sFrag, T* sU, int* sConn,
+                                            const typename Real<X>::type* sFrag,
+                                            typename Real<X>::type* sU, int* sConn,
                                             int64_t tile0, int64_t tile_end, int64_t stride) {
-  using O = Order<N, T>;
+  typedef typename Real<X>::type T;
+  using O = Order<N, X>;
+  constexpr bool BF = O::BF;
+  constexpr int KS16 = O::KS16, KF16 = O::KF16;
   typedef typename Vec4<T>::type V4;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF = O::NF, S = O::S, NT = O::NT, KS = O::KS,
                 KF = O::KF, RS = O::RS, HRS = O::HRS, FIT = O::FIT, ROWC = O::ROWC,
@@ -320,11 +373,20 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       V4 aR = {T(0), T(0), T(0), T(0)}, aS = {T(0), T(0), T(0), T(0)};
+      if constexpr (BF) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const T av = sU[arow * RS + 4 * s + acol];
-        aR = mfma(av, sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aR);
-        aS = mfma(av, sFrag[OFF_DS + (tt * KS + s) * 64 + lane], aS);
+        for (int s = 0; s < KS16; ++s) {
+          const bf16x4_t av = bf16_row((const float*)sU + arow * RS + 16 * s + 4 * acol);
+          aR = mfma_bf16(av, bf16_frag((const float*)sFrag + OFF_DR + (tt * KS16 + s) * 128, lane), aR);
+          aS = mfma_bf16(av, bf16_frag((const float*)sFrag + OFF_DS + (tt * KS16 + s) * 128, lane), aS);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const T av = sU[arow * RS + 4 * s + acol];
+          aR = mfma(av, sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aR);
+          aS = mfma(av, sFrag[OFF_DS + (tt * KS + s) * 64 + lane], aS);
+        }
       }
       const int n = 16 * tt + rn;
       const bool ok = (re < nel) && (n < Np);
@@ -434,8 +496,19 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         const int dbase = ((n2 >> 4) * KS) * 64 + (n2 & 15);
 #pragma unroll 4
         for (int m = 0; m < Np; ++m) {
-          const int fi = dbase + (m >> 2) * 64 + (m & 3) * 16;
-          const T dr = sFrag[OFF_DR + fi], ds = sFrag[OFF_DS + fi];
+          T dr, ds;
+          if constexpr (BF) {
+            // D_r[n2][m] in the bfloat16 fragment order (four values per lane)
+            const unsigned short* f16 = (const unsigned short*)sFrag;
+            const int wi = (((n2 >> 4) * KS16 + (m >> 4)) * 64 + 16 * ((m & 15) >> 2) + (n2 & 15)) * 4 +
+                           (m & 3);
+            dr = __uint_as_float((unsigned)f16[2 * OFF_DR + wi] << 16);
+            ds = __uint_as_float((unsigned)f16[2 * OFF_DS + wi] << 16);
+          } else {
+            const int fi = dbase + (m >> 2) * 64 + (m & 3) * 16;
+            dr = sFrag[OFF_DR + fi];
+            ds = sFrag[OFF_DS + fi];
+          }
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const T uu = nbU[c * Np + m];
@@ -590,17 +663,37 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       V4 aD = {T(0), T(0), T(0), T(0)}, aL = {T(0), T(0), T(0), T(0)};
+      if constexpr (BF) {
+        const float* fr = (const float*)sFrag;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        aD = mfma(sFr[arow * RS + 4 * s + acol], sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aD);
-        aD = mfma(sFs[arow * RS + 4 * s + acol], sFrag[OFF_DS + (tt * KS + s) * 64 + lane], aD);
-      }
+        for (int s = 0; s < KS16; ++s) {
+          const int fo = (tt * KS16 + s) * 128;
+          aD = mfma_bf16(bf16_row((const float*)sFr + arow * RS + 16 * s + 4 * acol),
+                         bf16_frag(fr + OFF_DR + fo, lane), aD);
+          aD = mfma_bf16(bf16_row((const float*)sFs + arow * RS + 16 * s + 4 * acol),
+                         bf16_frag(fr + OFF_DS + fo, lane), aD);
+        }
 #pragma unroll
-      for (int s = 0; s < KF; ++s) {
-        const int fi = (tt * KF + s) * 64 + lane;
-        aL = mfma(sH[arow * HRS + 4 * s + acol], sFrag[OFF_L + fi], aL);
-        aL = mfma(sQr[arow * HRS + 4 * s + acol], sFrag[OFF_LR + fi], aL);
-        aL = mfma(sQs[arow * HRS + 4 * s + acol], sFrag[OFF_LS + fi], aL);
+        for (int s = 0; s < KF16; ++s) {
+          const int fo = (tt * KF16 + s) * 128;
+          const int ao = arow * HRS + 16 * s + 4 * acol;
+          aL = mfma_bf16(bf16_row((const float*)sH + ao), bf16_frag(fr + OFF_L + fo, lane), aL);
+          aL = mfma_bf16(bf16_row((const float*)sQr + ao), bf16_frag(fr + OFF_LR + fo, lane), aL);
+          aL = mfma_bf16(bf16_row((const float*)sQs + ao), bf16_frag(fr + OFF_LS + fo, lane), aL);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          aD = mfma(sFr[arow * RS + 4 * s + acol], sFrag[OFF_DR + (tt * KS + s) * 64 + lane], aD);
+          aD = mfma(sFs[arow * RS + 4 * s + acol], sFrag[OFF_DS + (tt * KS + s) * 64 + lane], aD);
+        }
+#pragma unroll
+        for (int s = 0; s < KF; ++s) {
+          const int fi = (tt * KF + s) * 64 + lane;
+          aL = mfma(sH[arow * HRS + 4 * s + acol], sFrag[OFF_L + fi], aL);
+          aL = mfma(sQr[arow * HRS + 4 * s + acol], sFrag[OFF_LR + fi], aL);
+          aL = mfma(sQs[arow * HRS + 4 * s + acol], sFrag[OFF_LS + fi], aL);
+        }
       }
       const int n = 16 * tt + rn;
       if (re < nel && n < Np) {
@@ -625,9 +718,12 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
 
 // Copy the operator fragments of order N into LDS and zero this workgroup's
 // wave areas (their pads are read as zeros by the matrix-core products).
-template <int N, typename T, int W>
-__device__ __forceinline__ void stage_lds_init(const T* __restrict__ frag, T* sFrag, T* sWave) {
-  using O = Order<N, T>;
+template <int N, typename X, int W>
+__device__ __forceinline__ void stage_lds_init(const typename Real<X>::type* __restrict__ frag,
+                                               typename Real<X>::type* sFrag,
+                                               typename Real<X>::type* sWave) {
+  typedef typename Real<X>::type T;
+  using O = Order<N, X>;
   for (int i = threadIdx.x; i < O::FRAG_SZ; i += 64 * W) sFrag[i] = frag[i];
   for (int i = threadIdx.x; i < W * O::WAVE_SZ; i += 64 * W) sWave[i] = T(0);
   __syncthreads();
@@ -637,23 +733,24 @@ __device__ __forceinline__ void stage_lds_init(const T* __restrict__ frag, T* sF
 // runs on XCD b % 8, the grid is a multiple of 8) so that neighbour reads stay
 // in that XCD's L2; within a range the waves stride over the tiles (a
 // persistent grid) or take one tile each (a grid of one tile per wave).
-template <int N, typename T, bool PERT, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(Order<N, T>::MIN_WAVES_EU))) void
+template <int N, typename X, bool PERT, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(Order<N, X>::MIN_WAVES_EU))) void
 stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
              double* __restrict__ Uout, double* __restrict__ K1, double a, double b, double dt,
              int rhs_only) {
-  using O = Order<N, T>;
-  __shared__ T sFrag[O::FRAG_SZ];
+  typedef typename Real<X>::type T;
+  using O = Order<N, X>;
+  __shared__ __attribute__((aligned(16))) T sFrag[O::FRAG_SZ];
   __shared__ T sWave[W * O::WAVE_SZ];
   __shared__ int sConnW[W * 12];
-  stage_lds_init<N, T, W>(frag_of<T>(t), sFrag, sWave);
+  stage_lds_init<N, X, W>(frag_of<X>(t), sFrag, sWave);
   const int wid = threadIdx.x >> 6;
   const int64_t ntiles = (t.K + 3) / 4;
   const int xcd = blockIdx.x & 7;
   const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
   const int64_t w0 = (int64_t)(blockIdx.x >> 3) * W + wid;
   const int64_t wstride = (int64_t)(gridDim.x >> 3) * W;
-  stage_tiles<N, T, PERT>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, sFrag, sWave + wid * O::WAVE_SZ,
+  stage_tiles<N, X, PERT>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, sFrag, sWave + wid * O::WAVE_SZ,
                           sConnW + 12 * wid, tb + w0, te, wstride);
 }
 
@@ -662,16 +759,17 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
 // and numbers the tiles of its instances consecutively.  Per-instance dt and
 // v_w, and the parity of the state buffers, come from device memory, so a
 // captured graph of the five stages stays valid from step to step.
-template <int N, typename T, bool PERT, int W>
+template <int N, typename X, bool PERT, int W>
 __device__ __forceinline__ void batch_group(const BatchItem* __restrict__ items,
                                             const BatchStep* __restrict__ steps, int par,
                                             const BatchGroup& g, int stage, double a, double b,
                                             unsigned char* smem) {
-  using O = Order<N, T>;
+  typedef typename Real<X>::type T;
+  using O = Order<N, X>;
   T* sFrag = (T*)smem;
   T* sWave = sFrag + O::FRAG_SZ;
   int* sConnW = (int*)(sWave + W * O::WAVE_SZ);
-  stage_lds_init<N, T, W>(frag_of<T>(items[g.first_item].t), sFrag, sWave);
+  stage_lds_init<N, X, W>(frag_of<X>(items[g.first_item].t), sFrag, sWave);
   const int wid = threadIdx.x >> 6;
   const int local = blockIdx.x - g.block_begin;
   const int xcd = local & 7;
@@ -685,17 +783,18 @@ __device__ __forceinline__ void batch_group(const BatchItem* __restrict__ items,
     ph.vw[0] = steps[i].vw[0];
     ph.vw[1] = steps[i].vw[1];
     const int src = (par + stage) & 1;
-    stage_tiles<N, T, PERT>(it.t, ph, it.buf[src], it.buf[src ^ 1], it.K1, a, b, steps[i].dt, 0,
+    stage_tiles<N, X, PERT>(it.t, ph, it.buf[src], it.buf[src ^ 1], it.K1, a, b, steps[i].dt, 0,
                             sFrag, sWave + wid * O::WAVE_SZ, sConnW + 12 * wid,
                             tile - it.tile_begin, tile - it.tile_begin + 1, 1);
   }
 }
 
-template <typename T, int W>
+template <typename X, int W>
 struct BatchLds {
   template <int N>
   static constexpr size_t of() {
-    return (Order<N, T>::FRAG_SZ + W * Order<N, T>::WAVE_SZ) * sizeof(T) + W * 12 * sizeof(int);
+    return (Order<N, X>::FRAG_SZ + W * Order<N, X>::WAVE_SZ) * sizeof(typename Real<X>::type) +
+           W * 12 * sizeof(int);
   }
   static constexpr size_t mx(size_t x, size_t y) { return x > y ? x : y; }
   static constexpr size_t bytes =
@@ -893,6 +992,8 @@ int launch_stage_n(int form, const StageTuning& tune, const DeviceTables& t,
       return launch_stage_w<N, double, true>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
     case 2:
       return launch_stage_w<N, float, true>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 3:
+      return launch_stage_w<N, bf16ops, true>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
     default: err = "precision mode not built"; return -5;
   }
 }
@@ -940,6 +1041,7 @@ int default_waves(int, int) { return 4; }
 int batch_resident_blocks(int form, int waves) {
   if (form == 0) return waves == 4 ? batch_resident_t<double, false, 4>() : batch_resident_t<double, false, 2>();
   if (form == 1) return waves == 4 ? batch_resident_t<double, true, 4>() : batch_resident_t<double, true, 2>();
+  if (form == 3) return waves == 4 ? batch_resident_t<bf16ops, true, 4>() : batch_resident_t<bf16ops, true, 2>();
   return waves == 4 ? batch_resident_t<float, true, 4>() : batch_resident_t<float, true, 2>();
 }
 
@@ -962,6 +1064,9 @@ int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchS
     case 2:
       return w4 ? launch_batch_t<float, true, 4>(items, steps, parity, G, blocks, stage, a, b, s, err)
                 : launch_batch_t<float, true, 2>(items, steps, parity, G, blocks, stage, a, b, s, err);
+    case 3:
+      return w4 ? launch_batch_t<bf16ops, true, 4>(items, steps, parity, G, blocks, stage, a, b, s, err)
+                : launch_batch_t<bf16ops, true, 2>(items, steps, parity, G, blocks, stage, a, b, s, err);
     default: err = "precision mode not built"; return -5;
   }
 }

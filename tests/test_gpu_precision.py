@@ -25,6 +25,11 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 1e-5
+# bfloat16 operator products: both operands of every product rounded to
+# 8 significant bits (u = 2^-9), FP32 accumulation; the operands of the
+# divergence and lifts are themselves built from rounded gradients: about
+# ten u of the perturbation-term scale
+TOLBF = 2e-2
 
 
 def _torch():
@@ -131,6 +136,13 @@ def test_rhs_perturbation_forms(case):
     R2 = s.rhs(Ud, v_w=vw)
     torch.cuda.synchronize()
     assert torch.equal(R, R2)
+    s.close()
+    from paper_2508_17917_amd import DG_FP32_PERT_BF16OPS
+    _say("rhs bf16-ops %s K=%d p=%d" % (name, dg.mesh.K, p))
+    s = _solver(mesh, p, dg.phys, DG_FP32_PERT_BF16OPS)
+    R = s.rhs(Ud, v_w=vw)
+    torch.cuda.synchronize()
+    _check(_from_dev(R), want, TOLBF, pert_term_scale(dg, parts, vw), "bf16-ops " + name)
     s.close()
 
 
