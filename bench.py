@@ -5,9 +5,12 @@ of 80 x 128 cells (radial ratio 1.05, wall r = 0.5, far field r = 30) split
 into K = 20480 triangles, p = 4 (Np = 15), Re = 100, M = 0.2, SIPG, paper
 penalty, free stream plus seeded 1e-3 uniform noise per node and field.
 Other workloads (--workload): cylinder327k (the same O-grid refined 4 x 4,
-K = 327,680, states beyond the last-level cache) and viv16 (16 elastically
-mounted cylinders, K = 5k-31k each, p in {4, 5, 6}, U* in [3, 8], coupled to
-a host Newmark step every step, advanced as one batch).
+K = 327,680, states beyond the last-level cache), periodic51k (160x160x2
+periodic triangles, p = 6, three seeded Fourier modes of amplitude 1e-2),
+viv16 (16 elastically mounted cylinders, K = 5k-31k each, p in {4, 5, 6},
+U* in [3, 8], coupled to a host Newmark step every step, advanced as one
+batch) and closure20k (the learned closure: order-4 snapshots, bfloat16
+training throughput, gain at Re = 120).
 
 A step is one pass of the hot path: the five fused RHS + stage launches of
 one LSERK step and the wall-force integral (viv16: plus the host Newmark step
@@ -273,6 +276,134 @@ def rel_l2(solvers, got, ref, U_inf):
     return float(np.sqrt(num / np.maximum(den, 1e-300)).max())
 
 
+def run_closure(args):
+    """Learned closure on cylinder20k: order-4 snapshots of impulsively started
+    flows at seeded Re in [60, 150] (FP64 plain form), bfloat16 training on the
+    GPU (timed), evaluation at Re = 120 against the plain order-4 solve."""
+    import numpy as np
+    import torch
+
+    import meshgen as mg
+    from paper_2508_17917_amd import Solver
+    from paper_2508_17917_amd.closure import Closure
+    base = mg.workload("cylinder20k")
+    mesh = base["mesh"]
+    K = len(mesh["EToV"])
+    n_runs = 8
+    per_run = max(1, args.snapshots // n_runs)
+    every, dt = 4, 1e-7
+    Res = np.sort(mg.rng_for(4).uniform(60.0, 150.0, n_runs))
+    N = n_runs * per_run * K
+    X = torch.empty((N, 28), dtype=torch.float32, device="cuda")
+    T = torch.empty((N, 60), dtype=torch.float32, device="cuda")
+
+    def pair(Re):
+        ph = mg.physics_params(Re=Re, M=0.2)
+        mk = lambda p: Solver(p, mesh, gamma=ph["gamma"], Pr=ph["Pr"], mu=ph["mu"], theta=1.0,
+                              penalty_mode=0, C_pen=1.0, U_inf=ph["U_inf"])
+        return mk(2), mk(4), ph["U_inf"]
+
+    def uniform_state(hi, U_inf):
+        u = np.broadcast_to(np.asarray(U_inf)[None, :, None], (hi.K, 4, hi.Np))
+        return torch.from_numpy(np.ascontiguousarray(u)).cuda()
+
+    cl, keep = None, []
+    row = 0
+    t0 = time.perf_counter()
+    for Re in Res:
+        lo, hi, U_inf = pair(Re)
+        if cl is None:
+            cl = Closure(lo, hi, max_batch=args.batch,
+                         params=mg.mlp_init(mg.rng_for(4, salt=1), 28, 128, 60))
+        else:
+            cl.rebind(lo, hi)
+        keep.append((lo, hi))
+        U = uniform_state(hi, U_inf)
+        K1 = torch.zeros_like(U)
+        for _ in range(per_run):
+            hi.rk_steps(U, K1, every, dt)
+            cl.features(U, True, out=X[row:row + K])
+            cl.targets(U, out=T[row:row + K])
+            row += K
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log("closure data: %d snapshots, %d samples, %.1f s" % (n_runs * per_run, N, t_data))
+    cl.fit_normalization(X, T)
+    stream = torch.cuda.current_stream()
+    cl.train(X, T, epochs=1, batch=args.batch, lr=1e-3, seed=0, loss_every=10 ** 9)  # warm-up
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    losses = cl.train(X, T, epochs=args.epochs, batch=args.batch, lr=1e-3, seed=1,
+                      loss_every=200)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_train = ev0.elapsed_time(ev1) / 1e3
+    steps = args.epochs * (N // args.batch)
+    samples = steps * args.batch
+    flops_sample = 2.0 * (28 * 128 + 128 * 128 + 128 * 60)
+    # evaluation at Re = 120
+    lo, hi, U_inf = pair(120.0)
+    cl.rebind(lo, hi)
+    U4 = uniform_state(hi, U_inf)
+    K14 = torch.zeros_like(U4)
+    hi.rk_steps(U4, K14, per_run * every // 2, dt)
+    U2 = cl.restrict(U4)
+    K12 = torch.zeros_like(U2)
+    M4 = hi.table("M").reshape(15, 15)
+    geo = hi.table("geo").reshape(hi.K, 16)
+    J = 1.0 / (geo[:, 0] * geo[:, 3] - geo[:, 1] * geo[:, 2])
+
+    def norm(D):
+        d = D.cpu().numpy()
+        return float(np.sqrt(np.einsum("kcn,nm,kcm,k->", d, M4, d, J)))
+
+    evals = []
+    for seg in range(3):
+        base_err = norm(cl.interpolate(U2) - U4)
+        corr_err = norm(cl.correct(U2) - U4)
+        evals.append({"steps": seg * 20, "interp_err": base_err, "closure_err": corr_err,
+                      "ratio": corr_err / base_err, "fallback": cl.needs_fallback(U2)})
+        hi.rk_steps(U4, K14, 20, dt)
+        lo.rk_steps(U2, K12, 20, dt)
+    # inference: samples + network + apply for every element
+    Ucorr = hi.empty_state()
+    for _ in range(3):
+        cl.correct(U2, out=Ucorr)
+    ev0.record(stream)
+    for _ in range(20):
+        cl.correct(U2, out=Ucorr)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_inf = ev0.elapsed_time(ev1) / 1e3 / 20
+    out = {
+        "metric": "closure MLP training samples/s (bfloat16 matrix cores, FP32 accumulation)",
+        "value": samples / t_train, "unit": "samples/s", "n_gpus": 1,
+        "steps": steps, "warmup": N // args.batch, "ms_per_step": t_train * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "closure20k: 28->128->128->60 GELU MLP, %d order-4 snapshots of "
+                               "impulsively started cylinder20k flows at Re in [60,150] (%d runs), "
+                               "%d samples, batch %d, %d epochs; evaluated at Re=120"
+                               % (n_runs * per_run, n_runs, N, args.batch, args.epochs),
+                   "samples": N, "loss_first": losses[0] if losses else None,
+                   "loss_last": losses[-1] if losses else None, "data_s": t_data,
+                   "eval": evals, "inference_us_per_state": t_inf * 1e6,
+                   "inference_elements_per_s": K / t_inf},
+        "roofline": {"bound": "mfma", "achieved": 3 * flops_sample * samples / t_train / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": 3 * flops_sample * samples / t_train / 1e12 / 2500.0,
+                     "traffic": None, "kernel": "dense_kernel / wgrad_kernel (training step)"},
+    }
+    cl.close()
+    for a, b in keep:
+        a.close()
+        b.close()
+    lo.close()
+    hi.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,7 +413,11 @@ def main():
     ap.add_argument("--form", choices=sorted(FORMS), default="fp32-pert")
     ap.add_argument("--compare-forms", action="store_true",
                     help="also run every other form and report its rate and L2 error")
-    ap.add_argument("--workload", choices=["cylinder20k", "cylinder327k", "periodic51k", "viv16"],
+    ap.add_argument("--snapshots", type=int, default=2000, help="closure20k: training snapshots")
+    ap.add_argument("--epochs", type=int, default=2, help="closure20k: timed training epochs")
+    ap.add_argument("--batch", type=int, default=65536, help="closure20k: minibatch size")
+    ap.add_argument("--workload", choices=["cylinder20k", "cylinder327k", "periodic51k", "viv16",
+                                           "closure20k"],
                     default="cylinder20k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -299,6 +434,9 @@ def main():
     import meshgen as mg
 
     prec = FORMS[args.form]
+    if args.workload == "closure20k":
+        run_closure(args)
+        return
     if args.workload == "viv16":
         cases, phys = mg.viv_sweep_cases()
         if args.p is not None:

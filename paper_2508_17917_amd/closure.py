@@ -87,21 +87,26 @@ class Closure:
             L.dg_mlp_forward(self.m, X[b0:b1], out[b0:b1])
         return out
 
-    def train(self, X, T, epochs=1, batch=8192, lr=1e-3, seed=0, log=None):
+    def train(self, X, T, epochs=1, batch=8192, lr=1e-3, seed=0, log=None, loss_every=1):
         """Minibatch Adam over the sample set (X, T: device arrays of equal
         length, rows in any order).  Minibatches are contiguous row ranges,
-        visited in a seeded random order each epoch.  Returns the losses."""
+        visited in a seeded random order each epoch.  Returns the losses read
+        back every `loss_every` steps (each read synchronises the stream)."""
         n = X.shape[0]
         batch = min(batch, self.max_batch, n)
         starts = np.arange(0, n - batch + 1, batch)
         rng = np.random.default_rng(seed)
         losses = []
+        step = 0
         for ep in range(epochs):
             for b0 in rng.permutation(starts):
+                want = (step % loss_every) == 0
                 loss = L.dg_mlp_backward(self.m, X[b0:b0 + batch], T[b0:b0 + batch],
-                                         want_loss=True)
+                                         want_loss=want)
                 L.dg_mlp_adam(self.m, lr)
-                losses.append(loss)
+                if want:
+                    losses.append(loss)
+                step += 1
             if log:
                 log("epoch %d: loss %.4e" % (ep, losses[-1] if losses else float("nan")))
         return losses

@@ -234,12 +234,10 @@ int dg_mlp_backward(dg_mlp* m, const float* X, int64_t ldx, const float* T, int6
   if (rc != DG_OK) return rc;
   if (!T || ldt < m->d.n_out) return mfail(m, DG_EINVAL, "target array NULL or stride too small");
   std::string err;
-  rc = dgmi::mlp_backward(m->d, X, ldx, T, ldt, B, stream, err);
+  int blocks = 0;
+  rc = dgmi::mlp_backward(m->d, X, ldx, T, ldt, B, &blocks, stream, err);
   if (rc != 0) return mfail(m, rc, err);
   if (loss) {
-    const int64_t tiles = (B + 15) / 16;
-    int blocks = (int)((tiles + 3) / 4);
-    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
     std::vector<double> h(blocks);
     hipError_t e = hipMemcpyAsync(h.data(), m->d.loss_part, blocks * sizeof(double),
                                   hipMemcpyDeviceToHost, (hipStream_t)stream);

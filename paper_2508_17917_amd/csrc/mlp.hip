@@ -188,13 +188,16 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
 #pragma unroll 1
   for (int64_t c = b0; c < b1; c += 64) {
     __syncthreads();
-    for (int i = threadIdx.x; i < 64 * NG; i += 256) {
-      const int r = i / NG, n = i - r * NG;
-      sG[r * ldg + n] = (c + r < b1) ? g.G[(c + r) * NG + n] : (unsigned short)0;
+    // 8-byte loads and stores (widths are multiples of 16, rows 8-byte aligned)
+    for (int i = threadIdx.x; i < 16 * NG; i += 256) {
+      const int r = i / (NG / 4), n = 4 * (i - r * (NG / 4));
+      const uint2 v = (c + r < b1) ? *(const uint2*)(g.G + (c + r) * NG + n) : make_uint2(0u, 0u);
+      *(uint2*)(sG + r * ldg + n) = v;
     }
-    for (int i = threadIdx.x; i < 64 * KA; i += 256) {
-      const int r = i / KA, k = i - r * KA;
-      sA[r * lda + k] = (c + r < b1) ? g.A[(c + r) * KA + k] : (unsigned short)0;
+    for (int i = threadIdx.x; i < 16 * KA; i += 256) {
+      const int r = i / (KA / 4), k = 4 * (i - r * (KA / 4));
+      const uint2 v = (c + r < b1) ? *(const uint2*)(g.A + (c + r) * KA + k) : make_uint2(0u, 0u);
+      *(uint2*)(sA + r * lda + k) = v;
     }
     __syncthreads();
     if (threadIdx.x < NG)
@@ -461,9 +464,10 @@ int wgrad(const WgradArgs& a, int blocks, hipStream_t s, std::string& err) {
   return -5;
 }
 
+// two 16-row tiles per wave: the weight staging in LDS is shared by eight tiles
 int dense_blocks(int64_t B) {
   const int64_t tiles = (B + 15) / 16;
-  const int64_t b = (tiles + 3) / 4;
+  const int64_t b = (tiles + 7) / 8;
   return (int)(b < 1024 ? (b > 0 ? b : 1) : 1024);
 }
 }  // namespace
@@ -495,9 +499,10 @@ int mlp_forward(const MlpDev& d, const float* X, int64_t ldx, int64_t B, float* 
 }
 
 int mlp_backward(const MlpDev& d, const float* X, int64_t ldx, const float* T, int64_t ldt,
-                 int64_t B, void* stream, std::string& err) {
+                 int64_t B, int* loss_parts, void* stream, std::string& err) {
   hipStream_t s = (hipStream_t)stream;
   const int blocks = dense_blocks(B);
+  if (loss_parts) *loss_parts = blocks;  // the loss layer writes one partial per workgroup
   const int NTH = d.H / 16, NTO = d.out_pad / 16;
   DenseArgs a{};
   a.B = B;

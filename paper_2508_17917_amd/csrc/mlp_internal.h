@@ -46,7 +46,7 @@ struct MlpDev {
 int mlp_forward(const MlpDev& d, const float* X, int64_t ldx, int64_t B, float* Y, int64_t ldy,
                 void* stream, std::string& err);
 int mlp_backward(const MlpDev& d, const float* X, int64_t ldx, const float* T, int64_t ldt,
-                 int64_t B, void* stream, std::string& err);
+                 int64_t B, int* loss_parts, void* stream, std::string& err);
 int mlp_adam(const MlpDev& d, float lr, float beta1, float beta2, float eps, int step, void* stream,
              std::string& err);
 int mlp_refresh_bf16(const MlpDev& d, void* stream, std::string& err);
