@@ -273,8 +273,11 @@ __device__ __forceinline__ T normal_diffusion_norm(const Gas<T>& g, const VState
                s02 * (s01 * s12 - s11 * s02);
   T lam = root(s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12));
   T step = T(0);
+  // quadratic convergence from the close upper bound: three steps reach the
+  // binary32 tolerance, five the binary64 one (else the fallback below)
+  constexpr int kIters = sizeof(T) == 8 ? 5 : 3;
 #pragma unroll
-  for (int it = 0; it < 5; ++it) {
+  for (int it = 0; it < kIters; ++it) {
     const T f = ((lam - c2) * lam + c1) * lam - c0;
     const T df = (T(3) * lam - T(2) * c2) * lam + c1;
     // the step only needs an approximate reciprocal: Newton corrects the rest

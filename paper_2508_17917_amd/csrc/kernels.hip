@@ -546,6 +546,19 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
       }
     }
     wave_sync();
+    // the stage update's K1 (and, in the perturbation form, K0) values, loaded
+    // here so that face pass 2 covers their latency
+    double rk[NT][4], r0[NT][4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int n = 16 * tt + rn;
+      const bool ok = !rhs_only && re < nel && n < Np;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        rk[tt][c] = (ok && a != 0.0) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
+        r0[tt][c] = (PERT && ok) ? Uin[(e0 + re) * S + c * Np + n] : 0.0;
+      }
+    }
     // ---- face nodes, pass 2: gather what the Roe flux, penalty and theta term
     // need, then (after every read of the neighbour area) write the face terms
     T fup[FIT][4], fuo[FIT][4], fvn[FIT][4], fgb[FIT];
@@ -646,20 +659,9 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     wave_sync();
 
     // ---- divergence and lifts on the matrix cores, then the RK stage in FP64;
-    // the K1 (and, in the perturbation form, K0) loads, and those of the next
-    // tile's own data, are issued first so the matrix work covers their latency
+    // the next tile's own data are loaded first so the matrix work covers
+    // their latency
     load_own(tile + stride);
-    double rk[NT][4], r0[NT][4];
-#pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      const int n = 16 * tt + rn;
-      const bool ok = !rhs_only && re < nel && n < Np;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        rk[tt][c] = (ok && a != 0.0) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
-        r0[tt][c] = (PERT && ok) ? Uin[(e0 + re) * S + c * Np + n] : 0.0;
-      }
-    }
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       V4 aD = {T(0), T(0), T(0), T(0)}, aL = {T(0), T(0), T(0), T(0)};
