@@ -93,7 +93,7 @@ int mlp_build(dg_mlp* m, int n_in, int n_hidden, int n_out, int64_t max_batch) {
   d.ldwt[2] = d.out_pad;
   const int wb_rows[3] = {n_hidden, n_hidden, d.out_pad};
   const int wt_rows[3] = {d.in_pad, n_hidden, n_hidden};
-  d.nparts = 64;
+  d.nparts = 256;  // weight-gradient workgroups: one per CU at most batch sizes
   const int64_t B = max_batch;
   const int64_t part_len = (int64_t)n_hidden * n_hidden + n_hidden;
   hipError_t e;
