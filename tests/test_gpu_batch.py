@@ -212,3 +212,33 @@ def test_viv_sweep_matches_oracle_coupling():
             U = _from_dev(sweep.get_state(i))
             assert np.abs(U - states[i]).max() <= 1e-12 * np.abs(states[i]).max()
     sweep.close()
+
+
+def test_batch_viv16_full_size_equals_single_instances():
+    """The 16-instance sweep at full size (230k elements, p 4-6): one batched
+    step (graph replay) equals single-instance steps, bitwise."""
+    torch = _torch()
+    from paper_2508_17917_amd import Batch, Solver
+    cases, phys = mg.viv_sweep_cases()
+    solvers, states = [], []
+    for i, c in enumerate(cases):
+        s = Solver(c["p"], c["mesh"], precision=2, **phys)
+        U = mg.noisy_free_stream((4, s.Np, s.K), phys["U_inf"], mg.rng_for(2, salt=i + 1))
+        solvers.append(s)
+        states.append(_to_dev(torch, U))
+    _say("viv16 batch K=%d" % sum(s.K for s in solvers))
+    b = Batch(solvers)
+    for i, U in enumerate(states):
+        b.set_state(i, U)
+    dt = np.full(len(cases), 1e-8)
+    vw = np.array([[0.0, 0.001 * i] for i in range(len(cases))])
+    b.rk_step(dt, vw)
+    for i, s in enumerate(solvers):
+        K1 = torch.zeros_like(states[i])
+        s.rk_step(states[i], K1, dt[i], v_w=vw[i])
+    torch.cuda.synchronize()
+    for i in range(len(cases)):
+        assert torch.equal(b.get_state(i), states[i]), i
+    b.close()
+    for s in solvers:
+        s.close()

@@ -212,3 +212,31 @@ def test_rhs_fp32_pert_cylinder20k_full_size():
     _check(_from_dev(R), want, TOL32, pert_term_scale(dg, parts, (0.0, 0.0)),
            "fp32-pert cylinder20k")
     s.close()
+
+
+@pytest.mark.timeout(900)
+def test_rhs_periodic51k_full_size_all_forms():
+    """The precision-stress workload at full size (160x160x2 periodic, p = 6,
+    three Fourier modes of amplitude 1e-2): every form against the oracle."""
+    from paper_2508_17917_amd import DG_FP32_PERT, DG_FP32_PERT_BF16OPS, DG_FP64, DG_FP64_PERT
+    torch = _torch()
+    w = mg.workload("periodic51k")
+    dg = build(w["mesh"], w["p"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+               penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"])
+    m = dg.mesh
+    U = mg.fourier_modes(m.x, m.y, mg.rng_for(3), L=10.0, amp=1e-2,
+                         q0=(1.0, 0.3, 0.0, 1.0 / w["gamma"]), gamma=w["gamma"])
+    _say("oracle rhs periodic51k K=%d p=%d" % (m.K, w["p"]))
+    want, parts = dg.rhs(U, return_parts=True)
+    pts = pert_term_scale(dg, parts, (0.0, 0.0))
+    Ud = _to_dev(torch, U)
+    for prec, tol, terms, name in ((DG_FP64, TOL64, 0.1 * term_scale(parts), "fp64"),
+                                   (DG_FP64_PERT, TOL64, 0.1 * term_scale(parts), "fp64-pert"),
+                                   (DG_FP32_PERT, TOL32, pts, "fp32-pert"),
+                                   (DG_FP32_PERT_BF16OPS, TOLBF, pts, "bf16-ops")):
+        _say("rhs periodic51k %s" % name)
+        s = _solver(w["mesh"], w["p"], dg.phys, prec)
+        R = s.rhs(Ud)
+        torch.cuda.synchronize()
+        _check(_from_dev(R), want, tol, terms, name + " periodic51k")
+        s.close()
