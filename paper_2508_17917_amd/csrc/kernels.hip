@@ -446,7 +446,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
 
     // ---- face nodes, pass 1: traces, ghosts, ||n^T G n||_2 on both sides and the
     // mean viscous normal flux (one lane per face node)
-#pragma unroll
+#pragma nounroll
     for (int q = 0; q < FIT; ++q) {
       const int it = lane + 64 * q;
       int e = it / NF;
