@@ -133,6 +133,14 @@ class Closure:
         L.dg_closure_apply(self.c, U_lo, None, out)
         return out
 
+    def correct_or_fallback(self, U_lo, reference, tol=4.0, out=None):
+        """The corrected order-hi state, or reference() (the caller's order-hi
+        solve) when the samples of U_lo leave the training distribution.
+        Returns (state, used_fallback)."""
+        if self.needs_fallback(U_lo, tol):
+            return reference(), True
+        return self.correct(U_lo, out), False
+
     def needs_fallback(self, U_lo, tol=4.0):
         if self.in_stats is None:
             return True

@@ -273,6 +273,14 @@ def test_closure_gain_over_interpolation():
         _run(hi, U4, K14, dt, 10)
         _run(lo, U2, K12, dt, 10)
     assert ratios[0] < 0.7 and max(ratios) < 0.95, ratios
+    # fallback: a state far outside the training samples (a 30 % density
+    # bump) is handed to the reference solve
+    bumped = U2.clone()
+    bumped[:, 0, :] *= 1.3
+    state, used = cl.correct_or_fallback(bumped, lambda: U4)
+    assert used and state is U4
+    state, used = cl.correct_or_fallback(U2, lambda: U4)
+    assert not used and state.shape == U4.shape
     cl.close()
     lo.close()
     hi.close()
