@@ -275,7 +275,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   T* sQr = sX + 16 * HRS;
   T* sQs = sX + 32 * HRS;
   T* sNorm = sX + O::X_SZ;
-  T* sVn = sNorm + O::NORM_SZ;      // [4 NF][4]
+  T* sVn = sNorm + O::NORM_SZ;      // [4 fields][4 NF]
   T* sGeo = sVn + O::VN_SZ;         // [4][16]
   T* sNGeo = sGeo + 64;             // [4][3][4]
 
@@ -542,7 +542,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           }
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sVn[(e * NF + fn) * 4 + c] = vn[c];
+        for (int c = 0; c < 4; ++c) sVn[c * 4 * NF + e * NF + fn] = vn[c];  // field-major: consecutive lanes, consecutive banks
       }
     }
     wave_sync();
@@ -580,7 +580,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         ghost_state<T, PERT>(tag, fup[q], upf, sX + (e * 3 + f) * S + n2, Np, vwx, vwy, gas, base,
                              fuo[q]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fvn[q][c] = sVn[(e * NF + fn) * 4 + c];
+        for (int c = 0; c < 4; ++c) fvn[q][c] = sVn[c * 4 * NF + e * NF + fn];
         T gbar = T(0);
 #pragma unroll
         for (int jj = 0; jj < Nfp; ++jj) {
