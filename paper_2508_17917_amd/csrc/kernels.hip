@@ -546,22 +546,10 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
       }
     }
     wave_sync();
-    // the stage update's K1 (and, in the perturbation form, K0) values, loaded
-    // here so that face pass 2 covers their latency
-    double rk[NT][4], r0[NT][4];
-#pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      const int n = 16 * tt + rn;
-      const bool ok = !rhs_only && re < nel && n < Np;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        rk[tt][c] = (ok && a != 0.0) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
-        r0[tt][c] = (PERT && ok) ? Uin[(e0 + re) * S + c * Np + n] : 0.0;
-      }
-    }
-    // ---- face nodes, pass 2: gather what the Roe flux, penalty and theta term
-    // need, then (after every read of the neighbour area) write the face terms
-    T fup[FIT][4], fuo[FIT][4], fvn[FIT][4], fgb[FIT];
+    // ---- face nodes, pass 2: gather the other side's state (the only input
+    // that lives in the neighbour area), then, after every read of that area,
+    // the Roe flux, penalty and theta term, written over it as face terms
+    T fuo[FIT][4];
 #pragma unroll
     for (int q = 0; q < FIT; ++q) {
       const int it = lane + 64 * q;
@@ -572,22 +560,13 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         const int n = face_node<N>(f, j);
         const int conn = sConn[e * 3 + f];
         const int tag = conn & 3, nf = (conn >> 2) & 3;
+        T up[4], upf[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fup[q][c] = sU[(ROWC * c + ROWE * e) * RS + n];
-        T upf[4];
-        full_state<T, PERT>(fup[q], base, upf);
+        for (int c = 0; c < 4; ++c) up[c] = sU[(ROWC * c + ROWE * e) * RS + n];
+        full_state<T, PERT>(up, base, upf);
         const int n2 = face_node<N>(nf, Nfp - 1 - j);
-        ghost_state<T, PERT>(tag, fup[q], upf, sX + (e * 3 + f) * S + n2, Np, vwx, vwy, gas, base,
+        ghost_state<T, PERT>(tag, up, upf, sX + (e * 3 + f) * S + n2, Np, vwx, vwy, gas, base,
                              fuo[q]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) fvn[q][c] = sVn[c * 4 * NF + e * NF + fn];
-        T gbar = T(0);
-#pragma unroll
-        for (int jj = 0; jj < Nfp; ++jj) {
-          const T v = sNorm[e * NF + f * Nfp + jj];
-          gbar = v > gbar ? v : gbar;
-        }
-        fgb[q] = gbar;
       }
     }
     wave_sync();
@@ -602,12 +581,25 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         const int tag = sConn[e * 3 + f] & 3;
         const T* g = sGeo + e * kGeoStride;
         const T nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f];
-        const T sigma = g[7 + 4 * f] * fgb[q];
+        // G-bar_e: largest norm over the face nodes of both sides (pass 1)
+        T gbar = T(0);
+#pragma unroll
+        for (int jj = 0; jj < Nfp; ++jj) {
+          const T v = sNorm[e * NF + f * Nfp + jj];
+          gbar = v > gbar ? v : gbar;
+        }
+        const T sigma = g[7 + 4 * f] * gbar;
+        T up[4], vn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          up[c] = sU[(ROWC * c + ROWE * e) * RS + n];
+          vn[c] = sVn[c * 4 * NF + e * NF + fn];
+        }
         const T vwn = vwx * nx + vwy * ny;
         T upf[4], uof[4];
-        full_state<T, PERT>(fup[q], base, upf);
+        full_state<T, PERT>(up, base, upf);
         full_state<T, PERT>(fuo[q], base, uof);
-        const Prim<T> pp = prim_of<T, PERT>(upf, fup[q], base, gas.gm1);
+        const Prim<T> pp = prim_of<T, PERT>(upf, up, base, gas.gm1);
         T Fc[4];
         if (tag == 1) {
           // pressure through the moving wall (minus the free-stream flux in the
@@ -627,7 +619,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         } else {
           const Prim<T> po = prim_of<T, PERT>(uof, fuo[q], base, gas.gm1);
           T FL[4], FR[4];
-          normal_flux<T, PERT>(upf, fup[q], pp, base, nx, ny, vwn, FL);
+          normal_flux<T, PERT>(upf, up, pp, base, nx, ny, vwn, FL);
           normal_flux<T, PERT>(uof, fuo[q], po, base, nx, ny, vwn, FR);
           roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
         }
@@ -638,8 +630,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
           const T fr = sFr[(ROWC * c + ROWE * e) * RS + n], fs = sFs[(ROWC * c + ROWE * e) * RS + n];
           const T own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
-          w[c] = fup[q][c] - fuo[q][c];
-          sH[(ROWC * c + ROWE * e) * HRS + fn] = own - fsc * (Fc[c] - fvn[q][c] + sigma * w[c]);
+          w[c] = up[c] - fuo[q][c];
+          sH[(ROWC * c + ROWE * e) * HRS + fn] = own - fsc * (Fc[c] - vn[c] + sigma * w[c]);
         }
         T qx[4], qy[4];
         viscous_transpose(gas, vstate(gas, tag == 1 ? uof : upf), nx, ny, w, qx, qy);
@@ -659,9 +651,20 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     wave_sync();
 
     // ---- divergence and lifts on the matrix cores, then the RK stage in FP64;
-    // the next tile's own data are loaded first so the matrix work covers
-    // their latency
+    // the K1 (and, in the perturbation form, K0) loads, and those of the next
+    // tile's own data, are issued first so the matrix work covers their latency
     load_own(tile + stride);
+    double rk[NT][4], r0[NT][4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int n = 16 * tt + rn;
+      const bool ok = !rhs_only && re < nel && n < Np;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        rk[tt][c] = (ok && a != 0.0) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
+        r0[tt][c] = (PERT && ok) ? Uin[(e0 + re) * S + c * Np + n] : 0.0;
+      }
+    }
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       V4 aD = {T(0), T(0), T(0), T(0)}, aL = {T(0), T(0), T(0), T(0)};
