@@ -189,6 +189,8 @@ def run_single(w, U0, precision, steps, warmup, dt):
     K1 = torch.zeros_like(U)
     F = torch.zeros((warmup + steps, 3), dtype=torch.float64, device=U.device)
     stream = torch.cuda.current_stream()
+    # launch shape from the autotuner (set-up, outside the timed region)
+    s.autotune(U, reps=20, stream=stream)
     s.rk_steps(U, K1, warmup, dt, force=F[:warmup], stream=stream)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -200,6 +202,12 @@ def run_single(w, U0, precision, steps, warmup, dt):
     t_steps = ev0.elapsed_time(ev1) / 1e3
     t_launch = stage_time(s, U, dt, stream)
     return U, t_steps, t_launch, s
+
+
+def tuning_of(s):
+    w, g = s.get_tuning()
+    return "%d waves/workgroup, %s" % (w, ("persistent grid", "one tile per wave",
+                                            "two tiles per wave", "three tiles per wave")[g])
 
 
 def run_viv(cases, phys, states, precision, steps, warmup, dts, batched):
@@ -514,7 +522,8 @@ def main():
         nbytes = algorithmic_bytes_per_element(Np) * K
         dofs = 4 * Np * K
         config = {"workload": desc, "K": K, "p": p, "dofs": dofs, "form": args.form, "dt": dt,
-                  "finite": finite}
+                  "finite": finite, "launch_shape": tuning_of(s),
+                  "launch_shape_fp64": tuning_of(s64)}
         if args.compare_forms:
             forms = {}
             for name in FORMS:

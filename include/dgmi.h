@@ -183,7 +183,8 @@ int dg_newmark_step(double state[3], double F_new, double dt, double M, double C
  * owns tiles of 4 elements, the workgroup shares the operator fragments held
  * in LDS; 0 = the default for the order and precision) and the grid (0 =
  * persistent: the resident workgroups stride over the tiles, 1 = one tile per
- * wave).  Results do not depend on the shape (bitwise).  Host only. */
+ * wave, 2 or 3 = that many tiles per wave, within the resident workgroups).
+ * Results do not depend on the shape (bitwise).  Host only. */
 int dg_set_tuning(dg_ctx* ctx, int waves, int grid);
 int dg_get_tuning(const dg_ctx* ctx, int* waves, int* grid);
 

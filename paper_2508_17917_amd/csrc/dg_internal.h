@@ -73,7 +73,8 @@ struct KernelPhysics {
 
 // Launch shape of the stage kernel: waves (= elements / 4) per workgroup, 0
 // for the default of the order and form; grid 0 persistent (the resident
-// workgroups stride over the tiles), 1 one tile per wave.
+// workgroups stride over the tiles), 1 one tile per wave, 2 or 3 that many
+// tiles per wave (within the resident workgroups).
 struct StageTuning {
   int waves = 0;
   int grid = 0;

@@ -954,6 +954,13 @@ int64_t stage_grid(int64_t ntiles, int waves, int resident, int mode) {
   int64_t grid;
   if (mode == 1) {
     grid = (want + 7) / 8 * 8;
+  } else if (mode >= 2) {
+    // `mode` tiles per wave (at most the resident workgroups): every wave
+    // does the same number of tiles, none waits on a partly filled last round
+    const int64_t g = (ntiles + (int64_t)waves * mode - 1) / ((int64_t)waves * mode);
+    grid = g < resident ? g : resident;
+    grid = grid >= 8 ? (grid + 7) / 8 * 8 : 8;
+    if (grid > resident) grid = resident / 8 * 8;
   } else {
     grid = want < resident ? want : resident;
     grid = grid >= 8 ? grid / 8 * 8 : 8;

@@ -52,7 +52,7 @@ bool cache_lookup(const char* path, const char* arch, int p, int precision, long
 }
 
 bool valid_shape(int waves, int grid) {
-  return (waves == 0 || waves == 2 || waves == 4) && (grid == 0 || grid == 1);
+  return (waves == 0 || waves == 2 || waves == 4) && (grid >= 0 && grid <= 3);
 }
 
 }  // namespace
@@ -61,7 +61,7 @@ extern "C" {
 
 int dg_set_tuning(dg_ctx* c, int waves, int grid) {
   if (!c) return DG_EINVAL;
-  if (!valid_shape(waves, grid)) return dgmi::ctx_fail(c, DG_EINVAL, "waves 0/2/4, grid 0/1");
+  if (!valid_shape(waves, grid)) return dgmi::ctx_fail(c, DG_EINVAL, "waves 0/2/4, grid 0..3");
   c->tune.waves = waves;
   c->tune.grid = grid;
   return DG_OK;
@@ -112,7 +112,7 @@ int dg_autotune(dg_ctx* c, const double* U, int reps, const char* cache_path, vo
   std::string err;
   if (e != hipSuccess) rc = dgmi::ctx_hip_fail(c, e, "hipEventCreate");
   for (int w : {2, 4})
-    for (int grid = 0; grid < 2 && rc == DG_OK; ++grid) {
+    for (int grid = 0; grid < 4 && rc == DG_OK; ++grid) {
       dgmi::StageTuning tune;
       tune.waves = w;
       tune.grid = grid;

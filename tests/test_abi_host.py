@@ -169,7 +169,7 @@ def test_tuning_and_batch_error_paths():
         assert L.dg_get_tuning(h) == (4, 0)  # defaults at p = 3, FP64
         L.dg_set_tuning(h, 2, 1)
         assert L.dg_get_tuning(h) == (2, 1)
-        for bad in ((3, 0), (4, 2), (-1, 0)):
+        for bad in ((3, 0), (4, 4), (-1, 0)):
             with pytest.raises(L.DGError) as e:
                 L.dg_set_tuning(h, *bad)
             assert e.value.code == L.DG_EINVAL
