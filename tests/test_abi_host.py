@@ -98,8 +98,16 @@ def test_error_codes():
     with pytest.raises(L.DGError) as e:
         L.dg_create(3, precision=7)
     assert e.value.code == L.DG_EUNSUPPORTED
-    for prec in (L.DG_FP64, L.DG_FP64_PERT, L.DG_FP32_PERT):
+    for prec in (L.DG_FP64, L.DG_FP64_PERT, L.DG_FP32_PERT, L.DG_FP32_PERT_BF16OPS):
         L.dg_destroy(L.dg_create(4, precision=prec))
+    # empty mesh
+    h0 = L.dg_create(2)
+    try:
+        with pytest.raises(L.DGError) as e:
+            L.dg_set_mesh(h0, np.zeros(3), np.zeros(3), np.zeros((0, 3), dtype=np.int32))
+        assert e.value.code == L.DG_EINVAL
+    finally:
+        L.dg_destroy(h0)
     h = L.dg_create(2)
     try:
         # set-up before physics/mesh -> out of order
