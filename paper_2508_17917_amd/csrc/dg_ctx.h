@@ -48,6 +48,9 @@ struct dg_ctx {
   double* d_wall_xy = nullptr;
   double* d_scratch = nullptr;
   double* d_force = nullptr;
+  double* d_force_part = nullptr;
+  unsigned* d_force_ticket = nullptr;
+  int force_blocks = 0;
   bool dev_ready = false;
   std::string err;
 };

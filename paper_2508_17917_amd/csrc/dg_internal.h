@@ -63,6 +63,9 @@ struct DeviceTables {
   const double* wall_xy = nullptr; // node coordinates of the wall faces, (x, y) per face node
   int64_t K = 0;
   int nwall = 0;
+  double* force_part = nullptr;     // per-workgroup partials of the wall force
+  unsigned* force_ticket = nullptr; // workgroups done (the last resets it to 0)
+  int force_blocks = 0;             // capacity of force_part, in workgroups
 };
 
 struct KernelPhysics {
@@ -115,6 +118,8 @@ int batch_resident_blocks(int form, int waves);
 int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchStep* steps,
                        const int* parity, const BatchGroups& G, int blocks, int stage, double a,
                        double b, void* stream, std::string& err);
+// one thread per wall face node, 64 per workgroup
+int force_blocks_for(int N, int nwall);
 int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
                  double* out_dev, void* stream, std::string& err);
 // operator packing: Dr | Ds | LIFT | LIFTr | LIFTs | Fmask (as doubles) | wface

@@ -28,8 +28,9 @@ int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 void free_device(dg_ctx* c) {
-  void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,  c->d_frag32, c->d_frag16,
-                  c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force};
+  void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,       c->d_frag32,
+                  c->d_frag16, c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force,
+                  c->d_force_part, c->d_force_ticket};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   c->d_geo = nullptr;
@@ -42,6 +43,9 @@ void free_device(dg_ctx* c) {
   c->d_wall_xy = nullptr;
   c->d_scratch = nullptr;
   c->d_force = nullptr;
+  c->d_force_part = nullptr;
+  c->d_force_ticket = nullptr;
+  c->force_blocks = 0;
   c->dev_ready = false;
 }
 
@@ -67,6 +71,9 @@ dgmi::DeviceTables tables(const dg_ctx* c) {
   t.wall_xy = c->d_wall_xy;
   t.K = c->K;
   t.nwall = (int)c->mesh.wall_faces.size();
+  t.force_part = c->d_force_part;
+  t.force_ticket = c->d_force_ticket;
+  t.force_blocks = c->force_blocks;
   return t;
 }
 
@@ -195,8 +202,13 @@ int dg_setup(dg_ctx* c) {
     return hip_fail(c, e, "uploading set-up tables");
   }
   size_t state = (size_t)c->K * 4 * c->ref.Np * sizeof(double);
+  c->force_blocks = dgmi::force_blocks_for(c->N, (int)c->mesh.wall_faces.size());
+  const int fb = c->force_blocks > 0 ? c->force_blocks : 1;
   if ((e = hipMalloc((void**)&c->d_scratch, state)) != hipSuccess ||
-      (e = hipMalloc((void**)&c->d_force, 4 * sizeof(double))) != hipSuccess) {
+      (e = hipMalloc((void**)&c->d_force, 4 * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&c->d_force_part, 3 * fb * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&c->d_force_ticket, sizeof(unsigned))) != hipSuccess ||
+      (e = hipMemset(c->d_force_ticket, 0, sizeof(unsigned))) != hipSuccess) {
     free_device(c);
     return e == hipErrorOutOfMemory ? fail(c, DG_ENOMEM, "device allocation failed")
                                     : hip_fail(c, e, "hipMalloc");

@@ -829,17 +829,19 @@ batch_stage_kernel(const BatchItem* __restrict__ items, const BatchStep* __restr
   }
 }
 
-// Wall force: one workgroup of 1024 threads walks the wall face nodes in a
-// fixed order (16 waves on one CU hide the latency of the per-node loads);
-// each thread accumulates its share, then a fixed-shape tree reduction in LDS.
-constexpr int kForceThreads = 1024;
+// Wall force: one thread per wall face node (in the fixed order of the wall
+// face list), a fixed-shape wave reduction per workgroup, per-workgroup
+// partials, and the last workgroup to finish (an atomic ticket) sums the
+// partials in workgroup order and resets the ticket: deterministic, one
+// launch, no host synchronisation and no wait inside the kernel.
+constexpr int kForceThreads = 64;
 template <int N>
 __global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, KernelPhysics ph,
-                                                    const double* __restrict__ U,
-                                                    double* __restrict__ out) {
+                                                              const double* __restrict__ U,
+                                                              double* __restrict__ out) {
   using O = Order<N, double>;
   constexpr int Np = O::Np, Nfp = O::Nfp, S = 4 * Np;
-  __shared__ double red[3][kForceThreads];
+  __shared__ int last;
   Gas<double> gas;
   gas.gamma = ph.gamma;
   gas.gm1 = ph.gamma - 1.0;
@@ -851,7 +853,8 @@ __global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, Ke
   const double* wface = t.ops + 2 * Np * Np + 3 * Np * 3 * Nfp;
   double fx = 0.0, fy = 0.0, mz = 0.0;
   const int total = t.nwall * Nfp;
-  for (int i = threadIdx.x; i < total; i += blockDim.x) {
+  const int i = blockIdx.x * kForceThreads + threadIdx.x;
+  if (i < total) {
     const int wf = t.wall[i / Nfp];
     const int j = i % Nfp;
     const int64_t k = wf / 3;
@@ -860,14 +863,17 @@ __global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, Ke
     const double* Uk = U + k * S;
     const double* g = t.geo + k * kGeoStride;
     double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
+#pragma unroll
     for (int m = 0; m < Np; ++m) {
-      double dr = Dr[n * Np + m], ds = Ds[n * Np + m];
+      const double dr = Dr[n * Np + m], ds = Ds[n * Np + m];
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
         ur[c] += dr * Uk[c * Np + m];
         us[c] += ds * Uk[c * Np + m];
       }
     }
     double Up[4], dx[4], dy[4];
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
       Up[c] = Uk[c * Np + n];
       dx[c] = g[0] * ur[c] + g[2] * us[c];
@@ -884,21 +890,32 @@ __global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, Ke
     const double tx = p * nx - (vx[1] * nx + vy[1] * ny);
     const double ty = p * ny - (vx[2] * nx + vy[2] * ny);
     const double xw = t.wall_xy[2 * i], yw = t.wall_xy[2 * i + 1];
-    fx += w * tx;
-    fy += w * ty;
-    mz += w * (xw * ty - yw * tx);
+    fx = w * tx;
+    fy = w * ty;
+    mz = w * (xw * ty - yw * tx);
   }
-  red[0][threadIdx.x] = fx;
-  red[1][threadIdx.x] = fy;
-  red[2][threadIdx.x] = mz;
+  // fixed-shape reduction over the wave (one wave per workgroup)
+  for (int o = 32; o > 0; o >>= 1) {
+    fx += __shfl_down(fx, o, 64);
+    fy += __shfl_down(fy, o, 64);
+    mz += __shfl_down(mz, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    t.force_part[3 * blockIdx.x + 0] = fx;
+    t.force_part[3 * blockIdx.x + 1] = fy;
+    t.force_part[3 * blockIdx.x + 2] = mz;
+    __threadfence();
+    last = atomicAdd(t.force_ticket, 1u) == gridDim.x - 1;
+  }
   __syncthreads();
-  for (int s = kForceThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
-    __syncthreads();
+  if (last && threadIdx.x < 3) {
+    __threadfence();
+    const volatile double* part = t.force_part;
+    double sum = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b) sum += part[3 * b + threadIdx.x];
+    out[threadIdx.x] = sum;
+    if (threadIdx.x == 0) atomicExch(t.force_ticket, 0u);
   }
-  if (threadIdx.x == 0)
-    for (int c = 0; c < 3; ++c) out[c] = red[c][0];
 }
 
 namespace {
@@ -1013,7 +1030,12 @@ int launch_stage_n(int form, const StageTuning& tune, const DeviceTables& t,
 template <int N>
 int launch_force_n(const DeviceTables& t, const KernelPhysics& ph, const double* U, double* out,
                    hipStream_t s, std::string& err) {
-  hipLaunchKernelGGL(force_kernel<N>, dim3(1), dim3(kForceThreads), 0, s, t, ph, U, out);
+  const int blocks = (t.nwall * (N + 1) + kForceThreads - 1) / kForceThreads;
+  if (blocks < 1 || blocks > t.force_blocks) {
+    err = "wall force: workgroup count outside the set-up partial buffer";
+    return -1;
+  }
+  hipLaunchKernelGGL(force_kernel<N>, dim3(blocks), dim3(kForceThreads), 0, s, t, ph, U, out);
   return launch_error(err, "force kernel launch");
 }
 
@@ -1081,6 +1103,10 @@ int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchS
                 : launch_batch_t<bf16ops, true, 2>(items, steps, parity, G, blocks, stage, a, b, s, err);
     default: err = "precision mode not built"; return -5;
   }
+}
+
+int force_blocks_for(int N, int nwall) {
+  return (nwall * (N + 1) + kForceThreads - 1) / kForceThreads;
 }
 
 int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
