@@ -63,6 +63,8 @@ struct DenseArgs {
   int64_t B;
 };
 
+constexpr int KSMAX = 8;  // dense layers take K <= 128 inputs
+
 template <int NT, int EPI, bool NORM_IN>
 __global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
   constexpr int N = 16 * NT;
@@ -71,9 +73,13 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
   const int ldl = K + 4;  // padded LDS row: rows start 2 banks apart
   unsigned short* sW = (unsigned short*)smem;
   double* sLoss = (double*)(smem + ((N * ldl * 2 + 15) / 16) * 16);
-  for (int i = threadIdx.x; i < N * K; i += blockDim.x) {
-    const int n = i / K, k = i - n * K;
-    sW[n * ldl + k] = g.W[(int64_t)n * g.ldw + k];
+  // 8-byte words (K and ldw are multiples of 16, rows 8-byte aligned), all of a
+  // thread's loads in flight together
+  const int kw = K / 4;
+#pragma unroll 8
+  for (int i = threadIdx.x; i < N * kw; i += blockDim.x) {
+    const int n = i / kw, k = 4 * (i - n * kw);
+    *(uint2*)(sW + n * ldl + k) = *(const uint2*)(g.W + (int64_t)n * g.ldw + k);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -86,9 +92,15 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < K / 16; ++ks) {
+    // the tile's whole A row slice is loaded first (K <= 16 KSMAX), so one
+    // memory latency covers every k-step
+    const int nks = K / 16;
+    bf16x4 a[KSMAX];
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks) {
+      a[ks] = bf16x4{0, 0, 0, 0};
+      if (ks >= nks) continue;
       const int k0 = ks * 16 + ak;
-      bf16x4 a;
       if (NORM_IN) {
         const float* X = (const float*)g.A;
         unsigned short h[4];
@@ -97,23 +109,26 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
           const int k = k0 + j;
           const float x = (rok && k < g.kvalid) ? (X[row * g.lda + k] - g.in_mean[k]) * g.in_rstd[k] : 0.f;
           h[j] = f2bf(x);
-          if (rok) g.Aout[row * K + k] = h[j];
         }
-        a = bf16x4{(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
-      } else {
+        if (rok)
+          *(uint2*)(g.Aout + row * K + k0) =
+              make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
+        a[ks] = bf16x4{(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
+      } else if (rok) {
         const unsigned short* A = (const unsigned short*)g.A;
-        if (rok) {
-          const uint2 v = *(const uint2*)(A + row * g.lda + k0);
-          a = bf16x4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
-        } else {
-          a = bf16x4{0, 0, 0, 0};
-        }
+        const uint2 v = *(const uint2*)(A + row * g.lda + k0);
+        a[ks] = bf16x4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
       }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks) {
+      if (ks >= nks) break;
+      const int k0 = ks * 16 + ak;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const uint2 w = *(const uint2*)(sW + (t * 16 + ar) * ldl + k0);
         const bf16x4 b{(short)(w.x & 0xffff), (short)(w.x >> 16), (short)(w.y & 0xffff), (short)(w.y >> 16)};
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc[t], 0, 0, 0);
       }
     }
     // epilogue: lane holds rows 4(l/16) + v, column 16 t + l%16
@@ -185,24 +200,49 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   float bsum = 0.f;  // thread t < NG: bias column t
   const int64_t b0 = (int64_t)blockIdx.x * g.chunk;
   const int64_t b1 = b0 + g.chunk < g.B ? b0 + g.chunk : g.B;
+  // A chunk of 64 samples is 16 NG + 16 KA 8-byte words (NG, KA <= 128): at
+  // most eight of each per thread, held in registers so that the next chunk's
+  // loads are in flight during this chunk's matrix-core work
+  constexpr int PW = 8;
+  const int gw = NG / 4, aw = KA / 4;
+  uint2 pg[PW], pa[PW];
+  auto fetch = [&](int64_t c) {
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      const int rg = i / gw, ra = i / aw;
+      pg[j] = (i < 16 * NG && c + rg < b1) ? *(const uint2*)(g.G + (c + rg) * NG + 4 * (i - rg * gw))
+                                           : make_uint2(0u, 0u);
+      pa[j] = (i < 16 * KA && c + ra < b1) ? *(const uint2*)(g.A + (c + ra) * KA + 4 * (i - ra * aw))
+                                           : make_uint2(0u, 0u);
+    }
+  };
+  if (b0 < b1) fetch(b0);
 #pragma unroll 1
   for (int64_t c = b0; c < b1; c += 64) {
     __syncthreads();
-    // 8-byte loads and stores (widths are multiples of 16, rows 8-byte aligned)
-    for (int i = threadIdx.x; i < 16 * NG; i += 256) {
-      const int r = i / (NG / 4), n = 4 * (i - r * (NG / 4));
-      const uint2 v = (c + r < b1) ? *(const uint2*)(g.G + (c + r) * NG + n) : make_uint2(0u, 0u);
-      *(uint2*)(sG + r * ldg + n) = v;
-    }
-    for (int i = threadIdx.x; i < 16 * KA; i += 256) {
-      const int r = i / (KA / 4), k = 4 * (i - r * (KA / 4));
-      const uint2 v = (c + r < b1) ? *(const uint2*)(g.A + (c + r) * KA + k) : make_uint2(0u, 0u);
-      *(uint2*)(sA + r * lda + k) = v;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      const int rg = i / gw, ra = i / aw;
+      if (i < 16 * NG) *(uint2*)(sG + rg * ldg + 4 * (i - rg * gw)) = pg[j];
+      if (i < 16 * KA) *(uint2*)(sA + ra * lda + 4 * (i - ra * aw)) = pa[j];
     }
     __syncthreads();
-    if (threadIdx.x < NG)
-      for (int r = 0; r < 64; ++r) bsum += bf2f(sG[r * ldg + threadIdx.x]);
-#pragma unroll 1
+    if (c + 64 < b1) fetch(c + 64);
+    if (threadIdx.x < NG) {
+      // sequential over the samples (fixed order); the LDS reads are issued
+      // ahead of the adds
+#pragma unroll
+      for (int r0 = 0; r0 < 64; r0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = bf2f(sG[(r0 + r) * ldg + threadIdx.x]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) bsum += v[r];
+      }
+    }
+#pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       // A operand: row n, k-index sample; B operand: k-index sample, column k
       const int sb = ks * 16 + 4 * (lane >> 4);
@@ -242,14 +282,30 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   if (threadIdx.x < g.nvalid) out[(int64_t)g.nvalid * g.kvalid + threadIdx.x] = bsum;
 }
 
-// gradient = sum over the workgroup partials, in workgroup order
-__global__ void reduce_parts_kernel(const float* __restrict__ part, int nparts, int64_t stride,
-                                    int64_t n, float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// gradient = sum over the workgroup partials in a fixed order: wave w of a
+// workgroup sums the partials p = w mod 4 in increasing p for 64 consecutive
+// entries, then the four wave sums are added in wave order
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restrict__ part, int nparts,
+                                                           int64_t stride, int64_t n,
+                                                           float* __restrict__ out) {
+  __shared__ float sw[4][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * stride + i];
-  out[i] = s;
+  if (i < n) {
+    int p = wid;
+    for (; p + 28 < nparts; p += 32) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(p + 4 * j) * stride + i];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; p < nparts; p += 4) s += part[(int64_t)p * stride + i];
+  }
+  sw[wid][lane] = s;
+  __syncthreads();
+  if (wid == 0 && i < n) out[i] = ((sw[0][lane] + sw[1][lane]) + sw[2][lane]) + sw[3][lane];
 }
 
 // Adam with bias correction on the FP32 master parameters; the bfloat16 copies
@@ -326,81 +382,107 @@ __global__ __launch_bounds__(256) void column_stats_kernel(const float* __restri
 }
 
 // ---------------------------------------------------------------- order maps
-// One thread per element.  Samples x = [P (U - U_inf) field-major, rx ry sx sy]
-// (from_hi) or [(U_lo - U_inf), rx ry sx sy]; targets t = U_hi - I P U_hi;
-// apply: U_hi = I U_lo + Y.
-__global__ void closure_features_kernel(ClosureDev c, const double* __restrict__ U, int from_hi,
-                                        float* __restrict__ X, int64_t ldx) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One thread per (element, field).  Samples x = [P (U - U_inf) field-major,
+// rx ry sx sy] (from_hi) or [(U_lo - U_inf), rx ry sx sy]; targets
+// t = U_hi - I P U_hi; apply: U_hi = I U_lo + Y.  A thread's input row and
+// intermediate row live in LDS columns (thread t at word t of every row, so the
+// lanes of a wave touch consecutive banks); the operator entries are
+// wave-uniform loads.  Sums run in increasing node order.
+constexpr int kMapThreads = 64;
+
+__device__ __forceinline__ double field_of(const double v[4], int f) {
+  return f == 0 ? v[0] : (f == 1 ? v[1] : (f == 2 ? v[2] : v[3]));
+}
+
+__global__ __launch_bounds__(kMapThreads) void closure_features_kernel(ClosureDev c, const double* __restrict__ U,
+                                                                       int from_hi, float* __restrict__ X,
+                                                                       int64_t ldx) {
+  __shared__ double sv[kMaxNodes * kMapThreads];
+  const int64_t gid = (int64_t)blockIdx.x * kMapThreads + threadIdx.x;
+  const int64_t k = gid >> 2;
+  const int f = (int)(gid & 3);
   if (k >= c.K) return;
   const int nl = c.np_lo, nh = c.np_hi;
+  const double u0 = field_of(c.U_inf, f);
   float* x = X + k * ldx;
-  for (int f = 0; f < 4; ++f) {
-    const double u0 = c.U_inf[f];
-    if (from_hi) {
-      const double* u = U + (k * 4 + f) * nh;
-      for (int m = 0; m < nl; ++m) {
-        double s = 0.0;
-        for (int n = 0; n < nh; ++n) s += c.P[m * nh + n] * (u[n] - u0);
-        x[f * nl + m] = (float)s;
-      }
-    } else {
-      const double* u = U + (k * 4 + f) * nl;
-      for (int m = 0; m < nl; ++m) x[f * nl + m] = (float)(u[m] - u0);
-    }
-  }
-  for (int j = 0; j < 4; ++j) x[4 * nl + j] = (float)c.geo[k * kGeoStride + j];
-}
-
-__global__ void closure_targets_kernel(ClosureDev c, const double* __restrict__ U,
-                                       float* __restrict__ T, int64_t ldt) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= c.K) return;
-  const int nl = c.np_lo, nh = c.np_hi;
-  for (int f = 0; f < 4; ++f) {
+  if (from_hi) {
     const double* u = U + (k * 4 + f) * nh;
-    double lo[kMaxNodes];
+    double* col = sv + threadIdx.x;
+#pragma unroll 8
+    for (int n = 0; n < nh; ++n) col[n * kMapThreads] = u[n] - u0;
     for (int m = 0; m < nl; ++m) {
-      double s = 0.0;
-      for (int n = 0; n < nh; ++n) s += c.P[m * nh + n] * u[n];
-      lo[m] = s;
+      double acc = 0.0;
+      for (int n = 0; n < nh; ++n) acc += c.P[m * nh + n] * col[n * kMapThreads];
+      x[f * nl + m] = (float)acc;
     }
-    for (int n = 0; n < nh; ++n) {
-      double s = 0.0;
-      for (int m = 0; m < nl; ++m) s += c.I[n * nl + m] * lo[m];
-      T[k * ldt + f * nh + n] = (float)(u[n] - s);
-    }
+  } else {
+    const double* u = U + (k * 4 + f) * nl;
+    for (int m = 0; m < nl; ++m) x[f * nl + m] = (float)(u[m] - u0);
+  }
+  x[4 * nl + f] = (float)c.geo[k * kGeoStride + f];
+}
+
+__global__ __launch_bounds__(kMapThreads) void closure_targets_kernel(ClosureDev c, const double* __restrict__ U,
+                                                                      float* __restrict__ T, int64_t ldt) {
+  __shared__ double sv[2 * kMaxNodes * kMapThreads];
+  const int64_t gid = (int64_t)blockIdx.x * kMapThreads + threadIdx.x;
+  const int64_t k = gid >> 2;
+  const int f = (int)(gid & 3);
+  if (k >= c.K) return;
+  const int nl = c.np_lo, nh = c.np_hi;
+  const double* u = U + (k * 4 + f) * nh;
+  double* col = sv + threadIdx.x;                             // the row
+  double* lo = sv + kMaxNodes * kMapThreads + threadIdx.x;    // P row
+#pragma unroll 8
+  for (int n = 0; n < nh; ++n) col[n * kMapThreads] = u[n];
+  for (int m = 0; m < nl; ++m) {
+    double acc = 0.0;
+    for (int n = 0; n < nh; ++n) acc += c.P[m * nh + n] * col[n * kMapThreads];
+    lo[m * kMapThreads] = acc;
+  }
+  for (int n = 0; n < nh; ++n) {
+    double acc = 0.0;
+    for (int m = 0; m < nl; ++m) acc += c.I[n * nl + m] * lo[m * kMapThreads];
+    T[k * ldt + f * nh + n] = (float)(col[n * kMapThreads] - acc);
   }
 }
 
-__global__ void closure_restrict_kernel(ClosureDev c, const double* __restrict__ Uhi,
-                                        double* __restrict__ Ulo) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kMapThreads) void closure_restrict_kernel(ClosureDev c, const double* __restrict__ Uhi,
+                                                                       double* __restrict__ Ulo) {
+  __shared__ double sv[kMaxNodes * kMapThreads];
+  const int64_t gid = (int64_t)blockIdx.x * kMapThreads + threadIdx.x;
+  const int64_t k = gid >> 2;
+  const int f = (int)(gid & 3);
   if (k >= c.K) return;
   const int nl = c.np_lo, nh = c.np_hi;
-  for (int f = 0; f < 4; ++f) {
-    const double* u = Uhi + (k * 4 + f) * nh;
-    for (int m = 0; m < nl; ++m) {
-      double s = 0.0;
-      for (int n = 0; n < nh; ++n) s += c.P[m * nh + n] * u[n];
-      Ulo[(k * 4 + f) * nl + m] = s;
-    }
+  const double* u = Uhi + (k * 4 + f) * nh;
+  double* col = sv + threadIdx.x;
+#pragma unroll 8
+  for (int n = 0; n < nh; ++n) col[n * kMapThreads] = u[n];
+  for (int m = 0; m < nl; ++m) {
+    double acc = 0.0;
+    for (int n = 0; n < nh; ++n) acc += c.P[m * nh + n] * col[n * kMapThreads];
+    Ulo[(k * 4 + f) * nl + m] = acc;
   }
 }
 
-__global__ void closure_apply_kernel(ClosureDev c, const double* __restrict__ Ulo,
-                                     const float* __restrict__ Y, int64_t ldy,
-                                     double* __restrict__ Uhi) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kMapThreads) void closure_apply_kernel(ClosureDev c, const double* __restrict__ Ulo,
+                                                                    const float* __restrict__ Y, int64_t ldy,
+                                                                    double* __restrict__ Uhi) {
+  __shared__ double sv[kMaxNodes * kMapThreads];
+  const int64_t gid = (int64_t)blockIdx.x * kMapThreads + threadIdx.x;
+  const int64_t k = gid >> 2;
+  const int f = (int)(gid & 3);
   if (k >= c.K) return;
   const int nl = c.np_lo, nh = c.np_hi;
-  for (int f = 0; f < 4; ++f) {
-    const double* u = Ulo + (k * 4 + f) * nl;
-    for (int n = 0; n < nh; ++n) {
-      double s = 0.0;
-      for (int m = 0; m < nl; ++m) s += c.I[n * nl + m] * u[m];
-      Uhi[(k * 4 + f) * nh + n] = s + (Y ? (double)Y[k * ldy + f * nh + n] : 0.0);
-    }
+  const double* u = Ulo + (k * 4 + f) * nl;
+  double* col = sv + threadIdx.x;
+#pragma unroll 8
+  for (int m = 0; m < nl; ++m) col[m * kMapThreads] = u[m];
+  for (int n = 0; n < nh; ++n) {
+    double acc = 0.0;
+    for (int m = 0; m < nl; ++m) acc += c.I[n * nl + m] * col[m * kMapThreads];
+    Uhi[(k * 4 + f) * nh + n] = acc + (Y ? (double)Y[k * ldy + f * nh + n] : 0.0);
   }
 }
 
@@ -545,7 +627,7 @@ int mlp_backward(const MlpDev& d, const float* X, int64_t ldx, const float* T, i
     w.B = B; w.chunk = chunk; w.part = d.part;
     if ((rc = wgrad(w, parts, s, err))) return rc;
     const int64_t n = (int64_t)w.nvalid * w.kvalid + w.nvalid;  // W then b: contiguous
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s,
                        (const float*)d.part, parts, n, n, d.grad + layers[l].off);
     if ((rc = lerr(err, "reduce kernel launch"))) return rc;
   }
@@ -574,30 +656,32 @@ int column_stats(const float* A, int64_t rows, int64_t ld, int cols, double* par
   return lerr(err, "column statistics kernel launch");
 }
 
+dim3 map_grid(int64_t K) { return dim3((unsigned)((4 * K + kMapThreads - 1) / kMapThreads)); }
+
 int closure_features(const ClosureDev& c, const double* U, int from_hi, float* X, int64_t ldx,
                      void* stream, std::string& err) {
-  hipLaunchKernelGGL(closure_features_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+  hipLaunchKernelGGL(closure_features_kernel, map_grid(c.K), dim3(kMapThreads), 0,
                      (hipStream_t)stream, c, U, from_hi, X, ldx);
   return lerr(err, "closure features kernel launch");
 }
 
 int closure_targets(const ClosureDev& c, const double* U, float* T, int64_t ldt, void* stream,
                     std::string& err) {
-  hipLaunchKernelGGL(closure_targets_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+  hipLaunchKernelGGL(closure_targets_kernel, map_grid(c.K), dim3(kMapThreads), 0,
                      (hipStream_t)stream, c, U, T, ldt);
   return lerr(err, "closure targets kernel launch");
 }
 
 int closure_restrict(const ClosureDev& c, const double* Uhi, double* Ulo, void* stream,
                      std::string& err) {
-  hipLaunchKernelGGL(closure_restrict_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+  hipLaunchKernelGGL(closure_restrict_kernel, map_grid(c.K), dim3(kMapThreads), 0,
                      (hipStream_t)stream, c, Uhi, Ulo);
   return lerr(err, "closure restrict kernel launch");
 }
 
 int closure_apply(const ClosureDev& c, const double* Ulo, const float* Y, int64_t ldy, double* Uhi,
                   void* stream, std::string& err) {
-  hipLaunchKernelGGL(closure_apply_kernel, dim3((unsigned)((c.K + 127) / 128)), dim3(128), 0,
+  hipLaunchKernelGGL(closure_apply_kernel, map_grid(c.K), dim3(kMapThreads), 0,
                      (hipStream_t)stream, c, Ulo, Y, ldy, Uhi);
   return lerr(err, "closure apply kernel launch");
 }
