@@ -80,7 +80,9 @@ void release(dg_batch* b) {
 // Work of one tile of order p relative to the others (operator products and
 // face work both grow like Np (Np + 3 Nfp)); used to share the resident
 // workgroups of a single launch among the order groups.
-double tile_cost(int p) { return (double)np_of(p) * (np_of(p) + 3 * (p + 1)); }
+double tile_cost(int p) {
+  return (double)dgmi::elements_per_tile(p) * np_of(p) * (np_of(p) + 3 * (p + 1));
+}
 
 // Workgroups for each group and the launches of one stage, for the current
 // shape.  Group block counts are multiples of 8 (one tile range per XCD).
@@ -283,7 +285,8 @@ static int batch_build(dg_batch* b, dg_ctx* const* ctxs, int n) {
     it.buf[0] = b->A[i];
     it.buf[1] = b->B[i];
     it.K1 = b->K1[i];
-    const int64_t ntiles = (c->K + 3) / 4;
+    const int ept = dgmi::elements_per_tile(c->N);
+    const int64_t ntiles = (c->K + ept - 1) / ept;
     if (b->groups.empty() || b->groups.back().p != c->N) {
       dgmi::BatchGroup g{};
       g.p = c->N;

@@ -10,6 +10,11 @@ namespace dgmi {
 constexpr int kMaxOrder = 8;
 constexpr int kGeoStride = 16;   // doubles per element in the geometry table
 
+// Elements per tile of the stage kernel (one wavefront's unit of work): four,
+// or three at orders 5 and 6, where four elements' 3(p + 1) face nodes each
+// (72, 84) would take two passes over the 64 lanes and three (54, 63) take one.
+constexpr int elements_per_tile(int N) { return (N == 5 || N == 6) ? 3 : 4; }
+
 // Reference-element operators, row-major, FP64 (built once on K^).
 struct RefOps {
   int N = 0, Np = 0, Nfp = 0;

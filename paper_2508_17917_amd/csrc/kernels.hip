@@ -1,7 +1,7 @@
 // HIP kernels for gfx950: the fused right-hand side + low-storage RK stage,
 // and the wall-force reduction.
 //
-// Stage kernel, per wavefront and tile of four elements, in the order of
+// Stage kernel, per wavefront and tile of four element slots, in the order of
 // Alg. 2 (the neighbour exchange becomes reads of the neighbours' nodal
 // states, resident in HBM / L2 on one GPU):
 //   1  own states, neighbour states and geometry -> LDS
@@ -63,7 +63,8 @@ struct Order {
   // padded LDS rows (odd: no bank aliasing), long enough for the k-steps
   static constexpr int RS = (BF && 16 * KS16 > 4 * KS ? 16 * KS16 : 4 * KS) + 1;
   static constexpr int HRS = (BF && 16 * KF16 > 4 * KF ? 16 * KF16 : 4 * KF) + 1;
-  static constexpr int FIT = (4 * NF + 63) / 64; // face items per lane
+  static constexpr int EPT = elements_per_tile(N);  // elements per tile (4 slots)
+  static constexpr int FIT = (EPT * NF + 63) / 64;  // face items per lane
   // default waves per workgroup (each wave owns its own tiles; the workgroup
   // shares the operator fragments)
   // (4 measured fastest for every order and form on MI355X: the fragments
@@ -244,8 +245,11 @@ __device__ __forceinline__ const float* frag_of<bf16ops>(const DeviceTables& t) 
 }
 
 // The fused right-hand side + LSERK stage for the tiles tile0, tile0 + stride,
-// ... < tile_end of one mesh, run by one wavefront.  A tile is four elements
-// (16 matrix-core rows = 4 fields x 4 elements).  sFrag holds the operator
+// ... < tile_end of one mesh, run by one wavefront.  A tile has four element
+// slots (16 matrix-core rows = 4 fields x 4 elements) and holds EPT elements:
+// four, or three at orders 5 and 6 so that its face nodes fit one pass over
+// the lanes (the fourth slot then idles like those of a ragged last tile).
+// sFrag holds the operator
 // fragments (shared by the workgroup), sU this wave's LDS area (WAVE_SZ
 // elements, pads zeroed once), sConn 12 ints of this wave.
 template <int N, typename X, bool PERT>
@@ -263,7 +267,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   typedef typename Vec4<T>::type V4;
   constexpr int Np = O::Np, Nfp = O::Nfp, NF = O::NF, S = O::S, NT = O::NT, KS = O::KS,
                 KF = O::KF, RS = O::RS, HRS = O::HRS, FIT = O::FIT, ROWC = O::ROWC,
-                ROWE = O::ROWE;
+                ROWE = O::ROWE, EPT = O::EPT;
   constexpr int OFF_DR = 0, OFF_DS = O::FD, OFF_L = 2 * O::FD, OFF_LR = 2 * O::FD + O::FL,
                 OFF_LS = 2 * O::FD + 2 * O::FL;
   const int lane = threadIdx.x & 63;
@@ -327,8 +331,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   double rg = 0.0;
   int rc = 0;
   auto load_own = [&](int64_t tl) {
-    const int64_t b = tl * 4;
-    const int ne = (int)((K - b) < 4 ? (K - b) : 4);
+    const int64_t b = tl * EPT;
+    const int ne = (int)((K - b) < EPT ? (K - b) : EPT);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -340,8 +344,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   load_own(tile0);
 
   for (int64_t tile = tile0; tile < tile_end; tile += stride) {
-    const int64_t e0 = tile * 4;
-    const int nel = (int)((K - e0) < 4 ? (K - e0) : 4);
+    const int64_t e0 = tile * EPT;
+    const int nel = (int)((K - e0) < EPT ? (K - e0) : EPT);
     wave_sync();
     // ---- own states, geometry, connectivity (loaded ahead).  Lane l owns
     // values r = l + 64 q of every element block, so addresses are a per-lane
@@ -750,7 +754,7 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
   __shared__ int sConnW[W * 12];
   stage_lds_init<N, X, W>(frag_of<X>(t), sFrag, sWave);
   const int wid = threadIdx.x >> 6;
-  const int64_t ntiles = (t.K + 3) / 4;
+  const int64_t ntiles = (t.K + O::EPT - 1) / O::EPT;
   const int xcd = blockIdx.x & 7;
   const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
   const int64_t w0 = (int64_t)(blockIdx.x >> 3) * W + wid;
@@ -991,7 +995,8 @@ int launch_stage_t(const StageTuning& tune, const DeviceTables& t, const KernelP
                    int rhs_only, hipStream_t s, std::string& err) {
   static int cache[kMaxDev] = {0};
   const int resident = resident_blocks(stage_kernel<N, T, PERT, W>, 64 * W, cache);
-  const int64_t grid = stage_grid((t.K + 3) / 4, W, resident, tune.grid);
+  constexpr int EPT = elements_per_tile(N);
+  const int64_t grid = stage_grid((t.K + EPT - 1) / EPT, W, resident, tune.grid);
   hipLaunchKernelGGL((stage_kernel<N, T, PERT, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, t,
                      ph, Uin, Uout, K1, a, b, dt, rhs_only);
   return launch_error(err, "stage kernel launch");
