@@ -85,6 +85,23 @@ def algorithmic_flops_per_element(Np, Nfp):
     return 32 * Np * Np + 24 * Np * NF + 75 * Np + (16 * Np + 460) * NF + 16 * Np
 
 
+def closure_bytes_per_sample(n_in, H, n_out):
+    """HBM bytes per sample of one training step of the layer-by-layer
+    schedule: every stored quantity written once and read once by each
+    consumer.  Inputs FP32 (n_in) and targets FP32 (n_out); the normalised
+    inputs (padded to 16), activations, GELU derivatives and back-propagated
+    gradients bfloat16 (output gradient padded to 64).  Forward: read x, write
+    x_n, g1, h1; read h1, write g2, h2; read h2 and t, write dy.  Backward:
+    read dy and g2, write dz2; read dz2 and g1, write dz1.  Weight gradients:
+    read (dz1, x_n), (dz2, h1), (dy, h2).  The per-step weight traffic and the
+    weight-gradient partials do not grow with the batch and are left out."""
+    in_pad, out_pad = (n_in + 15) // 16 * 16, 64
+    fwd = 4 * n_in + 2 * in_pad + 2 * H + 2 * H + 2 * H + 2 * H + 2 * H + 2 * H + 4 * n_out + 2 * out_pad
+    bwd = 2 * out_pad + 2 * H + 2 * H + 2 * H + 2 * H + 2 * H
+    wgr = 2 * H + 2 * in_pad + 2 * H + 2 * H + 2 * out_pad + 2 * H
+    return fwd + bwd + wgr
+
+
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -350,6 +367,7 @@ def run_closure(args):
     steps = args.epochs * (N // args.batch)
     samples = steps * args.batch
     flops_sample = 2.0 * (28 * 128 + 128 * 128 + 128 * 60)
+    bytes_sample = closure_bytes_per_sample(28, 128, 60)
     # evaluation at Re = 120
     lo, hi, U_inf = pair(120.0)
     cl.rebind(lo, hi)
@@ -398,10 +416,15 @@ def run_closure(args):
                    "loss_last": losses[-1] if losses else None, "data_s": t_data,
                    "eval": evals, "inference_us_per_state": t_inf * 1e6,
                    "inference_elements_per_s": K / t_inf},
-        "roofline": {"bound": "mfma", "achieved": 3 * flops_sample * samples / t_train / 1e12,
-                     "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": 3 * flops_sample * samples / t_train / 1e12 / 2500.0,
-                     "traffic": None, "kernel": "dense_kernel / wgrad_kernel (training step)"},
+        "roofline": {"bound": "hbm", "achieved": bytes_sample * samples / t_train / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bytes_sample * samples / t_train / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "kernel": "dense_kernel / wgrad_kernel / reduce_parts_kernel / adam_kernel "
+                               "(one training step)",
+                     "bytes_per_sample": bytes_sample,
+                     "mfma_tflops": 3 * flops_sample * samples / t_train / 1e12,
+                     "mfma_frac": 3 * flops_sample * samples / t_train / 1e12 / 2500.0},
     }
     cl.close()
     for a, b in keep:

@@ -93,7 +93,7 @@ int mlp_build(dg_mlp* m, int n_in, int n_hidden, int n_out, int64_t max_batch) {
   d.ldwt[2] = d.out_pad;
   const int wb_rows[3] = {n_hidden, n_hidden, d.out_pad};
   const int wt_rows[3] = {d.in_pad, n_hidden, n_hidden};
-  d.nparts = 256;  // weight-gradient workgroups: one per CU at most batch sizes
+  d.nparts = 512;  // weight-gradient workgroups: two per CU at most batch sizes
   const int64_t B = max_batch;
   const int64_t part_len = (int64_t)n_hidden * n_hidden + n_hidden;
   hipError_t e;
@@ -109,8 +109,8 @@ int mlp_build(dg_mlp* m, int n_in, int n_hidden, int n_out, int64_t max_batch) {
       (e = dalloc(m, &d.wt[2], (size_t)wt_rows[2] * d.ldwt[2])) != hipSuccess ||
       (e = dalloc(m, &m->norm, 4 * 64)) != hipSuccess ||
       (e = dalloc(m, &d.Xn, (size_t)B * d.in_pad)) != hipSuccess ||
-      (e = dalloc(m, &d.Z1, (size_t)B * n_hidden)) != hipSuccess ||
-      (e = dalloc(m, &d.Z2, (size_t)B * n_hidden)) != hipSuccess ||
+      (e = dalloc(m, &d.G1, (size_t)B * n_hidden)) != hipSuccess ||
+      (e = dalloc(m, &d.G2, (size_t)B * n_hidden)) != hipSuccess ||
       (e = dalloc(m, &d.H1, (size_t)B * n_hidden)) != hipSuccess ||
       (e = dalloc(m, &d.H2, (size_t)B * n_hidden)) != hipSuccess ||
       (e = dalloc(m, &d.dY, (size_t)B * d.out_pad)) != hipSuccess ||

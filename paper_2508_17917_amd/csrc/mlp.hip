@@ -24,10 +24,22 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+// GELU (erf form) and its derivative from one exponential:
+//   gelu(z) = z Phi(z), gelu'(z) = Phi(z) + z phi(z), Phi(z) = (1 + erf(z/sqrt2))/2,
+// with erfc(x) = (a1 t + ... + a5 t^5) exp(-x^2), t = 1/(1 + p x), x >= 0
+// (Abramowitz and Stegun, formula 7.1.26; absolute error <= 1.5e-7, far below
+// the bfloat16 rounding of everything the layers store).  Phi(z) is taken as
+// erfc(|x|)/2 on the negative side, so there is no cancellation there.
+__device__ __forceinline__ void gelu_pair(float z, float& g, float& gp) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float e = __expf(-x * x);                 // exp(-z^2/2)
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float half_erfc = 0.5f * poly * e;        // Phi(-|z|)
+  const float Phi = z >= 0.f ? 1.0f - half_erfc : half_erfc;
+  g = z * Phi;
+  gp = Phi + z * e * 0.39894228040143268f;        // 1/sqrt(2 pi)
 }
 
 // ---------------------------------------------------------------- dense layer
@@ -50,7 +62,8 @@ struct DenseArgs {
   int K, ldw;
   const float* bias;         // [N] (EPI_GELU, EPI_OUT, EPI_LOSS)
   int nvalid;                // valid output columns
-  float* Z;                  // EPI_GELU: pre-activation out [B][N]; EPI_DGELU: pre-activation in
+  unsigned short* Gd;        // GELU derivative at the pre-activations, bfloat16 [B][N]:
+                             // EPI_GELU output (skipped when null), EPI_DGELU input
   unsigned short* H;         // EPI_GELU / EPI_LOSS / EPI_DGELU output bfloat16 [B][N]
   float* Y;                  // EPI_OUT output [B][ldy]
   int64_t ldy;
@@ -63,39 +76,30 @@ struct DenseArgs {
   int64_t B;
 };
 
-constexpr int KSMAX = 8;  // dense layers take K <= 128 inputs
+constexpr int KSMAX = 8;        // dense layers take K <= 128 inputs
+constexpr int kDenseWaves = 8;  // one 16-row tile per wave; the workgroup shares the weights
 
 template <int NT, int EPI, bool NORM_IN>
-__global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
+__global__ __launch_bounds__(64 * kDenseWaves) void dense_kernel(DenseArgs g) {
   constexpr int N = 16 * NT;
   extern __shared__ unsigned char smem[];
   const int K = g.K;
   const int ldl = K + 4;  // padded LDS row: rows start 2 banks apart
   unsigned short* sW = (unsigned short*)smem;
   double* sLoss = (double*)(smem + ((N * ldl * 2 + 15) / 16) * 16);
-  // 8-byte words (K and ldw are multiples of 16, rows 8-byte aligned), all of a
-  // thread's loads in flight together
-  const int kw = K / 4;
-#pragma unroll 8
-  for (int i = threadIdx.x; i < N * kw; i += blockDim.x) {
-    const int n = i / kw, k = 4 * (i - n * kw);
-    *(uint2*)(sW + n * ldl + k) = *(const uint2*)(g.W + (int64_t)n * g.ldw + k);
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int ar = lane & 15, ak = 4 * (lane >> 4);
   const int64_t ntiles = (g.B + 15) / 16;
-  double loss = 0.0;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wid; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t row = tile * 16 + ar;
+  const int64_t stride = (int64_t)gridDim.x * kDenseWaves;
+  const int nks = K / 16;
+  // a tile's inputs in registers: the whole A row slice (K <= 16 KSMAX) and
+  // what the epilogue reads (the stored GELU derivative, the targets for the
+  // loss), all issued together so that one memory latency covers them
+  bf16x4 a[KSMAX];
+  float ez[NT][4];
+  auto load_tile = [&](int64_t tl) {
+    const int64_t row = tl * 16 + ar;
     const bool rok = row < g.B;
-    f32x4 acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // the tile's whole A row slice is loaded first (K <= 16 KSMAX), so one
-    // memory latency covers every k-step
-    const int nks = K / 16;
-    bf16x4 a[KSMAX];
 #pragma unroll
     for (int ks = 0; ks < KSMAX; ++ks) {
       a[ks] = bf16x4{0, 0, 0, 0};
@@ -121,6 +125,49 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
       }
     }
 #pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c0 = t * 16 + ak;
+      if (EPI == EPI_DGELU) {
+        uint2 w = make_uint2(0u, 0u);
+        if (rok) w = *(const uint2*)(g.Gd + row * N + c0);
+        ez[t][0] = bf2f((unsigned short)(w.x & 0xffff));
+        ez[t][1] = bf2f((unsigned short)(w.x >> 16));
+        ez[t][2] = bf2f((unsigned short)(w.y & 0xffff));
+        ez[t][3] = bf2f((unsigned short)(w.y >> 16));
+      } else if (EPI == EPI_LOSS) {
+        // four consecutive targets: one 16-byte load where the row stride and
+        // the columns allow it
+        const float* tp = g.T + row * g.ldt + c0;
+        if (rok && c0 + 3 < g.nvalid && (g.ldt & 3) == 0 && (((uintptr_t)g.T) & 15) == 0) {
+          const float4 q = *(const float4*)tp;
+          ez[t][0] = q.x; ez[t][1] = q.y; ez[t][2] = q.z; ez[t][3] = q.w;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ez[t][v] = (rok && c0 + v < g.nvalid) ? tp[v] : 0.f;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ez[t][v] = 0.f;
+      }
+    }
+  };
+  int64_t tile = (int64_t)blockIdx.x * kDenseWaves + wid;
+  load_tile(tile);
+  // weights: 8-byte words (K and ldw are multiples of 16, rows 8-byte aligned),
+  // all of a thread's loads in flight together
+  const int kw = K / 4;
+#pragma unroll 8
+  for (int i = threadIdx.x; i < N * kw; i += blockDim.x) {
+    const int n = i / kw, k = 4 * (i - n * kw);
+    *(uint2*)(sW + n * ldl + k) = *(const uint2*)(g.W + (int64_t)n * g.ldw + k);
+  }
+  __syncthreads();
+  double loss = 0.0;
+  for (; tile < ntiles; tile += stride) {
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int ks = 0; ks < KSMAX; ++ks) {
       if (ks >= nks) break;
       const int k0 = ks * 16 + ak;
@@ -128,45 +175,63 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs g) {
       for (int t = 0; t < NT; ++t) {
         const uint2 w = *(const uint2*)(sW + (t * 16 + ar) * ldl + k0);
         const bf16x4 b{(short)(w.x & 0xffff), (short)(w.x >> 16), (short)(w.y & 0xffff), (short)(w.y >> 16)};
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b, a[ks], acc[t], 0, 0, 0);
       }
     }
-    // epilogue: lane holds rows 4(l/16) + v, column 16 t + l%16
+    // the product is formed transposed (weights as the row operand), so lane l
+    // holds sample row l%16 of the tile and the four consecutive output columns
+    // 16 t + 4(l/16) + v: the bfloat16 outputs go out as one 8-byte store each
+    const int64_t r = tile * 16 + ar;
+    const bool rok = r < g.B;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int col = t * 16 + ar;
+      const int c0 = t * 16 + ak;
+      unsigned short h[4] = {0, 0, 0, 0}, hd[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t r = tile * 16 + 4 * (lane >> 4) + v;
-        if (r >= g.B) continue;
+        const int col = c0 + v;
         const float s = acc[t][v];
         if (EPI == EPI_GELU) {
           const float z = s + g.bias[col];
-          g.Z[r * N + col] = z;
-          g.H[r * N + col] = f2bf(gelu(z));
+          float act, der;
+          gelu_pair(z, act, der);
+          h[v] = f2bf(act);
+          hd[v] = f2bf(der);
         } else if (EPI == EPI_OUT) {
-          if (col < g.nvalid) g.Y[r * g.ldy + col] = g.out_mean[col] + g.out_std[col] * (s + g.bias[col]);
+          if (rok && col < g.nvalid) g.Y[r * g.ldy + col] = g.out_mean[col] + g.out_std[col] * (s + g.bias[col]);
         } else if (EPI == EPI_LOSS) {
           float d = 0.f;
-          if (col < g.nvalid) {
-            const float tn = (g.T[r * g.ldt + col] - g.out_mean[col]) / g.out_std[col];
+          if (rok && col < g.nvalid) {
+            const float tn = (ez[t][v] - g.out_mean[col]) / g.out_std[col];
             const float res = s + g.bias[col] - tn;
             loss += (double)res * (double)res;
             d = g.loss_scale * res;
           }
-          g.H[r * N + col] = f2bf(d);
+          h[v] = f2bf(d);
         } else {  // EPI_DGELU
-          g.H[r * N + col] = f2bf(s * gelu_grad(g.Z[r * N + col]));
+          h[v] = f2bf(s * ez[t][v]);
         }
       }
+      if (EPI != EPI_OUT && rok) {
+        *(uint2*)(g.H + r * N + c0) =
+            make_uint2((unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16));
+        if (EPI == EPI_GELU && g.Gd)
+          *(uint2*)(g.Gd + r * N + c0) =
+              make_uint2((unsigned)hd[0] | ((unsigned)hd[1] << 16), (unsigned)hd[2] | ((unsigned)hd[3] << 16));
+      }
     }
+    if (tile + stride < ntiles) load_tile(tile + stride);
   }
   if (EPI == EPI_LOSS) {
     // fixed-shape reduction of the squared residuals of this workgroup
     for (int o = 32; o > 0; o >>= 1) loss += __shfl_down(loss, o, 64);
     if (lane == 0) sLoss[wid] = loss;
     __syncthreads();
-    if (threadIdx.x == 0) g.loss_part[blockIdx.x] = sLoss[0] + sLoss[1] + sLoss[2] + sLoss[3];
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kDenseWaves; ++w) t += sLoss[w];
+      g.loss_part[blockIdx.x] = t;
+    }
   }
 }
 
@@ -497,11 +562,13 @@ int lerr(std::string& err, const char* what) {
   return 0;
 }
 
-size_t dense_lds(int N, int K) { return ((size_t)N * (K + 4) * 2 + 15) / 16 * 16 + 4 * sizeof(double); }
+size_t dense_lds(int N, int K) {
+  return ((size_t)N * (K + 4) * 2 + 15) / 16 * 16 + kDenseWaves * sizeof(double);
+}
 
 template <int NT, int EPI, bool NORM>
 int dense_go(const DenseArgs& a, int blocks, hipStream_t s, std::string& err) {
-  hipLaunchKernelGGL((dense_kernel<NT, EPI, NORM>), dim3(blocks), dim3(256), dense_lds(16 * NT, a.K), s, a);
+  hipLaunchKernelGGL((dense_kernel<NT, EPI, NORM>), dim3(blocks), dim3(64 * kDenseWaves), dense_lds(16 * NT, a.K), s, a);
   return lerr(err, "dense kernel launch");
 }
 
@@ -546,10 +613,11 @@ int wgrad(const WgradArgs& a, int blocks, hipStream_t s, std::string& err) {
   return -5;
 }
 
-// two 16-row tiles per wave: the weight staging in LDS is shared by eight tiles
+// one 16-row tile per wave (grid-stride beyond 1024 workgroups, the size of the
+// loss partial buffer)
 int dense_blocks(int64_t B) {
   const int64_t tiles = (B + 15) / 16;
-  const int64_t b = (tiles + 7) / 8;
+  const int64_t b = (tiles + kDenseWaves - 1) / kDenseWaves;
   return (int)(b < 1024 ? (b > 0 ? b : 1) : 1024);
 }
 }  // namespace
@@ -564,13 +632,13 @@ int mlp_forward(const MlpDev& d, const float* X, int64_t ldx, int64_t B, float* 
   // layer 1 (normalised inputs)
   a.A = X; a.lda = ldx; a.in_mean = d.in_mean; a.in_rstd = d.in_rstd; a.Aout = d.Xn;
   a.kvalid = d.n_in; a.W = d.wb[0]; a.K = d.in_pad; a.ldw = d.ldw[0]; a.bias = d.params + d.boff[0];
-  a.Z = d.Z1; a.H = d.H1;
+  a.H = d.H1;
   int rc = dense(NTH, EPI_GELU, true, a, blocks, s, err);
   if (rc) return rc;
   // layer 2
   a = DenseArgs{}; a.B = B;
   a.A = d.H1; a.lda = d.H; a.W = d.wb[1]; a.K = d.H; a.ldw = d.ldw[1]; a.bias = d.params + d.boff[1];
-  a.Z = d.Z2; a.H = d.H2;
+  a.H = d.H2;
   rc = dense(NTH, EPI_GELU, false, a, blocks, s, err);
   if (rc) return rc;
   // layer 3 (denormalised outputs)
@@ -590,12 +658,12 @@ int mlp_backward(const MlpDev& d, const float* X, int64_t ldx, const float* T, i
   a.B = B;
   a.A = X; a.lda = ldx; a.in_mean = d.in_mean; a.in_rstd = d.in_rstd; a.Aout = d.Xn;
   a.kvalid = d.n_in; a.W = d.wb[0]; a.K = d.in_pad; a.ldw = d.ldw[0]; a.bias = d.params + d.boff[0];
-  a.Z = d.Z1; a.H = d.H1;
+  a.Gd = d.G1; a.H = d.H1;
   int rc = dense(NTH, EPI_GELU, true, a, blocks, s, err);
   if (rc) return rc;
   a = DenseArgs{}; a.B = B;
   a.A = d.H1; a.lda = d.H; a.W = d.wb[1]; a.K = d.H; a.ldw = d.ldw[1]; a.bias = d.params + d.boff[1];
-  a.Z = d.Z2; a.H = d.H2;
+  a.Gd = d.G2; a.H = d.H2;
   if ((rc = dense(NTH, EPI_GELU, false, a, blocks, s, err))) return rc;
   // output layer + loss: dY = 2 (y - t) / (B n_out) in normalised units
   a = DenseArgs{}; a.B = B;
@@ -603,15 +671,15 @@ int mlp_backward(const MlpDev& d, const float* X, int64_t ldx, const float* T, i
   a.nvalid = d.n_out; a.T = T; a.ldt = ldt; a.out_mean = d.out_mean; a.out_std = d.out_std;
   a.loss_scale = (float)(2.0 / ((double)B * d.n_out)); a.loss_part = d.loss_part; a.H = d.dY;
   if ((rc = dense(NTO, EPI_LOSS, false, a, blocks, s, err))) return rc;
-  // dZ2 = (dY W3) * gelu'(Z2): W3^T is [H][out_pad]
+  // dZ2 = (dY W3) * gelu'(Z2): W3^T is [H][out_pad]; gelu' as stored by the forward pass
   a = DenseArgs{}; a.B = B;
   a.A = d.dY; a.lda = d.out_pad; a.W = d.wt[2]; a.K = d.out_pad; a.ldw = d.ldwt[2];
-  a.Z = d.Z2; a.H = d.dZ2;
+  a.Gd = d.G2; a.H = d.dZ2;
   if ((rc = dense(NTH, EPI_DGELU, false, a, blocks, s, err))) return rc;
   // dZ1 = (dZ2 W2) * gelu'(Z1)
   a = DenseArgs{}; a.B = B;
   a.A = d.dZ2; a.lda = d.H; a.W = d.wt[1]; a.K = d.H; a.ldw = d.ldwt[1];
-  a.Z = d.Z1; a.H = d.dZ1;
+  a.Gd = d.G1; a.H = d.dZ1;
   if ((rc = dense(NTH, EPI_DGELU, false, a, blocks, s, err))) return rc;
   // weight gradients: partials per workgroup, then a fixed-order sum
   const int64_t chunk = ((B + d.nparts - 1) / d.nparts + 63) / 64 * 64;

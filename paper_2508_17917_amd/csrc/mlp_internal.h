@@ -31,8 +31,8 @@ struct MlpDev {
   const float* out_std;
   // activations, [max_batch][width]
   unsigned short* Xn;          // normalised inputs, bfloat16 [B][in_pad]
-  float* Z1;                   // pre-activations, FP32 [B][H]
-  float* Z2;
+  unsigned short* G1;          // GELU derivative at the pre-activations, bfloat16 [B][H]
+  unsigned short* G2;
   unsigned short* H1;          // activations, bfloat16 [B][H]
   unsigned short* H2;
   unsigned short* dY;          // [B][out_pad]

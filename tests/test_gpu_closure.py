@@ -8,9 +8,12 @@ Network tolerance.  The GPU rounds every matrix-core operand to bfloat16
 bfloat16 weights and normalised inputs and computes everything else in FP64.
 What remains is the rounding of the activations and back-propagated
 quantities fed to the next product: about 2u per product, three products
-forward and five backward, so the normwise relative error is bounded by
-about 6u ~ 1.2e-2 forward and 10u ~ 2e-2 for the gradients; the bounds below
-are 1.5e-2 and 3e-2.
+forward and five backward, plus the bfloat16 GELU derivative the forward pass
+stores for the backward one (u at each of the two hidden layers), so the
+normwise relative error is bounded by about 6u ~ 1.2e-2 forward and
+12u ~ 2.3e-2 for the gradients; the bounds below are 1.5e-2 and 3e-2.  The
+GPU's erf (Abramowitz and Stegun 7.1.26, absolute error 1.5e-7) is far inside
+these.
 """
 import numpy as np
 import pytest
