@@ -25,6 +25,9 @@ struct dg_batch {
   int* h_parity = nullptr;
   double* d_force = nullptr;
   double* h_force = nullptr;
+  dgmi::ForceItem* d_fitems = nullptr;  // wall-force launch descriptors
+  dgmi::ForceItem* h_fitems = nullptr;  // pinned staging
+  std::vector<int> inst_of;             // item -> instance
   hipEvent_t upload_ev = nullptr;
   bool upload_pending = false;
   int mode = 0, waves = 0, grid = 0, use_graph = 1;
@@ -67,12 +70,13 @@ void release(dg_batch* b) {
   for (auto* v : {&b->A, &b->B, &b->K1})
     for (double* p : *v)
       if (p) (void)hipFree(p);
-  void* dev[] = {b->d_items, b->d_steps, b->d_parity, b->d_force};
+  void* dev[] = {b->d_items, b->d_steps, b->d_parity, b->d_force, b->d_fitems};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (b->h_steps) (void)hipHostFree(b->h_steps);
   if (b->h_parity) (void)hipHostFree(b->h_parity);
   if (b->h_force) (void)hipHostFree(b->h_force);
+  if (b->h_fitems) (void)hipHostFree(b->h_fitems);
   if (b->upload_ev) (void)hipEventDestroy(b->upload_ev);
   if (b->cap) (void)hipStreamDestroy(b->cap);
 }
@@ -262,6 +266,7 @@ static int batch_build(dg_batch* b, dg_ctx* const* ctxs, int n) {
   for (int i = 0; i < n; ++i) idx[i] = i;
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return ctxs[x]->N < ctxs[y]->N; });
   b->item_of.assign(n, 0);
+  b->inst_of = idx;
   std::vector<dgmi::BatchItem> items(n);
   b->A.assign(n, nullptr);
   b->B.assign(n, nullptr);
@@ -313,6 +318,8 @@ static int batch_build(dg_batch* b, dg_ctx* const* ctxs, int n) {
       (e = hipHostMalloc((void**)&b->h_steps, n * sizeof(dgmi::BatchStep))) != hipSuccess ||
       (e = hipHostMalloc((void**)&b->h_parity, sizeof(int))) != hipSuccess ||
       (e = hipHostMalloc((void**)&b->h_force, 4 * n * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&b->d_fitems, n * sizeof(dgmi::ForceItem))) != hipSuccess ||
+      (e = hipHostMalloc((void**)&b->h_fitems, n * sizeof(dgmi::ForceItem))) != hipSuccess ||
       (e = hipEventCreateWithFlags(&b->upload_ev, hipEventDisableTiming)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
     return bhip(b, e, "allocating batch tables");
@@ -368,17 +375,42 @@ int dg_batch_force(dg_batch* b, const double* v_w, double* out, void* stream) {
   if (!out) return bfail(b, DG_EINVAL, "out is NULL");
   hipStream_t s = (hipStream_t)stream;
   std::string err;
-  for (int i = 0; i < b->n; ++i) {
-    dg_ctx* c = b->ctx[i];
-    const double vw[2] = {v_w ? v_w[2 * i] : 0.0, v_w ? v_w[2 * i + 1] : 0.0};
-    if (c->mesh.wall_faces.empty()) {
-      hipError_t e = hipMemsetAsync(b->d_force + 4 * i, 0, 3 * sizeof(double), s);
-      if (e != hipSuccess) return bhip(b, e, "hipMemsetAsync");
-      continue;
+  // one launch per order group over the instances that have wall faces; the
+  // others report zero
+  struct Launch { int N, first, count, blocks; };
+  std::vector<Launch> launches;
+  int pos = 0;
+  for (const dgmi::BatchGroup& g : b->groups) {
+    const int first = pos;
+    int blocks = 0;
+    for (int j = g.first_item; j < g.first_item + g.n_items; ++j) {
+      const int i = b->inst_of[j];
+      dg_ctx* c = b->ctx[i];
+      if (c->mesh.wall_faces.empty()) {
+        hipError_t e = hipMemsetAsync(b->d_force + 4 * i, 0, 3 * sizeof(double), s);
+        if (e != hipSuccess) return bhip(b, e, "hipMemsetAsync");
+        continue;
+      }
+      const double vw[2] = {v_w ? v_w[2 * i] : 0.0, v_w ? v_w[2 * i + 1] : 0.0};
+      dgmi::ForceItem& f = b->h_fitems[pos++];
+      f.t = dgmi::ctx_tables(c);
+      f.ph = dgmi::ctx_phys(c, vw);
+      f.U = b->parity ? b->B[i] : b->A[i];
+      f.out = b->d_force + 4 * i;
+      f.block_begin = blocks;
+      f.nblocks = c->force_blocks;
+      blocks += c->force_blocks;
     }
-    const double* U = b->parity ? b->B[i] : b->A[i];
-    int rc = dgmi::launch_force(c->N, dgmi::ctx_tables(c), dgmi::ctx_phys(c, vw), U,
-                                b->d_force + 4 * i, s, err);
+    if (pos > first) launches.push_back({g.p, first, pos - first, blocks});
+  }
+  if (pos > 0) {
+    // the staging is free again: the previous call ended with a synchronisation
+    hipError_t e = hipMemcpyAsync(b->d_fitems, b->h_fitems, pos * sizeof(dgmi::ForceItem),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return bhip(b, e, "uploading force descriptors");
+  }
+  for (const Launch& l : launches) {
+    int rc = dgmi::launch_batch_force(l.N, b->d_fitems + l.first, l.count, l.blocks, s, err);
     if (rc != 0) return bfail(b, rc, err);
   }
   hipError_t e = hipMemcpyAsync(b->h_force, b->d_force, 4 * b->n * sizeof(double),

@@ -103,6 +103,13 @@ struct BatchItem {              // one instance, in device memory
   double* K1;
   int64_t tile_begin, tile_end; // its tiles in the numbering of its group
 };
+struct ForceItem {              // one instance's wall force in a batched launch (device memory)
+  DeviceTables t;
+  KernelPhysics ph;             // with the wall velocity of the state
+  const double* U;
+  double* out;                  // Fx, Fy, Mz
+  int block_begin, nblocks;     // its workgroups within the launch of its order
+};
 struct BatchStep {              // per instance and step, in device memory
   double dt;
   double vw[2];
@@ -125,6 +132,10 @@ int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchS
                        double b, void* stream, std::string& err);
 // one thread per wall face node, 64 per workgroup
 int force_blocks_for(int N, int nwall);
+// the wall forces of `count` instances of order N in one launch of `blocks`
+// workgroups (items in device memory, block ranges consecutive from 0)
+int launch_batch_force(int N, const ForceItem* items, int count, int blocks, void* stream,
+                       std::string& err);
 int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
                  double* out_dev, void* stream, std::string& err);
 // operator packing: Dr | Ds | LIFT | LIFTr | LIFTs | Fmask (as doubles) | wface

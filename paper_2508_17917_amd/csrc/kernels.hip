@@ -839,10 +839,11 @@ batch_stage_kernel(const BatchItem* __restrict__ items, const BatchStep* __restr
 // partials in workgroup order and resets the ticket: deterministic, one
 // launch, no host synchronisation and no wait inside the kernel.
 constexpr int kForceThreads = 64;
+// Workgroup blk of the nblk that cover one mesh's wall face nodes.
 template <int N>
-__global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, KernelPhysics ph,
-                                                              const double* __restrict__ U,
-                                                              double* __restrict__ out) {
+__device__ __forceinline__ void force_block(const DeviceTables& t, const KernelPhysics& ph,
+                                            const double* __restrict__ U, double* __restrict__ out,
+                                            unsigned blk, unsigned nblk) {
   using O = Order<N, double>;
   constexpr int Np = O::Np, Nfp = O::Nfp, S = 4 * Np;
   __shared__ int last;
@@ -857,7 +858,7 @@ __global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, Ke
   const double* wface = t.ops + 2 * Np * Np + 3 * Np * 3 * Nfp;
   double fx = 0.0, fy = 0.0, mz = 0.0;
   const int total = t.nwall * Nfp;
-  const int i = blockIdx.x * kForceThreads + threadIdx.x;
+  const int i = (int)blk * kForceThreads + threadIdx.x;
   if (i < total) {
     const int wf = t.wall[i / Nfp];
     const int j = i % Nfp;
@@ -905,21 +906,40 @@ __global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, Ke
     mz += __shfl_down(mz, o, 64);
   }
   if (threadIdx.x == 0) {
-    t.force_part[3 * blockIdx.x + 0] = fx;
-    t.force_part[3 * blockIdx.x + 1] = fy;
-    t.force_part[3 * blockIdx.x + 2] = mz;
+    t.force_part[3 * blk + 0] = fx;
+    t.force_part[3 * blk + 1] = fy;
+    t.force_part[3 * blk + 2] = mz;
     __threadfence();
-    last = atomicAdd(t.force_ticket, 1u) == gridDim.x - 1;
+    last = atomicAdd(t.force_ticket, 1u) == nblk - 1;
   }
   __syncthreads();
   if (last && threadIdx.x < 3) {
     __threadfence();
     const volatile double* part = t.force_part;
     double sum = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) sum += part[3 * b + threadIdx.x];
+    for (unsigned b = 0; b < nblk; ++b) sum += part[3 * b + threadIdx.x];
     out[threadIdx.x] = sum;
     if (threadIdx.x == 0) atomicExch(t.force_ticket, 0u);
   }
+}
+
+template <int N>
+__global__ __launch_bounds__(kForceThreads) void force_kernel(DeviceTables t, KernelPhysics ph,
+                                                              const double* __restrict__ U,
+                                                              double* __restrict__ out) {
+  force_block<N>(t, ph, U, out, blockIdx.x, gridDim.x);
+}
+
+// Many meshes of one order: instance i owns the workgroups
+// [block_begin_i, block_begin_i + nblocks_i), each instance reduced through
+// its own partials and ticket.
+template <int N>
+__global__ __launch_bounds__(kForceThreads) void batch_force_kernel(const ForceItem* __restrict__ items,
+                                                                    int count) {
+  int i = 0;
+  while (i + 1 < count && (int)blockIdx.x >= items[i + 1].block_begin) ++i;
+  const ForceItem& it = items[i];
+  force_block<N>(it.t, it.ph, it.U, it.out, blockIdx.x - it.block_begin, it.nblocks);
 }
 
 namespace {
@@ -1112,6 +1132,31 @@ int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchS
 
 int force_blocks_for(int N, int nwall) {
   return (nwall * (N + 1) + kForceThreads - 1) / kForceThreads;
+}
+
+template <int N>
+int launch_batch_force_n(const ForceItem* items, int count, int blocks, hipStream_t s,
+                         std::string& err) {
+  hipLaunchKernelGGL(batch_force_kernel<N>, dim3(blocks), dim3(kForceThreads), 0, s, items, count);
+  return launch_error(err, "batched force kernel launch");
+}
+
+int launch_batch_force(int N, const ForceItem* items, int count, int blocks, void* stream,
+                       std::string& err) {
+  if (count < 1 || blocks < count) {
+    err = "batched force: no instances or fewer workgroups than instances";
+    return -1;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  switch (N) {
+    case 1: return launch_batch_force_n<1>(items, count, blocks, s, err);
+    case 2: return launch_batch_force_n<2>(items, count, blocks, s, err);
+    case 3: return launch_batch_force_n<3>(items, count, blocks, s, err);
+    case 4: return launch_batch_force_n<4>(items, count, blocks, s, err);
+    case 5: return launch_batch_force_n<5>(items, count, blocks, s, err);
+    case 6: return launch_batch_force_n<6>(items, count, blocks, s, err);
+    default: err = "order not built"; return -5;
+  }
 }
 
 int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
