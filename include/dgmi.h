@@ -232,6 +232,21 @@ int dg_batch_rk_step(dg_batch* b, const double* dt, const double* v_w, void* str
  * array of 3n doubles.  Synchronises `stream`. */
 int dg_batch_force(dg_batch* b, const double* v_w, double* out, void* stream);
 
+/* One step of the weakly coupled fluid-structure loop (Alg. 3) for every
+ * instance, each a 1-DOF oscillator M y'' + C y' + K y = s F_y
+ * (eq. 1dof_oscillator, Sec. 3.3.1): the host Newmark step (as
+ * dg_newmark_step) under the last lift, the wall velocity for the step
+ * v_w = (0, (y_new - y)/dt), one RK step of the whole batch (as
+ * dg_batch_rk_step) and the forces on the new states (as dg_batch_force).
+ * Host arrays: osc n x 4 (M, C, K, s), body n x 3 (y, y', y'') updated in
+ * place, F n x 3 whose lifts F[3i+1] are read and which receives the new
+ * forces, dt n doubles, v_w_out n x 2 doubles receiving the wall velocities
+ * (may be NULL).  Synchronises `stream`.  DG_EINVAL (nothing changed) for a
+ * NULL array, a non-positive dt or a singular oscillator; after a failure
+ * of the step itself body may already hold the new displacements. */
+int dg_batch_coupled_step(dg_batch* b, const double* osc, double* body, double* F,
+                          const double* dt, double* v_w_out, void* stream);
+
 /* Launch shape: mode 0 one launch per stage for all instances, 1 one launch
  * per order group; waves and grid as dg_set_tuning; use_graph 0 launches the
  * stages directly instead of replaying the captured graph. */

@@ -55,6 +55,7 @@ SIGNATURES = {
     "dg_batch_get_state": (_I, [_P, _I, _P, _P]),
     "dg_batch_rk_step": (_I, [_P, _DP, _DP, _P]),
     "dg_batch_force": (_I, [_P, _DP, _DP, _P]),
+    "dg_batch_coupled_step": (_I, [_P, _DP, _DP, _DP, _DP, _DP, _P]),
     "dg_batch_configure": (_I, [_P, _I, _I, _I, _I]),
     "dg_batch_autotune": (_I, [_P, _I, _P, _DP]),
     "dg_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -313,6 +314,23 @@ def dg_batch_force(b, n, v_w=None, stream=None):
     out = np.zeros(3 * n)
     _bcheck(load().dg_batch_force(b, _dp(vw), _dp(out), _stream(stream)), b)
     return out.reshape(n, 3)
+
+
+def dg_batch_coupled_step(b, osc, body, F, dt, stream=None):
+    """Newmark under the lifts in F, one batch RK step, new forces; body (n x 3)
+    and F (n x 3) are float64 C-contiguous arrays updated in place.  Returns
+    the wall velocities (n x 2) used for the step."""
+    n = body.shape[0]
+    for name, a, shape in (("body", body, (n, 3)), ("F", F, (n, 3))):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.shape == shape
+                and a.flags.c_contiguous):
+            raise ValueError("%s must be a C-contiguous float64 array of shape %s" % (name, shape))
+    o = np.ascontiguousarray(np.asarray(osc, dtype=np.float64).reshape(n, 4))
+    d = np.ascontiguousarray(np.asarray(dt, dtype=np.float64).reshape(n))
+    vw = np.zeros((n, 2))
+    _bcheck(load().dg_batch_coupled_step(b, _dp(o), _dp(body), _dp(F), _dp(d), _dp(vw),
+                                         _stream(stream)), b)
+    return vw
 
 
 def dg_batch_configure(b, mode=0, waves=0, grid=0, use_graph=1):

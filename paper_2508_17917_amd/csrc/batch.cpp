@@ -422,6 +422,33 @@ int dg_batch_force(dg_batch* b, const double* v_w, double* out, void* stream) {
   return DG_OK;
 }
 
+int dg_batch_coupled_step(dg_batch* b, const double* osc, double* body, double* F,
+                          const double* dt, double* v_w_out, void* stream) {
+  if (!b) return DG_EINVAL;
+  if (!osc || !body || !F || !dt) return bfail(b, DG_EINVAL, "osc, body, F and dt are required");
+  const int n = b->n;
+  std::vector<double> st(3 * n), vw(2 * n);
+  for (int i = 0; i < n; ++i) {
+    const double* o = osc + 4 * i;
+    double* y = st.data() + 3 * i;
+    y[0] = body[3 * i];
+    y[1] = body[3 * i + 1];
+    y[2] = body[3 * i + 2];
+    if (dg_newmark_step(y, F[3 * i + 1] * o[3], dt[i], o[0], o[1], o[2]) != DG_OK)
+      return bfail(b, DG_EINVAL, "Newmark step: non-positive dt or singular oscillator");
+    vw[2 * i] = 0.0;
+    vw[2 * i + 1] = (y[0] - body[3 * i]) / dt[i];
+  }
+  for (int k = 0; k < 3 * n; ++k) body[k] = st[k];
+  int rc = dg_batch_rk_step(b, dt, vw.data(), stream);
+  if (rc != DG_OK) return rc;
+  rc = dg_batch_force(b, vw.data(), F, stream);
+  if (rc != DG_OK) return rc;
+  if (v_w_out)
+    for (int k = 0; k < 2 * n; ++k) v_w_out[k] = vw[k];
+  return DG_OK;
+}
+
 int dg_batch_configure(dg_batch* b, int mode, int waves, int grid, int use_graph) {
   if (!b) return DG_EINVAL;
   if ((mode != 0 && mode != 1) || (waves != 0 && waves != 2 && waves != 4) ||

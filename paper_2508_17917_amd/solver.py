@@ -122,6 +122,12 @@ class Batch:
     def force(self, v_w=None, stream=None):
         return L.dg_batch_force(self.b, self.n, v_w, stream)
 
+    def coupled_step(self, osc, body, F, dt, stream=None):
+        """Newmark (host) of every instance under its lift in F, one RK step
+        with the resulting wall velocities, the new forces into F; body and F
+        are updated in place (float64 n x 3).  Returns the wall velocities."""
+        return L.dg_batch_coupled_step(self.b, osc, body, F, dt, stream)
+
     def configure(self, mode=0, waves=0, grid=0, use_graph=True):
         L.dg_batch_configure(self.b, mode, waves, grid, 1 if use_graph else 0)
 

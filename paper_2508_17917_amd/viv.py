@@ -40,6 +40,7 @@ class VIVSweep:
         v_inf = float(np.hypot(U_inf[1], U_inf[2]) / U_inf[0])
         self.coef = [oscillator(c["U_star"], c["m_star"], c["xi"], v_inf, U_inf[0], c.get("D", 1.0))
                      for c in cases]
+        self.osc = np.array(self.coef, dtype=np.float64)  # M, C, K, 1/m per instance
         self.body = np.zeros((self.n, 3))   # y, y', y'' per instance
         self.vw = np.zeros((self.n, 2))
         self.F = np.zeros((self.n, 3))      # Fx, Fy, Mz on the current states
@@ -52,18 +53,17 @@ class VIVSweep:
         return self.batch.get_state(i, out, stream)
 
     def update_forces(self, stream=None):
-        self.F = self.batch.force(self.vw, stream)
+        self.F = np.ascontiguousarray(self.batch.force(self.vw, stream))
         return self.F
 
     def step(self, dt, stream=None):
+        """Newmark under the last forces, one RK step of every instance with
+        the resulting wall velocities, forces on the new states -- one library
+        call for the whole batch."""
         dts = np.broadcast_to(np.asarray(dt, dtype=np.float64), (self.n,)).copy()
-        for i, (M, C, K, inv_m) in enumerate(self.coef):
-            st = L.dg_newmark_step(self.body[i], self.F[i, 1] * inv_m, dts[i], M, C, K)
-            self.vw[i] = (0.0, (st[0] - self.body[i, 0]) / dts[i])
-            self.body[i] = st
-        self.batch.rk_step(dts, self.vw, stream)
+        self.vw = self.batch.coupled_step(self.osc, self.body, self.F, dts, stream)
         self.t += float(dts.max())
-        return self.update_forces(stream)
+        return self.F
 
     def close(self):
         self.batch.close()

@@ -242,3 +242,52 @@ def test_batch_viv16_full_size_equals_single_instances():
     b.close()
     for s in solvers:
         s.close()
+
+
+def test_coupled_step_equals_its_parts():
+    """dg_batch_coupled_step (Newmark, batch RK step, batch forces in one call)
+    gives the same bits as the three steps taken one call at a time."""
+    torch = _torch()
+    from paper_2508_17917_amd import Batch, Solver
+    from paper_2508_17917_amd import _lib as L
+    from paper_2508_17917_amd.viv import oscillator
+    phys = dict(gamma=1.4, Pr=0.72, mu=1e-2, theta=1.0, penalty_mode=0, C_pen=1.0,
+                U_inf=mg.free_stream(0.2))
+    meshes = [(mg.ogrid(10, 4, 0.5, 5.0, 1.3), 3), (mg.ogrid(12, 4, 0.5, 5.0, 1.3), 4),
+              (mg.ogrid(9, 4, 0.5, 5.0, 1.3), 5)]
+    batches, Us = [], []
+    for copy in range(2):
+        solvers = [Solver(p, m, precision=2, **phys) for m, p in meshes]
+        b = Batch(solvers)
+        for i, s in enumerate(solvers):
+            U = mg.noisy_free_stream((4, s.Np, s.K), phys["U_inf"], mg.rng_for(3, salt=i))
+            b.set_state(i, _to_dev(torch, U))
+        batches.append((b, solvers))
+    n = len(meshes)
+    osc = np.array([oscillator(u, 10.0, 0.01, 0.2) for u in (4.0, 5.5, 7.0)])
+    dt = np.array([1e-4, 2e-4, 1.5e-4])
+    body_a, body_b = np.zeros((n, 3)), np.zeros((n, 3))
+    F_a = np.ascontiguousarray(batches[0][0].force())
+    F_b = batches[1][0].force()
+    assert np.array_equal(F_a, F_b)
+    _say("coupled step vs parts, %d instances, 3 steps" % n)
+    for step in range(3):
+        vw_a = batches[0][0].coupled_step(osc, body_a, F_a, dt)
+        vw_b = np.zeros((n, 2))
+        for i in range(n):
+            M, C, K, s = osc[i]
+            st = L.dg_newmark_step(body_b[i], F_b[i, 1] * s, dt[i], M, C, K)
+            vw_b[i] = (0.0, (st[0] - body_b[i, 0]) / dt[i])
+            body_b[i] = st
+        batches[1][0].rk_step(dt, vw_b)
+        F_b = batches[1][0].force(vw_b)
+        assert np.array_equal(vw_a, vw_b) and np.array_equal(body_a, body_b), step
+        assert np.array_equal(F_a, F_b), step
+        for i in range(n):
+            assert torch.equal(batches[0][0].get_state(i), batches[1][0].get_state(i)), (step, i)
+    with pytest.raises(L.DGError):
+        batches[0][0].coupled_step(osc, body_a, F_a, np.array([1e-4, 0.0, 1e-4]))
+    for b, solvers in batches:
+        b.close()
+        for s in solvers:
+            s.close()
