@@ -231,7 +231,7 @@ def run_viv(cases, phys, states, precision, steps, warmup, dts, batched):
     """Coupled sweep: per step Newmark under the last force, v_w = dy/dt, one
     RK step of every instance (batched: one launch per stage for all; else one
     launch per stage and instance), forces.  Returns (states, timed seconds,
-    stage seconds or None, solvers)."""
+    stage seconds or None, solvers, batch launch shape or None)."""
     import numpy as np
     import torch
 
@@ -245,6 +245,10 @@ def run_viv(cases, phys, states, precision, steps, warmup, dts, batched):
         for i, U in enumerate(states):
             sw.set_state(i, U)
         t_launch = sw.batch.autotune(reps=20) / 1e6
+        mode, waves, grid, _ = sw.batch.get_config()
+        shape = "%s, %d waves/workgroup, %s" % (
+            ("one launch per stage for all orders", "one launch per order group and stage")[mode],
+            waves, ("persistent grid", "one tile per wave")[grid])
         sw.update_forces()
         for _ in range(warmup):
             sw.step(dts)
@@ -256,7 +260,7 @@ def run_viv(cases, phys, states, precision, steps, warmup, dts, batched):
         torch.cuda.synchronize()
         out = [sw.get_state(i) for i in range(len(cases))]
         torch.cuda.synchronize()
-        return out, ev0.elapsed_time(ev1) / 1e3, t_launch, sw.solvers
+        return out, ev0.elapsed_time(ev1) / 1e3, t_launch, sw.solvers, shape
     U_inf = np.asarray(phys["U_inf"])
     solvers = [make_solver(dict(phys), c["p"], c["mesh"], precision) for c in cases]
     Us = [U.clone() for U in states]
@@ -284,7 +288,7 @@ def run_viv(cases, phys, states, precision, steps, warmup, dts, batched):
         step()
     ev1.record(stream)
     torch.cuda.synchronize()
-    return Us, ev0.elapsed_time(ev1) / 1e3, None, solvers
+    return Us, ev0.elapsed_time(ev1) / 1e3, None, solvers, None
 
 
 def rel_l2(solvers, got, ref, U_inf):
@@ -487,22 +491,24 @@ def main():
             desc.append("%dx%d p%d" % (c["ntheta"], c["nr"], c["p"]))
         dts = np.array(dts)
         log("viv16 (%s): chosen form %s batched" % (", ".join(desc), args.form))
-        U, t_steps, t_launch, solvers = run_viv(cases, phys, states, prec, args.steps,
-                                                args.warmup, dts, batched=True)
+        U, t_steps, t_launch, solvers, shape = run_viv(cases, phys, states, prec, args.steps,
+                                                       args.warmup, dts, batched=True)
         log("plain fp64 beside it (one launch per stage and instance)")
-        U64, t64, _, solvers64 = run_viv(cases, phys, states, FORMS["fp64"], args.steps,
-                                         args.warmup, dts, batched=False)
+        U64, t64, _, solvers64, _ = run_viv(cases, phys, states, FORMS["fp64"], args.steps,
+                                            args.warmup, dts, batched=False)
         finite = all(bool(torch.isfinite(u).all().item()) for u in U)
         err = rel_l2(solvers64, U, U64, U_inf)
         tl64 = None
         config = {"workload": "viv16: 16 elastically mounted cylinders (m*=10, xi=0, U* = "
                               "linspace(3,8)), O-grids %s, total K=%d, Re=100, M=0.2, SIPG, "
-                              "coupled to host Newmark each step, batched one launch per stage "
-                              "+ HIP graph, %s form" % (", ".join(desc),
-                                                        sum(s.K for s in solvers64), args.form),
+                              "coupled to host Newmark each step, batched (the stages of a "
+                              "step replayed from a HIP graph), %s form" % (
+                                  ", ".join(desc), sum(s.K for s in solvers64), args.form),
                   "instances": len(cases), "dofs": dofs, "form": args.form,
+                  "launch_shape": shape,
                   "dt": [float(x) for x in dts], "finite": finite}
-        kernel = "batch_stage_kernel<%s>" % args.form
+        kernel = ("batch_stage_kernel<%s>" if shape.startswith("one launch per stage")
+                  else "batch_order_kernel<p, %s> (one launch per order)") % args.form
         cpu = None
     else:
         w = mg.workload(args.workload, args.p)

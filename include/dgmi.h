@@ -248,9 +248,14 @@ int dg_batch_coupled_step(dg_batch* b, const double* osc, double* body, double* 
                           const double* dt, double* v_w_out, void* stream);
 
 /* Launch shape: mode 0 one launch per stage for all instances, 1 one launch
- * per order group; waves and grid as dg_set_tuning; use_graph 0 launches the
+ * per order group (in a kernel sized for that order); waves as
+ * dg_set_tuning, grid 0 persistent or 1 one tile per wave; use_graph 0 launches the
  * stages directly instead of replaying the captured graph. */
 int dg_batch_configure(dg_batch* b, int mode, int waves, int grid, int use_graph);
+
+/* The batch's current launch shape (as dg_batch_configure takes it; after
+ * dg_batch_autotune, the one it picked).  Any pointer may be NULL. */
+int dg_batch_get_config(const dg_batch* b, int* mode, int* waves, int* grid, int* use_graph);
 
 /* Time every (mode, waves, grid) on the batch (reps first-stage launches
  * each; the states are left unchanged, K1 is overwritten) and keep the

@@ -56,6 +56,7 @@ SIGNATURES = {
     "dg_batch_rk_step": (_I, [_P, _DP, _DP, _P]),
     "dg_batch_force": (_I, [_P, _DP, _DP, _P]),
     "dg_batch_coupled_step": (_I, [_P, _DP, _DP, _DP, _DP, _DP, _P]),
+    "dg_batch_get_config": (_I, [_P] + [ctypes.POINTER(_I)] * 4),
     "dg_batch_configure": (_I, [_P, _I, _I, _I, _I]),
     "dg_batch_autotune": (_I, [_P, _I, _P, _DP]),
     "dg_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -331,6 +332,13 @@ def dg_batch_coupled_step(b, osc, body, F, dt, stream=None):
     _bcheck(load().dg_batch_coupled_step(b, _dp(o), _dp(body), _dp(F), _dp(d), _dp(vw),
                                          _stream(stream)), b)
     return vw
+
+
+def dg_batch_get_config(b):
+    """(mode, waves, grid, use_graph) of the batch's current launch shape."""
+    v = [ctypes.c_int() for _ in range(4)]
+    _bcheck(load().dg_batch_get_config(b, *[ctypes.byref(x) for x in v]), b)
+    return tuple(x.value for x in v)
 
 
 def dg_batch_configure(b, mode=0, waves=0, grid=0, use_graph=1):

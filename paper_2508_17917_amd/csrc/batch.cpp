@@ -107,7 +107,8 @@ int plan(dg_batch* b) {
     if (b->grid == 1) {
       blocks = need[g];
     } else if (b->mode == 1) {
-      blocks = std::min<int64_t>(need[g], resident / 8 * 8);
+      const int res = dgmi::batch_order_resident_blocks(b->groups[g].p, b->form, W);
+      blocks = std::min<int64_t>(need[g], res / 8 * 8);
     } else {
       const double share = b->groups[g].ntiles * tile_cost(b->groups[g].p) / total;
       blocks = std::min<int64_t>(need[g], (int64_t)(share * resident) / 8 * 8);
@@ -146,9 +147,16 @@ int plan(dg_batch* b) {
 int launch_stage_i(dg_batch* b, int stage, hipStream_t s) {
   std::string err;
   for (size_t l = 0; l < b->launches.size(); ++l) {
-    int rc = dgmi::launch_batch_stage(b->form, b->plan_waves, b->d_items, b->d_steps, b->d_parity,
-                                      b->launches[l], b->launch_blocks[l], stage, dgmi::kRkA[stage],
-                                      dgmi::kRkB[stage], s, err);
+    // one launch for all groups, or one per group in a kernel sized for its order
+    const dgmi::BatchGroups& G = b->launches[l];
+    int rc = b->mode == 0
+                 ? dgmi::launch_batch_stage(b->form, b->plan_waves, b->d_items, b->d_steps,
+                                            b->d_parity, G, b->launch_blocks[l], stage,
+                                            dgmi::kRkA[stage], dgmi::kRkB[stage], s, err)
+                 : dgmi::launch_batch_order_stage(G.g[0].p, b->form, b->plan_waves, b->d_items,
+                                                  b->d_steps, b->d_parity, G.g[0],
+                                                  b->launch_blocks[l], stage, dgmi::kRkA[stage],
+                                                  dgmi::kRkB[stage], s, err);
     if (rc != 0) return bfail(b, rc, err);
   }
   return DG_OK;
@@ -460,6 +468,15 @@ int dg_batch_configure(dg_batch* b, int mode, int waves, int grid, int use_graph
   b->use_graph = use_graph ? 1 : 0;
   drop_graph(b);
   return plan(b);
+}
+
+int dg_batch_get_config(const dg_batch* b, int* mode, int* waves, int* grid, int* use_graph) {
+  if (!b) return DG_EINVAL;
+  if (mode) *mode = b->mode;
+  if (waves) *waves = b->plan_waves;
+  if (grid) *grid = b->grid;
+  if (use_graph) *use_graph = b->use_graph;
+  return DG_OK;
 }
 
 int dg_batch_autotune(dg_batch* b, int reps, void* stream, double* best_us) {

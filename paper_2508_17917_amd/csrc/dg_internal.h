@@ -126,6 +126,13 @@ struct BatchGroups {
   BatchGroup g[kMaxOrder];
 };
 int batch_resident_blocks(int form, int waves);
+// the same for the one-order kernel of a group launched on its own
+int batch_order_resident_blocks(int N, int form, int waves);
+// one stage of one order group (g.block_begin = 0), in a kernel sized for order N
+int launch_batch_order_stage(int N, int form, int waves, const BatchItem* items,
+                             const BatchStep* steps, const int* parity, const BatchGroup& g,
+                             int blocks, int stage, double a, double b, void* stream,
+                             std::string& err);
 // stage i of a step reads buf[(parity + i) & 1] and writes the other buffer
 int launch_batch_stage(int form, int waves, const BatchItem* items, const BatchStep* steps,
                        const int* parity, const BatchGroups& G, int blocks, int stage, double a,

@@ -833,6 +833,17 @@ batch_stage_kernel(const BatchItem* __restrict__ items, const BatchStep* __restr
   }
 }
 
+// One order group per launch, sized for its own order: LDS and registers of
+// order N only (the kernel above is sized for the largest order it may meet),
+// so low orders keep the occupancy of the single-mesh kernel.
+template <int N, typename X, bool PERT, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(Order<N, X>::MIN_WAVES_EU))) void
+batch_order_kernel(const BatchItem* __restrict__ items, const BatchStep* __restrict__ steps,
+                   const int* __restrict__ parity, BatchGroup g, int stage, double a, double b) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[BatchLds<X, W>::template of<N>()];
+  batch_group<N, X, PERT, W>(items, steps, parity[0], g, stage, a, b, smem);
+}
+
 // Wall force: one thread per wall face node (in the fixed order of the wall
 // face list), a fixed-shape wave reduction per workgroup, per-workgroup
 // partials, and the last workgroup to finish (an atomic ticket) sums the
@@ -1064,6 +1075,54 @@ int launch_force_n(const DeviceTables& t, const KernelPhysics& ph, const double*
   return launch_error(err, "force kernel launch");
 }
 
+template <int N, typename X, bool PERT, int W>
+int launch_batch_order_t(const BatchItem* items, const BatchStep* steps, const int* parity,
+                         const BatchGroup& g, int blocks, int stage, double a, double b,
+                         hipStream_t s, std::string& err) {
+  hipLaunchKernelGGL((batch_order_kernel<N, X, PERT, W>), dim3((unsigned)blocks), dim3(64 * W), 0, s,
+                     items, steps, parity, g, stage, a, b);
+  return launch_error(err, "batched stage kernel launch");
+}
+
+template <int N, typename X, bool PERT>
+int launch_batch_order_w(int waves, const BatchItem* items, const BatchStep* steps,
+                         const int* parity, const BatchGroup& g, int blocks, int stage, double a,
+                         double b, hipStream_t s, std::string& err) {
+  return waves == 4
+             ? launch_batch_order_t<N, X, PERT, 4>(items, steps, parity, g, blocks, stage, a, b, s, err)
+             : launch_batch_order_t<N, X, PERT, 2>(items, steps, parity, g, blocks, stage, a, b, s, err);
+}
+
+template <int N>
+int launch_batch_order_n(int form, int waves, const BatchItem* items, const BatchStep* steps,
+                         const int* parity, const BatchGroup& g, int blocks, int stage, double a,
+                         double b, hipStream_t s, std::string& err) {
+  switch (form) {
+    case 0: return launch_batch_order_w<N, double, false>(waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 1: return launch_batch_order_w<N, double, true>(waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 2: return launch_batch_order_w<N, float, true>(waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 3: return launch_batch_order_w<N, bf16ops, true>(waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    default: err = "precision mode not built"; return -5;
+  }
+}
+
+template <int N, typename X, bool PERT>
+int batch_order_resident_x(int waves) {
+  static int cache4[kMaxDev] = {0}, cache2[kMaxDev] = {0};
+  return waves == 4 ? resident_blocks(batch_order_kernel<N, X, PERT, 4>, 256, cache4)
+                    : resident_blocks(batch_order_kernel<N, X, PERT, 2>, 128, cache2);
+}
+
+template <int N>
+int batch_order_resident_n(int form, int waves) {
+  switch (form) {
+    case 0: return batch_order_resident_x<N, double, false>(waves);
+    case 1: return batch_order_resident_x<N, double, true>(waves);
+    case 3: return batch_order_resident_x<N, bf16ops, true>(waves);
+    default: return batch_order_resident_x<N, float, true>(waves);
+  }
+}
+
 template <typename T, bool PERT, int W>
 int launch_batch_t(const BatchItem* items, const BatchStep* steps, const int* parity,
                    const BatchGroups& G, int blocks, int stage, double a, double b, hipStream_t s,
@@ -1096,6 +1155,38 @@ int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t
 }
 
 int default_waves(int, int) { return 4; }
+
+int batch_order_resident_blocks(int N, int form, int waves) {
+  switch (N) {
+    case 1: return batch_order_resident_n<1>(form, waves);
+    case 2: return batch_order_resident_n<2>(form, waves);
+    case 3: return batch_order_resident_n<3>(form, waves);
+    case 4: return batch_order_resident_n<4>(form, waves);
+    case 5: return batch_order_resident_n<5>(form, waves);
+    case 6: return batch_order_resident_n<6>(form, waves);
+    default: return 0;
+  }
+}
+
+int launch_batch_order_stage(int N, int form, int waves, const BatchItem* items,
+                             const BatchStep* steps, const int* parity, const BatchGroup& g,
+                             int blocks, int stage, double a, double b, void* stream,
+                             std::string& err) {
+  if (waves != 2 && waves != 4) {
+    err = "waves per workgroup must be 2 or 4";
+    return -1;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  switch (N) {
+    case 1: return launch_batch_order_n<1>(form, waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 2: return launch_batch_order_n<2>(form, waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 3: return launch_batch_order_n<3>(form, waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 4: return launch_batch_order_n<4>(form, waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 5: return launch_batch_order_n<5>(form, waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    case 6: return launch_batch_order_n<6>(form, waves, items, steps, parity, g, blocks, stage, a, b, s, err);
+    default: err = "polynomial order not built"; return -5;
+  }
+}
 
 int batch_resident_blocks(int form, int waves) {
   if (form == 0) return waves == 4 ? batch_resident_t<double, false, 4>() : batch_resident_t<double, false, 2>();

@@ -134,6 +134,10 @@ class Batch:
     def autotune(self, reps=10, stream=None):
         return L.dg_batch_autotune(self.b, reps, stream)
 
+    def get_config(self):
+        """(mode, waves, grid, use_graph) of the current launch shape."""
+        return L.dg_batch_get_config(self.b)
+
     def close(self):
         if self.b is not None:
             L.dg_batch_destroy(self.b)

@@ -82,6 +82,7 @@ def test_batch_steps_equal_single_instance_steps(precision):
                                                         [s.K for s, _ in inst]))
         b = Batch([s for s, _ in inst])
         b.configure(*shape[:3], use_graph=shape[3])
+        assert b.get_config() == (shape[0], shape[1] or 4, shape[2], int(shape[3]))
         ref, K1s = [], []
         for i, (s, U) in enumerate(inst):
             Ud = _to_dev(torch, U)
@@ -126,6 +127,8 @@ def test_batch_autotune_keeps_results():
     _say("batch autotune")
     us = b.autotune(reps=5)
     assert us > 0.0
+    mode, waves, grid, _ = b.get_config()
+    assert mode in (0, 1) and waves in (2, 4) and grid in (0, 1)
     # the timed first-stage launches leave the states alone
     for i in range(n):
         assert torch.equal(b.get_state(i), ref[i])
