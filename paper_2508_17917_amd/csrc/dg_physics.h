@@ -148,10 +148,10 @@ __device__ __forceinline__ void normal_flux_pert(const T Ud[4], const Prim<T>& s
 }
 
 // Per-state quantities shared by the viscous operators: 1/rho, velocity,
-// mu/rho, eps/rho - |v|^2 and the (4,1) entries of G11 and G22.
+// mu/rho and eps/rho - |v|^2.
 template <typename T>
 struct VState {
-  T ir, v1, v2, m, ek, g41a, g41b;
+  T ir, v1, v2, m, ek;
 };
 
 template <typename T>
@@ -163,8 +163,6 @@ __device__ __forceinline__ VState<T> vstate(const Gas<T>& g, const T U[4]) {
   s.m = g.mu * s.ir;
   const T vv = s.v1 * s.v1 + s.v2 * s.v2;
   s.ek = U[3] * s.ir - vv;  // eps/rho - |v|^2, as in the printed (4,1) entries
-  s.g41a = -s.v1 * s.v1 * T(1.0 / 3.0) - vv - g.k * s.ek;
-  s.g41b = -s.v2 * s.v2 * T(1.0 / 3.0) - vv - g.k * s.ek;
   return s;
 }
 
@@ -250,22 +248,24 @@ __device__ __noinline__ double sym3_lambda_max_trig(double s00, double s11, doub
 template <typename T>
 __device__ __forceinline__ T normal_diffusion_norm(const Gas<T>& g, const VState<T>& st, T nx,
                                                    T ny) {
-  const T v1 = st.v1, v2 = st.v2, k = g.k;
-  const T c43 = T(4.0 / 3.0), c23 = T(2.0 / 3.0), c13 = T(1.0 / 3.0);
-  const T xx = nx * nx, xy = nx * ny, yy = ny * ny;
-  // rows of B (the fourth column of the momentum rows is zero)
-  const T a0 = -(c43 * xx + yy) * v1 - c13 * xy * v2, a1 = c43 * xx + yy, a2 = c13 * xy;
-  const T b0 = -(xx + c43 * yy) * v2 - c13 * xy * v1, b1 = c13 * xy, b2 = xx + c43 * yy;
-  const T e0 = xx * st.g41a + yy * st.g41b - c23 * xy * v1 * v2;
-  const T e1 = (c43 - k) * v1 * xx + c13 * v2 * xy + (T(1) - k) * v1 * yy;
-  const T e2 = (T(1) - k) * v2 * xx + c13 * v1 * xy + (c43 - k) * v2 * yy;
-  const T e3 = k * (xx + yy);
-  const T s00 = a0 * a0 + a1 * a1 + a2 * a2;
-  const T s11 = b0 * b0 + b1 * b1 + b2 * b2;
-  const T s22 = e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
-  const T s01 = a0 * b0 + a1 * b1 + a2 * b2;
-  const T s02 = a0 * e0 + a1 * e1 + a2 * e2;
-  const T s12 = b0 * e0 + b1 * e1 + b2 * e2;
+  // B in the face frame: rotating the momentum rows and columns by the same
+  // orthogonal map (x, y) -> (n, t) leaves its singular values unchanged, and
+  // for the unit normal its rows become
+  //   (-4/3 v_n, 4/3, 0, 0), (-v_t, 0, 1, 0), (e0, (4/3 - k) v_n, (1 - k) v_t, k)
+  // with v_n = v.n, v_t = v.t and e0 = -(4/3 v_n^2 + v_t^2 + k ek) (the
+  // energy row's density entry, the same in both frames).
+  const T k = g.k;
+  const T c43 = T(4.0 / 3.0);
+  const T vn = st.v1 * nx + st.v2 * ny, vt = st.v2 * nx - st.v1 * ny;
+  const T vn2 = vn * vn, vt2 = vt * vt;
+  const T e0 = -(c43 * vn2 + vt2 + k * st.ek);
+  const T a = c43 - k, b = T(1) - k;
+  const T s00 = T(16.0 / 9.0) * (vn2 + T(1));
+  const T s11 = vt2 + T(1);
+  const T s22 = e0 * e0 + a * a * vn2 + b * b * vt2 + k * k;
+  const T s01 = c43 * vn * vt;
+  const T s02 = c43 * vn * (a - e0);
+  const T s12 = vt * (b - e0);
   // characteristic polynomial lambda^3 - c2 lambda^2 + c1 lambda - c0
   const T c2 = s00 + s11 + s22;
   const T c1 = s00 * s11 + s00 * s22 + s11 * s22 - s01 * s01 - s02 * s02 - s12 * s12;
