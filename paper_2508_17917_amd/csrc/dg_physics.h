@@ -194,6 +194,26 @@ __device__ __forceinline__ void viscous_flux(const Gas<T>& g, const VState<T>& s
   Fy[3] = m * (v1 * txy + v2 * tyy + k * ey);
 }
 
+// The same flux projected on n: Fn = Fx nx + Fy ny, formed from the normal
+// stress and heat-flux components directly.
+template <typename T>
+__device__ __forceinline__ void viscous_normal_flux(const Gas<T>& g, const VState<T>& st,
+                                                    const T dx[4], const T dy[4], T nx, T ny,
+                                                    T Fn[4]) {
+  const T v1 = st.v1, v2 = st.v2, m = st.m, k = g.k;
+  const T c43 = T(4.0 / 3.0), c23 = T(2.0 / 3.0);
+  const T ux = dx[1] - v1 * dx[0], vx = dx[2] - v2 * dx[0];
+  const T uy = dy[1] - v1 * dy[0], vy = dy[2] - v2 * dy[0];
+  const T ex = dx[3] - st.ek * dx[0] - v1 * dx[1] - v2 * dx[2];
+  const T ey = dy[3] - st.ek * dy[0] - v1 * dy[1] - v2 * dy[2];
+  const T txx = c43 * ux - c23 * vy, tyy = c43 * vy - c23 * ux, txy = uy + vx;
+  const T tn1 = txx * nx + txy * ny, tn2 = txy * nx + tyy * ny;
+  Fn[0] = T(0);
+  Fn[1] = m * tn1;
+  Fn[2] = m * tn2;
+  Fn[3] = m * (v1 * tn1 + v2 * tn2 + k * (ex * nx + ey * ny));
+}
+
 // q = G(U)^T (n (x) w) = (mu/rho) (T^T z_x, T^T z_y) with z = C^T (n (x) w):
 // qx = nx G11^T w + ny G21^T w, qy = nx G12^T w + ny G22^T w.
 template <typename T>

@@ -530,19 +530,16 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         // mean of G(U+) grad U+ and G(U-) grad U- inside; G(U^b) grad U+ on the
         // wall (grad U+ from the staged copy of the element itself); G(U+) grad U+
         // on the far field
-        T vx[4], vy[4], vn[4];
+        T vn[4];
         if (tag == 1) {
-          viscous_flux(gas, so, gxm, gym, vx, vy);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) vn[c] = vx[c] * nx + vy[c] * ny;
+          viscous_normal_flux(gas, so, gxm, gym, nx, ny, vn);
         } else {
-          viscous_flux(gas, sp, gxp, gyp, vx, vy);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) vn[c] = vx[c] * nx + vy[c] * ny;
+          viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
           if (tag == 0) {
-            viscous_flux(gas, so, gxm, gym, vx, vy);
+            T vm[4];
+            viscous_normal_flux(gas, so, gxm, gym, nx, ny, vm);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) vn[c] = T(0.5) * (vn[c] + vx[c] * nx + vy[c] * ny);
+            for (int c = 0; c < 4; ++c) vn[c] = T(0.5) * (vn[c] + vm[c]);
           }
         }
 #pragma unroll
