@@ -112,6 +112,20 @@ int dg_setup_host(dg_ctx* ctx);
  * current HIP device and allocation of the scratch state buffer. */
 int dg_setup(dg_ctx* ctx);
 
+/* Over-integration (Sec. 2.2, the oversampling remedy for aliasing of the
+ * rational fluxes): with on != 0, every later dg_rhs, dg_rk_stage, dg_rk_step,
+ * dg_rk_steps and dg_autotune of this context evaluates the weak form of eq.
+ * weak_matrices_calc with quadrature exact for degree 3p -- a collapsed
+ * Gauss product rule of q^2 points on the element and Gauss-Legendre with q
+ * points on each face, q = floor((3p + 2) / 2) -- instead of the nodal
+ * interpolants of the fluxes; G-bar_e is then the maximum over the face's
+ * quadrature points.  Same boundary conditions, penalty and theta term.
+ * Plain FP64 form (precision DG_FP64) and p = 1..6 only, else
+ * DG_EUNSUPPORTED; such contexts cannot be batched.  Any time after
+ * dg_create; on = 0 returns to the nodal evaluation.  The tables it needs are
+ * built by dg_setup_host / dg_setup in every case ("oi_*" host tables). */
+int dg_set_overintegration(dg_ctx* ctx, int on);
+
 /* Sizes: number of elements K, nodes per element Np, nodes per face Nfp. */
 int64_t dg_num_elements(const dg_ctx* ctx);
 int dg_num_nodes(const dg_ctx* ctx);
@@ -122,8 +136,15 @@ int dg_num_face_nodes(const dg_ctx* ctx);
  * matrix (V V^T)^-1), "LIFT", "LIFTr", "LIFTs"
  * (Np*3Nfp), "Fmask" (3*Nfp, as doubles), "wface" (3*Nfp face quadrature
  * weights), "geo" (K*16: rx ry sx sy, then per face nx ny Fscale sigma_geo),
- * "nbr" (K*3 neighbour element, as doubles), "nbr_face" (K*3).  count must
- * equal the table size; out is a host array of that many doubles. */
+ * "nbr" (K*3 neighbour element, as doubles), "nbr_face" (K*3); the
+ * over-integration tables (q points per direction, Nq = q^2): "oi_wq" (Nq
+ * element weights), "oi_xg", "oi_wg" (q face points and weights), "oi_Iq",
+ * "oi_Drq", "oi_Dsq" (Nq*Np: l_j and its r/s derivatives at the element
+ * points), "oi_Wr", "oi_Ws" (Np*Nq: M^-1 (d l_i w)^T), "oi_If1" (q*Nfp: face
+ * nodes to face points), "oi_Drf", "oi_Dsf" (3q*Np, face f's points in rows
+ * f*q..), "oi_LIFTq", "oi_LIFTrq", "oi_LIFTsq" (Np*3q: M^-1 (l_i w)^T and with
+ * d_r l_i, d_s l_i).  count must equal the table size; out is a host array of
+ * that many doubles. */
 int dg_get_host_table(const dg_ctx* ctx, const char* name, double* out, int64_t count);
 
 /* Physical node coordinates, host arrays x[K*Np], y[K*Np] (element-major). */

@@ -39,6 +39,7 @@ SIGNATURES = {
     "dg_num_nodes": (_I, [_P]),
     "dg_num_face_nodes": (_I, [_P]),
     "dg_get_host_table": (_I, [_P, ctypes.c_char_p, _DP, _L]),
+    "dg_set_overintegration": (_I, [_P, _I]),
     "dg_get_nodes": (_I, [_P, _DP, _DP]),
     "dg_rhs": (_I, [_P, _P, _P, _DP, _P]),
     "dg_rk_step": (_I, [_P, _P, _P, _D, _DP, _P]),
@@ -154,6 +155,10 @@ def _vw(v_w):
 
 
 # ---- the C-ABI calls ------------------------------------------------------
+def dg_set_overintegration(h, on):
+    return _check(load().dg_set_overintegration(h, 1 if on else 0), h)
+
+
 def dg_create(p, precision=DG_FP64):
     h = ctypes.c_void_p()
     _check(load().dg_create(int(p), int(precision), ctypes.byref(h)))

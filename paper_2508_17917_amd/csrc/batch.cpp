@@ -261,6 +261,8 @@ static int batch_build(dg_batch* b, dg_ctx* const* ctxs, int n) {
     if (!c || !c->dev_ready) return bfail(b, DG_ESTATE, "every context must be set up (dg_setup)");
     if (c->precision != ctxs[0]->precision)
       return bfail(b, DG_EINVAL, "contexts of a batch must share the precision mode");
+    if (c->overint)
+      return bfail(b, DG_EUNSUPPORTED, "over-integrated contexts are not batched");
   }
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);

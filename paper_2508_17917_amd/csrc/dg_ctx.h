@@ -42,6 +42,10 @@ struct dg_ctx {
   int32_t* d_conn = nullptr;
   double* d_ops = nullptr;
   double* d_frag = nullptr;
+  double* d_oi = nullptr;         // over-integration fragments and tables
+  int64_t oi_len = 0;
+  dgmi::OIOps oi;
+  bool overint = false;
   float* d_frag32 = nullptr;
   uint16_t* d_frag16 = nullptr;
   int32_t* d_wall = nullptr;
@@ -59,5 +63,8 @@ namespace dgmi {
 int ctx_fail(dg_ctx* c, int code, const std::string& msg);
 int ctx_hip_fail(dg_ctx* c, hipError_t e, const char* what);
 DeviceTables ctx_tables(const dg_ctx* c);
+// the form launch_stage runs for this context (its precision mode, or the
+// over-integrated FP64 stage)
+inline int ctx_form(const dg_ctx* c) { return c->overint ? kFormOverint : c->precision; }
 KernelPhysics ctx_phys(const dg_ctx* c, const double vw[2]);
 }  // namespace dgmi

@@ -27,6 +27,24 @@ struct RefOps {
   std::vector<double> wface;           // 3 x Nfp face quadrature weights in xi
 };
 
+// Over-integration operators of order N (quadrature exact for degree 3N on
+// the element and on each face), row-major, FP64.
+struct OIOps {
+  int q = 0, Nq = 0;                   // points per direction; q^2 element points
+  std::vector<double> wq;              // Nq element weights
+  std::vector<double> xg, wg;          // q Gauss points and weights in the face parameter
+  std::vector<double> Iq, Drq, Dsq;    // Nq x Np: l_j, d_r l_j, d_s l_j at the element points
+  std::vector<double> Wr, Ws;          // Np x Nq: M^-1 (d_r l_i w)^T, M^-1 (d_s l_i w)^T
+  std::vector<double> If1;             // q x Nfp: face-node values -> face points (any face)
+  std::vector<double> Drf, Dsf;        // 3q x Np: d_r l_j, d_s l_j at the face points
+  std::vector<double> LIFTq, LIFTrq, LIFTsq;  // Np x 3q: M^-1 (l_i w)^T, M^-1 (d_r l_i w)^T, ...
+};
+// launch_stage's form for the over-integrated FP64 stage (the precision modes
+// are 0..3)
+constexpr int kFormOverint = 4;
+// the order's over-integration points per direction (degree 3N exact)
+constexpr int oi_points(int N) { return (3 * N + 2) / 2; }
+
 struct Physics {
   double gamma = 1.4, Pr = 0.72, mu = 0.0, theta = 1.0;
   int penalty_mode = 0;
@@ -49,6 +67,10 @@ struct MeshTables {
 
 // host_setup.cpp
 bool build_ref_ops(int N, RefOps& out, std::string& err);
+bool build_oi_ops(const RefOps& ref, OIOps& out, std::string& err);
+// matrix-core fragments of the over-integration operators, then the face-point
+// tables: (D_r, D_s) pairs of the 3q face-point rows, and If1
+void pack_oi(const RefOps& ref, const OIOps& oi, std::vector<double>& out);
 bool build_mesh_tables(const RefOps& ref, const Physics& phys, int64_t Nv, const double* VX,
                        const double* VY, int64_t K, const int32_t* EToV, const int8_t* face_tag,
                        const double period[2], MeshTables& out, std::string& err);
@@ -61,6 +83,8 @@ struct DeviceTables {
   const double* geo = nullptr;     // K x 16
   const int32_t* conn = nullptr;   // K x 3
   const double* ops = nullptr;     // packed operators (pack_ops)
+  const double* oi = nullptr;      // over-integration fragments and tables (pack_oi)
+  int64_t oi_len = 0;              // its length in doubles
   const double* frag = nullptr;    // operator fragments in matrix-core lane order (pack_frags)
   const float* frag32 = nullptr;   // the same fragments rounded to FP32 (FP32 form)
   const unsigned short* frag16 = nullptr;  // bfloat16 fragments of the 16x16x16 instruction

@@ -30,7 +30,7 @@ int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
 void free_device(dg_ctx* c) {
   void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,       c->d_frag32,
                   c->d_frag16, c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force,
-                  c->d_force_part, c->d_force_ticket};
+                  c->d_force_part, c->d_force_ticket, c->d_oi};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   c->d_geo = nullptr;
@@ -45,6 +45,7 @@ void free_device(dg_ctx* c) {
   c->d_force = nullptr;
   c->d_force_part = nullptr;
   c->d_force_ticket = nullptr;
+  c->d_oi = nullptr;
   c->force_blocks = 0;
   c->dev_ready = false;
 }
@@ -65,6 +66,8 @@ dgmi::DeviceTables tables(const dg_ctx* c) {
   t.conn = c->d_conn;
   t.ops = c->d_ops;
   t.frag = c->d_frag;
+  t.oi = c->d_oi;
+  t.oi_len = c->oi_len;
   t.frag32 = c->d_frag32;
   t.frag16 = c->d_frag16;
   t.wall = c->d_wall;
@@ -167,6 +170,7 @@ int dg_setup_host(dg_ctx* c) {
     return fail(c, DG_ESTATE, "dg_set_physics and dg_set_mesh must precede set-up");
   std::string err;
   if (!dgmi::build_ref_ops(c->N, c->ref, err)) return fail(c, DG_EUNSUPPORTED, err);
+  if (!dgmi::build_oi_ops(c->ref, c->oi, err)) return fail(c, DG_EUNSUPPORTED, err);
   if (!dgmi::build_mesh_tables(c->ref, c->phys, c->Nv, c->VX.data(), c->VY.data(), c->K,
                                c->EToV.data(), c->tag.data(), c->period, c->mesh, err))
     return fail(c, DG_EMESH, err);
@@ -183,19 +187,22 @@ int dg_setup(dg_ctx* c) {
   free_device(c);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
-  std::vector<double> ops, frag;
+  std::vector<double> ops, frag, oi;
   std::vector<float> frag32;
   std::vector<uint16_t> frag16;
   dgmi::pack_ops(c->ref, ops);
   dgmi::pack_frags(c->ref, frag);
   dgmi::pack_frags32(c->ref, frag32);
   dgmi::pack_frags_bf16(c->ref, frag16);
+  dgmi::pack_oi(c->ref, c->oi, oi);
+  c->oi_len = (int64_t)oi.size();
   if ((e = upload(&c->d_geo, c->mesh.geo)) != hipSuccess ||
       (e = upload(&c->d_conn, c->mesh.conn)) != hipSuccess ||
       (e = upload(&c->d_ops, ops)) != hipSuccess ||
       (e = upload(&c->d_frag, frag)) != hipSuccess ||
       (e = upload(&c->d_frag32, frag32)) != hipSuccess ||
       (e = upload(&c->d_frag16, frag16)) != hipSuccess ||
+      (e = upload(&c->d_oi, oi)) != hipSuccess ||
       (e = upload(&c->d_wall, c->mesh.wall_faces)) != hipSuccess ||
       (e = upload(&c->d_wall_xy, c->mesh.wall_xy)) != hipSuccess) {
     free_device(c);
@@ -214,6 +221,15 @@ int dg_setup(dg_ctx* c) {
                                     : hip_fail(c, e, "hipMalloc");
   }
   c->dev_ready = true;
+  return DG_OK;
+}
+
+int dg_set_overintegration(dg_ctx* c, int on) {
+  if (!c) return DG_EINVAL;
+  if (on && c->precision != DG_FP64)
+    return fail(c, DG_EUNSUPPORTED, "over-integration runs in the plain FP64 form only");
+  if (on && (c->N < 1 || c->N > 6)) return fail(c, DG_EUNSUPPORTED, "over-integration is built for p = 1..6");
+  c->overint = on != 0;
   return DG_OK;
 }
 
@@ -242,6 +258,20 @@ int dg_get_host_table(const dg_ctx* cc, const char* name, double* out, int64_t c
   else if (n == "geo") v = m.geo;
   else if (n == "nbr") v.assign(m.nbr.begin(), m.nbr.end());
   else if (n == "nbr_face") v.assign(m.nbr_face.begin(), m.nbr_face.end());
+  else if (n == "oi_wq") v = c->oi.wq;
+  else if (n == "oi_xg") v = c->oi.xg;
+  else if (n == "oi_wg") v = c->oi.wg;
+  else if (n == "oi_Iq") v = c->oi.Iq;
+  else if (n == "oi_Drq") v = c->oi.Drq;
+  else if (n == "oi_Dsq") v = c->oi.Dsq;
+  else if (n == "oi_Wr") v = c->oi.Wr;
+  else if (n == "oi_Ws") v = c->oi.Ws;
+  else if (n == "oi_If1") v = c->oi.If1;
+  else if (n == "oi_Drf") v = c->oi.Drf;
+  else if (n == "oi_Dsf") v = c->oi.Dsf;
+  else if (n == "oi_LIFTq") v = c->oi.LIFTq;
+  else if (n == "oi_LIFTrq") v = c->oi.LIFTrq;
+  else if (n == "oi_LIFTsq") v = c->oi.LIFTsq;
   else return fail(c, DG_EINVAL, "unknown table " + n);
   if ((int64_t)v.size() != count)
     return fail(c, DG_EINVAL, "table " + n + " has " + std::to_string(v.size()) + " entries");
@@ -263,7 +293,7 @@ int dg_rhs(dg_ctx* c, const double* U, double* R, const double v_w[2], void* str
   if (rc != DG_OK) return rc;
   if (!U || !R || U == R) return fail(c, DG_EINVAL, "U and R must be distinct device arrays");
   std::string err;
-  rc = dgmi::launch_stage(c->N, c->precision, c->tune, tables(c), kphys(c, v_w), U, nullptr, R, 0.0, 0.0, 1.0, 1, stream,
+  rc = dgmi::launch_stage(c->N, dgmi::ctx_form(c), c->tune, tables(c), kphys(c, v_w), U, nullptr, R, 0.0, 0.0, 1.0, 1, stream,
                           err);
   return rc == 0 ? DG_OK : fail(c, rc, err);
 }
@@ -275,7 +305,7 @@ int dg_rk_stage(dg_ctx* c, const double* Uin, double* Uout, double* K1, double a
   if (!Uin || !Uout || !K1 || Uin == Uout || K1 == Uin || K1 == Uout)
     return fail(c, DG_EINVAL, "U_in, U_out and K1 must be distinct device arrays");
   std::string err;
-  rc = dgmi::launch_stage(c->N, c->precision, c->tune, tables(c), kphys(c, v_w), Uin, Uout, K1, a, b, dt, 0, stream, err);
+  rc = dgmi::launch_stage(c->N, dgmi::ctx_form(c), c->tune, tables(c), kphys(c, v_w), Uin, Uout, K1, a, b, dt, 0, stream, err);
   return rc == 0 ? DG_OK : fail(c, rc, err);
 }
 
@@ -289,7 +319,7 @@ int dg_rk_step(dg_ctx* c, double* U, double* K1, double dt, const double v_w[2],
   dgmi::KernelPhysics k = kphys(c, v_w);
   double* bufs[2] = {U, c->d_scratch};
   for (int i = 0; i < 5; ++i) {
-    rc = dgmi::launch_stage(c->N, c->precision, c->tune, t, k, bufs[i & 1], bufs[(i + 1) & 1], K1, dgmi::kRkA[i], dgmi::kRkB[i], dt, 0,
+    rc = dgmi::launch_stage(c->N, dgmi::ctx_form(c), c->tune, t, k, bufs[i & 1], bufs[(i + 1) & 1], K1, dgmi::kRkA[i], dgmi::kRkB[i], dt, 0,
                             stream, err);
     if (rc != 0) return fail(c, rc, err);
   }
@@ -316,7 +346,7 @@ int dg_rk_steps(dg_ctx* c, double* U, double* K1, int nsteps, double dt, const d
   int cur = 0;
   for (int n = 0; n < nsteps; ++n) {
     for (int i = 0; i < 5; ++i) {
-      rc = dgmi::launch_stage(c->N, c->precision, c->tune, t, k, bufs[(cur + i) & 1],
+      rc = dgmi::launch_stage(c->N, dgmi::ctx_form(c), c->tune, t, k, bufs[(cur + i) & 1],
                               bufs[(cur + i + 1) & 1], K1, dgmi::kRkA[i], dgmi::kRkB[i], dt, 0,
                               stream, err);
       if (rc != 0) return fail(c, rc, err);

@@ -256,6 +256,161 @@ bool build_ref_ops(int N, RefOps& o, std::string& err) {
   return true;
 }
 
+// Gauss points and weights of the weight (1 - x)^a (1 + x)^b on [-1, 1]:
+// the roots of P_q^(a,b) (Newton with deflation from Chebyshev-like starts)
+// and w_i = 1 / sum_{k<q} p_k(x_i)^2 with the orthonormal p_k (Christoffel
+// numbers).
+static void gauss_jacobi(int q, double a, double b, std::vector<double>& x, std::vector<double>& w) {
+  x.clear();
+  for (int k = 0; k < q; ++k) {
+    double z = -std::cos(M_PI * (k + 0.5) / q);
+    for (int it = 0; it < 300; ++it) {
+      double f = jacobi(z, a, b, q), df = djacobi(z, a, b, q), sum = 0.0;
+      for (double r : x) sum += 1.0 / (z - r);
+      double dz = f / (df - f * sum);
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x.push_back(z);
+  }
+  std::sort(x.begin(), x.end());
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double sum = 0.0;
+    for (int k = 0; k < q; ++k) {
+      double v = jacobi(x[i], a, b, k);
+      sum += v * v;
+    }
+    w[i] = 1.0 / sum;
+  }
+}
+
+// Basis values and derivatives at points (r, s): rows = points, cols = nodes.
+static void basis_at(const RefOps& ref, const std::vector<double>& Vinv, const std::vector<double>& r,
+                     const std::vector<double>& s, std::vector<double>& L, std::vector<double>& Lr,
+                     std::vector<double>& Ls) {
+  const int N = ref.N, Np = ref.Np, n = (int)r.size();
+  std::vector<double> V(n * Np), Vr(n * Np), Vs(n * Np);
+  for (int k = 0; k < n; ++k) {
+    int col = 0;
+    for (int i = 0; i <= N; ++i)
+      for (int j = 0; j <= N - i; ++j, ++col) {
+        double v, dr, ds;
+        pkd(r[k], s[k], i, j, v, dr, ds);
+        V[k * Np + col] = v;
+        Vr[k * Np + col] = dr;
+        Vs[k * Np + col] = ds;
+      }
+  }
+  L = matmul(V, Vinv, n, Np, Np);
+  Lr = matmul(Vr, Vinv, n, Np, Np);
+  Ls = matmul(Vs, Vinv, n, Np, Np);
+}
+
+bool build_oi_ops(const RefOps& ref, OIOps& o, std::string& err) {
+  const int N = ref.N, Np = ref.Np, Nfp = ref.Nfp;
+  const int q = oi_points(N);
+  o.q = q;
+  o.Nq = q * q;
+  // nodal Vandermonde and its inverse, M^-1 = V V^T
+  std::vector<double> V(Np * Np), dummy_r(Np * Np), dummy_s(Np * Np);
+  for (int n = 0; n < Np; ++n) {
+    int col = 0;
+    for (int i = 0; i <= N; ++i)
+      for (int j = 0; j <= N - i; ++j, ++col) pkd(ref.r[n], ref.s[n], i, j, V[n * Np + col], dummy_r[n * Np + col], dummy_s[n * Np + col]);
+  }
+  std::vector<double> Vinv = V;
+  if (!invert(Vinv, Np)) {
+    err = "singular Vandermonde matrix";
+    return false;
+  }
+  const std::vector<double> Minv = matmul(V, transpose(V, Np, Np), Np, Np, Np);
+  // element rule: collapsed coordinates, Gauss-Legendre in a, Gauss-Jacobi
+  // (weight 1 - b) in b; r = (1 + a)(1 - b)/2 - 1, s = b, dr ds = (1 - b)/2 da db
+  std::vector<double> xa, wa, xb, wb;
+  gauss_jacobi(q, 0.0, 0.0, xa, wa);
+  gauss_jacobi(q, 1.0, 0.0, xb, wb);
+  std::vector<double> rq, sq;
+  o.wq.clear();
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) {
+      rq.push_back(0.5 * (1.0 + xa[i]) * (1.0 - xb[j]) - 1.0);
+      sq.push_back(xb[j]);
+      o.wq.push_back(0.5 * wa[i] * wb[j]);
+    }
+  basis_at(ref, Vinv, rq, sq, o.Iq, o.Drq, o.Dsq);
+  const int Nq = o.Nq;
+  // M^-1 (D^T W): the weights folded in
+  std::vector<double> DrW(Np * Nq), DsW(Np * Nq);
+  for (int i = 0; i < Np; ++i)
+    for (int k = 0; k < Nq; ++k) {
+      DrW[i * Nq + k] = o.Drq[k * Np + i] * o.wq[k];
+      DsW[i * Nq + k] = o.Dsq[k * Np + i] * o.wq[k];
+    }
+  o.Wr = matmul(Minv, DrW, Np, Np, Nq);
+  o.Ws = matmul(Minv, DsW, Np, Np, Nq);
+  // face rule: Gauss-Legendre in the counter-clockwise face parameter xi;
+  // face 0 (xi, -1), face 1 (-xi, xi), face 2 (-1, -xi)
+  gauss_jacobi(q, 0.0, 0.0, o.xg, o.wg);
+  std::vector<double> rf, sf;
+  for (int f = 0; f < 3; ++f)
+    for (int g = 0; g < q; ++g) {
+      const double xi = o.xg[g];
+      rf.push_back(f == 0 ? xi : (f == 1 ? -xi : -1.0));
+      sf.push_back(f == 0 ? -1.0 : (f == 1 ? xi : -xi));
+    }
+  std::vector<double> If;
+  basis_at(ref, Vinv, rf, sf, If, o.Drf, o.Dsf);
+  // the face-node part of face 0's rows: the 1D interpolation from the face
+  // nodes (counter-clockwise) to the points, the same on every face
+  o.If1.assign(q * Nfp, 0.0);
+  for (int g = 0; g < q; ++g)
+    for (int i = 0; i < Nfp; ++i) o.If1[g * Nfp + i] = If[g * Np + ref.Fmask[i]];
+  const int NG = 3 * q;
+  std::vector<double> LW(Np * NG), LrW(Np * NG), LsW(Np * NG);
+  for (int i = 0; i < Np; ++i)
+    for (int k = 0; k < NG; ++k) {
+      const double w = o.wg[k % q];
+      LW[i * NG + k] = If[k * Np + i] * w;
+      LrW[i * NG + k] = o.Drf[k * Np + i] * w;
+      LsW[i * NG + k] = o.Dsf[k * Np + i] * w;
+    }
+  o.LIFTq = matmul(Minv, LW, Np, Np, NG);
+  o.LIFTrq = matmul(Minv, LrW, Np, Np, NG);
+  o.LIFTsq = matmul(Minv, LsW, Np, Np, NG);
+  return true;
+}
+
+void pack_oi(const RefOps& ref, const OIOps& o, std::vector<double>& out) {
+  const int Np = ref.Np, Nq = o.Nq, NG = 3 * o.q;
+  out.clear();
+  // B operand of the 16x16x4 instruction: lane l of fragment (t, s) holds
+  // Op[16 t + l % 16][4 s + l / 16] (rows = outputs, cols = the k index)
+  auto emit = [&](const std::vector<double>& M, int rows, int cols) {
+    const int nt = (rows + 15) / 16, ks = (cols + 3) / 4;
+    for (int t = 0; t < nt; ++t)
+      for (int s = 0; s < ks; ++s)
+        for (int l = 0; l < 64; ++l) {
+          int row = 16 * t + l % 16, col = 4 * s + l / 16;
+          out.push_back((row < rows && col < cols) ? M[row * cols + col] : 0.0);
+        }
+  };
+  emit(o.Iq, Nq, Np);
+  emit(o.Drq, Nq, Np);
+  emit(o.Dsq, Nq, Np);
+  emit(o.Wr, Np, Nq);
+  emit(o.Ws, Np, Nq);
+  emit(o.LIFTq, Np, NG);
+  emit(o.LIFTrq, Np, NG);
+  emit(o.LIFTsq, Np, NG);
+  for (int k = 0; k < NG; ++k)
+    for (int j = 0; j < Np; ++j) {
+      out.push_back(o.Drf[k * Np + j]);
+      out.push_back(o.Dsf[k * Np + j]);
+    }
+  out.insert(out.end(), o.If1.begin(), o.If1.end());
+}
+
 namespace {
 struct KeyHash {
   size_t operator()(const std::pair<int64_t, int64_t>& k) const {

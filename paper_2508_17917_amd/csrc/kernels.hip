@@ -760,6 +760,382 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
                           sConnW + 12 * wid, tb + w0, te, wstride);
 }
 
+// ---------------------------------------------------------------------------
+// Over-integrated stage (FP64, plain form): the weak form with every integral
+// taken by rules exact for degree 3p -- a collapsed Gauss rule of q^2 points on
+// the element and Gauss-Legendre with q points on each face -- instead of the
+// nodal interpolants of the fluxes (the anti-aliasing remedy of Sec. 2.2):
+//   R = M^-1 [ sum_q w_q (F_r d_r l_i + F_s d_s l_i)(x_q)
+//              - sum_faces sum_g w_g Fscale H_m l_i (x_g)
+//              + sum_faces sum_g w_g Fscale (q_r d_r l_i + q_s d_s l_i)(x_g) ]
+// with M^-1 and the weights folded into the operators.  Per tile:
+//   1  own and neighbour states, geometry (as the nodal kernel, no pipelining)
+//   2  element points in chunks of 16: U, d_r U, d_s U there on the matrix
+//      cores, the total flux pointwise, and the chunk's part of the weighted
+//      divergence accumulated at once (only one chunk of flux lives in LDS)
+//   3  face points, one lane each: both sides' values (face-node
+//      interpolation) and gradients (rows of the point derivative matrices),
+//      ghosts, ||n^T G n||_2, viscous average; then G-bar_e over the face's
+//      points, sigma_e, Roe, penalty and theta terms
+//   4  the three weighted lifts on the matrix cores into the same
+//      accumulator, then the RK stage in FP64.
+// The operator fragments are read from global memory (L2-resident); only the
+// face-point derivative rows sit in LDS.
+template <int N>
+struct OIOrder {
+  using O = Order<N, double>;
+  static constexpr int Np = O::Np, Nfp = O::Nfp, S = O::S, NT = O::NT, KS = O::KS, RS = O::RS;
+  static constexpr int q = oi_points(N), Nq = q * q, NG = 3 * q;
+  static constexpr int NQT = (Nq + 15) / 16;   // 16-point chunks of the element rule
+  static constexpr int KQ = (Nq + 3) / 4;      // k-steps over the element points
+  static constexpr int KG = (NG + 3) / 4;      // k-steps over the face points
+  static constexpr int EPT = (64 / NG) < 4 ? ((64 / NG) > 0 ? 64 / NG : 1) : 4;
+  static constexpr int FRS = 17;               // padded LDS row of one flux chunk
+  static constexpr int GRS = 4 * KG + 1;       // padded LDS row of the face terms
+  static constexpr int U_SZ = 16 * RS, F_SZ = 32 * FRS;
+  static constexpr int N_SZ = 12 * S, H_SZ = 48 * GRS;
+  static constexpr int X_SZ = N_SZ > H_SZ ? N_SZ : H_SZ;
+  static constexpr int NORM_SZ = 4 * NG, VN_SZ = 16 * NG;
+  static constexpr int WAVE_SZ = (U_SZ + F_SZ + X_SZ + NORM_SZ + VN_SZ + 64 + 48 + 3) / 4 * 4;
+  // global fragment offsets (doubles), in the order the host packs them
+  static constexpr int FI = NQT * KS * 64, FW = NT * KQ * 64, FL = NT * KG * 64;
+  static constexpr int OFF_IQ = 0, OFF_DRQ = FI, OFF_DSQ = 2 * FI, OFF_WR = 3 * FI,
+                       OFF_WS = 3 * FI + FW, OFF_LQ = 3 * FI + 2 * FW, OFF_LRQ = OFF_LQ + FL,
+                       OFF_LSQ = OFF_LQ + 2 * FL, OFF_DRSF = OFF_LQ + 3 * FL,
+                       OFF_IF1 = OFF_DRSF + 2 * NG * Np, TOTAL = OFF_IF1 + q * Nfp;
+  static constexpr int LDS_TAB = 2 * NG * Np + q * Nfp;  // face-point tables in LDS
+};
+
+template <int N>
+__device__ __forceinline__ void oi_tiles(const DeviceTables& t, const KernelPhysics& ph,
+                                         const double* __restrict__ Uin, double* __restrict__ Uout,
+                                         double* __restrict__ K1, double a, double b, double dt,
+                                         int rhs_only, const double* sTab, double* sU, int* sConn,
+                                         int64_t tile0, int64_t tile_end, int64_t stride) {
+  typedef double T;
+  using P = OIOrder<N>;
+  using O = Order<N, double>;
+  typedef Vec4<double>::type V4;
+  constexpr int Np = P::Np, Nfp = P::Nfp, S = P::S, NT = P::NT, KS = P::KS, RS = P::RS, q = P::q,
+                Nq = P::Nq, NG = P::NG, NQT = P::NQT, KQ = P::KQ, KG = P::KG, EPT = P::EPT,
+                FRS = P::FRS, GRS = P::GRS, ROWC = O::ROWC, ROWE = O::ROWE;
+  const int lane = threadIdx.x & 63;
+  const double* G = t.oi;
+  const double* sDRS = sTab;               // [NG][Np] (d_r, d_s) pairs
+  const double* sIf1 = sTab + 2 * NG * Np; // [q][Nfp]
+  T* sF = sU + P::U_SZ;                    // flux chunk: F_r rows | F_s rows
+  T* sX = sF + P::F_SZ;                    // neighbour states, later face terms
+  T* sH = sX;
+  T* sQr = sX + 16 * GRS;
+  T* sQs = sX + 32 * GRS;
+  T* sNorm = sX + P::X_SZ;
+  T* sVn = sNorm + P::NORM_SZ;             // [4 fields][4 NG]
+  T* sGeo = sVn + P::VN_SZ;
+  T* sNGeo = sGeo + 64;
+
+  Gas<T> gas;
+  gas.gamma = ph.gamma;
+  gas.gm1 = ph.gamma - 1.0;
+  gas.igm1 = 1.0 / (ph.gamma - 1.0);
+  gas.mu = ph.mu;
+  gas.k = ph.gamma / ph.Pr;
+  const T theta = ph.theta, vwx = ph.vw[0], vwy = ph.vw[1];
+  Base<T> base;
+  {
+    const double r0 = ph.U_inf[0], ux0 = ph.U_inf[1] / r0, uy0 = ph.U_inf[2] / r0;
+    base.rho = r0;
+    base.mx = ph.U_inf[1];
+    base.my = ph.U_inf[2];
+    base.E = ph.U_inf[3];
+    base.p = (ph.gamma - 1.0) * (ph.U_inf[3] - 0.5 * (ph.U_inf[1] * ux0 + ph.U_inf[2] * uy0));
+    base.ux = ux0;
+    base.uy = uy0;
+  }
+  const int64_t K = t.K;
+  const int arow = lane & 15, acol = lane >> 4;
+  const int re = lane >> 4, rn = lane & 15;
+  constexpr int NQL = (S + 63) / 64;
+  int lds_u[NQL];
+  bool lr_ok[NQL];
+#pragma unroll
+  for (int qq = 0; qq < NQL; ++qq) {
+    const int r = lane + 64 * qq;
+    lr_ok[qq] = r < S;
+    lds_u[qq] = lr_ok[qq] ? ROWC * (r / Np) * RS + (r - (r / Np) * Np) : 0;
+  }
+
+  for (int64_t tile = tile0; tile < tile_end; tile += stride) {
+    const int64_t e0 = tile * EPT;
+    const int nel = (int)((K - e0) < EPT ? (K - e0) : EPT);
+    wave_sync();
+    // ---- 1: own states, geometry, connectivity; neighbour states and metrics
+    if (lane < nel * 3) sConn[lane] = t.conn[e0 * 3 + lane];
+    if (lane < nel * kGeoStride) sGeo[lane] = t.geo[e0 * kGeoStride + lane];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int qq = 0; qq < NQL; ++qq)
+        if (lr_ok[qq] && e < nel) sU[lds_u[qq] + ROWE * e * RS] = Uin[(e0 + e) * S + lane + 64 * qq];
+    wave_sync();
+    if (lane < nel * 12) sNGeo[lane] = t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)];
+    for (int bb = 0; bb < 3 * nel; ++bb) {
+      const int64_t nb = (int64_t)(sConn[bb] >> 4) * S;
+#pragma unroll
+      for (int qq = 0; qq < NQL; ++qq)
+        if (lr_ok[qq]) sX[bb * S + lane + 64 * qq] = Uin[nb + lane + 64 * qq];
+    }
+    wave_sync();
+
+    // ---- 2: element points, chunk by chunk; the divergence accumulates in acc
+    V4 acc[NT];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[tt] = V4{0.0, 0.0, 0.0, 0.0};
+    for (int tq = 0; tq < NQT; ++tq) {
+      V4 aU = {0.0, 0.0, 0.0, 0.0}, aR = aU, aS = aU;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const T av = sU[arow * RS + 4 * s + acol];
+        const int fo = (tq * KS + s) * 64 + lane;
+        aU = mfma(av, G[P::OFF_IQ + fo], aU);
+        aR = mfma(av, G[P::OFF_DRQ + fo], aR);
+        aS = mfma(av, G[P::OFF_DSQ + fo], aS);
+      }
+      const int k = 16 * tq + rn;
+      T Fr[4] = {0.0, 0.0, 0.0, 0.0}, Fs[4] = {0.0, 0.0, 0.0, 0.0};
+      if (re < nel && k < Nq) {
+        const T* g = sGeo + re * kGeoStride;
+        const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+        T u[4], gx[4], gy[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          u[c] = aU[c];
+          gx[c] = rx * aR[c] + sx * aS[c];
+          gy[c] = ry * aR[c] + sy * aS[c];
+        }
+        T fvx[4], fvy[4], Fx[4], Fy[4];
+        viscous_flux(gas, vstate(gas, u), gx, gy, fvx, fvy);
+        const Prim<T> pr = prim_plain(u, gas.gm1);
+        normal_flux<T, false>(u, u, pr, base, 1.0, 0.0, vwx, Fx);
+        normal_flux<T, false>(u, u, pr, base, 0.0, 1.0, vwy, Fy);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const T fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
+          Fr[c] = rx * fx + ry * fy;
+          Fs[c] = sx * fx + sy * fy;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sF[(ROWC * c + ROWE * re) * FRS + rn] = Fr[c];
+        sF[(16 + ROWC * c + ROWE * re) * FRS + rn] = Fs[c];
+      }
+      wave_sync();
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int s = 4 * tq + s4;
+          if (s < KQ) {
+            const int fo = (tt * KQ + s) * 64 + lane;
+            acc[tt] = mfma(sF[arow * FRS + 4 * s4 + acol], G[P::OFF_WR + fo], acc[tt]);
+            acc[tt] = mfma(sF[(16 + arow) * FRS + 4 * s4 + acol], G[P::OFF_WS + fo], acc[tt]);
+          }
+        }
+      wave_sync();
+    }
+
+    // ---- 3: face points, one lane each
+    const int e = lane / NG < 3 ? lane / NG : 3;
+    const int fg = lane - (lane / NG) * NG;
+    const bool ok = lane < EPT * NG && (lane / NG) < nel;
+    const int f = fg / q, gp = fg - f * q;
+    T up[4] = {0.0, 0.0, 0.0, 0.0}, uo[4] = {0.0, 0.0, 0.0, 0.0};
+    int tag = 0;
+    if (ok) {
+      const int conn = sConn[e * 3 + f];
+      tag = conn & 3;
+      const int nf = (conn >> 2) & 3;
+      const T* g = sGeo + e * kGeoStride;
+      const T nx = g[4 + 4 * f], ny = g[5 + 4 * f];
+      // own value and gradient at the point
+      T ur[4] = {0.0, 0.0, 0.0, 0.0}, us[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int j = 0; j < Np; ++j) {
+        const T dr = sDRS[2 * (fg * Np + j)], ds = sDRS[2 * (fg * Np + j) + 1];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const T v = sU[(ROWC * c + ROWE * e) * RS + j];
+          ur[c] += dr * v;
+          us[c] += ds * v;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < Nfp; ++i) {
+        const T w = sIf1[gp * Nfp + i];
+        const int n = face_node<N>(f, i);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) up[c] += w * sU[(ROWC * c + ROWE * e) * RS + n];
+      }
+      T gxp[4], gyp[4], gxm[4], gym[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        gxp[c] = g[0] * ur[c] + g[2] * us[c];
+        gyp[c] = g[1] * ur[c] + g[3] * us[c];
+        gxm[c] = gxp[c];
+        gym[c] = gyp[c];
+      }
+      if (tag == 0) {
+        // the neighbour's value and gradient at its mirrored point
+        const T* nbU = sX + (e * 3 + f) * S;
+        const int gm = q - 1 - gp, row = nf * q + gm;
+        T vr[4] = {0.0, 0.0, 0.0, 0.0}, vs[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int j = 0; j < Np; ++j) {
+          const T dr = sDRS[2 * (row * Np + j)], ds = sDRS[2 * (row * Np + j) + 1];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const T v = nbU[c * Np + j];
+            vr[c] += dr * v;
+            vs[c] += ds * v;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < Nfp; ++i) {
+          const T w = sIf1[gm * Nfp + i];
+          const int n = face_node<N>(nf, i);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) uo[c] += w * nbU[c * Np + n];
+        }
+        const T* ng = sNGeo + (e * 3 + f) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          gxm[c] = ng[0] * vr[c] + ng[2] * vs[c];
+          gym[c] = ng[1] * vr[c] + ng[3] * vs[c];
+        }
+      } else {
+        ghost_state<T, false>(tag, up, up, nullptr, 1, vwx, vwy, gas, base, uo);
+      }
+      const VState<T> sp = vstate(gas, up), so = vstate(gas, uo);
+      const T n1 = normal_diffusion_norm(gas, sp, nx, ny), n2 = normal_diffusion_norm(gas, so, nx, ny);
+      sNorm[e * NG + fg] = n1 > n2 ? n1 : n2;
+      T vn[4];
+      if (tag == 1) {
+        viscous_normal_flux(gas, so, gxp, gyp, nx, ny, vn);
+      } else {
+        viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
+        if (tag == 0) {
+          T vm[4];
+          viscous_normal_flux(gas, so, gxm, gym, nx, ny, vm);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) vn[c] = 0.5 * (vn[c] + vm[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sVn[c * 4 * NG + e * NG + fg] = vn[c];
+    }
+    wave_sync();
+    if (ok) {
+      const T* g = sGeo + e * kGeoStride;
+      const T nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f];
+      T gbar = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < q; ++jj) {
+        const T v = sNorm[e * NG + f * q + jj];
+        gbar = v > gbar ? v : gbar;
+      }
+      const T sigma = g[7 + 4 * f] * gbar;
+      const T vwn = vwx * nx + vwy * ny;
+      const Prim<T> pp = prim_plain(up, gas.gm1);
+      T Fc[4];
+      if (tag == 1) {
+        Fc[0] = 0.0;
+        Fc[1] = pp.p * nx;
+        Fc[2] = pp.p * ny;
+        Fc[3] = pp.p * vwn;
+      } else {
+        const Prim<T> po = prim_plain(uo, gas.gm1);
+        T FL[4], FR[4];
+        normal_flux<T, false>(up, up, pp, base, nx, ny, vwn, FL);
+        normal_flux<T, false>(uo, uo, po, base, nx, ny, vwn, FR);
+        roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
+      }
+      T w[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        w[c] = up[c] - uo[c];
+        sH[(ROWC * c + ROWE * e) * GRS + fg] = -fsc * (Fc[c] - sVn[c * 4 * NG + e * NG + fg] + sigma * w[c]);
+      }
+      T qx[4], qy[4];
+      viscous_transpose(gas, vstate(gas, tag == 1 ? uo : up), nx, ny, w, qx, qy);
+      const T ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
+      const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sQr[(ROWC * c + ROWE * e) * GRS + fg] = ce * (rx * qx[c] + ry * qy[c]);
+        sQs[(ROWC * c + ROWE * e) * GRS + fg] = ce * (sx * qx[c] + sy * qy[c]);
+      }
+    }
+    for (int i = lane; i < 48 * (GRS - NG); i += 64) {
+      const int row = i / (GRS - NG);
+      sX[row * GRS + NG + (i - row * (GRS - NG))] = 0.0;
+    }
+    wave_sync();
+
+    // ---- 4: lifts into the accumulator, then the RK stage
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int s = 0; s < KG; ++s) {
+        const int fo = (tt * KG + s) * 64 + lane;
+        const int ao = arow * GRS + 4 * s + acol;
+        acc[tt] = mfma(sH[ao], G[P::OFF_LQ + fo], acc[tt]);
+        acc[tt] = mfma(sQr[ao], G[P::OFF_LRQ + fo], acc[tt]);
+        acc[tt] = mfma(sQs[ao], G[P::OFF_LSQ + fo], acc[tt]);
+      }
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int n = 16 * tt + rn;
+      if (re < nel && n < Np) {
+        const int64_t base_i = (e0 + re) * S + n;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double R = acc[tt][c];
+          const int64_t idx = base_i + c * Np;
+          if (rhs_only) {
+            K1[idx] = R;
+          } else {
+            const double kk = (a == 0.0) ? dt * R : a * K1[idx] + dt * R;
+            K1[idx] = kk;
+            Uout[idx] = sU[(ROWC * c + ROWE * re) * RS + n] + b * kk;
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int N, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(1))) void
+oi_stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
+                double* __restrict__ Uout, double* __restrict__ K1, double a, double b, double dt,
+                int rhs_only) {
+  using P = OIOrder<N>;
+  __shared__ __attribute__((aligned(16))) double sTab[P::LDS_TAB];
+  __shared__ __attribute__((aligned(16))) double sWave[W * P::WAVE_SZ];
+  __shared__ int sConnW[W * 12];
+  for (int i = threadIdx.x; i < P::LDS_TAB; i += 64 * W) sTab[i] = t.oi[P::OFF_DRSF + i];
+  for (int i = threadIdx.x; i < W * P::WAVE_SZ; i += 64 * W) sWave[i] = 0.0;
+  __syncthreads();
+  const int wid = threadIdx.x >> 6;
+  const int64_t ntiles = (t.K + P::EPT - 1) / P::EPT;
+  const int xcd = blockIdx.x & 7;
+  const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
+  const int64_t w0 = (int64_t)(blockIdx.x >> 3) * W + wid;
+  const int64_t wstride = (int64_t)(gridDim.x >> 3) * W;
+  oi_tiles<N>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, sTab, sWave + wid * P::WAVE_SZ,
+              sConnW + 12 * wid, tb + w0, te, wstride);
+}
+
 // Many meshes in one launch.  The instances are grouped by order; group g
 // owns the workgroups [block_begin, block_begin + nblocks) (multiples of 8)
 // and numbers the tiles of its instances consecutively.  Per-instance dt and
@@ -1043,6 +1419,34 @@ int launch_stage_w(const StageTuning& tune, const DeviceTables& t, const KernelP
   return -1;
 }
 
+template <int N, int W>
+int launch_oi_t(const StageTuning& tune, const DeviceTables& t, const KernelPhysics& ph,
+                const double* Uin, double* Uout, double* K1, double a, double b, double dt,
+                int rhs_only, hipStream_t s, std::string& err) {
+  static int cache[kMaxDev] = {0};
+  const int resident = resident_blocks(oi_stage_kernel<N, W>, 64 * W, cache);
+  constexpr int EPT = OIOrder<N>::EPT;
+  const int64_t grid = stage_grid((t.K + EPT - 1) / EPT, W, resident, tune.grid);
+  hipLaunchKernelGGL((oi_stage_kernel<N, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, t, ph, Uin,
+                     Uout, K1, a, b, dt, rhs_only);
+  return launch_error(err, "over-integrated stage kernel launch");
+}
+
+template <int N>
+int launch_oi_w(const StageTuning& tune, const DeviceTables& t, const KernelPhysics& ph,
+                const double* Uin, double* Uout, double* K1, double a, double b, double dt,
+                int rhs_only, hipStream_t s, std::string& err) {
+  if (!t.oi || t.oi_len != OIOrder<N>::TOTAL) {
+    err = "over-integration tables not set up for this order";
+    return -7;
+  }
+  const int w = tune.waves ? tune.waves : 2;
+  if (w == 2) return launch_oi_t<N, 2>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+  if (w == 4) return launch_oi_t<N, 4>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+  err = "waves per workgroup must be 2 or 4";
+  return -1;
+}
+
 template <int N>
 int launch_stage_n(int form, const StageTuning& tune, const DeviceTables& t,
                    const KernelPhysics& ph, const double* Uin, double* Uout, double* K1, double a,
@@ -1056,6 +1460,8 @@ int launch_stage_n(int form, const StageTuning& tune, const DeviceTables& t,
       return launch_stage_w<N, float, true>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
     case 3:
       return launch_stage_w<N, bf16ops, true>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case kFormOverint:
+      return launch_oi_w<N>(tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
     default: err = "precision mode not built"; return -5;
   }
 }

@@ -69,7 +69,7 @@ int dg_set_tuning(dg_ctx* c, int waves, int grid) {
 
 int dg_get_tuning(const dg_ctx* c, int* waves, int* grid) {
   if (!c || !waves || !grid) return DG_EINVAL;
-  *waves = c->tune.waves ? c->tune.waves : dgmi::default_waves(c->N, c->precision);
+  *waves = c->tune.waves ? c->tune.waves : (c->overint ? 2 : dgmi::default_waves(c->N, c->precision));
   *grid = c->tune.grid;
   return DG_OK;
 }
@@ -88,7 +88,7 @@ int dg_autotune(dg_ctx* c, const double* U, int reps, const char* cache_path, vo
     if (*q == '"' || *q == '\\') *q = '_';
   if (cache_path) {
     CacheEntry hit;
-    if (cache_lookup(cache_path, arch, c->N, c->precision, (long long)c->K, hit)) {
+    if (cache_lookup(cache_path, arch, c->N, dgmi::ctx_form(c), (long long)c->K, hit)) {
       c->tune.waves = hit.waves;
       c->tune.grid = hit.grid;
       if (best_us) *best_us = 0.0;
@@ -118,7 +118,7 @@ int dg_autotune(dg_ctx* c, const double* U, int reps, const char* cache_path, vo
       tune.grid = grid;
       // the first RK stage (A_1 = 0): reads U, writes scratch and K1
       auto go = [&]() {
-        return dgmi::launch_stage(c->N, c->precision, tune, t, ph, U, c->d_scratch, K1, 0.0,
+        return dgmi::launch_stage(c->N, dgmi::ctx_form(c), tune, t, ph, U, c->d_scratch, K1, 0.0,
                                   dgmi::kRkB[0], 1e-7, 0, s, err);
       };
       for (int r = 0; r < 3 && rc == DG_OK; ++r)
@@ -153,7 +153,7 @@ int dg_autotune(dg_ctx* c, const double* U, int reps, const char* cache_path, vo
     std::fprintf(f,
                  "{\"arch\": \"%s\", \"p\": %d, \"precision\": %d, \"K\": %lld, \"waves\": %d, "
                  "\"grid\": %d, \"us\": %.3f}\n",
-                 arch, c->N, c->precision, (long long)c->K, pick.waves, pick.grid, best);
+                 arch, c->N, dgmi::ctx_form(c), (long long)c->K, pick.waves, pick.grid, best);
     std::fclose(f);
   }
   return DG_OK;

@@ -10,11 +10,14 @@ from . import _lib as L
 
 class Solver:
     def __init__(self, p, mesh, gamma=1.4, Pr=0.72, mu=0.0, theta=1.0, penalty_mode=0, C_pen=0.01,
-                 U_inf=(1.0, 0.0, 0.0, 1.0), device=True, precision=L.DG_FP64):
+                 U_inf=(1.0, 0.0, 0.0, 1.0), device=True, precision=L.DG_FP64,
+                 overintegration=False):
         self.p = int(p)
         self.precision = int(precision)
         self.h = L.dg_create(self.p, self.precision)
         try:
+            if overintegration:
+                L.dg_set_overintegration(self.h, True)
             L.dg_set_physics(self.h, gamma, Pr, mu, theta, penalty_mode, C_pen, U_inf)
             L.dg_set_mesh(self.h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh.get("face_tag"),
                           mesh.get("period", (0.0, 0.0)))
@@ -41,7 +44,18 @@ class Solver:
                  "LIFT": self.Np * 3 * self.Nfp, "LIFTr": self.Np * 3 * self.Nfp,
                  "LIFTs": self.Np * 3 * self.Nfp, "Fmask": 3 * self.Nfp, "wface": 3 * self.Nfp,
                  "geo": self.K * 16, "nbr": self.K * 3, "nbr_face": self.K * 3}
+        q = (3 * self.p + 2) // 2
+        Nq, NG = q * q, 3 * q
+        sizes.update({"oi_wq": Nq, "oi_xg": q, "oi_wg": q, "oi_Iq": Nq * self.Np,
+                      "oi_Drq": Nq * self.Np, "oi_Dsq": Nq * self.Np, "oi_Wr": self.Np * Nq,
+                      "oi_Ws": self.Np * Nq, "oi_If1": q * self.Nfp, "oi_Drf": NG * self.Np,
+                      "oi_Dsf": NG * self.Np, "oi_LIFTq": self.Np * NG, "oi_LIFTrq": self.Np * NG,
+                      "oi_LIFTsq": self.Np * NG})
         return L.dg_get_host_table(self.h, name, sizes[name])
+
+    def set_overintegration(self, on):
+        """Switch the quadrature-based (degree-3p) evaluation on or off."""
+        L.dg_set_overintegration(self.h, on)
 
     # -- device calls
     def empty_state(self):

@@ -212,3 +212,40 @@ def test_mlp_and_closure_argument_checks():
         assert e.value.code == L.DG_ESTATE
     finally:
         L.dg_destroy(h)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 6])
+def test_host_overintegration_operators_match_oracle(p):
+    from oracle.overint import OverIntegration
+    mesh = mg.periodic_square(3, 2, 2.0, 1.5)
+    s = _host_solver(mesh, p)
+    ref = build(mesh, p).ref
+    oi = OverIntegration(ref)
+    q, Np, Nfp = oi.q, ref.Np, ref.Nfp
+    Nq, NG = q * q, 3 * q
+    tol = 1e-12 * p * p
+    assert np.abs(s.table("oi_wq") - oi.wq).max() < 1e-14
+    assert np.abs(s.table("oi_wg") - oi.wg).max() < 1e-14
+    for name, M in (("oi_Iq", oi.Iq), ("oi_Drq", oi.Drq), ("oi_Dsq", oi.Dsq)):
+        assert np.abs(s.table(name).reshape(Nq, Np) - M).max() < tol, name
+    W = np.diag(oi.wq)
+    assert np.abs(s.table("oi_Wr").reshape(Np, Nq) - ref.Minv @ oi.Drq.T @ W).max() < tol
+    assert np.abs(s.table("oi_Ws").reshape(Np, Nq) - ref.Minv @ oi.Dsq.T @ W).max() < tol
+    assert np.abs(s.table("oi_Drf").reshape(NG, Np) - np.vstack(oi.Drf)).max() < tol
+    assert np.abs(s.table("oi_Dsf").reshape(NG, Np) - np.vstack(oi.Dsf)).max() < tol
+    assert np.abs(s.table("oi_If1").reshape(q, Nfp) - oi.If[0][:, ref.Fmask[0]]).max() < tol
+    Wg = np.diag(np.tile(oi.wg, 3))
+    for name, mats in (("oi_LIFTq", oi.If), ("oi_LIFTrq", oi.Drf), ("oi_LIFTsq", oi.Dsf)):
+        want = ref.Minv @ np.vstack(mats).T @ Wg
+        assert np.abs(s.table(name).reshape(Np, NG) - want).max() < tol, name
+    s.close()
+
+
+def test_overintegration_needs_the_plain_fp64_form():
+    from paper_2508_17917_amd import _lib as L
+    mesh = mg.periodic_square(2, 2, 1.0, 1.0)
+    with pytest.raises(L.DGError):
+        _host_solver(mesh, 3, precision=2, overintegration=True)
+    s = _host_solver(mesh, 3, overintegration=True)
+    s.set_overintegration(False)
+    s.close()
