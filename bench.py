@@ -45,6 +45,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "DG RHS DOF-updates/s at p=4–6, chosen form vs plain FP64 at stated L2 err"
+METRIC_OI = "DG RHS DOF-updates/s, over-integrated (degree-3p quadrature) FP64 vs the nodal FP64 stage"
 HBM_PEAK_GBS = 8000.0
 # vector ALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 # = 78.6 TFLOP/s, the same for FP64 and for FP32 without packed instructions
@@ -102,6 +103,20 @@ def closure_bytes_per_sample(n_in, H, n_out):
     return fwd + bwd + wgr
 
 
+def algorithmic_flops_per_element_oi(Np, Nfp):
+    """FP64 flops of one over-integrated RHS + stage per element (q points per
+    direction, q^2 element points, 3q face points), counted from the method:
+    U, d_r U, d_s U at the element points 3 x 8 Nq Np, weighted divergence
+    2 x 8 Np Nq, three lifts 24 Np 3q, volume flux 75 per element point, per
+    face point both sides' value and gradient 2 (8 Nfp + 16 Np) plus the face
+    fluxes 460 as in the nodal count, stage update 16 Np."""
+    p = Nfp - 1
+    q = (3 * p + 2) // 2
+    Nq, NG = q * q, 3 * q
+    return (24 * Nq * Np + 16 * Np * Nq + 24 * Np * NG + 75 * Nq
+            + (32 * Np + 16 * Nfp + 460) * NG + 16 * Np)
+
+
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -118,7 +133,7 @@ def measured_traffic(p, form):
     return t["fetch_bytes"] + t["write_bytes"]
 
 
-def cpu_baseline(w, p, budget_s=20.0):
+def cpu_baseline(w, p, budget_s=20.0, overint=False):
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -132,6 +147,9 @@ def cpu_baseline(w, p, budget_s=20.0):
     mesh = Mesh(ref, m["VX"], m["VY"], m["EToV"], m["face_tag"], m["period"])
     dg = DGOracle(mesh, Physics(gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
                                 penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"]))
+    if overint:
+        from oracle.overint import DGOracleOI
+        dg = DGOracleOI(dg.mesh, dg.phys)
     U = mg.noisy_free_stream((4, ref.Np, mesh.K), w["U_inf"], mg.rng_for(1))
     n = 0
     with threadpool_limits(limits=1):
@@ -144,8 +162,9 @@ def cpu_baseline(w, p, budget_s=20.0):
                 break
     dofs = 4 * ref.Np * mesh.K
     return {"value": dofs * n / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d weak-form RHS evaluations of the full K=%d p=%d workload (NumPy FP64, "
-                      "1 BLAS thread, %.1f s)" % (n, mesh.K, p, el)}
+            "sample": "%d %sweak-form RHS evaluations of the full K=%d p=%d workload (NumPy FP64, "
+                      "1 BLAS thread, %.1f s)" % (n, "over-integrated " if overint else "", mesh.K,
+                                                  p, el)}
 
 
 def stable_dt(mesh, p, mu, rho=1.0, C=0.01):
@@ -170,11 +189,11 @@ def mass_norms(solver, D):
     return np.sqrt(np.einsum("kcn,nm,kcm,k->c", d, M, d, J))
 
 
-def make_solver(w, p, mesh, precision):
+def make_solver(w, p, mesh, precision, overint=False):
     from paper_2508_17917_amd import Solver
     return Solver(p, mesh, gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
                   penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"],
-                  precision=precision)
+                  precision=precision, overintegration=overint)
 
 
 def stage_time(s, U, dt, stream, nl=100):
@@ -195,13 +214,13 @@ def stage_time(s, U, dt, stream, nl=100):
     return e0.elapsed_time(e1) / 1e3 / nl
 
 
-def run_single(w, U0, precision, steps, warmup, dt):
+def run_single(w, U0, precision, steps, warmup, dt, overint=False):
     """One mesh: warmup + steps LSERK steps, each followed by the wall-force
     integral into device memory (one library call per phase; the state
     alternates between two buffers, so no per-step copy).  Returns (final
     state, timed seconds, stage kernel seconds, solver)."""
     import torch
-    s = make_solver(w, w["p"], w["mesh"], precision)
+    s = make_solver(w, w["p"], w["mesh"], precision, overint)
     U = U0.clone()
     K1 = torch.zeros_like(U)
     F = torch.zeros((warmup + steps, 3), dtype=torch.float64, device=U.device)
@@ -455,6 +474,9 @@ def main():
                                            "closure20k"],
                     default="cylinder20k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--overint", action="store_true",
+                    help="single-mesh workloads: the over-integrated FP64 stage (degree-3p "
+                         "quadrature), the nodal FP64 stage beside it")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -468,6 +490,12 @@ def main():
 
     import meshgen as mg
 
+    if args.overint:
+        if args.workload in ("closure20k", "viv16"):
+            print("--overint applies to the single-mesh workloads", file=sys.stderr)
+            sys.exit(2)
+        args.form = "fp64"
+        args.compare_forms = False
     prec = FORMS[args.form]
     if args.workload == "closure20k":
         run_closure(args)
@@ -539,15 +567,17 @@ def main():
                  stable_dt(w["mesh"], p, w["mu"]) * 1.5)
         log("%s p=%d form %s, warmup %d, steps %d" % (args.workload, p, args.form, args.warmup,
                                                     args.steps))
-        U, t_steps, t_launch, s = run_single(w, U0, prec, args.steps, args.warmup, dt)
+        U, t_steps, t_launch, s = run_single(w, U0, prec, args.steps, args.warmup, dt,
+                                             overint=args.overint)
         finite = bool(torch.isfinite(U).all().item())
-        if args.form != "fp64":
+        if args.form != "fp64" or args.overint:
             log("plain fp64 beside it")
             U64, t64, tl64, s64 = run_single(w, U0, FORMS["fp64"], args.steps, args.warmup, dt)
         else:
             U64, t64, tl64, s64 = U, t_steps, t_launch, s
         err = rel_l2([s64], [U], [U64], w["U_inf"])
-        flops = algorithmic_flops_per_element(Np, p + 1) * K
+        flops = (algorithmic_flops_per_element_oi(Np, p + 1) if args.overint
+                 else algorithmic_flops_per_element(Np, p + 1)) * K
         nbytes = algorithmic_bytes_per_element(Np) * K
         dofs = 4 * Np * K
         config = {"workload": desc, "K": K, "p": p, "dofs": dofs, "form": args.form, "dt": dt,
@@ -564,11 +594,17 @@ def main():
                                "l2_rel_err": rel_l2([s64], [Uf], [U64], w["U_inf"])}
                 sf.close()
             config["other_forms"] = forms
-        kernel = "stage_kernel<%d, %s>" % (p, args.form)
+        kernel = ("oi_stage_kernel<%d> (over-integrated, fp64)" % p if args.overint
+                  else "stage_kernel<%d, %s>" % (p, args.form))
+        if args.overint:
+            config["workload"] = desc.replace("fp64 form", "fp64 form, over-integrated "
+                                              "(degree-%d quadrature, %d element and %d face "
+                                              "points)" % (3 * p, ((3 * p + 2) // 2) ** 2,
+                                                           3 * ((3 * p + 2) // 2)))
         cpu = None
         if not args.no_cpu_baseline and args.workload == "cylinder20k":
             log("cpu baseline (oracle)")
-            cpu = cpu_baseline(w, p)
+            cpu = cpu_baseline(w, p, overint=args.overint)
         s.close()
         if s64 is not s:
             s64.close()
@@ -576,7 +612,7 @@ def main():
     achieved = flops / t_launch / 1e12
     value = dofs * 5 * args.steps / t_steps
     out = {
-        "metric": METRIC,
+        "metric": METRIC_OI if args.overint else METRIC,
         "value": value,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
@@ -589,15 +625,17 @@ def main():
         "dtype": "f32" if args.form == "fp32-pert" else "f64",
         "data": "synthetic",
         "config": config,
-        "vs_plain_fp64": {"value": dofs * 5 * args.steps / t64,
+        ("vs_nodal_fp64" if args.overint else "vs_plain_fp64"): {
+                          "value": dofs * 5 * args.steps / t64,
                           "avg_launch_us": None if tl64 is None else tl64 * 1e6,
-                          "speedup": t64 / t_steps, "l2_rel_err": err,
+                          "speedup": t64 / t_steps,
+                          ("l2_rel_diff" if args.overint else "l2_rel_err"): err,
                           "l2_norm": "max over fields of ||U - U_fp64||_M / ||U_fp64 - U_inf||_M",
                           "steps_compared": args.warmup + args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
                      "traffic": measured_traffic(config.get("p"), args.form)
-                     if args.workload == "cylinder20k" else None,
+                     if args.workload == "cylinder20k" and not args.overint else None,
                      "kernel": kernel, "avg_launch_us": t_launch * 1e6,
                      "flops_per_launch": flops, "bytes_per_launch": nbytes,
                      "hbm_achieved_GBs": nbytes / t_launch / 1e9,
