@@ -18,7 +18,11 @@ Readings (paper silent or garbled at these points):
   on boundary faces, with G taken at the own trace U+ (wall: at the ghost U^b),
   following Table "jump and average" and eq. ip_flux.
 * Viscous average {G grad U} = (G(U+) grad U+ + G(U-) grad U-) / 2; on the far
-  field G(U+) grad U+, on the wall G(U^b) grad U+ (the printed wall flux).
+  field G(U+) grad U+, on the wall G(U^b) grad U+ (the printed wall flux)
+  without its heat conduction, and the wall's theta term with G(U^b) likewise
+  without conduction: the wall is adiabatic (Neumann conditions on pressure
+  and temperature, Sec. 2.2.4), and the printed G(U^b) grad U+ would carry
+  the interior's conductive flux through it.
 * grad U is the broken element gradient (no lifting operator).
 * G-bar_e = max over the face nodes of both sides (boundary: own trace and
   ghost) of ||N G N^T||_2; recomputed from the current state at every call.
@@ -158,7 +162,8 @@ class DGOracle:
         # viscous normal flux (average of products inside, one-sided on the boundary)
         vxp, vyp = ph.viscous_flux(Up, fs['Uxp'], fs['Uyp'], p.mu, p.Pr, g)
         vxm, vym = ph.viscous_flux(Uo, fs['Uxm'], fs['Uym'], p.mu, p.Pr, g)
-        vxw, vyw = ph.viscous_flux(Uo, fs['Uxp'], fs['Uyp'], p.mu, p.Pr, g)
+        # adiabatic wall: the stress and its work, no heat conduction (Pr -> inf)
+        vxw, vyw = ph.viscous_flux(Uo, fs['Uxp'], fs['Uyp'], p.mu, np.inf, g)
         vn_int = 0.5 * ((vxp + vxm) * nx + (vyp + vym) * ny)
         vn_far = vxp * nx + vyp * ny
         vn_wall = vxw * nx + vyw * ny
@@ -174,6 +179,7 @@ class DGOracle:
         # theta term: c_e theta G(U*)^T (n (x) [U]), lifted with M^-1 D^T E
         Ustar = np.where(wall[None], Uo, Up)
         G = ph.g_matrix(Ustar, p.mu, p.Pr, g)                      # (3, Nfp, K, 8, 8)
+        G = np.where(wall[..., None, None], ph.g_matrix(Ustar, p.mu, np.inf, g), G)
         nvec = np.concatenate([np.moveaxis(jump, 0, -1) * m.nx[:, None, :, None],
                                np.moveaxis(jump, 0, -1) * m.ny[:, None, :, None]], axis=-1)
         q = np.einsum('...ji,...j->...i', G, nvec)                 # G^T (n (x) [U])

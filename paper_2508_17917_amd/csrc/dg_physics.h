@@ -26,6 +26,17 @@ struct Gas {
   T gamma, gm1, igm1, mu, k;  // igm1 = 1/(gamma-1), k = gamma / Pr
 };
 
+// The gas as seen by the viscous terms of an adiabatic wall face (Sec.
+// 2.2.4: Neumann conditions on pressure and temperature there): the same
+// stress, no heat conduction (k = gamma / Pr taken as 0), so that neither
+// the wall's viscous flux nor its theta term carries heat through the wall.
+template <typename T>
+__device__ __forceinline__ Gas<T> gas_wall(const Gas<T>& g) {
+  Gas<T> w = g;
+  w.k = T(0);
+  return w;
+}
+
 // Free-stream quantities used by the perturbation form.
 template <typename T>
 struct Base {

@@ -532,7 +532,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         // on the far field
         T vn[4];
         if (tag == 1) {
-          viscous_normal_flux(gas, so, gxm, gym, nx, ny, vn);
+          // adiabatic wall: stress and its work, no heat conduction
+          viscous_normal_flux(gas_wall(gas), so, gxm, gym, nx, ny, vn);
         } else {
           viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
           if (tag == 0) {
@@ -635,7 +636,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           sH[(ROWC * c + ROWE * e) * HRS + fn] = own - fsc * (Fc[c] - vn[c] + sigma * w[c]);
         }
         T qx[4], qy[4];
-        viscous_transpose(gas, vstate(gas, tag == 1 ? uof : upf), nx, ny, w, qx, qy);
+        viscous_transpose(tag == 1 ? gas_wall(gas) : gas, vstate(gas, tag == 1 ? uof : upf), nx, ny, w, qx, qy);
         const T ce = theta * (tag == 0 ? T(0.5) : T(1)) * fsc;
         const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll
@@ -1020,7 +1021,8 @@ __device__ __forceinline__ void oi_tiles(const DeviceTables& t, const KernelPhys
       sNorm[e * NG + fg] = n1 > n2 ? n1 : n2;
       T vn[4];
       if (tag == 1) {
-        viscous_normal_flux(gas, so, gxp, gyp, nx, ny, vn);
+        // adiabatic wall: stress and its work, no heat conduction
+        viscous_normal_flux(gas_wall(gas), so, gxp, gyp, nx, ny, vn);
       } else {
         viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
         if (tag == 0) {
@@ -1066,7 +1068,7 @@ __device__ __forceinline__ void oi_tiles(const DeviceTables& t, const KernelPhys
         sH[(ROWC * c + ROWE * e) * GRS + fg] = -fsc * (Fc[c] - sVn[c * 4 * NG + e * NG + fg] + sigma * w[c]);
       }
       T qx[4], qy[4];
-      viscous_transpose(gas, vstate(gas, tag == 1 ? uo : up), nx, ny, w, qx, qy);
+      viscous_transpose(tag == 1 ? gas_wall(gas) : gas, vstate(gas, tag == 1 ? uo : up), nx, ny, w, qx, qy);
       const T ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
       const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll
