@@ -194,6 +194,23 @@ int dg_force(dg_ctx* ctx, const double* U, const double v_w[2], double out[3], v
 int dg_force_device(dg_ctx* ctx, const double* U, const double v_w[2], double* out_dev,
                     void* stream);
 
+/* Time step from the CFL condition (eq. cfl_general; Alg. 3, "Calculate Time
+ * Step"): out[0] = Lambda, the bound of eq. rayleigh_bound on the numerical
+ * range of the operator at the state U (binary64 [K][4][Np], device) with
+ * wall velocity v_w,
+ *   Lambda = max_K (3/2 C_inv,2(K) G_K + 3 C_inv,K (3 sigma_K + beta_K) + beta'_K),
+ * C_inv,K = Np max_e |e|/|K|, C_inv,2(K) = C_grad p^4 / rho_K^2 (rho_K the
+ * inscribed radius, C_grad the generic constant of the inverse estimate),
+ * sigma_K the largest face penalty of K as the right-hand side forms it,
+ * beta_K = max over K's nodes of |v - v_w| + c, beta'_K = 1/2 max |div v|
+ * (nodal derivative of the interpolated velocity), G_K the largest
+ * directional norm ||e_a^T G e_a||_2 (a = x, y) over the nodes of K and its
+ * face neighbours; out[1] = C_cfl / Lambda.  C_cfl > 0 and C_grad >= 0, else
+ * DG_EINVAL; a non-finite bound gives DG_ENONFINITE.  Uses the context's
+ * work buffer (set up by dg_setup); synchronises `stream`. */
+int dg_cfl_time_step(dg_ctx* ctx, const double* U, const double v_w[2], double C_cfl, double C_grad,
+                     double out[2], void* stream);
+
 /* Host Newmark-beta step (beta 1/4, gamma 1/2) of M y'' + C y' + K y = F
  * (eq. 1dof_oscillator): state[3] = (y, y', y'') at t, updated to t + dt
  * with the load F_new. */

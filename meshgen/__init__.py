@@ -91,6 +91,25 @@ def ogrid(ntheta, nr, R0=0.5, R1=30.0, ratio=1.05):
                 face_tag=np.array(tags, dtype=np.int8), period=(0.0, 0.0))
 
 
+def growth_ratio(R0, R1, nr, h_wall):
+    """Geometric growth ratio q > 1 of nr radial cells from R0 to R1 whose
+    first cell is h_wall thick: h_wall (q^nr - 1) / (q - 1) = R1 - R0, solved
+    by bisection (requires h_wall < (R1 - R0) / nr)."""
+    L = R1 - R0
+    if not (0.0 < h_wall < L / nr):
+        raise ValueError("h_wall must lie in (0, (R1 - R0) / nr)")
+    lo, hi = 1.0 + 1e-12, 2.0
+    while h_wall * (hi ** nr - 1.0) / (hi - 1.0) < L:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if h_wall * (mid ** nr - 1.0) / (mid - 1.0) < L:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
 # --------------------------------------------------------------------------
 # flow parameters
 # --------------------------------------------------------------------------
@@ -138,6 +157,22 @@ def noisy_free_stream(shape, U_inf, rng, amp=1e-3):
     return np.asarray(U_inf).reshape((4,) + (1,) * (len(shape) - 1)) * (1.0 + amp * xi)
 
 
+def wake_kick(x, y, U_inf, amp=0.1, xc=1.5, R=0.5, gamma=1.4):
+    """Free stream with a transverse velocity blob behind the cylinder,
+    v += amp |v_inf| exp(-((x - xc)^2 + y^2) / R^2) (density and pressure of
+    the free stream): breaks the up-down symmetry so that shedding starts
+    early instead of growing from rounding."""
+    U_inf = np.asarray(U_inf, dtype=np.float64)
+    rho = U_inf[0]
+    u, v = U_inf[1] / rho, U_inf[2] / rho
+    p = (gamma - 1.0) * (U_inf[3] - 0.5 * rho * (u * u + v * v))
+    vel = math.hypot(u, v)
+    vv = v + amp * vel * np.exp(-((x - xc) ** 2 + y ** 2) / (R * R))
+    uu = np.full(np.shape(x), u)
+    r = np.full(np.shape(x), rho)
+    return np.stack([r, r * uu, r * vv, p / (gamma - 1.0) + 0.5 * r * (uu * uu + vv * vv)])
+
+
 def fourier_modes(x, y, rng, L=10.0, amp=1e-2, q0=(1.0, 0.3, 0.0, 1.0 / 1.4), gamma=1.4, nmodes=3):
     """Smooth periodic state: each primitive q0 + amp sum_m a_m sin(2 pi k_m.x / L + phi_m)."""
     prim = []
@@ -176,6 +211,14 @@ def workload(name, p=None):
         mesh = periodic_square(160, 160, 10.0, 10.0)
         phys = physics_params(Re=100.0, M=0.3, L=1.0)
         return dict(mesh=mesh, p=6 if p is None else p, penalty_mode=0, C_pen=1.0, theta=1.0, **phys)
+    if name == "shedding20k":
+        # stand-in for the stationary-cylinder mesh of the shedding study
+        # (about 20k cells, 17 mm first layer at the wall, far field 50 D
+        # away): an O-grid of 128 x 80 quads, K = 20,480, interior penalty
+        # with theta = 0 (IIP) and C1 = 0.01, Re = 200, M = 0.1
+        mesh = ogrid(128, 80, 0.5, 50.0, growth_ratio(0.5, 50.0, 80, 0.017))
+        phys = physics_params(Re=200.0, M=0.1, L=1.0)
+        return dict(mesh=mesh, p=3 if p is None else p, penalty_mode=0, C_pen=0.01, theta=0.0, **phys)
     raise KeyError(name)
 
 

@@ -1,4 +1,4 @@
-"""Body force, rigid-body Newmark step and CFL time step (oracle; test infrastructure).
+"""Body force and rigid-body Newmark step (oracle; test infrastructure).
 
 * Force (Alg. 3, "Calculate Aerodynamic Forces"): the paper gives no formula.
   Reading: the traction the fluid exerts on the body, integrated over the wall
@@ -9,12 +9,6 @@
 * Rigid body (eq. 1dof_oscillator): Newmark with beta_N = 1/4, gamma_N = 1/2;
   coefficients M_r = 1, C_r = 4 pi f_n xi, K_r = (1 + 1/m*)(2 pi f_n)^2,
   F_r = Lift / m (Sec. 3.3.1).
-* CFL (eq. cfl_general, eq. rayleigh_bound): dt = C_CFL / Lambda with
-  Lambda = max_K (3/2 C_inv2(K) G_K + (d+1) C_inv,K (3 sigma_K + beta_K) + beta'_K),
-  C_inv2 = p^4 / rho_K^2 (C_grad = 1, rho_K the inradius), G_K the largest nodal
-  ||G||_2 over K and its face neighbours, beta_K the largest |v - v_w| + c on K,
-  beta'_K = 0 (uniform v_w).  Parity unpinned beyond its ingredients: the
-  paper's constant C_grad is not given and dt is only ever passed explicitly.
 """
 import math
 
@@ -64,24 +58,3 @@ def newmark_step(y, yd, ydd, F_new, dt, M, C, K, beta=0.25, gam=0.5):
     yd_n = yd + dt * ((1.0 - gam) * ydd + gam * ydd_n)
     y_n = y + dt * yd + 0.5 * dt * dt * ((1.0 - 2.0 * beta) * ydd + 2.0 * beta * ydd_n)
     return y_n, yd_n, ydd_n
-
-
-def cfl_dt(dg, U, C_cfl=0.3, vw=(0.0, 0.0)):
-    m, ref, p = dg.mesh, dg.ref, dg.phys
-    N = ref.N
-    rho, u, v, pres = ph.primitives(U, p.gamma)
-    c = np.sqrt(p.gamma * pres / rho)
-    beta = (np.hypot(u - vw[0], v - vw[1]) + c).max(axis=0)                 # (K,)
-    G = ph.g_matrix(U, p.mu, p.Pr, p.gamma)
-    gK = np.linalg.norm(G, ord=2, axis=(-2, -1)).max(axis=0)                # (K,)
-    nb = np.where(m.EToE >= 0, m.EToE, np.arange(m.K)[:, None])
-    gK = np.maximum(gK, gK[nb].max(axis=1))
-    perim = m.face_len.sum(axis=0)
-    inradius = 2.0 * m.area / perim
-    cinv2 = N ** 4 / inradius ** 2
-    cinv = ((N + 1) * (N + 2) * m.face_len / (2.0 * m.area[None, :])).max(axis=0)
-    Ux, Uy = dg.gradient(U)
-    fs = dg.face_states(U, Ux, Uy, np.asarray(vw, dtype=np.float64))
-    sigK = dg.penalty(dg.gbar(fs)).max(axis=0)
-    lam = (1.5 * cinv2 * gK + 3.0 * cinv * (3.0 * sigK + beta)).max()
-    return C_cfl / lam

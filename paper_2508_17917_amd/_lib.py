@@ -47,6 +47,7 @@ SIGNATURES = {
     "dg_rk_stage": (_I, [_P, _P, _P, _P, _D, _D, _D, _DP, _P]),
     "dg_force": (_I, [_P, _P, _DP, _DP, _P]),
     "dg_force_device": (_I, [_P, _P, _DP, _P, _P]),
+    "dg_cfl_time_step": (_I, [_P, _P, _DP, _D, _D, _DP, _P]),
     "dg_newmark_step": (_I, [_DP, _D, _D, _D, _D, _D]),
     "dg_set_tuning": (_I, [_P, _I, _I]),
     "dg_get_tuning": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -247,6 +248,13 @@ def dg_force(h, U, v_w=(0.0, 0.0), stream=None):
 def dg_force_device(h, U, out, v_w=(0.0, 0.0), stream=None):
     vw = _vw(v_w)
     return _check(load().dg_force_device(h, _ptr(U), _dp(vw), _ptr(out), _stream(stream)), h)
+
+
+def dg_cfl_time_step(h, U, v_w=(0.0, 0.0), C_cfl=1.0, C_grad=1.0, stream=None):
+    vw = _vw(v_w)
+    out = np.zeros(2)
+    _check(load().dg_cfl_time_step(h, _ptr(U), _dp(vw), C_cfl, C_grad, _dp(out), _stream(stream)), h)
+    return float(out[0]), float(out[1])
 
 
 def dg_newmark_step(state, F_new, dt, M, C, K):

@@ -167,9 +167,14 @@ int force_blocks_for(int N, int nwall);
 // workgroups (items in device memory, block ranges consecutive from 0)
 int launch_batch_force(int N, const ForceItem* items, int count, int blocks, void* stream,
                        std::string& err);
+// cfl.hip: Lambda of the CFL bound on the state U into work[6K] (work holds
+// cfl_work_size(K) doubles)
+size_t cfl_work_size(int64_t K);
+int launch_cfl(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U, double C_grad,
+               double* work, void* stream, std::string& err);
 int launch_force(int N, const DeviceTables& t, const KernelPhysics& ph, const double* U,
                  double* out_dev, void* stream, std::string& err);
-// operator packing: Dr | Ds | LIFT | LIFTr | LIFTs | Fmask (as doubles) | wface
+// operator packing: Dr | Ds | LIFT | LIFTr | LIFTs | wface
 size_t ops_packed_size(int N);
 void pack_ops(const RefOps& ref, std::vector<double>& out);
 // Dr | Ds | LIFT | LIFTr | LIFTs as B-operand fragments of the 16x16x4 FP64

@@ -30,7 +30,7 @@ int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
 void free_device(dg_ctx* c) {
   void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,       c->d_frag32,
                   c->d_frag16, c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force,
-                  c->d_force_part, c->d_force_ticket, c->d_oi};
+                  c->d_force_part, c->d_force_ticket, c->d_oi, c->d_cfl};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   c->d_geo = nullptr;
@@ -46,6 +46,7 @@ void free_device(dg_ctx* c) {
   c->d_force_part = nullptr;
   c->d_force_ticket = nullptr;
   c->d_oi = nullptr;
+  c->d_cfl = nullptr;
   c->force_blocks = 0;
   c->dev_ready = false;
 }
@@ -215,6 +216,7 @@ int dg_setup(dg_ctx* c) {
       (e = hipMalloc((void**)&c->d_force, 4 * sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void**)&c->d_force_part, 3 * fb * sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void**)&c->d_force_ticket, sizeof(unsigned))) != hipSuccess ||
+      (e = hipMalloc((void**)&c->d_cfl, dgmi::cfl_work_size(c->K) * sizeof(double))) != hipSuccess ||
       (e = hipMemset(c->d_force_ticket, 0, sizeof(unsigned))) != hipSuccess) {
     free_device(c);
     return e == hipErrorOutOfMemory ? fail(c, DG_ENOMEM, "device allocation failed")
@@ -390,6 +392,26 @@ int dg_force(dg_ctx* c, const double* U, const double v_w[2], double out[3], voi
   out[0] = h[0];
   out[1] = h[1];
   out[2] = h[2];
+  return DG_OK;
+}
+
+int dg_cfl_time_step(dg_ctx* c, const double* U, const double v_w[2], double C_cfl, double C_grad,
+                     double out[2], void* stream) {
+  int rc = check_ready(c);
+  if (rc != DG_OK) return rc;
+  if (!U || !out) return fail(c, DG_EINVAL, "NULL argument");
+  if (!(C_cfl > 0.0) || !(C_grad >= 0.0)) return fail(c, DG_EINVAL, "C_cfl must be > 0, C_grad >= 0");
+  std::string err;
+  rc = dgmi::launch_cfl(c->N, tables(c), kphys(c, v_w), U, C_grad, c->d_cfl, stream, err);
+  if (rc != 0) return fail(c, rc, err);
+  double lam = 0.0;
+  hipError_t e = hipMemcpyAsync(&lam, c->d_cfl + 6 * c->K, sizeof(double), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "CFL read-back");
+  if (!std::isfinite(lam) || !(lam > 0.0)) return fail(c, DG_ENONFINITE, "CFL bound is not finite and positive");
+  out[0] = lam;
+  out[1] = C_cfl / lam;
   return DG_OK;
 }
 

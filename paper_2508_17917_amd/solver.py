@@ -89,6 +89,10 @@ class Solver:
         L.dg_force_device(self.h, U, out, v_w, stream)
         return out
 
+    def cfl_time_step(self, U, v_w=(0.0, 0.0), C_cfl=1.0, C_grad=1.0, stream=None):
+        """(Lambda, C_cfl / Lambda): the CFL bound at the state U."""
+        return L.dg_cfl_time_step(self.h, U, v_w, C_cfl, C_grad, stream)
+
     # -- launch shape
     def set_tuning(self, waves=0, grid=0):
         L.dg_set_tuning(self.h, waves, grid)

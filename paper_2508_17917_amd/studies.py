@@ -1,0 +1,332 @@
+"""The paper's flow studies, run on the library's kernels.
+
+* Stationary cylinder, p-sensitivity (Sec. 3.2.1): mean and RMS of the lift
+  and drag coefficients of eq. lift_drag over a window past the transient,
+  the Strouhal number from a DFT of the lift, and the differences
+  delta_p f = f(p + 1) - f(p) between successive orders.
+* Elastically mounted cylinder (Sec. 3.3): per reduced velocity U*, the
+  maximum amplitude, the maximum lift coefficient and the primary frequency
+  of the displacement (DFT) over a sampling window, all instances advanced
+  as one batch with the weak coupling of Alg. 3.
+
+Time steps follow the CFL condition of eq. cfl_general (dg_cfl_time_step,
+recomputed every `cfl_every` steps from the current state).  Times are in
+convective units t* = t |v_inf| / D (the library works in units of D / c_inf;
+the paper's seconds with D = 1 m and |v_inf| = 1 m/s are convective units).
+
+Run as  python -m paper_2508_17917_amd.studies {cylinder,viv} ...  from the
+repository root (the synthetic meshes come from the meshgen module there).
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import _lib as L
+from .solver import Solver
+from .viv import VIVSweep
+
+FORMS = {"fp64": L.DG_FP64, "fp64-pert": L.DG_FP64_PERT, "fp32-pert": L.DG_FP32_PERT}
+
+
+# --------------------------------------------------------------------------
+# post-processing (host)
+# --------------------------------------------------------------------------
+def free_stream_speed(U_inf):
+    U_inf = np.asarray(U_inf, dtype=np.float64)
+    return float(math.hypot(U_inf[1], U_inf[2]) / U_inf[0])
+
+
+def force_coefficients(F, U_inf, D=1.0):
+    """(C_D, C_L) of eq. lift_drag from force rows F[..., (Fx, Fy, ...)]:
+    drag along the free stream, lift perpendicular to it (90 degrees
+    counter-clockwise), both over 1/2 rho_inf |v_inf|^2 D."""
+    U_inf = np.asarray(U_inf, dtype=np.float64)
+    rho = U_inf[0]
+    vx, vy = U_inf[1] / rho, U_inf[2] / rho
+    v = math.hypot(vx, vy)
+    ex, ey = vx / v, vy / v
+    q = 0.5 * rho * v * v * D
+    F = np.asarray(F)
+    return (F[..., 0] * ex + F[..., 1] * ey) / q, (-F[..., 0] * ey + F[..., 1] * ex) / q
+
+
+def window(t, a, t0, t1):
+    m = (t >= t0) & (t <= t1)
+    if m.sum() < 2:
+        raise ValueError("no samples in the window [%g, %g]" % (t0, t1))
+    return t[m], a[m]
+
+
+def window_stats(t, a, t0, t1):
+    """mean, root mean square and maximum magnitude of a over [t0, t1]."""
+    _, w = window(t, a, t0, t1)
+    return float(w.mean()), float(np.sqrt(np.mean(w * w))), float(np.abs(w).max())
+
+
+def dominant_frequency(t, a, t0, t1, pad=16):
+    """Frequency of the largest DFT magnitude of a (mean removed, Hann
+    window, zero-padded `pad` times) over [t0, t1], refined by a parabola
+    through the peak bin and its neighbours.  Uniform sampling assumed."""
+    tw, w = window(t, a, t0, t1)
+    dt = (tw[-1] - tw[0]) / (len(tw) - 1)
+    x = (w - w.mean()) * np.hanning(len(w))
+    n = pad * len(x)
+    mag = np.abs(np.fft.rfft(x, n))
+    i = int(np.argmax(mag[1:])) + 1
+    if 1 <= i < len(mag) - 1:
+        y0, y1, y2 = mag[i - 1], mag[i], mag[i + 1]
+        den = y0 - 2.0 * y1 + y2
+        d = 0.5 * (y0 - y2) / den if den != 0.0 else 0.0
+    else:
+        d = 0.0
+    return (i + d) / (n * dt)
+
+
+def p_differences(rows, keys):
+    """delta_p f = f(p + 1) - f(p) for consecutive orders in rows (sorted by p)."""
+    rows = sorted(rows, key=lambda r: r["p"])
+    out = []
+    for a, b in zip(rows[:-1], rows[1:]):
+        out.append(dict(p=a["p"], **{"d_" + k: b[k] - a[k] for k in keys}))
+    return out
+
+
+# --------------------------------------------------------------------------
+# stationary cylinder
+# --------------------------------------------------------------------------
+class CylinderRun:
+    """One order of the stationary-cylinder study: a solver, a state and its
+    force history (coefficients recorded every `record_every` steps)."""
+
+    def __init__(self, mesh, p, phys, U0, precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0,
+                 cfl_every=2000, record_every=10):
+        import torch
+        self.phys = phys
+        self.s = Solver(p, mesh, gamma=phys["gamma"], Pr=phys["Pr"], mu=phys["mu"],
+                        theta=phys["theta"], penalty_mode=phys["penalty_mode"], C_pen=phys["C_pen"],
+                        U_inf=phys["U_inf"], precision=precision)
+        self.p = p
+        self.U = torch.from_numpy(np.ascontiguousarray(U0)).cuda()
+        self.K1 = torch.zeros_like(self.U)
+        self.F = torch.zeros(3 * cfl_every, dtype=torch.float64, device="cuda")
+        self.C_cfl, self.C_grad = C_cfl, C_grad
+        self.cfl_every, self.record_every = cfl_every, record_every
+        self.vel = free_stream_speed(phys["U_inf"])
+        self.t = 0.0          # library units
+        self.steps = 0
+        self.t_rec, self.CD, self.CL, self.dts = [], [], [], []
+        self.log_every = 25
+
+    def advance(self, t_end_conv, log=None):
+        """Step until the convective time t_end_conv; False if the state
+        stopped being finite."""
+        import torch
+        t_end = t_end_conv / self.vel
+        t0 = time.time()
+        while self.t < t_end:
+            _, dt = self.s.cfl_time_step(self.U, C_cfl=self.C_cfl, C_grad=self.C_grad)
+            n = self.cfl_every
+            self.s.rk_steps(self.U, self.K1, n, dt, force=self.F)
+            F = self.F.view(n, 3).cpu().numpy()
+            if not np.isfinite(F).all():
+                return False
+            sel = np.arange(self.record_every - 1, n, self.record_every)
+            cd, cl = force_coefficients(F[sel], self.phys["U_inf"])
+            self.t_rec.append((self.t + (sel + 1) * dt) * self.vel)
+            self.CD.append(cd)
+            self.CL.append(cl)
+            self.dts.append(dt * self.vel)
+            self.t += n * dt
+            self.steps += n
+            if log is not None and len(self.dts) % self.log_every == 0:
+                log("p=%d t*=%.2f steps=%d dt*=%.4g C_D=%.4f C_L=%+.4f (%.0f s)"
+                    % (self.p, self.t * self.vel, self.steps, dt * self.vel, cd[-1], cl[-1],
+                       time.time() - t0))
+        torch.cuda.synchronize()
+        return True
+
+    def series(self):
+        return np.concatenate(self.t_rec), np.concatenate(self.CD), np.concatenate(self.CL)
+
+    def summary(self, t0, t1):
+        t, cd, cl = self.series()
+        cd_m, cd_rms, _ = window_stats(t, cd, t0, t1)
+        cl_m, cl_rms, cl_max = window_stats(t, cl, t0, t1)
+        return dict(p=self.p, steps=self.steps, dt=float(np.median(self.dts)),
+                    CL_mean=cl_m, CL_rms=cl_rms, CD_mean=cd_m, CD_rms=cd_rms, CL_max=cl_max,
+                    St=dominant_frequency(t, cl, t0, t1))
+
+    def close(self):
+        self.s.close()
+
+
+def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0,
+                   kick=0.1, log=None, series_out=None):
+    """Strouhal number (f D / |v_inf| = the lift's frequency in convective
+    units, D = 1), mean and RMS of C_L and C_D over
+    [t0, t1] for every order in ps, and their differences between orders."""
+    import meshgen as mg
+    rows, series = [], {}
+    for p in ps:
+        s0 = Solver(p, mesh, gamma=phys["gamma"], Pr=phys["Pr"], mu=phys["mu"], device=False,
+                    U_inf=phys["U_inf"])
+        x, y = s0.nodes()
+        s0.close()
+        U0 = np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=kick, gamma=phys["gamma"]), (1, 0, 2))
+        run = CylinderRun(mesh, p, phys, U0, precision, C_cfl, C_grad)
+        w0 = time.time()
+        ok = run.advance(t_end, log)
+        wall = time.time() - w0
+        if not ok:
+            rows.append(dict(p=p, finite=False, steps=run.steps))
+            run.close()
+            continue
+        r = run.summary(t0, t1)
+        r.update(finite=True, wall_s=wall,
+                 dof_updates_per_s=5.0 * 4 * run.s.Np * run.s.K * run.steps / wall)
+        rows.append(r)
+        if series_out is not None:
+            series[p] = run.series()
+        if log is not None:
+            log("p=%d done: St=%.4f C_D mean %.4f rms %.4f C_L mean %+.5f rms %.4f, %d steps, %.1f s"
+                % (p, r["St"], r["CD_mean"], r["CD_rms"], r["CL_mean"], r["CL_rms"], run.steps, wall))
+        run.close()
+    good = [r for r in rows if r.get("finite")]
+    diffs = p_differences(good, ["CL_mean", "CL_rms", "CD_mean", "CD_rms", "St"])
+    if series_out is not None and series:
+        np.savez_compressed(series_out, **{"p%d_%s" % (p, k): v for p, ser in series.items()
+                                           for k, v in zip(("t", "CD", "CL"), ser)})
+    return dict(rows=rows, differences=diffs)
+
+
+# --------------------------------------------------------------------------
+# elastically mounted cylinder
+# --------------------------------------------------------------------------
+def viv_study(mesh, phys, p, U_stars, t_end, t0, t1, m_star=1.0, xi=0.01,
+              precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0, kick=0.1, cfl_every=2000,
+              record_every=10, log=None, series_out=None):
+    """Per U*: max |y| / D, max |C_L| and the primary frequency of y over
+    [t0, t1] (convective units), as f D / |v_inf| and as f / f_n; all
+    instances share the mesh, the order and one time step (the smallest of
+    their CFL steps)."""
+    import torch
+
+    import meshgen as mg
+    cases = [dict(mesh=mesh, p=p, U_star=float(u), m_star=m_star, xi=xi) for u in U_stars]
+    sw = VIVSweep(cases, phys["gamma"], phys["Pr"], phys["mu"], phys["theta"], phys["penalty_mode"],
+                  phys["C_pen"], phys["U_inf"], precision=precision)
+    vel = free_stream_speed(phys["U_inf"])
+    x, y = sw.solvers[0].nodes()
+    U0 = torch.from_numpy(np.ascontiguousarray(
+        np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=kick, gamma=phys["gamma"]), (1, 0, 2)))).cuda()
+    for i in range(sw.n):
+        sw.set_state(i, U0)
+    sw.update_forces()
+    n = sw.n
+    t_lib, steps = 0.0, 0
+    rec_t, rec_y, rec_cl = [], [], []
+    w0 = time.time()
+    finite = True
+    while t_lib * vel < t_end:
+        dts = np.empty(n)
+        for i in range(n):
+            Ui = sw.get_state(i)
+            dts[i] = sw.solvers[i].cfl_time_step(Ui, v_w=tuple(sw.vw[i]), C_cfl=C_cfl, C_grad=C_grad)[1]
+        dt = float(dts.min())       # one clock for the whole sweep
+        for k in range(cfl_every):
+            sw.step(dt)
+            if (k + 1) % record_every == 0:
+                rec_t.append((t_lib + (k + 1) * dt) * vel)
+                rec_y.append(sw.body[:, 0].copy())
+                rec_cl.append(force_coefficients(sw.F, phys["U_inf"])[1])
+        t_lib += cfl_every * dt
+        steps += cfl_every
+        if not (np.isfinite(sw.F).all() and np.isfinite(sw.body).all()):
+            finite = False
+            break
+        if log is not None and (steps // cfl_every) % 25 == 0:
+            log("viv t*=%.2f steps=%d dt*=%.4g max|y|=%.4f (%.0f s)"
+                % (t_lib * vel, steps, dt * vel, np.abs(sw.body[:, 0]).max(), time.time() - w0))
+    wall = time.time() - w0
+    t = np.array(rec_t)
+    Y = np.array(rec_y)
+    CL = np.array(rec_cl)
+    rows = []
+    for i, u in enumerate(U_stars):
+        # natural frequency in convective units: f_n D / |v_inf| = 1 / U*
+        r = dict(U_star=float(u), f_n=1.0 / float(u))
+        if finite:
+            _, _, amax = window_stats(t, Y[:, i], t0, t1)
+            _, _, clmax = window_stats(t, CL[:, i], t0, t1)
+            f = dominant_frequency(t, Y[:, i], t0, t1)     # convective units
+            r.update(A_max=amax, CL_max=clmax, f_prim=f, f_ratio=f * float(u))
+        rows.append(r)
+    if series_out is not None and finite:
+        np.savez_compressed(series_out, t=t, y=Y, CL=CL, U_star=np.asarray(U_stars, dtype=float))
+    dofs = sum(s.K * 4 * s.Np for s in sw.solvers)
+    sw.close()
+    return dict(rows=rows, finite=finite, steps=steps, wall_s=wall,
+                dof_updates_per_s=5.0 * dofs * steps / wall)
+
+
+# --------------------------------------------------------------------------
+def _log(msg):
+    print("[study] " + msg, file=sys.stderr, flush=True)
+
+
+def main(argv=None):
+    import meshgen as mg
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    sub = ap.add_subparsers(dest="study", required=True)
+    for name in ("cylinder", "viv"):
+        a = sub.add_parser(name)
+        a.add_argument("--t-end", type=float, required=True, help="convective time")
+        a.add_argument("--window", type=float, nargs=2, required=True, help="t0 t1, convective")
+        a.add_argument("--form", default="fp32-pert", choices=sorted(FORMS))
+        a.add_argument("--c-cfl", type=float, default=8.0)
+        a.add_argument("--c-grad", type=float, default=1.0)
+        a.add_argument("--kick", type=float, default=0.1)
+        a.add_argument("--c-pen", type=float, default=None, help="penalty constant (default 0.01)")
+        a.add_argument("--theta", type=float, default=None, help="theta (default 0, IIP)")
+        a.add_argument("--out", default=None, help="JSON result file")
+        a.add_argument("--series", default=None, help=".npz file for the recorded series")
+        if name == "cylinder":
+            a.add_argument("--p", type=int, nargs="+", default=[1, 2, 3, 4])
+        else:
+            a.add_argument("--p", type=int, default=3)
+            a.add_argument("--ustar", type=float, nargs="+", required=True)
+            a.add_argument("--m-star", type=float, default=1.0)
+            a.add_argument("--xi", type=float, default=0.01)
+    args = ap.parse_args(argv)
+    w = mg.workload("shedding20k")
+    phys = {k: w[k] for k in ("gamma", "Pr", "mu", "theta", "penalty_mode", "C_pen", "U_inf")}
+    if args.c_pen is not None:
+        phys["C_pen"] = args.c_pen
+    if args.theta is not None:
+        phys["theta"] = args.theta
+    t0, t1 = args.window
+    if args.study == "cylinder":
+        res = cylinder_study(w["mesh"], phys, args.p, args.t_end, t0, t1, FORMS[args.form],
+                             args.c_cfl, args.c_grad, args.kick, log=_log, series_out=args.series)
+    else:
+        res = viv_study(w["mesh"], phys, args.p, args.ustar, args.t_end, t0, t1, args.m_star,
+                        args.xi, FORMS[args.form], args.c_cfl, args.c_grad, args.kick, log=_log,
+                        series_out=args.series)
+    res.update(study=args.study, mesh="shedding20k: O-grid 128x80 cells, first layer 0.017 D, "
+               "far field at 50 D, K=20480", Re=200.0, M=0.1, form=args.form, C_cfl=args.c_cfl,
+               C_grad=args.c_grad, C_pen=phys["C_pen"], theta=phys["theta"], window=[t0, t1],
+               t_end=args.t_end)
+    line = json.dumps(res, default=float)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

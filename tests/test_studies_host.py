@@ -1,0 +1,75 @@
+"""Host logic of the flow studies (paper_2508_17917_amd.studies) and of
+their synthetic inputs: force coefficients of eq. lift_drag, window
+statistics, the DFT frequency estimate, differences between orders, the
+graded O-grid of the shedding mesh and its initial state."""
+import math
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+from paper_2508_17917_amd.studies import (dominant_frequency, force_coefficients, p_differences,
+                                          window_stats)
+
+
+def test_force_coefficients_along_and_across_the_stream():
+    U = mg.free_stream(0.1)
+    q = 0.5 * 1.0 * 0.1 ** 2
+    cd, cl = force_coefficients(np.array([[2.0 * q, 0.5 * q, 0.0]]), U)
+    assert cd[0] == pytest.approx(2.0) and cl[0] == pytest.approx(0.5)
+    # a stream at 30 degrees: drag along it, lift 90 degrees counter-clockwise
+    a = math.radians(30.0)
+    U = mg.free_stream(0.1, angle=a)
+    F = np.array([[q * (1.5 * math.cos(a) - 0.2 * math.sin(a)), q * (1.5 * math.sin(a) + 0.2 * math.cos(a)), 0.0]])
+    cd, cl = force_coefficients(F, U)
+    assert cd[0] == pytest.approx(1.5) and cl[0] == pytest.approx(0.2)
+
+
+def test_window_stats_of_a_sine():
+    t = np.linspace(0.0, 100.0, 100001)
+    a = 0.3 + np.sin(2.0 * math.pi * 0.2 * t)
+    m, rms, amax = window_stats(t, a, 20.0, 70.0)     # ten whole periods
+    assert m == pytest.approx(0.3, abs=1e-4)
+    assert rms == pytest.approx(math.sqrt(0.09 + 0.5), abs=1e-4)
+    assert amax == pytest.approx(1.3, abs=1e-6)
+
+
+@pytest.mark.parametrize("f0", [0.1987, 0.2, 0.37])
+def test_dominant_frequency(f0):
+    rng = np.random.default_rng(0)
+    t = np.arange(0.0, 120.0, 0.01)
+    a = 0.8 * np.sin(2.0 * math.pi * f0 * t + 0.4) + 0.1 * np.sin(2.0 * math.pi * 2 * f0 * t) \
+        + 0.01 * rng.standard_normal(t.shape) + 2.0
+    assert dominant_frequency(t, a, 30.0, 120.0) == pytest.approx(f0, rel=2e-3)
+
+
+def test_p_differences():
+    rows = [dict(p=3, a=1.0), dict(p=1, a=4.0), dict(p=2, a=2.5)]
+    d = p_differences(rows, ["a"])
+    assert [r["p"] for r in d] == [1, 2]
+    assert [r["d_a"] for r in d] == [-1.5, -1.5]
+
+
+def test_shedding_mesh_grading():
+    q = mg.growth_ratio(0.5, 50.0, 80, 0.017)
+    assert 0.017 * (q ** 80 - 1.0) / (q - 1.0) == pytest.approx(49.5, rel=1e-12)
+    w = mg.workload("shedding20k")
+    m = w["mesh"]
+    r = np.hypot(m["VX"], m["VY"]).reshape(81, 128)[:, 0]
+    assert r[1] - r[0] == pytest.approx(0.017, rel=1e-9)
+    assert r[-1] == 50.0 and len(m["EToV"]) == 20480
+    assert w["theta"] == 0.0 and w["C_pen"] == 0.01
+    assert w["mu"] == pytest.approx(0.1 / 200.0)
+    with pytest.raises(ValueError):
+        mg.growth_ratio(0.5, 50.0, 80, 1.0)
+
+
+def test_wake_kick():
+    x = np.linspace(-3.0, 5.0, 81)
+    y = np.zeros_like(x)
+    U = mg.wake_kick(x, y, mg.free_stream(0.1), amp=0.1)
+    rho = U[0]
+    v = U[2] / rho
+    p = 0.4 * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / rho)
+    assert np.allclose(rho, 1.0) and np.allclose(p, 1.0 / 1.4) and np.allclose(U[1] / rho, 0.1)
+    assert v.max() == pytest.approx(0.01, rel=1e-12) and x[np.argmax(v)] == pytest.approx(1.5)
