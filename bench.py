@@ -59,7 +59,7 @@ FORMS = {"fp64": 0, "fp64-pert": 1, "fp32-pert": 2, "bf16-ops": 3}
 # plain 512 MiB device copy (FETCH x 2.000, WRITE x 1.000); valid only for the
 # kernel sources and form they were taken on (hash of kernels.hip +
 # dg_physics.h).
-MEASURED_TRAFFIC = {"sources": "fa2bb834df3bd242", "p": 4, "form": "fp32-pert",
+MEASURED_TRAFFIC = {"sources": "16531448c4e8da51", "p": 4, "form": "fp32-pert",
                     "fetch_bytes": 11502.0 * 2.0 * 1024, "write_bytes": 19200.0 * 1.0 * 1024}
 
 
