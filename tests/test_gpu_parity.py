@@ -208,6 +208,32 @@ def test_rk_steps_equal_repeated_steps():
     s.close()
 
 
+def test_rk_steps_with_forces_at_full_size():
+    """cylinder20k (K = 20,480, p = 4, FP32 perturbation form): the
+    multi-step call with a force after every step equals single steps with a
+    force after each, bit for bit, over an odd number of steps."""
+    torch = _torch()
+    from paper_2508_17917_amd import Solver
+    w = mg.workload("cylinder20k")
+    s = Solver(4, w["mesh"], gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+               penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"], precision=2)
+    U0 = mg.noisy_free_stream((4, s.Np, s.K), w["U_inf"], mg.rng_for(1))
+    U0 = torch.from_numpy(np.ascontiguousarray(np.transpose(U0, (2, 0, 1)))).cuda()
+    n, dt, vw = 7, 1e-7, (0.0, 0.002)
+    _say("rk_steps with forces cylinder20k n=%d" % n)
+    Ua, Ka = U0.clone(), torch.zeros_like(U0)
+    Fa = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    s.rk_steps(Ua, Ka, n, dt, v_w=vw, force=Fa)
+    Ub, Kb = U0.clone(), torch.zeros_like(U0)
+    Fb = torch.zeros_like(Fa)
+    for i in range(n):
+        s.rk_step(Ub, Kb, dt, v_w=vw)
+        s.force_device(Ub, Fb[i], v_w=vw)
+    torch.cuda.synchronize()
+    assert torch.equal(Ua, Ub) and torch.equal(Fa, Fb)
+    s.close()
+
+
 def test_conservation_and_free_stream_at_large_size():
     """Properties that hold at any size, on a 320x320x2 periodic mesh
     (K = 204,800, p = 4): the discrete integral sum_K J_K 1^T M R_K of every
