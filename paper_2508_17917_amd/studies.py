@@ -116,6 +116,7 @@ class CylinderRun:
         self.C_cfl, self.C_grad = C_cfl, C_grad
         self.cfl_every, self.record_every = cfl_every, record_every
         self.vel = free_stream_speed(phys["U_inf"])
+        self.s.autotune(self.U, reps=10)   # launch shape of the stage kernel
         self.t = 0.0          # library units
         self.steps = 0
         self.t_rec, self.CD, self.CL, self.dts = [], [], [], []
@@ -225,6 +226,10 @@ def viv_study(mesh, phys, p, U_stars, t_end, t0, t1, m_star=1.0, xi=0.01,
         np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=kick, gamma=phys["gamma"]), (1, 0, 2)))).cuda()
     for i in range(sw.n):
         sw.set_state(i, U0)
+    # launch plan of the batch (one kernel for all orders or one sized for
+    # each order group, waves, grid) from timed trials; every plan gives the
+    # same bits
+    sw.batch.autotune(reps=10)
     sw.update_forces()
     n = sw.n
     t_lib, steps = 0.0, 0
