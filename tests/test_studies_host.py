@@ -73,3 +73,14 @@ def test_wake_kick():
     p = 0.4 * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / rho)
     assert np.allclose(rho, 1.0) and np.allclose(p, 1.0 / 1.4) and np.allclose(U[1] / rho, 0.1)
     assert v.max() == pytest.approx(0.01, rel=1e-12) and x[np.argmax(v)] == pytest.approx(1.5)
+
+
+def test_study_command_line():
+    from paper_2508_17917_amd import studies
+    for study in ("cylinder", "viv"):
+        with pytest.raises(SystemExit) as e:
+            studies.main([study, "--help"])
+        assert e.value.code == 0
+    with pytest.raises(SystemExit) as e:
+        studies.main(["viv", "--t-end", "1", "--window", "0", "1"])   # --ustar is required
+    assert e.value.code == 2
