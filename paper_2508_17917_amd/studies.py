@@ -29,7 +29,8 @@ from . import _lib as L
 from .solver import Solver
 from .viv import VIVSweep
 
-FORMS = {"fp64": L.DG_FP64, "fp64-pert": L.DG_FP64_PERT, "fp32-pert": L.DG_FP32_PERT}
+FORMS = {"fp64": L.DG_FP64, "fp64-pert": L.DG_FP64_PERT, "fp32-pert": L.DG_FP32_PERT,
+         "bf16-ops": L.DG_FP32_PERT_BF16OPS}
 
 
 # --------------------------------------------------------------------------
@@ -103,12 +104,12 @@ class CylinderRun:
     force history (coefficients recorded every `record_every` steps)."""
 
     def __init__(self, mesh, p, phys, U0, precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0,
-                 cfl_every=2000, record_every=10):
+                 cfl_every=2000, record_every=10, overint=False):
         import torch
         self.phys = phys
         self.s = Solver(p, mesh, gamma=phys["gamma"], Pr=phys["Pr"], mu=phys["mu"],
                         theta=phys["theta"], penalty_mode=phys["penalty_mode"], C_pen=phys["C_pen"],
-                        U_inf=phys["U_inf"], precision=precision)
+                        U_inf=phys["U_inf"], precision=precision, overintegration=overint)
         self.p = p
         self.U = torch.from_numpy(np.ascontiguousarray(U0)).cuda()
         self.K1 = torch.zeros_like(self.U)
@@ -166,7 +167,7 @@ class CylinderRun:
 
 
 def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0,
-                   kick=0.1, log=None, series_out=None):
+                   kick=0.1, log=None, series_out=None, overint=False):
     """Strouhal number (f D / |v_inf| = the lift's frequency in convective
     units, D = 1), mean and RMS of C_L and C_D over
     [t0, t1] for every order in ps, and their differences between orders."""
@@ -178,7 +179,7 @@ def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cf
         x, y = s0.nodes()
         s0.close()
         U0 = np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=kick, gamma=phys["gamma"]), (1, 0, 2))
-        run = CylinderRun(mesh, p, phys, U0, precision, C_cfl, C_grad)
+        run = CylinderRun(mesh, p, phys, U0, precision, C_cfl, C_grad, overint=overint)
         w0 = time.time()
         ok = run.advance(t_end, log)
         wall = time.time() - w0
@@ -301,6 +302,8 @@ def main(argv=None):
         a.add_argument("--series", default=None, help=".npz file for the recorded series")
         if name == "cylinder":
             a.add_argument("--p", type=int, nargs="+", default=[1, 2, 3, 4])
+            a.add_argument("--overint", action="store_true",
+                           help="over-integrated weak form (plain FP64 form only)")
         else:
             a.add_argument("--p", type=int, default=3)
             a.add_argument("--ustar", type=float, nargs="+", required=True)
@@ -316,7 +319,9 @@ def main(argv=None):
     t0, t1 = args.window
     if args.study == "cylinder":
         res = cylinder_study(w["mesh"], phys, args.p, args.t_end, t0, t1, FORMS[args.form],
-                             args.c_cfl, args.c_grad, args.kick, log=_log, series_out=args.series)
+                             args.c_cfl, args.c_grad, args.kick, log=_log, series_out=args.series,
+                             overint=args.overint)
+        res["overint"] = bool(args.overint)
     else:
         res = viv_study(w["mesh"], phys, args.p, args.ustar, args.t_end, t0, t1, args.m_star,
                         args.xi, FORMS[args.form], args.c_cfl, args.c_grad, args.kick, log=_log,
