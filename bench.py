@@ -500,6 +500,7 @@ def main():
     if args.workload == "closure20k":
         run_closure(args)
         return
+    cfl_info = None
     if args.workload == "viv16":
         cases, phys = mg.viv_sweep_cases()
         if args.p is not None:
@@ -601,6 +602,16 @@ def main():
                                               "(degree-%d quadrature, %d element and %d face "
                                               "points)" % (3 * p, ((3 * p + 2) // 2) ** 2,
                                                            3 * ((3 * p + 2) // 2)))
+        # the CFL time step of Alg. 3 on the final state (outside the timed
+        # region): the bound's value and the cost of one call (two kernels and
+        # a synchronising read-back)
+        lam, _ = s.cfl_time_step(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            s.cfl_time_step(U)
+        cfl_info = {"Lambda": lam, "us_per_call": (time.perf_counter() - t0) / 20 * 1e6,
+                    "note": "dg_cfl_time_step on the final state, C_grad = 1; not in the timed steps"}
         cpu = None
         if not args.no_cpu_baseline and args.workload == "cylinder20k":
             log("cpu baseline (oracle)")
@@ -651,6 +662,8 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = src.numel() * 8
         del src, dst
+    if cfl_info is not None:
+        out["cfl_time_step"] = cfl_info
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

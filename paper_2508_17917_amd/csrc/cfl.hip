@@ -11,11 +11,12 @@
 // the largest directional norm ||e_a^T G e_a||_2 (a = x, y) over the nodes
 // of K and of its face neighbours.
 //
-// Two launches of one thread per element: the first forms the per-element
-// node maxima and, per face, the largest ||n^T G n||_2 over the face's own
-// nodes (and the boundary ghost); the second combines each element with its
-// neighbours and reduces Lambda to one value (maximum of non-negative
-// doubles, order-independent, taken with an integer atomic on their bits).
+// Two launches: the first (one thread per element and node) forms the
+// per-element node maxima and, per face, the largest ||n^T G n||_2 over the
+// face's own nodes (and the boundary ghost); the second (one thread per
+// element) combines each element with its neighbours and reduces Lambda to
+// one value (maximum of non-negative doubles, order-independent, taken with
+// an integer atomic on their bits).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -46,17 +47,23 @@ __device__ __forceinline__ double vmax(double a, double b) { return (a > b || a 
 
 // side[k*3 + f]: max ||n^T G n||_2 over face f's nodes of element k (with
 // the ghost state on wall and far-field faces); loc[k*3 + 0..2]: g_K (node max
-// of the directional norms), beta_K, beta'_K.
+// of the directional norms), beta_K, beta'_K.  One thread per (element, node),
+// floor(256 / Np) elements per workgroup; the per-element maxima are taken
+// through LDS by the element's node-0 thread.
 template <int N>
 __global__ __launch_bounds__(kCflThreads) void cfl_local_kernel(DeviceTables t, KernelPhysics ph,
                                                                 const double* __restrict__ U,
                                                                 double* __restrict__ side,
                                                                 double* __restrict__ loc,
                                                                 double* __restrict__ result) {
-  constexpr int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1;
-  const int64_t k = (int64_t)blockIdx.x * kCflThreads + threadIdx.x;
-  if (k == 0) result[0] = 0.0;
-  if (k >= t.K) return;
+  constexpr int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1, NF = 3 * Nfp;
+  constexpr int EPB = kCflThreads / Np;
+  __shared__ double su[EPB * Np], sv[EPB * Np], sb[EPB * Np], sg[EPB * Np], sd[EPB * Np];
+  __shared__ double sf[EPB * NF];
+  const int e = threadIdx.x / Np, n = threadIdx.x % Np;
+  const int64_t k = (int64_t)blockIdx.x * EPB + e;
+  const bool act = e < EPB && k < t.K;
+  if (blockIdx.x == 0 && threadIdx.x == 0) result[0] = 0.0;
   Gas<double> gas;
   gas.gamma = ph.gamma;
   gas.gm1 = ph.gamma - 1.0;
@@ -65,60 +72,69 @@ __global__ __launch_bounds__(kCflThreads) void cfl_local_kernel(DeviceTables t, 
   gas.k = ph.gamma / ph.Pr;
   const double* Uk = U + k * 4 * Np;
   const double* g = t.geo + k * kGeoStride;
-  const double* Dr = t.ops;
-  const double* Ds = t.ops + Np * Np;
-  double u[Np], v[Np];
-  double beta = 0.0, gmax = 0.0;
-#pragma unroll
-  for (int n = 0; n < Np; ++n) {
+  const int es = e * Np;
+  if (act) {
     const double S[4] = {Uk[n], Uk[Np + n], Uk[2 * Np + n], Uk[3 * Np + n]};
     const double ir = 1.0 / S[0];
-    u[n] = S[1] * ir;
-    v[n] = S[2] * ir;
-    const double p = gas.gm1 * (S[3] - 0.5 * (S[1] * u[n] + S[2] * v[n]));
-    const double du = u[n] - ph.vw[0], dv = v[n] - ph.vw[1];
-    beta = vmax(beta, sqrt(du * du + dv * dv) + sqrt(gas.gamma * p * ir));
+    const double u = S[1] * ir, v = S[2] * ir;
+    const double p = gas.gm1 * (S[3] - 0.5 * (S[1] * u + S[2] * v));
+    const double du = u - ph.vw[0], dv = v - ph.vw[1];
+    su[es + n] = u;
+    sv[es + n] = v;
+    sb[es + n] = sqrt(du * du + dv * dv) + sqrt(gas.gamma * p * ir);
     const VState<double> st = vstate(gas, S);
-    gmax = vmax(gmax, vmax(normal_diffusion_norm(gas, st, 1.0, 0.0),
-                           normal_diffusion_norm(gas, st, 0.0, 1.0)));
+    sg[es + n] = vmax(normal_diffusion_norm(gas, st, 1.0, 0.0),
+                      normal_diffusion_norm(gas, st, 0.0, 1.0));
   }
-  double div = 0.0;
-  for (int n = 0; n < Np; ++n) {
+  __syncthreads();
+  if (act) {
+    const double* Dr = t.ops;
+    const double* Ds = t.ops + Np * Np;
     double ur = 0.0, us = 0.0, vr = 0.0, vs = 0.0;
 #pragma unroll
     for (int m = 0; m < Np; ++m) {
       const double dr = Dr[n * Np + m], ds = Ds[n * Np + m];
-      ur += dr * u[m];
-      us += ds * u[m];
-      vr += dr * v[m];
-      vs += ds * v[m];
+      ur += dr * su[es + m];
+      us += ds * su[es + m];
+      vr += dr * sv[es + m];
+      vs += ds * sv[es + m];
     }
-    div = vmax(div, fabs(g[0] * ur + g[2] * us + g[1] * vr + g[3] * vs));
-  }
-  loc[k * 3 + 0] = gmax;
-  loc[k * 3 + 1] = beta;
-  loc[k * 3 + 2] = 0.5 * div;
-  const int32_t cw = t.conn[k * 3 + 0], cx = t.conn[k * 3 + 1], cy = t.conn[k * 3 + 2];
-  const int32_t cf[3] = {cw, cx, cy};
-#pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    const double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
-    const int tag = cf[f] & 3;
-    double s = 0.0;
-    for (int j = 0; j < Nfp; ++j) {
-      const int n = cfl_face_node<N>(f, j);
-      const double S[4] = {Uk[n], Uk[Np + n], Uk[2 * Np + n], Uk[3 * Np + n]};
-      s = vmax(s, normal_diffusion_norm(gas, vstate(gas, S), nx, ny));
+    sd[es + n] = fabs(g[0] * ur + g[2] * us + g[1] * vr + g[3] * vs);
+    for (int i = n; i < NF; i += Np) {
+      const int f = i / Nfp, j = i % Nfp;
+      const int node = cfl_face_node<N>(f, j);
+      const double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
+      const int tag = t.conn[k * 3 + f] & 3;
+      const double S[4] = {Uk[node], Uk[Np + node], Uk[2 * Np + node], Uk[3 * Np + node]};
+      double sfv = normal_diffusion_norm(gas, vstate(gas, S), nx, ny);
       if (tag == 1) {
         // wall ghost: own density and pressure, wall velocity
         const double p = gas.gm1 * (S[3] - 0.5 * (S[1] * S[1] + S[2] * S[2]) / S[0]);
         const double B[4] = {S[0], S[0] * ph.vw[0], S[0] * ph.vw[1],
                              p * gas.igm1 + 0.5 * S[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1])};
-        s = vmax(s, normal_diffusion_norm(gas, vstate(gas, B), nx, ny));
+        sfv = vmax(sfv, normal_diffusion_norm(gas, vstate(gas, B), nx, ny));
+      } else if (tag == 2) {
+        sfv = vmax(sfv, normal_diffusion_norm(gas, vstate(gas, ph.U_inf), nx, ny));
       }
+      sf[e * NF + i] = sfv;
     }
-    if (tag == 2) s = vmax(s, normal_diffusion_norm(gas, vstate(gas, ph.U_inf), nx, ny));
-    side[k * 3 + f] = s;
+  }
+  __syncthreads();
+  if (act && n == 0) {
+    double gm = 0.0, be = 0.0, dv = 0.0;
+    for (int m = 0; m < Np; ++m) {
+      gm = vmax(gm, sg[es + m]);
+      be = vmax(be, sb[es + m]);
+      dv = vmax(dv, sd[es + m]);
+    }
+    loc[k * 3 + 0] = gm;
+    loc[k * 3 + 1] = be;
+    loc[k * 3 + 2] = 0.5 * dv;
+    for (int f = 0; f < 3; ++f) {
+      double m = 0.0;
+      for (int j = 0; j < Nfp; ++j) m = vmax(m, sf[e * NF + f * Nfp + j]);
+      side[k * 3 + f] = m;
+    }
   }
 }
 
@@ -164,12 +180,14 @@ __global__ __launch_bounds__(kCflThreads) void cfl_reduce_kernel(DeviceTables t,
 template <int N>
 int launch_cfl_n(const DeviceTables& t, const KernelPhysics& ph, const double* U, double C_grad,
                  double* work, hipStream_t s, std::string& err) {
+  constexpr int EPB = kCflThreads / ((N + 1) * (N + 2) / 2);
+  const unsigned lblocks = (unsigned)((t.K + EPB - 1) / EPB);
   const unsigned blocks = (unsigned)((t.K + kCflThreads - 1) / kCflThreads);
   double* side = work;
   double* loc = work + 3 * t.K;
   double* result = work + 6 * t.K;
-  hipLaunchKernelGGL(cfl_local_kernel<N>, dim3(blocks), dim3(kCflThreads), 0, s, t, ph, U, side, loc,
-                     result);
+  hipLaunchKernelGGL(cfl_local_kernel<N>, dim3(lblocks), dim3(kCflThreads), 0, s, t, ph, U, side,
+                     loc, result);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
     hipLaunchKernelGGL(cfl_reduce_kernel, dim3(blocks), dim3(kCflThreads), 0, s, t, N, C_grad, side,

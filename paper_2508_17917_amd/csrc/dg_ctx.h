@@ -55,6 +55,7 @@ struct dg_ctx {
   double* d_force_part = nullptr;
   unsigned* d_force_ticket = nullptr;
   double* d_cfl = nullptr;          // CFL work: 3K face maxima, 3K element maxima, result
+  double* h_cfl = nullptr;          // pinned host word for the CFL result
   int force_blocks = 0;
   bool dev_ready = false;
   std::string err;

@@ -33,6 +33,8 @@ void free_device(dg_ctx* c) {
                   c->d_force_part, c->d_force_ticket, c->d_oi, c->d_cfl};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->h_cfl) (void)hipHostFree(c->h_cfl);
+  c->h_cfl = nullptr;
   c->d_geo = nullptr;
   c->d_conn = nullptr;
   c->d_ops = nullptr;
@@ -217,6 +219,7 @@ int dg_setup(dg_ctx* c) {
       (e = hipMalloc((void**)&c->d_force_part, 3 * fb * sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void**)&c->d_force_ticket, sizeof(unsigned))) != hipSuccess ||
       (e = hipMalloc((void**)&c->d_cfl, dgmi::cfl_work_size(c->K) * sizeof(double))) != hipSuccess ||
+      (e = hipHostMalloc((void**)&c->h_cfl, sizeof(double), hipHostMallocDefault)) != hipSuccess ||
       (e = hipMemset(c->d_force_ticket, 0, sizeof(unsigned))) != hipSuccess) {
     free_device(c);
     return e == hipErrorOutOfMemory ? fail(c, DG_ENOMEM, "device allocation failed")
@@ -404,11 +407,11 @@ int dg_cfl_time_step(dg_ctx* c, const double* U, const double v_w[2], double C_c
   std::string err;
   rc = dgmi::launch_cfl(c->N, tables(c), kphys(c, v_w), U, C_grad, c->d_cfl, stream, err);
   if (rc != 0) return fail(c, rc, err);
-  double lam = 0.0;
-  hipError_t e = hipMemcpyAsync(&lam, c->d_cfl + 6 * c->K, sizeof(double), hipMemcpyDeviceToHost,
-                                (hipStream_t)stream);
+  hipError_t e = hipMemcpyAsync(c->h_cfl, c->d_cfl + 6 * c->K, sizeof(double),
+                                hipMemcpyDeviceToHost, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "CFL read-back");
+  const double lam = *c->h_cfl;
   if (!std::isfinite(lam) || !(lam > 0.0)) return fail(c, DG_ENONFINITE, "CFL bound is not finite and positive");
   out[0] = lam;
   out[1] = C_cfl / lam;
