@@ -65,3 +65,21 @@ def test_cfl_rejects_bad_arguments():
     with pytest.raises(L.DGError):
         s.cfl_time_step(U)
     s.close()
+
+
+@pytest.mark.parametrize("p", [1, 7, 8])
+def test_cfl_bound_parity_edge_orders(p):
+    """The lowest and highest built orders (p = 1: several face nodes per
+    thread; p = 8: five elements per workgroup) on a graded O-grid with wall
+    and far field and a moving wall."""
+    torch = _torch()
+    mesh = mg.ogrid(10, 4, 0.5, 4.0, 1.3)
+    dg = build(mesh, p, mu=2e-3, penalty_mode=0, C_pen=1.0)
+    U = _state(dg, "noise", 13)
+    vw = (0.01, -0.02)
+    want, _ = CFLOracle(dg.mesh, dg.phys).time_step(U, vw)
+    _say("cfl edge order K=%d p=%d" % (dg.mesh.K, p))
+    s = _solver(mesh, p, dg.phys)
+    lam, _ = s.cfl_time_step(_to_dev(torch, U), v_w=vw)
+    assert abs(lam - want) <= 1e-12 * want, (p, lam, want)
+    s.close()
