@@ -150,6 +150,9 @@ def test_error_codes():
         with pytest.raises(L.DGError) as e:
             L.dg_rk_step(h, U, R, 1e-3, stream=0)
         assert e.value.code == L.DG_ESTATE
+        with pytest.raises(L.DGError) as e:
+            L.dg_cfl_time_step(h, U, stream=0)
+        assert e.value.code == L.DG_ESTATE
         assert "dg_setup" in L.dg_last_error(h)
     finally:
         L.dg_destroy(h)
