@@ -206,8 +206,11 @@ int dg_force_device(dg_ctx* ctx, const double* U, const double v_w[2], double* o
  * (nodal derivative of the interpolated velocity), G_K the largest
  * directional norm ||e_a^T G e_a||_2 (a = x, y) over the nodes of K and its
  * face neighbours; out[1] = C_cfl / Lambda.  C_cfl > 0 and C_grad >= 0, else
- * DG_EINVAL; a non-finite bound gives DG_ENONFINITE.  Uses the context's
- * work buffer (set up by dg_setup); synchronises `stream`. */
+ * DG_EINVAL; a non-finite bound gives DG_ENONFINITE (an unphysical state:
+ * negative pressure or density, NaN).  out is a host array of 2 doubles.
+ * Uses the context's work buffer (6K + 1 doubles, set up by dg_setup), so
+ * two calls of one context must not overlap on different streams;
+ * synchronises `stream`. */
 int dg_cfl_time_step(dg_ctx* ctx, const double* U, const double v_w[2], double C_cfl, double C_grad,
                      double out[2], void* stream);
 
