@@ -481,7 +481,7 @@ def main():
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the element partition would shard by domain decomposition)", file=sys.stderr)
         sys.exit(2)
 
