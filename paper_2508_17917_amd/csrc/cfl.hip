@@ -219,9 +219,7 @@ int launch_cfl(int N, const DeviceTables& t, const KernelPhysics& ph, const doub
     case 4: return launch_cfl_n<4>(t, ph, U, C_grad, work, s, err);
     case 5: return launch_cfl_n<5>(t, ph, U, C_grad, work, s, err);
     case 6: return launch_cfl_n<6>(t, ph, U, C_grad, work, s, err);
-    case 7: return launch_cfl_n<7>(t, ph, U, C_grad, work, s, err);
-    case 8: return launch_cfl_n<8>(t, ph, U, C_grad, work, s, err);
-    default: err = "order outside 1..8"; return -5;
+    default: err = "order outside 1..6"; return -5;
   }
 }
 

@@ -67,11 +67,11 @@ def test_cfl_rejects_bad_arguments():
     s.close()
 
 
-@pytest.mark.parametrize("p", [1, 7, 8])
+@pytest.mark.parametrize("p", [1, 6])
 def test_cfl_bound_parity_edge_orders(p):
     """The lowest and highest built orders (p = 1: several face nodes per
-    thread; p = 8: five elements per workgroup) on a graded O-grid with wall
-    and far field and a moving wall."""
+    thread, 85 elements per workgroup; p = 6: nine) on a graded O-grid with
+    wall and far field and a moving wall."""
     torch = _torch()
     mesh = mg.ogrid(10, 4, 0.5, 4.0, 1.3)
     dg = build(mesh, p, mu=2e-3, penalty_mode=0, C_pen=1.0)
