@@ -298,6 +298,8 @@ def main(argv=None):
         a.add_argument("--kick", type=float, default=0.1)
         a.add_argument("--c-pen", type=float, default=None, help="penalty constant (default 0.01)")
         a.add_argument("--theta", type=float, default=None, help="theta (default 0, IIP)")
+        a.add_argument("--re", type=float, default=None,
+                       help="Reynolds number |v_inf| D / nu (default 200)")
         a.add_argument("--out", default=None, help="JSON result file")
         a.add_argument("--series", default=None, help=".npz file for the recorded series")
         if name == "cylinder":
@@ -316,6 +318,11 @@ def main(argv=None):
         phys["C_pen"] = args.c_pen
     if args.theta is not None:
         phys["theta"] = args.theta
+    Re = 200.0
+    if args.re is not None:
+        # mu = rho_inf |v_inf| D / Re (D = 1)
+        Re = args.re
+        phys["mu"] = phys["U_inf"][0] * free_stream_speed(phys["U_inf"]) / Re
     t0, t1 = args.window
     if args.study == "cylinder":
         res = cylinder_study(w["mesh"], phys, args.p, args.t_end, t0, t1, FORMS[args.form],
@@ -327,7 +334,7 @@ def main(argv=None):
                         args.xi, FORMS[args.form], args.c_cfl, args.c_grad, args.kick, log=_log,
                         series_out=args.series)
     res.update(study=args.study, mesh="shedding20k: O-grid 128x80 cells, first layer 0.017 D, "
-               "far field at 50 D, K=20480", Re=200.0, M=0.1, form=args.form, C_cfl=args.c_cfl,
+               "far field at 50 D, K=20480", Re=Re, M=0.1, form=args.form, C_cfl=args.c_cfl,
                C_grad=args.c_grad, C_pen=phys["C_pen"], theta=phys["theta"], window=[t0, t1],
                t_end=args.t_end)
     line = json.dumps(res, default=float)
