@@ -162,17 +162,99 @@ class CylinderRun:
                     CL_mean=cl_m, CL_rms=cl_rms, CD_mean=cd_m, CD_rms=cd_rms, CL_max=cl_max,
                     St=dominant_frequency(t, cl, t0, t1))
 
+    def advance_to_phase(self, chunk=20, max_steps=400000):
+        """Step on (fixed dt, the force after every step) until the lift
+        crosses zero upwards, to within `chunk` steps: the common shedding
+        phase of the snapshots compared between orders."""
+        import torch
+        _, dt = self.s.cfl_time_step(self.U, C_cfl=self.C_cfl, C_grad=self.C_grad)
+        F = torch.zeros(3 * chunk, dtype=torch.float64, device="cuda")
+        last = None
+        for _ in range(max_steps // chunk):
+            self.s.rk_steps(self.U, self.K1, chunk, dt, force=F)
+            self.t += chunk * dt
+            self.steps += chunk
+            cl = force_coefficients(F.view(chunk, 3).cpu().numpy(), self.phys["U_inf"])[1]
+            if not np.isfinite(cl).all():
+                return False
+            seq = cl if last is None else np.concatenate(([last], cl))
+            if np.any((seq[:-1] < 0.0) & (seq[1:] >= 0.0)):
+                return True
+            last = cl[-1]
+        return False
+
+    def centreline_vorticity(self):
+        """(x, omega) at the nodes on the wake centreline y = 0, x > 0 (the
+        O-grid's theta = 0 grid line from the wall to the far field: whole
+        edges of p + 1 face nodes, each shared by the elements on both sides,
+        whose values are averaged), omega = dv/dx - du/dy from the element's
+        nodal derivative matrices and metric terms."""
+        U = self.U.cpu().numpy()                                  # (K, 4, Np)
+        K, Np = self.s.K, self.s.Np
+        Dr = self.s.table("Dr").reshape(Np, Np)
+        Ds = self.s.table("Ds").reshape(Np, Np)
+        geo = self.s.table("geo").reshape(K, 16)
+        x, y = self.s.nodes()
+        u = U[:, 1] / U[:, 0]
+        v = U[:, 2] / U[:, 0]
+        ur, us = u @ Dr.T, u @ Ds.T
+        vr, vs = v @ Dr.T, v @ Ds.T
+        rx, ry, sx, sy = (geo[:, i:i + 1] for i in range(4))
+        om = (rx * vr + sx * vs) - (ry * ur + sy * us)
+        on = (np.abs(y) < 1e-9) & (x > 0.0)
+        xs, ws = x[on], om[on]
+        key = np.round(xs, 9)
+        ux = np.unique(key)
+        wavg = np.array([ws[key == k].mean() for k in ux])
+        return ux, wavg
+
     def close(self):
         self.s.close()
 
 
+def _edge_resample(x, w, p, xs):
+    """Values at xs of the piecewise polynomial through (x, w): the sorted
+    centreline nodes of order p come in edges of p + 1 nodes sharing their
+    end nodes, and on each edge the trace is the degree-p Lagrange
+    interpolant of its nodes (linear when the count does not fit)."""
+    n = len(x)
+    if p < 1 or (n - 1) % p != 0:
+        return np.interp(xs, x, w)
+    ends = x[::p]
+    e = np.clip(np.searchsorted(ends, xs, side="right") - 1, 0, len(ends) - 2)
+    idx = e[:, None] * p + np.arange(p + 1)[None, :]
+    xn, wn = x[idx], w[idx]
+    out = np.zeros(len(xs))
+    for j in range(p + 1):
+        lj = np.ones(len(xs))
+        for k in range(p + 1):
+            if k != j:
+                lj *= (xs - xn[:, k]) / (xn[:, j] - xn[:, k])
+        out += lj * wn[:, j]
+    return out
+
+
+def centreline_differences(lines, x0=2.0, x1=40.0, n=8001):
+    """||delta_p omega|| in L2(I_x) and L_inf(I_x), I_x = (x0, x1), between
+    successive orders: each order's centreline vorticity (keyed by p) is
+    resampled onto n uniform points of I_x through its own edge polynomials."""
+    xs = np.linspace(x0, x1, n)
+    ps = sorted(lines)
+    res = {p: _edge_resample(np.asarray(lines[p][0]), np.asarray(lines[p][1]), p, xs) for p in ps}
+    out = []
+    for a, b in zip(ps[:-1], ps[1:]):
+        d = res[b] - res[a]
+        out.append(dict(p=a, L2=float(np.sqrt(np.trapezoid(d * d, xs))), Linf=float(np.abs(d).max())))
+    return out
+
+
 def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0,
-                   kick=0.1, log=None, series_out=None, overint=False):
+                   kick=0.1, log=None, series_out=None, overint=False, vorticity=False):
     """Strouhal number (f D / |v_inf| = the lift's frequency in convective
     units, D = 1), mean and RMS of C_L and C_D over
     [t0, t1] for every order in ps, and their differences between orders."""
     import meshgen as mg
-    rows, series = [], {}
+    rows, series, lines = [], {}, {}
     for p in ps:
         s0 = Solver(p, mesh, gamma=phys["gamma"], Pr=phys["Pr"], mu=phys["mu"], device=False,
                     U_inf=phys["U_inf"])
@@ -190,6 +272,10 @@ def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cf
         r = run.summary(t0, t1)
         r.update(finite=True, wall_s=wall,
                  dof_updates_per_s=5.0 * 4 * run.s.Np * run.s.K * run.steps / wall)
+        if vorticity:
+            if run.advance_to_phase():
+                lines[p] = run.centreline_vorticity()
+                r["phase_t"] = run.t * run.vel
         rows.append(r)
         if series_out is not None:
             series[p] = run.series()
@@ -199,10 +285,17 @@ def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cf
         run.close()
     good = [r for r in rows if r.get("finite")]
     diffs = p_differences(good, ["CL_mean", "CL_rms", "CD_mean", "CD_rms", "St"])
+    if vorticity and series_out is not None and lines:
+        np.savez_compressed(series_out.replace(".npz", "") + "_vorticity.npz",
+                            **{"p%d_%s" % (p, k): v for p, ln in lines.items()
+                               for k, v in zip(("x", "omega"), ln)})
     if series_out is not None and series:
         np.savez_compressed(series_out, **{"p%d_%s" % (p, k): v for p, ser in series.items()
                                            for k, v in zip(("t", "CD", "CL"), ser)})
-    return dict(rows=rows, differences=diffs)
+    res = dict(rows=rows, differences=diffs)
+    if vorticity:
+        res["vorticity_differences"] = centreline_differences(lines) if len(lines) > 1 else []
+    return res
 
 
 # --------------------------------------------------------------------------
@@ -306,6 +399,9 @@ def main(argv=None):
             a.add_argument("--p", type=int, nargs="+", default=[1, 2, 3, 4])
             a.add_argument("--overint", action="store_true",
                            help="over-integrated weak form (plain FP64 form only)")
+            a.add_argument("--vorticity", action="store_true",
+                           help="after t-end, advance to an upward zero crossing of the lift "
+                                "and compare the wake-centreline vorticity between orders")
         else:
             a.add_argument("--p", type=int, default=3)
             a.add_argument("--ustar", type=float, nargs="+", required=True)
@@ -327,7 +423,7 @@ def main(argv=None):
     if args.study == "cylinder":
         res = cylinder_study(w["mesh"], phys, args.p, args.t_end, t0, t1, FORMS[args.form],
                              args.c_cfl, args.c_grad, args.kick, log=_log, series_out=args.series,
-                             overint=args.overint)
+                             overint=args.overint, vorticity=args.vorticity)
         res["overint"] = bool(args.overint)
     else:
         res = viv_study(w["mesh"], phys, args.p, args.ustar, args.t_end, t0, t1, args.m_star,

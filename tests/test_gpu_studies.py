@@ -45,3 +45,28 @@ def test_viv_study_short_run():
     for r, u in zip(res["rows"], (3.0, 5.0)):
         assert r["U_star"] == u and r["f_n"] == pytest.approx(1.0 / u)
         assert np.isfinite([r["A_max"], r["CL_max"], r["f_prim"]]).all()
+
+
+def test_centreline_vorticity_on_the_shedding_mesh():
+    """The wake-centreline samples are the O-grid's theta = 0 grid line from
+    the wall (x = 0.5) to the far field (x = 50), 80 whole edges of p + 1
+    nodes, and carry the vorticity of the wake-kick state (a transverse
+    velocity blob around x = 1.5)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_17917_amd import Solver, studies
+    w, phys = _phys()
+    s0 = Solver(2, w["mesh"], device=False, U_inf=phys["U_inf"])
+    x, y = s0.nodes()
+    s0.close()
+    U0 = np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=0.1), (1, 0, 2))
+    print("[gpu-case] centreline vorticity p=2", flush=True)
+    run = studies.CylinderRun(w["mesh"], 2, phys, U0)
+    xs, om = run.centreline_vorticity()
+    run.close()
+    assert len(xs) == 80 * 2 + 1 and np.all(np.diff(xs) > 0)
+    assert xs[0] == pytest.approx(0.5) and xs[-1] == pytest.approx(50.0)
+    assert np.isfinite(om).all()
+    # dv/dx of the blob: positive on its upstream flank, negative downstream
+    assert om[np.argmin(np.abs(xs - 2.0))] < 0.0

@@ -84,3 +84,35 @@ def test_study_command_line():
     with pytest.raises(SystemExit) as e:
         studies.main(["viv", "--t-end", "1", "--window", "0", "1"])   # --ustar is required
     assert e.value.code == 2
+
+
+def test_centreline_differences():
+    from paper_2508_17917_amd.studies import centreline_differences
+    # linear profiles: reproduced exactly by every order's resampling
+    x = np.linspace(0.0, 50.0, 2001)
+    lines = {3: (x, 0.3 * x - 1.0), 4: (x, 0.3 * x - 0.9), 5: (x, 0.3 * x - 0.9)}
+    d = centreline_differences(lines)
+    assert [r["p"] for r in d] == [3, 4]
+    assert d[0]["L2"] == pytest.approx(0.1 * math.sqrt(38.0), rel=1e-9)
+    assert d[0]["Linf"] == pytest.approx(0.1, rel=1e-12)
+    assert d[1]["L2"] < 1e-12 and d[1]["Linf"] < 1e-12
+
+
+def test_edge_resampling_is_exact_for_the_edge_polynomials():
+    from paper_2508_17917_amd.studies import _edge_resample
+    rng = np.random.default_rng(0)
+    p = 4
+    ends = np.cumsum(rng.uniform(0.3, 1.5, 12))
+    # Gauss-Lobatto-like interior nodes on every edge, shared end nodes
+    ref = np.array([-1.0, -0.6546536707, 0.0, 0.6546536707, 1.0])
+    x = np.concatenate([0.5 * (a + b) + 0.5 * (b - a) * ref[:-1] for a, b in zip(ends[:-1], ends[1:])]
+                       + [ends[-1:]])
+    # a cubic is reproduced exactly by every degree-4 edge interpolant
+    coef = rng.standard_normal(4)
+    w = sum(coef[k] * x ** k for k in range(4))
+    xs = np.linspace(ends[0], ends[-1], 777)
+    want = sum(coef[k] * xs ** k for k in range(4))
+    got = _edge_resample(x, w, p, xs)
+    assert np.allclose(got, want, rtol=1e-9, atol=1e-9)
+    # and linear resampling would not be
+    assert not np.allclose(np.interp(xs, x, w), want, rtol=1e-6, atol=1e-6)
