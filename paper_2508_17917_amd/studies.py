@@ -298,6 +298,34 @@ def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cf
     return res
 
 
+def max_stable_step(mesh, phys, p, C_values, t_end, precision=L.DG_FP32_PERT, C_grad=1.0, kick=0.1,
+                    log=None):
+    """The largest C_CFL of C_values (tried in increasing order, stopping at
+    the first failure) for which a run from the wake-kick state stays finite
+    up to the convective time t_end, and its time step in convective units:
+    the heuristic search the paper reports its admissible time steps from."""
+    import meshgen as mg
+    s0 = Solver(p, mesh, gamma=phys["gamma"], Pr=phys["Pr"], mu=phys["mu"], device=False,
+                U_inf=phys["U_inf"])
+    x, y = s0.nodes()
+    s0.close()
+    U0 = np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=kick, gamma=phys["gamma"]), (1, 0, 2))
+    best = None
+    for C in sorted(C_values):
+        run = CylinderRun(mesh, p, phys, U0, precision, C, C_grad)
+        ok = run.advance(t_end)
+        dt = float(np.median(run.dts)) if run.dts else None
+        run.close()
+        if log is not None:
+            log("p=%d C_CFL=%g: %s (dt* %s)" % (p, C, "stable" if ok else "not finite",
+                                                 "%.4g" % dt if dt else "-"))
+        if not ok:
+            break
+        best = (C, dt)
+    return dict(p=p, C_cfl=None if best is None else best[0], dt=None if best is None else best[1],
+                t_end=t_end, tried=sorted(C_values))
+
+
 # --------------------------------------------------------------------------
 # elastically mounted cylinder
 # --------------------------------------------------------------------------
@@ -381,10 +409,15 @@ def main(argv=None):
     import meshgen as mg
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="study", required=True)
-    for name in ("cylinder", "viv"):
+    for name in ("cylinder", "viv", "dtmax"):
         a = sub.add_parser(name)
         a.add_argument("--t-end", type=float, required=True, help="convective time")
-        a.add_argument("--window", type=float, nargs=2, required=True, help="t0 t1, convective")
+        if name == "dtmax":
+            a.add_argument("--p", type=int, nargs="+", default=[1, 2, 3, 4, 5])
+            a.add_argument("--c-values", type=float, nargs="+", required=True,
+                           help="C_CFL values to try, in increasing order")
+        a.add_argument("--window", type=float, nargs=2, required=(name != "dtmax"),
+                       default=None, help="t0 t1, convective")
         a.add_argument("--form", default="fp32-pert", choices=sorted(FORMS))
         a.add_argument("--c-cfl", type=float, default=8.0)
         a.add_argument("--c-grad", type=float, default=1.0)
@@ -395,6 +428,8 @@ def main(argv=None):
                        help="Reynolds number |v_inf| D / nu (default 200)")
         a.add_argument("--out", default=None, help="JSON result file")
         a.add_argument("--series", default=None, help=".npz file for the recorded series")
+        if name == "dtmax":
+            continue
         if name == "cylinder":
             a.add_argument("--p", type=int, nargs="+", default=[1, 2, 3, 4])
             a.add_argument("--overint", action="store_true",
@@ -419,8 +454,12 @@ def main(argv=None):
         # mu = rho_inf |v_inf| D / Re (D = 1)
         Re = args.re
         phys["mu"] = phys["U_inf"][0] * free_stream_speed(phys["U_inf"]) / Re
-    t0, t1 = args.window
-    if args.study == "cylinder":
+    t0, t1 = args.window if args.window is not None else (None, None)
+    if args.study == "dtmax":
+        rows = [max_stable_step(w["mesh"], phys, p, args.c_values, args.t_end, FORMS[args.form],
+                                args.c_grad, args.kick, log=_log) for p in args.p]
+        res = dict(rows=rows)
+    elif args.study == "cylinder":
         res = cylinder_study(w["mesh"], phys, args.p, args.t_end, t0, t1, FORMS[args.form],
                              args.c_cfl, args.c_grad, args.kick, log=_log, series_out=args.series,
                              overint=args.overint, vorticity=args.vorticity)

@@ -77,7 +77,7 @@ def test_wake_kick():
 
 def test_study_command_line():
     from paper_2508_17917_amd import studies
-    for study in ("cylinder", "viv"):
+    for study in ("cylinder", "viv", "dtmax"):
         with pytest.raises(SystemExit) as e:
             studies.main([study, "--help"])
         assert e.value.code == 0
