@@ -3,7 +3,10 @@
 * Stationary cylinder, p-sensitivity (Sec. 3.2.1): mean and RMS of the lift
   and drag coefficients of eq. lift_drag over a window past the transient,
   the Strouhal number from a DFT of the lift, and the differences
-  delta_p f = f(p + 1) - f(p) between successive orders.
+  delta_p f = f(p + 1) - f(p) between successive orders; optionally the
+  wake-centreline vorticity at a common shedding phase compared between
+  orders, any Reynolds number (the validation range 100..250), and the
+  heuristic search for the largest stable time step per order.
 * Elastically mounted cylinder (Sec. 3.3): per reduced velocity U*, the
   maximum amplitude, the maximum lift coefficient and the primary frequency
   of the displacement (DFT) over a sampling window, all instances advanced
@@ -14,8 +17,9 @@ recomputed every `cfl_every` steps from the current state).  Times are in
 convective units t* = t |v_inf| / D (the library works in units of D / c_inf;
 the paper's seconds with D = 1 m and |v_inf| = 1 m/s are convective units).
 
-Run as  python -m paper_2508_17917_amd.studies {cylinder,viv} ...  from the
-repository root (the synthetic meshes come from the meshgen module there).
+Run as  python -m paper_2508_17917_amd.studies {cylinder,viv,dtmax} ...
+from the repository root (the synthetic meshes come from the meshgen module
+there).
 """
 import argparse
 import json
