@@ -70,3 +70,18 @@ def test_centreline_vorticity_on_the_shedding_mesh():
     assert np.isfinite(om).all()
     # dv/dx of the blob: positive on its upstream flank, negative downstream
     assert om[np.argmin(np.abs(xs - 2.0))] < 0.0
+
+
+def test_largest_stable_step_search():
+    """The ladder stops at the first C_CFL whose run stops being finite: 4 is
+    stable on a small O-grid at p = 1, 400 (|lambda| dt of order 100) is not
+    (the state turns non-finite within a few steps; no kernel faults)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_17917_amd import studies
+    w, phys = _phys()
+    mesh = mg.ogrid(32, 16, 0.5, 20.0, mg.growth_ratio(0.5, 20.0, 16, 0.05))
+    print("[gpu-case] largest stable step p=1 K=%d" % len(mesh["EToV"]), flush=True)
+    r = studies.max_stable_step(mesh, phys, 1, [4.0, 400.0, 800.0], t_end=0.5)
+    assert r["C_cfl"] == 4.0 and r["dt"] > 0.0
