@@ -24,6 +24,7 @@ there).
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -127,13 +128,16 @@ class CylinderRun:
         self.t_rec, self.CD, self.CL, self.dts = [], [], [], []
         self.log_every = 25
 
-    def advance(self, t_end_conv, log=None):
-        """Step until the convective time t_end_conv; False if the state
-        stopped being finite."""
+    def advance(self, t_end_conv, log=None, max_wall=None):
+        """Step until the convective time t_end_conv (or, with max_wall, until
+        that many seconds of wall time have passed: see `done`); False if the
+        state stopped being finite."""
         import torch
         t_end = t_end_conv / self.vel
         t0 = time.time()
         while self.t < t_end:
+            if max_wall is not None and time.time() - t0 > max_wall:
+                break
             _, dt = self.s.cfl_time_step(self.U, C_cfl=self.C_cfl, C_grad=self.C_grad)
             n = self.cfl_every
             self.s.rk_steps(self.U, self.K1, n, dt, force=self.F)
@@ -155,8 +159,29 @@ class CylinderRun:
         torch.cuda.synchronize()
         return True
 
+    def done(self, t_end_conv):
+        return self.t * self.vel >= t_end_conv
+
     def series(self):
         return np.concatenate(self.t_rec), np.concatenate(self.CD), np.concatenate(self.CL)
+
+    def save(self, path):
+        """Checkpoint: the state, the clock, the step count and the recorded
+        series (the CFL step is recomputed from the state, so a resumed run
+        takes the same steps as an uninterrupted one)."""
+        t, cd, cl = self.series() if self.t_rec else (np.zeros(0), np.zeros(0), np.zeros(0))
+        np.savez(path, U=self.U.cpu().numpy(), p=self.p, K=self.s.K, t=self.t, steps=self.steps,
+                 t_rec=t, CD=cd, CL=cl, dts=np.asarray(self.dts, dtype=np.float64))
+
+    def load(self, path):
+        import torch
+        z = np.load(path)
+        if int(z["p"]) != self.p or int(z["K"]) != self.s.K or z["U"].shape != tuple(self.U.shape):
+            raise ValueError("checkpoint of another order or mesh")
+        self.U.copy_(torch.from_numpy(z["U"]))
+        self.t, self.steps = float(z["t"]), int(z["steps"])
+        self.t_rec, self.CD, self.CL = [z["t_rec"]], [z["CD"]], [z["CL"]]
+        self.dts = [float(d) for d in z["dts"]]
 
     def summary(self, t0, t1):
         t, cd, cl = self.series()
@@ -253,11 +278,14 @@ def centreline_differences(lines, x0=2.0, x1=40.0, n=8001):
 
 
 def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0,
-                   kick=0.1, log=None, series_out=None, overint=False, vorticity=False):
+                   kick=0.1, log=None, series_out=None, overint=False, vorticity=False,
+                   checkpoint=None, max_wall=None):
     """Strouhal number (f D / |v_inf| = the lift's frequency in convective
     units, D = 1), mean and RMS of C_L and C_D over
     [t0, t1] for every order in ps, and their differences between orders."""
     import meshgen as mg
+    if max_wall is not None and checkpoint is None:
+        raise ValueError("a wall-time limit needs a checkpoint path")
     rows, series, lines = [], {}, {}
     for p in ps:
         s0 = Solver(p, mesh, gamma=phys["gamma"], Pr=phys["Pr"], mu=phys["mu"], device=False,
@@ -266,11 +294,23 @@ def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cf
         s0.close()
         U0 = np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=kick, gamma=phys["gamma"]), (1, 0, 2))
         run = CylinderRun(mesh, p, phys, U0, precision, C_cfl, C_grad, overint=overint)
+        ck = None if checkpoint is None else "%s_p%d.npz" % (checkpoint, p)
+        if ck is not None and os.path.exists(ck):
+            run.load(ck)
+            if log is not None:
+                log("p=%d resumed from %s at t*=%.2f" % (p, ck, run.t * run.vel))
         w0 = time.time()
-        ok = run.advance(t_end, log)
+        ok = run.advance(t_end, log, max_wall)
         wall = time.time() - w0
         if not ok:
             rows.append(dict(p=p, finite=False, steps=run.steps))
+            run.close()
+            continue
+        if not run.done(t_end):
+            # wall-time limit reached: keep the checkpoint, report progress
+            run.save(ck)
+            rows.append(dict(p=p, finite=True, complete=False, steps=run.steps,
+                             t=run.t * run.vel, checkpoint=ck))
             run.close()
             continue
         r = run.summary(t0, t1)
@@ -287,7 +327,7 @@ def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cf
             log("p=%d done: St=%.4f C_D mean %.4f rms %.4f C_L mean %+.5f rms %.4f, %d steps, %.1f s"
                 % (p, r["St"], r["CD_mean"], r["CD_rms"], r["CL_mean"], r["CL_rms"], run.steps, wall))
         run.close()
-    good = [r for r in rows if r.get("finite")]
+    good = [r for r in rows if r.get("finite") and r.get("complete", True)]
     diffs = p_differences(good, ["CL_mean", "CL_rms", "CD_mean", "CD_rms", "St"])
     if vorticity and series_out is not None and lines:
         np.savez_compressed(series_out.replace(".npz", "") + "_vorticity.npz",
@@ -438,6 +478,11 @@ def main(argv=None):
             a.add_argument("--p", type=int, nargs="+", default=[1, 2, 3, 4])
             a.add_argument("--overint", action="store_true",
                            help="over-integrated weak form (plain FP64 form only)")
+            a.add_argument("--checkpoint", default=None,
+                           help="path prefix of per-order checkpoints: resume from one "
+                                "if present; with --max-wall, save one when time runs out")
+            a.add_argument("--max-wall", type=float, default=None,
+                           help="wall seconds per order before checkpointing")
             a.add_argument("--vorticity", action="store_true",
                            help="after t-end, advance to an upward zero crossing of the lift "
                                 "and compare the wake-centreline vorticity between orders")
@@ -466,7 +511,8 @@ def main(argv=None):
     elif args.study == "cylinder":
         res = cylinder_study(w["mesh"], phys, args.p, args.t_end, t0, t1, FORMS[args.form],
                              args.c_cfl, args.c_grad, args.kick, log=_log, series_out=args.series,
-                             overint=args.overint, vorticity=args.vorticity)
+                             overint=args.overint, vorticity=args.vorticity,
+                             checkpoint=args.checkpoint, max_wall=args.max_wall)
         res["overint"] = bool(args.overint)
     else:
         res = viv_study(w["mesh"], phys, args.p, args.ustar, args.t_end, t0, t1, args.m_star,

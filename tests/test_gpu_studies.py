@@ -85,3 +85,39 @@ def test_largest_stable_step_search():
     print("[gpu-case] largest stable step p=1 K=%d" % len(mesh["EToV"]), flush=True)
     r = studies.max_stable_step(mesh, phys, 1, [4.0, 400.0, 800.0], t_end=0.5)
     assert r["C_cfl"] == 4.0 and r["dt"] > 0.0
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    """A run checkpointed at a chunk boundary and resumed in a fresh runner
+    takes the same CFL steps and ends in the same bits, with the same
+    recorded force series, as the uninterrupted run."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_17917_amd import Solver, studies
+    w, phys = _phys()
+    mesh = mg.ogrid(32, 16, 0.5, 20.0, mg.growth_ratio(0.5, 20.0, 16, 0.05))
+    s0 = Solver(2, mesh, device=False, U_inf=phys["U_inf"])
+    x, y = s0.nodes()
+    s0.close()
+    U0 = np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=0.1), (1, 0, 2))
+    print("[gpu-case] checkpoint and resume p=2 K=%d" % len(mesh["EToV"]), flush=True)
+    kw = dict(C_cfl=4.0, cfl_every=200, record_every=5)
+    a = studies.CylinderRun(mesh, 2, phys, U0, **kw)
+    assert a.advance(0.3)
+    path = str(tmp_path / "ck.npz")
+    a.save(path)
+    a.close()
+    b = studies.CylinderRun(mesh, 2, phys, U0, **kw)
+    b.load(path)
+    assert b.advance(0.6)
+    c = studies.CylinderRun(mesh, 2, phys, U0, **kw)
+    assert c.advance(0.6)
+    assert b.steps == c.steps and b.t == c.t
+    assert torch.equal(b.U, c.U)
+    for sb, sc in zip(b.series(), c.series()):
+        assert np.array_equal(sb, sc)
+    with pytest.raises(ValueError):
+        studies.CylinderRun(mesh, 3, phys, np.zeros((len(mesh["EToV"]), 4, 10)) + 1.0, **kw).load(path)
+    b.close()
+    c.close()
