@@ -120,11 +120,18 @@ class DGOracle:
         b = ph.normal_diffusion_norm(fs['Uo'], nx, ny, p.mu, p.Pr, p.gamma)
         return np.maximum(a.max(axis=1), b.max(axis=1))
 
+    def cinv(self):
+        """C_inv(e, K, p) = (p+1)(p+d)|e| / (d|K|), d = 2, per own face (3, K)
+        (eq. trace_inverse_estimate)."""
+        m, N = self.mesh, self.ref.N
+        d = 2
+        return (N + 1) * (N + d) * m.face_len / (d * m.area[None, :])
+
     def penalty(self, gbar):
         """sigma_e per face (3, K) (eq. penalty_final or the literature form)."""
         m, p, ref = self.mesh, self.phys, self.ref
         N = ref.N
-        cinv_own = (N + 1) * (N + 2) * m.face_len / (2.0 * m.area[None, :])
+        cinv_own = self.cinv()
         kn = np.where(m.EToE >= 0, m.EToE, np.arange(m.K)[:, None]).T      # (3, K)
         fn = np.where(m.EToE >= 0, m.EToF, np.arange(3)[None, :]).T
         cinv_nbr = cinv_own[fn, kn]
