@@ -254,8 +254,9 @@ int dg_autotune(dg_ctx* ctx, const double* U, int reps, const char* cache_path, 
  * again meanwhile. */
 typedef struct dg_batch dg_batch;
 
-/* Create a batch of the n contexts ctxs[0..n-1] (all set up by dg_setup).
- * Allocates device memory (3 states per instance) and pinned host memory. */
+/* Create a batch of the n contexts ctxs[0..n-1] (all set up by dg_setup,
+ * each at most once: DG_EINVAL for a repeated context).  Allocates device
+ * memory (3 states per instance) and pinned host memory. */
 int dg_batch_create(dg_ctx* const* ctxs, int n, dg_batch** out);
 
 /* Copy instance i's state in from / out to a device array [K_i][4][Np_i]

@@ -136,10 +136,55 @@ def _check(code, handle=None):
     return code
 
 
-def _ptr(t):
+# ---- argument checks --------------------------------------------------------
+# Every device array is checked on the host before its address reaches the
+# library: a tensor of the wrong type, on the host, non-contiguous or too short
+# would make a kernel read or write outside it.
+def _dtype(name):
+    import torch
+    return {"f64": torch.float64, "f32": torch.float32}[name]
+
+
+def _dev(t, dtype, count, what, optional=False):
+    """Address of a device array: a GPU tensor of `dtype` ("f64"/"f32"),
+    contiguous, with at least `count` elements (ValueError otherwise)."""
     if t is None:
-        return None
+        if optional:
+            return None
+        raise ValueError("%s: a device array is required" % what)
+    if not hasattr(t, "data_ptr") or not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a GPU tensor" % what)
+    if t.dtype != _dtype(dtype):
+        raise ValueError("%s must be %s, got %s" % (what, _dtype(dtype), t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.numel() < count:
+        raise ValueError("%s has %d elements, the call needs %d" % (what, t.numel(), count))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _rows(t, rows, cols, what, dtype="f32"):
+    """(address, row stride) of a 2-D device array of at least `rows` rows of
+    at least `cols` contiguous values (ValueError otherwise)."""
+    if t is None or not hasattr(t, "data_ptr") or not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a GPU tensor" % what)
+    if t.dtype != _dtype(dtype):
+        raise ValueError("%s must be %s, got %s" % (what, _dtype(dtype), t.dtype))
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be a 2-D array with contiguous rows" % what)
+    if t.shape[0] < rows or t.shape[1] < cols:
+        raise ValueError("%s has shape %s, the call needs at least (%d, %d)"
+                         % (what, tuple(t.shape), rows, cols))
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+
+
+def state_len(h):
+    """Values of one state [K][4][Np] of context h."""
+    return dg_num_elements(h) * 4 * dg_num_nodes(h)
+
+
+def _st(h, t, what):
+    return _dev(t, "f64", state_len(h), what)
 
 
 def _stream(stream):
@@ -218,42 +263,48 @@ def dg_get_nodes(h):
 
 def dg_rhs(h, U, R, v_w=(0.0, 0.0), stream=None):
     vw = _vw(v_w)
-    return _check(load().dg_rhs(h, _ptr(U), _ptr(R), _dp(vw), _stream(stream)), h)
+    return _check(load().dg_rhs(h, _st(h, U, "U"), _st(h, R, "R"), _dp(vw), _stream(stream)), h)
 
 
 def dg_rk_step(h, U, K1, dt, v_w=(0.0, 0.0), stream=None):
     vw = _vw(v_w)
-    return _check(load().dg_rk_step(h, _ptr(U), _ptr(K1), float(dt), _dp(vw), _stream(stream)), h)
+    return _check(load().dg_rk_step(h, _st(h, U, "U"), _st(h, K1, "K1"), float(dt), _dp(vw),
+                                    _stream(stream)), h)
 
 
 def dg_rk_steps(h, U, K1, nsteps, dt, v_w=(0.0, 0.0), force=None, stream=None):
     vw = _vw(v_w)
-    return _check(load().dg_rk_steps(h, _ptr(U), _ptr(K1), int(nsteps), float(dt), _dp(vw),
-                                     _ptr(force), _stream(stream)), h)
+    nsteps = int(nsteps)
+    f = _dev(force, "f64", 3 * max(nsteps, 0), "force", optional=True)
+    return _check(load().dg_rk_steps(h, _st(h, U, "U"), _st(h, K1, "K1"), nsteps, float(dt),
+                                     _dp(vw), f, _stream(stream)), h)
 
 
 def dg_rk_stage(h, U_in, U_out, K1, a, b, dt, v_w=(0.0, 0.0), stream=None):
     vw = _vw(v_w)
-    return _check(load().dg_rk_stage(h, _ptr(U_in), _ptr(U_out), _ptr(K1), float(a), float(b),
-                                     float(dt), _dp(vw), _stream(stream)), h)
+    return _check(load().dg_rk_stage(h, _st(h, U_in, "U_in"), _st(h, U_out, "U_out"),
+                                     _st(h, K1, "K1"), float(a), float(b), float(dt), _dp(vw),
+                                     _stream(stream)), h)
 
 
 def dg_force(h, U, v_w=(0.0, 0.0), stream=None):
     vw = _vw(v_w)
     out = np.zeros(3)
-    _check(load().dg_force(h, _ptr(U), _dp(vw), _dp(out), _stream(stream)), h)
+    _check(load().dg_force(h, _st(h, U, "U"), _dp(vw), _dp(out), _stream(stream)), h)
     return out
 
 
 def dg_force_device(h, U, out, v_w=(0.0, 0.0), stream=None):
     vw = _vw(v_w)
-    return _check(load().dg_force_device(h, _ptr(U), _dp(vw), _ptr(out), _stream(stream)), h)
+    return _check(load().dg_force_device(h, _st(h, U, "U"), _dp(vw), _dev(out, "f64", 3, "out"),
+                                         _stream(stream)), h)
 
 
 def dg_cfl_time_step(h, U, v_w=(0.0, 0.0), C_cfl=1.0, C_grad=1.0, stream=None):
     vw = _vw(v_w)
     out = np.zeros(2)
-    _check(load().dg_cfl_time_step(h, _ptr(U), _dp(vw), C_cfl, C_grad, _dp(out), _stream(stream)), h)
+    _check(load().dg_cfl_time_step(h, _st(h, U, "U"), _dp(vw), C_cfl, C_grad, _dp(out),
+                                   _stream(stream)), h)
     return float(out[0]), float(out[1])
 
 
@@ -287,7 +338,7 @@ def dg_get_tuning(h):
 
 def dg_autotune(h, U, reps=20, cache_path=None, stream=None):
     best = ctypes.c_double()
-    _check(load().dg_autotune(h, _ptr(U), int(reps),
+    _check(load().dg_autotune(h, _st(h, U, "U"), int(reps),
                               None if cache_path is None else os.fsencode(cache_path),
                               _stream(stream), ctypes.byref(best)), h)
     return best.value
@@ -301,19 +352,31 @@ def _bcheck(code, b=None):
     return code
 
 
+# state lengths of each batch's instances, for the argument checks
+_BATCH_STATES = {}
+
+
 def dg_batch_create(handles):
     arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
     b = ctypes.c_void_p()
     _bcheck(load().dg_batch_create(arr, len(handles), ctypes.byref(b)))
+    _BATCH_STATES[b.value] = [state_len(h) for h in handles]
     return b
 
 
+def _batch_state(b, i, U):
+    sizes = _BATCH_STATES.get(b.value)
+    if sizes is None or not 0 <= int(i) < len(sizes):
+        raise ValueError("instance %s is not in the batch" % i)
+    return _dev(U, "f64", sizes[int(i)], "U")
+
+
 def dg_batch_set_state(b, i, U, stream=None):
-    return _bcheck(load().dg_batch_set_state(b, int(i), _ptr(U), _stream(stream)), b)
+    return _bcheck(load().dg_batch_set_state(b, int(i), _batch_state(b, i, U), _stream(stream)), b)
 
 
 def dg_batch_get_state(b, i, U, stream=None):
-    return _bcheck(load().dg_batch_get_state(b, int(i), _ptr(U), _stream(stream)), b)
+    return _bcheck(load().dg_batch_get_state(b, int(i), _batch_state(b, i, U), _stream(stream)), b)
 
 
 def dg_batch_rk_step(b, dt, v_w, stream=None):
@@ -371,6 +434,7 @@ def dg_batch_last_error(b):
 
 def dg_batch_destroy(b):
     if b is not None and b.value:
+        _BATCH_STATES.pop(b.value, None)
         load().dg_batch_destroy(b)
 
 
@@ -380,13 +444,6 @@ _FP = ctypes.POINTER(ctypes.c_float)
 
 def _fp(a):
     return a.ctypes.data_as(_FP)
-
-
-def _ld(t):
-    """Row stride of a 2-D device array whose rows are contiguous."""
-    if t.dim() != 2 or t.stride(1) != 1:
-        raise ValueError("expected a 2-D array with contiguous rows")
-    return t.stride(0)
 
 
 def _mcheck(code, m=None):
@@ -403,11 +460,22 @@ def _ccheck(code, c=None):
     return code
 
 
+# (n_in, n_out) of each network, for the argument checks
+_MLP_SIZES = {}
+
+
 def dg_mlp_create(n_in, n_hidden, n_out, max_batch):
     m = ctypes.c_void_p()
     _mcheck(load().dg_mlp_create(int(n_in), int(n_hidden), int(n_out), int(max_batch),
                                  ctypes.byref(m)))
+    _MLP_SIZES[m.value] = (int(n_in), int(n_out))
     return m
+
+
+def _mlp_sizes(m):
+    if m is None or m.value not in _MLP_SIZES:
+        raise ValueError("not a network created by dg_mlp_create")
+    return _MLP_SIZES[m.value]
 
 
 def dg_mlp_num_params(m):
@@ -438,15 +506,20 @@ def dg_mlp_set_normalization(m, in_mean, in_std, out_mean, out_std):
 
 
 def dg_mlp_forward(m, X, Y, B=None, stream=None):
-    B = X.shape[0] if B is None else B
-    return _mcheck(load().dg_mlp_forward(m, _ptr(X), _ld(X), int(B), _ptr(Y), _ld(Y),
-                                         _stream(stream)), m)
+    n_in, n_out = _mlp_sizes(m)
+    B = X.shape[0] if B is None else int(B)
+    x, ldx = _rows(X, B, n_in, "X")
+    y, ldy = _rows(Y, B, n_out, "Y")
+    return _mcheck(load().dg_mlp_forward(m, x, ldx, B, y, ldy, _stream(stream)), m)
 
 
 def dg_mlp_backward(m, X, T, B=None, want_loss=True, stream=None):
-    B = X.shape[0] if B is None else B
+    n_in, n_out = _mlp_sizes(m)
+    B = X.shape[0] if B is None else int(B)
+    x, ldx = _rows(X, B, n_in, "X")
+    t, ldt = _rows(T, B, n_out, "T")
     loss = ctypes.c_double()
-    _mcheck(load().dg_mlp_backward(m, _ptr(X), _ld(X), _ptr(T), _ld(T), int(B),
+    _mcheck(load().dg_mlp_backward(m, x, ldx, t, ldt, B,
                                    ctypes.byref(loss) if want_loss else None, _stream(stream)), m)
     return loss.value if want_loss else None
 
@@ -463,24 +536,38 @@ def dg_mlp_last_error(m):
 
 def dg_mlp_destroy(m):
     if m is not None and m.value:
+        _MLP_SIZES.pop(m.value, None)
         load().dg_mlp_destroy(m)
 
 
 def dg_column_stats(A, cols=None, rows=None, stream=None):
-    rows = A.shape[0] if rows is None else rows
-    cols = A.shape[1] if cols is None else cols
+    rows = A.shape[0] if rows is None else int(rows)
+    cols = A.shape[1] if cols is None else int(cols)
+    a, lda = _rows(A, rows, cols, "A")
     mean, std = np.zeros(cols), np.zeros(cols)
-    code = load().dg_column_stats(_ptr(A), int(rows), _ld(A), int(cols), _dp(mean), _dp(std),
-                                  _stream(stream))
+    code = load().dg_column_stats(a, rows, lda, cols, _dp(mean), _dp(std), _stream(stream))
     if code != DG_OK:
         raise DGError(code, "dg_column_stats failed")
     return mean, std
 
 
+# (K, state length lo, state length hi, n_features, n_targets) of each
+# closure, for the argument checks
+_CLOSURE_SIZES = {}
+
+
 def dg_closure_create(lo, hi):
     c = ctypes.c_void_p()
     _ccheck(load().dg_closure_create(lo, hi, ctypes.byref(c)))
+    nf, nt = dg_closure_sizes(c)
+    _CLOSURE_SIZES[c.value] = (dg_num_elements(hi), state_len(lo), state_len(hi), nf, nt)
     return c
+
+
+def _closure_sizes(c):
+    if c is None or c.value not in _CLOSURE_SIZES:
+        raise ValueError("not a closure created by dg_closure_create")
+    return _CLOSURE_SIZES[c.value]
 
 
 def dg_closure_sizes(c):
@@ -490,21 +577,30 @@ def dg_closure_sizes(c):
 
 
 def dg_closure_features(c, U, X, from_hi, stream=None):
-    return _ccheck(load().dg_closure_features(c, _ptr(U), int(bool(from_hi)), _ptr(X), _ld(X),
-                                              _stream(stream)), c)
+    K, s_lo, s_hi, nf, _ = _closure_sizes(c)
+    u = _dev(U, "f64", s_hi if from_hi else s_lo, "U")
+    x, ldx = _rows(X, K, nf, "X")
+    return _ccheck(load().dg_closure_features(c, u, int(bool(from_hi)), x, ldx, _stream(stream)), c)
 
 
 def dg_closure_targets(c, U_hi, T, stream=None):
-    return _ccheck(load().dg_closure_targets(c, _ptr(U_hi), _ptr(T), _ld(T), _stream(stream)), c)
+    K, _, s_hi, _, nt = _closure_sizes(c)
+    t, ldt = _rows(T, K, nt, "T")
+    return _ccheck(load().dg_closure_targets(c, _dev(U_hi, "f64", s_hi, "U_hi"), t, ldt,
+                                             _stream(stream)), c)
 
 
 def dg_closure_restrict(c, U_hi, U_lo, stream=None):
-    return _ccheck(load().dg_closure_restrict(c, _ptr(U_hi), _ptr(U_lo), _stream(stream)), c)
+    _, s_lo, s_hi, _, _ = _closure_sizes(c)
+    return _ccheck(load().dg_closure_restrict(c, _dev(U_hi, "f64", s_hi, "U_hi"),
+                                              _dev(U_lo, "f64", s_lo, "U_lo"), _stream(stream)), c)
 
 
 def dg_closure_apply(c, U_lo, Y, U_hi, stream=None):
-    return _ccheck(load().dg_closure_apply(c, _ptr(U_lo), _ptr(Y), 0 if Y is None else _ld(Y),
-                                           _ptr(U_hi), _stream(stream)), c)
+    K, s_lo, s_hi, _, nt = _closure_sizes(c)
+    y, ldy = (None, 0) if Y is None else _rows(Y, K, nt, "Y")
+    return _ccheck(load().dg_closure_apply(c, _dev(U_lo, "f64", s_lo, "U_lo"), y, ldy,
+                                           _dev(U_hi, "f64", s_hi, "U_hi"), _stream(stream)), c)
 
 
 def dg_closure_last_error(c):
@@ -514,4 +610,5 @@ def dg_closure_last_error(c):
 
 def dg_closure_destroy(c):
     if c is not None and c.value:
+        _CLOSURE_SIZES.pop(c.value, None)
         load().dg_closure_destroy(c)

@@ -256,6 +256,12 @@ int dg_batch_create(dg_ctx* const* ctxs, int n, dg_batch** out) {
 static int batch_build(dg_batch* b, dg_ctx* const* ctxs, int n) {
   b->n = n;
   b->ctx.assign(ctxs, ctxs + n);
+  // an instance's wall force is reduced through its context's partials and
+  // ticket: two instances on one context would race on them
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (ctxs[i] && ctxs[i] == ctxs[j])
+        return bfail(b, DG_EINVAL, "a context appears twice in the batch");
   for (int i = 0; i < n; ++i) {
     dg_ctx* c = ctxs[i];
     if (!c || !c->dev_ready) return bfail(b, DG_ESTATE, "every context must be set up (dg_setup)");

@@ -140,19 +140,17 @@ def test_error_codes():
         assert e.value.code == L.DG_EMESH
         L.dg_set_mesh(h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh["face_tag"], mesh["period"])
         L.dg_setup_host(h)
-        # device calls before dg_setup -> out of order, no GPU touched
-        import torch
-        U = torch.zeros(1, dtype=torch.float64)
-        R = torch.zeros(1, dtype=torch.float64)
-        with pytest.raises(L.DGError) as e:
-            L.dg_rhs(h, U, R, stream=0)
-        assert e.value.code == L.DG_ESTATE
-        with pytest.raises(L.DGError) as e:
-            L.dg_rk_step(h, U, R, 1e-3, stream=0)
-        assert e.value.code == L.DG_ESTATE
-        with pytest.raises(L.DGError) as e:
-            L.dg_cfl_time_step(h, U, stream=0)
-        assert e.value.code == L.DG_ESTATE
+        # device calls before dg_setup -> out of order, no GPU touched (the C
+        # entry points directly: the binding would refuse host arrays first;
+        # the placeholder addresses are rejected before any use)
+        import ctypes
+        lib = L.load()
+        U, R = ctypes.c_void_p(16), ctypes.c_void_p(32)
+        vw = np.zeros(2)
+        out = np.zeros(2)
+        assert lib.dg_rhs(h, U, R, L._dp(vw), None) == L.DG_ESTATE
+        assert lib.dg_rk_step(h, U, R, 1e-3, L._dp(vw), None) == L.DG_ESTATE
+        assert lib.dg_cfl_time_step(h, U, L._dp(vw), 1.0, 1.0, L._dp(out), None) == L.DG_ESTATE
         assert "dg_setup" in L.dg_last_error(h)
     finally:
         L.dg_destroy(h)
@@ -185,11 +183,10 @@ def test_tuning_and_batch_error_paths():
                 L.dg_set_tuning(h, *bad)
             assert e.value.code == L.DG_EINVAL
         assert L.dg_get_tuning(h) == (2, 1)
-        import torch
-        U = torch.zeros(1, dtype=torch.float64)
-        with pytest.raises(L.DGError) as e:
-            L.dg_autotune(h, U, 5, None, stream=0)
-        assert e.value.code == L.DG_ESTATE
+        import ctypes
+        best = ctypes.c_double()
+        assert L.load().dg_autotune(h, ctypes.c_void_p(16), 5, None, None,
+                                    ctypes.byref(best)) == L.DG_ESTATE
         with pytest.raises(L.DGError) as e:
             L.dg_batch_create([h])
         assert e.value.code == L.DG_ESTATE
