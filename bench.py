@@ -4,13 +4,17 @@ Workload (default, cylinder20k): flow past a unit-diameter cylinder, O-grid
 of 80 x 128 cells (radial ratio 1.05, wall r = 0.5, far field r = 30) split
 into K = 20480 triangles, p = 4 (Np = 15), Re = 100, M = 0.2, SIPG, paper
 penalty, free stream plus seeded 1e-3 uniform noise per node and field.
-Other workloads (--workload): cylinder327k (the same O-grid refined 4 x 4,
-K = 327,680, states beyond the last-level cache), periodic51k (160x160x2
-periodic triangles, p = 6, three seeded Fourier modes of amplitude 1e-2),
-viv16 (16 elastically mounted cylinders, K = 5k-31k each, p in {4, 5, 6},
-U* in [3, 8], coupled to a host Newmark step every step, advanced as one
-batch) and closure20k (the learned closure: order-4 snapshots, bfloat16
-training throughput, gain at Re = 120).
+The default run also measures the rest of the metric's range and the
+out-of-cache mesh, each with plain FP64 beside it, and reports them as
+sub-objects of the same line: "orders" (cylinder20k at p = 5 and 6) and
+"cylinder327k" (the same O-grid refined 4 x 4, K = 327,680, p = 4, states
+beyond the last-level cache).
+Other workloads (--workload): cylinder327k, periodic51k (160x160x2 periodic
+triangles, p = 6, three seeded Fourier modes of amplitude 1e-2), viv16 (16
+elastically mounted cylinders, K = 5k-31k each, p in {4, 5, 6}, U* in [3, 8],
+coupled to a host Newmark step every step, advanced as one batch) and
+closure20k (the learned closure: order-4 snapshots, bfloat16 training
+throughput, gain at Re = 120).
 
 A step is one pass of the hot path: the five fused RHS + stage launches of
 one LSERK step and the wall-force integral (viv16: plus the host Newmark step
@@ -20,19 +24,22 @@ resident in HBM.
 
 Forms (--form): fp64 (plain, every step binary64), fp64-pert and fp32-pert
 (the right-hand side on U - U_inf with cancellation-free flux differences, in
-binary64 or binary32; the RK registers stay binary64).  Plain FP64 (single
-launches per instance) is run beside the chosen form from the same initial
-state for the same steps; the stated error is the per-field L2 norm (with
-the mass matrix, sum_K J_K dU^T M dU) of the difference of the final states,
-relative to that of the plain FP64 state's deviation from U_inf, largest
-over the four fields.
+binary64 or binary32; the RK registers stay binary64), bf16-ops.  Plain FP64
+is run beside the chosen form from the same initial state for the same
+steps; the stated error is the per-field L2 norm (with the mass matrix,
+sum_K J_K dU^T M dU) of the difference of the final states, relative to that
+of the plain FP64 state's deviation from U_inf, largest over the four fields.
 
-Also reported: the average duration of the stage kernel (HIP events on the
-launch stream) against its algorithmic flops and HBM bytes, and the FP64
-NumPy oracle timed on the host on a bounded sample (cylinder20k only).
+Roofline: the stage kernel's average launch time (HIP events on its stream)
+against HBM (algorithmic bytes), the matrix cores (operator products at the
+form's matrix peak) and the vector ALU (pointwise flops), the binding roof
+reported; measured HBM traffic per launch from the committed counter
+summaries when they match the current kernel sources, else null.
+cpu_baseline: the FP64 NumPy oracle on the host (RHS + stage update per
+order, one thread and the default pools, host core count).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--p P] [--form F]
-                       [--workload W] [--no-cpu-baseline]
+                       [--workload W] [--quick] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -46,21 +53,16 @@ if ROOT not in sys.path:
 
 METRIC = "DG RHS DOF-updates/s at p=4–6, chosen form vs plain FP64 at stated L2 err"
 METRIC_OI = "DG RHS DOF-updates/s, over-integrated (degree-3p quadrature) FP64 vs the nodal FP64 stage"
+# MI355X published peaks: HBM3E 8 TB/s; dense matrix cores FP64 78.6, FP32
+# 157.3, bfloat16 2500 TFLOP/s; vector ALU 256 CUs x 4 SIMDs x 16 lanes x 2
+# (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP64 and for FP32 without packed
+# instructions (packed FP32 is not used in this build)
 HBM_PEAK_GBS = 8000.0
-# vector ALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
-# = 78.6 TFLOP/s, the same for FP64 and for FP32 without packed instructions
-# (packed FP32 is disabled in the build; 157.3 is the packed FP32 figure)
-ALU_PEAK_TFLOPS = 78.6
-FP32_PACKED_PEAK_TFLOPS = 157.3
+VALU_PEAK_TFLOPS = 78.6
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 FORMS = {"fp64": 0, "fp64-pert": 1, "fp32-pert": 2, "bf16-ops": 3}
-
-# HBM bytes per stage launch measured with rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (cylinder20k, p = 4), each scaled by the counter's reading for a
-# plain 512 MiB device copy (FETCH x 2.000, WRITE x 1.000); valid only for the
-# kernel sources and form they were taken on (hash of kernels.hip +
-# dg_physics.h).
-MEASURED_TRAFFIC = {"sources": "16531448c4e8da51", "p": 4, "form": "fp32-pert",
-                    "fetch_bytes": 11502.0 * 2.0 * 1024, "write_bytes": 19200.0 * 1.0 * 1024}
+MFMA_DTYPE = {"fp64": "f64", "fp64-pert": "f64", "fp32-pert": "f32", "bf16-ops": "bf16"}
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -73,17 +75,58 @@ def algorithmic_bytes_per_element(Np):
     return 4 * 4 * Np * 8 + 16 * 8 + 3 * 4
 
 
-def algorithmic_flops_per_element(Np, Nfp):
-    """FP64 flops of one RHS + stage per element, counted from the method.
+def gemm_flops_per_element(Np, Nfp):
+    """Operator products of one RHS per element (matrix cores): gradient and
+    divergence 2 x 16 Np^2 (D_r, D_s on 4 fields, both ways), the three lifts
+    24 Np (3 Nfp)."""
+    return 32 * Np * Np + 24 * Np * 3 * Nfp
 
-    gradient and divergence 2 x 16 Np^2 (Dr, Ds on 4 fields), three lifts
-    24 Np (3 Nfp), volume-node flux 75 Np, face nodes (16 Np + 460) per
-    node of the 3 Nfp (neighbour gradient at the node 16 Np; two
+
+def pointwise_flops_per_element(Np, Nfp):
+    """Pointwise FP64 flops of one RHS + stage per element (vector ALU),
+    counted from the method: volume-node flux 75 Np, face nodes (16 Np + 460)
+    per node of the 3 Nfp (neighbour gradient at the node 16 Np; two
     ||n^T G n||_2 ~200, two viscous normal fluxes ~80, Roe ~110, penalty and
-    residual ~20, theta term ~50), stage update 16 Np.
-    """
+    residual ~20, theta term ~50), stage update 16 Np."""
     NF = 3 * Nfp
-    return 32 * Np * Np + 24 * Np * NF + 75 * Np + (16 * Np + 460) * NF + 16 * Np
+    return 75 * Np + (16 * Np + 460) * NF + 16 * Np
+
+
+def algorithmic_flops_per_element(Np, Nfp):
+    return gemm_flops_per_element(Np, Nfp) + pointwise_flops_per_element(Np, Nfp)
+
+
+def roofline(Np, Nfp, K, t_launch, form, traffic=None, overint=False):
+    """The stage kernel against each roof it could be bound by -- HBM
+    (algorithmic bytes at 8 TB/s), the matrix cores (operator products at the
+    form's matrix peak) and the vector ALU (pointwise flops at 78.6 TFLOP/s),
+    each taken alone as a lower bound on the launch time -- and the binding
+    one (the largest bound).  frac = that bound / the measured launch time."""
+    nbytes = algorithmic_bytes_per_element(Np) * K
+    if overint:
+        gemm, pw = (x * K for x in oi_flops_per_element(Np, Nfp))
+    else:
+        gemm = gemm_flops_per_element(Np, Nfp) * K
+        pw = pointwise_flops_per_element(Np, Nfp) * K
+    mdt = MFMA_DTYPE[form]
+    t = {"hbm": nbytes / (HBM_PEAK_GBS * 1e9),
+         "mfma": gemm / (MFMA_PEAK_TFLOPS[mdt] * 1e12),
+         "alu": pw / (VALU_PEAK_TFLOPS * 1e12)}
+    bound = max(t, key=t.get)
+    if bound == "hbm":
+        achieved, peak, unit = nbytes / t_launch / 1e9, HBM_PEAK_GBS, "GB/s"
+    elif bound == "mfma":
+        achieved, peak, unit = gemm / t_launch / 1e12, MFMA_PEAK_TFLOPS[mdt], "TFLOP/s"
+    else:
+        achieved, peak, unit = pw / t_launch / 1e12, VALU_PEAK_TFLOPS, "TFLOP/s"
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic,
+            "avg_launch_us": t_launch * 1e6,
+            "bytes_per_launch": nbytes, "gemm_flops_per_launch": gemm,
+            "pointwise_flops_per_launch": pw,
+            "frac_hbm": t["hbm"] / t_launch,
+            "frac_mfma_%s" % mdt: t["mfma"] / t_launch,
+            "frac_valu": t["alu"] / t_launch}
 
 
 def closure_bytes_per_sample(n_in, H, n_out):
@@ -103,18 +146,19 @@ def closure_bytes_per_sample(n_in, H, n_out):
     return fwd + bwd + wgr
 
 
-def algorithmic_flops_per_element_oi(Np, Nfp):
-    """FP64 flops of one over-integrated RHS + stage per element (q points per
-    direction, q^2 element points, 3q face points), counted from the method:
-    U, d_r U, d_s U at the element points 3 x 8 Nq Np, weighted divergence
-    2 x 8 Np Nq, three lifts 24 Np 3q, volume flux 75 per element point, per
-    face point both sides' value and gradient 2 (8 Nfp + 16 Np) plus the face
-    fluxes 460 as in the nodal count, stage update 16 Np."""
+def oi_flops_per_element(Np, Nfp):
+    """(operator products, pointwise) FP64 flops of one over-integrated RHS +
+    stage per element (q points per direction, q^2 element points, 3q face
+    points), counted from the method: U, d_r U, d_s U at the element points
+    3 x 8 Nq Np, weighted divergence 2 x 8 Np Nq, three lifts 24 Np 3q on the
+    matrix cores; volume flux 75 per element point, per face point both
+    sides' value and gradient 2 (8 Nfp + 16 Np) plus the face fluxes 460 as in
+    the nodal count, stage update 16 Np on the vector ALU."""
     p = Nfp - 1
     q = (3 * p + 2) // 2
     Nq, NG = q * q, 3 * q
-    return (24 * Nq * Np + 16 * Np * Nq + 24 * Np * NG + 75 * Nq
-            + (32 * Np + 16 * Nfp + 460) * NG + 16 * Np)
+    return (24 * Nq * Np + 16 * Np * Nq + 24 * Np * NG,
+            75 * Nq + (32 * Np + 16 * Nfp + 460) * NG + 16 * Np)
 
 
 def kernel_sources_hash():
@@ -126,45 +170,81 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(p, form):
-    t = MEASURED_TRAFFIC
-    if t["sources"] != kernel_sources_hash() or t["p"] != p or t["form"] != form:
-        return None
-    return t["fetch_bytes"] + t["write_bytes"]
+def measured_traffic(workload, p, form):
+    """HBM bytes per stage launch from the committed rocprofv3 counter
+    summaries (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a
+    plain device copy of known size): a line
+      traffic: workload=W p=P form=F sources=H bytes=B
+    in a profiles/*.md file.  None unless one matches this workload, order,
+    form and the current kernel sources (counters of other sources do not
+    describe this kernel)."""
+    import glob
+    import re
+    want = kernel_sources_hash()
+    pat = re.compile(r"traffic: workload=(\S+) p=(\d+) form=(\S+) sources=(\S+) bytes=([0-9.eE+]+)")
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                m = pat.search(line)
+                if (m and m.group(1) == workload and int(m.group(2)) == p and m.group(3) == form
+                        and m.group(4) == want):
+                    return float(m.group(5))
+    return None
 
 
-def cpu_baseline(w, p, budget_s=20.0, overint=False):
+def cpu_baseline(w, orders, overint=False):
+    """The oracle as it stands (NumPy FP64) on the host cores: per order, one
+    weak-form RHS of the full workload followed by its LSERK stage update
+    (K1 <- A_2 K1 + dt R, U <- U + B_2 K1), timed with the BLAS/OpenMP pools
+    limited to one thread and at their defaults.  DOF-updates/s = 4 Np K per
+    RHS + stage / wall time.  The oracle's arithmetic is NumPy einsum and
+    elementwise work, which runs on one thread either way."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import meshgen as mg
-    from oracle.dg import DGOracle, Physics
+    from oracle.dg import LSERK_A, LSERK_B, DGOracle, Physics
     from oracle.mesh import Mesh
     from oracle.nodes import RefElement
 
-    ref = RefElement(p)
+    host_cores = len(os.sched_getaffinity(0))
+    pools = sorted({i.get("num_threads", 1) for i in threadpool_info()}) or [1]
     m = w["mesh"]
-    mesh = Mesh(ref, m["VX"], m["VY"], m["EToV"], m["face_tag"], m["period"])
-    dg = DGOracle(mesh, Physics(gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
-                                penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"]))
-    if overint:
-        from oracle.overint import DGOracleOI
-        dg = DGOracleOI(dg.mesh, dg.phys)
-    U = mg.noisy_free_stream((4, ref.Np, mesh.K), w["U_inf"], mg.rng_for(1))
-    n = 0
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        while True:
-            dg.rhs(U)
-            n += 1
-            el = time.perf_counter() - t0
-            if el > budget_s or n >= 5 or el * (n + 1) / n > 1.5 * budget_s:
-                break
-    dofs = 4 * ref.Np * mesh.K
-    return {"value": dofs * n / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d %sweak-form RHS evaluations of the full K=%d p=%d workload (NumPy FP64, "
-                      "1 BLAS thread, %.1f s)" % (n, "over-integrated " if overint else "", mesh.K,
-                                                  p, el)}
+    per = {}
+    total = 0.0
+    for p in orders:
+        ref = RefElement(p)
+        mesh = Mesh(ref, m["VX"], m["VY"], m["EToV"], m["face_tag"], m["period"])
+        dg = DGOracle(mesh, Physics(gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
+                                    penalty_mode=w["penalty_mode"], C_pen=w["C_pen"],
+                                    U_inf=w["U_inf"]))
+        if overint:
+            from oracle.overint import DGOracleOI
+            dg = DGOracleOI(dg.mesh, dg.phys)
+        U = mg.noisy_free_stream((4, ref.Np, mesh.K), w["U_inf"], mg.rng_for(1))
+        K1 = np.zeros_like(U)
+        dofs = 4 * ref.Np * mesh.K
+        rates = {}
+        for label, lim in (("1_thread", 1), ("default_threads", None)):
+            with threadpool_limits(limits=lim):
+                t0 = time.perf_counter()
+                K1n = LSERK_A[1] * K1 + 1e-7 * dg.rhs(U)
+                U1 = U + LSERK_B[1] * K1n
+                el = time.perf_counter() - t0
+            assert np.isfinite(U1).all()
+            rates[label] = dofs / el
+            total += el
+        per[str(p)] = {"1_thread": rates["1_thread"], "default_threads": rates["default_threads"],
+                       "K": mesh.K, "Np": ref.Np}
+    head = per[str(orders[0])]
+    return {"value": head["1_thread"], "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "one %sweak-form RHS + LSERK stage update of the full K=%d workload per "
+                      "order p=%s, NumPy FP64, 1 thread and the default pools (%.1f s in all); "
+                      "value: p=%d, 1 thread"
+                      % ("over-integrated " if overint else "", head["K"],
+                         ",".join(str(q) for q in orders), total, orders[0]),
+            "host_cores": host_cores, "default_pool_threads": pools[-1],
+            "per_order": per}
 
 
 def stable_dt(mesh, p, mu, rho=1.0, C=0.01):
@@ -474,6 +554,9 @@ def main():
                                            "closure20k"],
                     default="cylinder20k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="cylinder20k: the headline order only (no p = 5, 6 and cylinder327k "
+                         "sub-objects, CPU baseline at the headline order only)")
     ap.add_argument("--overint", action="store_true",
                     help="single-mesh workloads: the over-integrated FP64 stage (degree-3p "
                          "quadrature), the nodal FP64 stage beside it")
@@ -485,7 +568,6 @@ def main():
               "(the element partition would shard by domain decomposition)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import meshgen as mg
@@ -500,158 +582,28 @@ def main():
     if args.workload == "closure20k":
         run_closure(args)
         return
-    cfl_info = None
     if args.workload == "viv16":
-        cases, phys = mg.viv_sweep_cases()
-        if args.p is not None:
-            for c in cases:
-                c["p"] = args.p
-        U_inf = phys["U_inf"]
-        states, dts, desc, flops, nbytes, dofs = [], [], [], 0.0, 0.0, 0
-        for i, c in enumerate(cases):
-            Np = (c["p"] + 1) * (c["p"] + 2) // 2
-            K = len(c["mesh"]["EToV"])
-            U0 = mg.noisy_free_stream((4, Np, K), U_inf, mg.rng_for(2, salt=i + 1))
-            states.append(torch.from_numpy(np.ascontiguousarray(np.transpose(U0, (2, 0, 1)))).cuda())
-            dts.append(min(1e-7, stable_dt(c["mesh"], c["p"], phys["mu"])))
-            flops += algorithmic_flops_per_element(Np, c["p"] + 1) * K
-            nbytes += algorithmic_bytes_per_element(Np) * K
-            dofs += 4 * Np * K
-            desc.append("%dx%d p%d" % (c["ntheta"], c["nr"], c["p"]))
-        dts = np.array(dts)
-        log("viv16 (%s): chosen form %s batched" % (", ".join(desc), args.form))
-        U, t_steps, t_launch, solvers, shape = run_viv(cases, phys, states, prec, args.steps,
-                                                       args.warmup, dts, batched=True)
-        log("plain fp64 beside it (one launch per stage and instance)")
-        U64, t64, _, solvers64, _ = run_viv(cases, phys, states, FORMS["fp64"], args.steps,
-                                            args.warmup, dts, batched=False)
-        finite = all(bool(torch.isfinite(u).all().item()) for u in U)
-        err = rel_l2(solvers64, U, U64, U_inf)
-        tl64 = None
-        config = {"workload": "viv16: 16 elastically mounted cylinders (m*=10, xi=0, U* = "
-                              "linspace(3,8)), O-grids %s, total K=%d, Re=100, M=0.2, SIPG, "
-                              "coupled to host Newmark each step, batched (the stages of a "
-                              "step replayed from a HIP graph), %s form" % (
-                                  ", ".join(desc), sum(s.K for s in solvers64), args.form),
-                  "instances": len(cases), "dofs": dofs, "form": args.form,
-                  "launch_shape": shape,
-                  "dt": [float(x) for x in dts], "finite": finite}
-        kernel = ("batch_stage_kernel<%s>" if shape.startswith("one launch per stage")
-                  else "batch_order_kernel<p, %s> (one launch per order)") % args.form
-        cpu = None
+        out = viv_report(args, prec)
     else:
-        w = mg.workload(args.workload, args.p)
-        p = w["p"]
-        Np = (p + 1) * (p + 2) // 2
-        K = len(w["mesh"]["EToV"])
-        if args.workload == "periodic51k":
-            # smooth field: three seeded Fourier modes of amplitude 1e-2
-            sv = make_solver(w, p, w["mesh"], FORMS["fp64"])
-            x, y = sv.nodes()
-            sv.close()
-            U0n = mg.fourier_modes(x.T, y.T, mg.rng_for(3), L=10.0, amp=1e-2,
-                                   q0=(1.0, 0.3, 0.0, 1.0 / w["gamma"]), gamma=w["gamma"])
-            desc = ("%s: periodic [0,10]^2, 160x160x2 -> K=%d triangles, p=%d (Np=%d), Re=100, "
-                    "M=0.3, 3 seeded Fourier modes (amplitude 1e-2), %s form"
-                    % (args.workload, K, p, Np, args.form))
-        else:
-            U0n = mg.noisy_free_stream((4, Np, K), w["U_inf"], mg.rng_for(1))
-            desc = ("%s: O-grid %s cells (ratio %s, r 0.5..30) -> K=%d triangles, p=%d (Np=%d), "
-                    "Re=100, M=0.2, SIPG, free stream + 1e-3 seeded noise, %s form"
-                    % (args.workload, "80x128" if args.workload == "cylinder20k" else "320x512",
-                       "1.05" if args.workload == "cylinder20k" else "1.0125", K, p, Np,
-                       args.form))
-        U0 = torch.from_numpy(np.ascontiguousarray(np.transpose(U0n, (2, 0, 1)))).cuda()
-        # SIPG with C1 = 1 on the 2.9e-3 wall layer at p = 4 is penalty-limited
-        # near 3e-7; 1e-7 keeps the impulsively started state bounded
-        dt = min(1e-7 if args.workload != "periodic51k" else 1.0,
-                 stable_dt(w["mesh"], p, w["mu"]) * 1.5)
-        log("%s p=%d form %s, warmup %d, steps %d" % (args.workload, p, args.form, args.warmup,
-                                                    args.steps))
-        U, t_steps, t_launch, s = run_single(w, U0, prec, args.steps, args.warmup, dt,
-                                             overint=args.overint)
-        finite = bool(torch.isfinite(U).all().item())
-        if args.form != "fp64" or args.overint:
-            log("plain fp64 beside it")
-            U64, t64, tl64, s64 = run_single(w, U0, FORMS["fp64"], args.steps, args.warmup, dt)
-        else:
-            U64, t64, tl64, s64 = U, t_steps, t_launch, s
-        err = rel_l2([s64], [U], [U64], w["U_inf"])
-        flops = (algorithmic_flops_per_element_oi(Np, p + 1) if args.overint
-                 else algorithmic_flops_per_element(Np, p + 1)) * K
-        nbytes = algorithmic_bytes_per_element(Np) * K
-        dofs = 4 * Np * K
-        config = {"workload": desc, "K": K, "p": p, "dofs": dofs, "form": args.form, "dt": dt,
-                  "finite": finite, "launch_shape": tuning_of(s),
-                  "launch_shape_fp64": tuning_of(s64)}
-        if args.compare_forms:
-            forms = {}
-            for name in FORMS:
-                if name in ("fp64", args.form):
-                    continue
-                log("form %s" % name)
-                Uf, tf, tlf, sf = run_single(w, U0, FORMS[name], args.steps, args.warmup, dt)
-                forms[name] = {"value": dofs * 5 * args.steps / tf, "avg_launch_us": tlf * 1e6,
-                               "l2_rel_err": rel_l2([s64], [Uf], [U64], w["U_inf"])}
-                sf.close()
-            config["other_forms"] = forms
-        kernel = ("oi_stage_kernel<%d> (over-integrated, fp64)" % p if args.overint
-                  else "stage_kernel<%d, %s>" % (p, args.form))
-        if args.overint:
-            config["workload"] = desc.replace("fp64 form", "fp64 form, over-integrated "
-                                              "(degree-%d quadrature, %d element and %d face "
-                                              "points)" % (3 * p, ((3 * p + 2) // 2) ** 2,
-                                                           3 * ((3 * p + 2) // 2)))
-        # the CFL time step of Alg. 3 on the final state (outside the timed
-        # region): the bound's value and the cost of one call (two kernels and
-        # a synchronising read-back)
-        lam, _ = s.cfl_time_step(U)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            s.cfl_time_step(U)
-        cfl_info = {"Lambda": lam, "us_per_call": (time.perf_counter() - t0) / 20 * 1e6,
-                    "note": "dg_cfl_time_step on the final state, C_grad = 1; not in the timed steps"}
-        cpu = None
+        orders = [args.p] if args.p is not None else [mg.workload(args.workload)["p"]]
+        head = measure(args.workload, orders[0], args.form, args.steps, args.warmup,
+                       overint=args.overint, compare_forms=args.compare_forms, cfl=True)
+        out = head.pop("line")
+        # the rest of the metric: the other orders on the same mesh, and the
+        # out-of-cache mesh at the headline order (same steps, same forms)
+        if args.workload == "cylinder20k" and args.p is None and not args.overint and not args.quick:
+            sub = {}
+            for p in (5, 6):
+                r = measure("cylinder20k", p, args.form, args.steps, args.warmup)
+                sub["p%d" % p] = r["summary"]
+            out["orders"] = sub
+            r = measure("cylinder327k", 4, args.form, args.steps, args.warmup)
+            out["cylinder327k"] = r["summary"]
         if not args.no_cpu_baseline and args.workload == "cylinder20k":
             log("cpu baseline (oracle)")
-            cpu = cpu_baseline(w, p, overint=args.overint)
-        s.close()
-        if s64 is not s:
-            s64.close()
-
-    achieved = flops / t_launch / 1e12
-    value = dofs * 5 * args.steps / t_steps
-    out = {
-        "metric": METRIC_OI if args.overint else METRIC,
-        "value": value,
-        "unit": "DOF-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": t_steps * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.form == "fp32-pert" else "f64",
-        "data": "synthetic",
-        "config": config,
-        ("vs_nodal_fp64" if args.overint else "vs_plain_fp64"): {
-                          "value": dofs * 5 * args.steps / t64,
-                          "avg_launch_us": None if tl64 is None else tl64 * 1e6,
-                          "speedup": t64 / t_steps,
-                          ("l2_rel_diff" if args.overint else "l2_rel_err"): err,
-                          "l2_norm": "max over fields of ||U - U_fp64||_M / ||U_fp64 - U_inf||_M",
-                          "steps_compared": args.warmup + args.steps},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
-                     "traffic": measured_traffic(config.get("p"), args.form)
-                     if args.workload == "cylinder20k" and not args.overint else None,
-                     "kernel": kernel, "avg_launch_us": t_launch * 1e6,
-                     "flops_per_launch": flops, "bytes_per_launch": nbytes,
-                     "hbm_achieved_GBs": nbytes / t_launch / 1e9,
-                     "hbm_frac": nbytes / t_launch / 1e9 / HBM_PEAK_GBS},
-    }
+            corders = [orders[0]] if (args.p is not None or args.quick or args.overint) else [4, 5, 6]
+            out["cpu_baseline"] = cpu_baseline(mg.workload("cylinder20k"), corders,
+                                               overint=args.overint)
     if args.copy_probe:
         # a plain copy kernel of known size: 512 MiB read + 512 MiB written per copy,
         # out of any cache, for scaling the FETCH_SIZE / WRITE_SIZE counters
@@ -662,11 +614,199 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = src.numel() * 8
         del src, dst
-    if cfl_info is not None:
-        out["cfl_time_step"] = cfl_info
-    if cpu is not None:
-        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def initial_state(wname, w, p):
+    """Seeded synthetic state of a single-mesh workload, (K, 4, Np) on the GPU."""
+    import numpy as np
+    import torch
+
+    import meshgen as mg
+    Np = (p + 1) * (p + 2) // 2
+    K = len(w["mesh"]["EToV"])
+    if wname == "periodic51k":
+        # smooth field: three seeded Fourier modes of amplitude 1e-2
+        sv = make_solver(w, p, w["mesh"], FORMS["fp64"])
+        x, y = sv.nodes()
+        sv.close()
+        U0n = mg.fourier_modes(x.T, y.T, mg.rng_for(3), L=10.0, amp=1e-2,
+                               q0=(1.0, 0.3, 0.0, 1.0 / w["gamma"]), gamma=w["gamma"])
+    else:
+        U0n = mg.noisy_free_stream((4, Np, K), w["U_inf"], mg.rng_for(1))
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(U0n, (2, 0, 1)))).cuda()
+
+
+def describe(wname, K, p, form):
+    Np = (p + 1) * (p + 2) // 2
+    if wname == "periodic51k":
+        return ("%s: periodic [0,10]^2, 160x160x2 -> K=%d triangles, p=%d (Np=%d), Re=100, "
+                "M=0.3, 3 seeded Fourier modes (amplitude 1e-2), %s form" % (wname, K, p, Np, form))
+    return ("%s: O-grid %s cells (ratio %s, r 0.5..30) -> K=%d triangles, p=%d (Np=%d), Re=100, "
+            "M=0.2, SIPG, free stream + 1e-3 seeded noise, %s form"
+            % (wname, "80x128" if wname == "cylinder20k" else "320x512",
+               "1.05" if wname == "cylinder20k" else "1.0125", K, p, Np, form))
+
+
+def measure(wname, p, form, steps, warmup, overint=False, compare_forms=False, cfl=False):
+    """One mesh and order: the chosen form and plain FP64 beside it from the
+    same state (warmup + steps LSERK steps with the wall force after each), the
+    stage kernel's launch time of each, the L2 difference, the roofline.
+    Returns {"line": the full bench record, "summary": its per-order digest}."""
+    import numpy as np
+    import torch
+
+    import meshgen as mg
+    w = mg.workload(wname, p)
+    Np = (p + 1) * (p + 2) // 2
+    K = len(w["mesh"]["EToV"])
+    U0 = initial_state(wname, w, p)
+    # SIPG with C1 = 1 on the 2.9e-3 wall layer at p = 4 is penalty-limited
+    # near 3e-7; 1e-7 keeps the impulsively started state bounded
+    dt = min(1e-7 if wname != "periodic51k" else 1.0, stable_dt(w["mesh"], p, w["mu"]) * 1.5)
+    log("%s p=%d form %s, warmup %d, steps %d" % (wname, p, form, warmup, steps))
+    U, t_steps, t_launch, s = run_single(w, U0, FORMS[form], steps, warmup, dt, overint=overint)
+    finite = bool(torch.isfinite(U).all().item())
+    if form != "fp64" or overint:
+        log("plain fp64 beside it")
+        U64, t64, tl64, s64 = run_single(w, U0, FORMS["fp64"], steps, warmup, dt)
+    else:
+        U64, t64, tl64, s64 = U, t_steps, t_launch, s
+    err = rel_l2([s64], [U], [U64], w["U_inf"])
+    dofs = 4 * Np * K
+    desc = describe(wname, K, p, form)
+    if overint:
+        desc = desc.replace("fp64 form", "fp64 form, over-integrated (degree-%d quadrature, %d "
+                            "element and %d face points)" % (3 * p, ((3 * p + 2) // 2) ** 2,
+                                                             3 * ((3 * p + 2) // 2)))
+    config = {"workload": desc, "K": K, "p": p, "dofs": dofs, "form": form, "dt": dt,
+              "finite": finite, "launch_shape": tuning_of(s), "launch_shape_fp64": tuning_of(s64)}
+    if compare_forms:
+        forms = {}
+        for name in FORMS:
+            if name in ("fp64", form):
+                continue
+            log("form %s" % name)
+            Uf, tf, tlf, sf = run_single(w, U0, FORMS[name], steps, warmup, dt)
+            forms[name] = {"value": dofs * 5 * steps / tf, "avg_launch_us": tlf * 1e6,
+                           "l2_rel_err": rel_l2([s64], [Uf], [U64], w["U_inf"])}
+            sf.close()
+        config["other_forms"] = forms
+    kernel = ("oi_stage_kernel<%d> (over-integrated, fp64)" % p if overint
+              else "stage_kernel<%d, %s>" % (p, form))
+    traffic = None if overint else measured_traffic(wname, p, form)
+    roof = roofline(Np, p + 1, K, t_launch, "fp64" if overint else form, traffic, overint)
+    roof["kernel"] = kernel
+    roof64 = roofline(Np, p + 1, K, tl64, "fp64", measured_traffic(wname, p, "fp64"))
+    value = dofs * 5 * steps / t_steps
+    cmp_key = "vs_nodal_fp64" if overint else "vs_plain_fp64"
+    cmp = {"value": dofs * 5 * steps / t64, "avg_launch_us": tl64 * 1e6, "speedup": t64 / t_steps,
+           ("l2_rel_diff" if overint else "l2_rel_err"): err,
+           "l2_norm": "max over fields of ||U - U_fp64||_M / ||U_fp64 - U_inf||_M",
+           "steps_compared": warmup + steps,
+           "roofline": {k: roof64[k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                "traffic", "frac_hbm", "frac_mfma_f64",
+                                                "frac_valu")}}
+    line = {
+        "metric": METRIC_OI if overint else METRIC,
+        "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": t_steps * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if form in ("fp32-pert", "bf16-ops") else "f64",
+        "data": "synthetic", "config": config, cmp_key: cmp, "roofline": roof,
+    }
+    if cfl:
+        # the CFL time step of Alg. 3 on the final state (outside the timed
+        # region): the bound's value and the cost of one call (two kernels and
+        # a synchronising read-back)
+        lam, _ = s.cfl_time_step(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            s.cfl_time_step(U)
+        line["cfl_time_step"] = {"Lambda": lam, "us_per_call": (time.perf_counter() - t0) / 20 * 1e6,
+                                 "note": "dg_cfl_time_step on the final state, C_grad = 1; not in "
+                                         "the timed steps"}
+    summary = {"workload": "%s p=%d" % (wname, p), "K": K, "dofs": dofs, "form": form,
+               "value": value, "ms_per_step": t_steps * 1e3 / steps,
+               "plain_fp64_value": cmp["value"], "speedup_vs_fp64": cmp["speedup"],
+               "l2_rel_err": err, "finite": finite,
+               "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                  "traffic", "kernel", "avg_launch_us", "frac_hbm",
+                                                  "frac_valu")},
+               "roofline_fp64": cmp["roofline"], "fp64_avg_launch_us": tl64 * 1e6,
+               "launch_shape": config["launch_shape"]}
+    s.close()
+    if s64 is not s:
+        s64.close()
+    del U, U64, U0
+    torch.cuda.empty_cache()
+    return {"line": line, "summary": summary}
+
+
+def viv_report(args, prec):
+    import numpy as np
+    import torch
+
+    import meshgen as mg
+    cases, phys = mg.viv_sweep_cases()
+    if args.p is not None:
+        for c in cases:
+            c["p"] = args.p
+    U_inf = phys["U_inf"]
+    states, dts, desc, nbytes, gemm, pw, dofs = [], [], [], 0.0, 0.0, 0.0, 0
+    for i, c in enumerate(cases):
+        Np = (c["p"] + 1) * (c["p"] + 2) // 2
+        K = len(c["mesh"]["EToV"])
+        U0 = mg.noisy_free_stream((4, Np, K), U_inf, mg.rng_for(2, salt=i + 1))
+        states.append(torch.from_numpy(np.ascontiguousarray(np.transpose(U0, (2, 0, 1)))).cuda())
+        dts.append(min(1e-7, stable_dt(c["mesh"], c["p"], phys["mu"])))
+        gemm += gemm_flops_per_element(Np, c["p"] + 1) * K
+        pw += pointwise_flops_per_element(Np, c["p"] + 1) * K
+        nbytes += algorithmic_bytes_per_element(Np) * K
+        dofs += 4 * Np * K
+        desc.append("%dx%d p%d" % (c["ntheta"], c["nr"], c["p"]))
+    dts = np.array(dts)
+    log("viv16 (%s): chosen form %s batched" % (", ".join(desc), args.form))
+    U, t_steps, t_launch, solvers, shape = run_viv(cases, phys, states, prec, args.steps,
+                                                   args.warmup, dts, batched=True)
+    log("plain fp64 beside it (one launch per stage and instance)")
+    U64, t64, _, solvers64, _ = run_viv(cases, phys, states, FORMS["fp64"], args.steps,
+                                        args.warmup, dts, batched=False)
+    finite = all(bool(torch.isfinite(u).all().item()) for u in U)
+    err = rel_l2(solvers64, U, U64, U_inf)
+    config = {"workload": "viv16: 16 elastically mounted cylinders (m*=10, xi=0, U* = "
+                          "linspace(3,8)), O-grids %s, total K=%d, Re=100, M=0.2, SIPG, "
+                          "coupled to host Newmark each step, batched (the stages of a "
+                          "step replayed from a HIP graph), %s form" % (
+                              ", ".join(desc), sum(s.K for s in solvers64), args.form),
+              "instances": len(cases), "dofs": dofs, "form": args.form,
+              "launch_shape": shape, "dt": [float(x) for x in dts], "finite": finite}
+    kernel = ("batch_stage_kernel<%s>" if shape.startswith("one launch per stage")
+              else "batch_order_kernel<p, %s> (one launch per order)") % args.form
+    mdt = MFMA_DTYPE[args.form]
+    t = {"hbm": nbytes / (HBM_PEAK_GBS * 1e9), "mfma": gemm / (MFMA_PEAK_TFLOPS[mdt] * 1e12),
+         "alu": pw / (VALU_PEAK_TFLOPS * 1e12)}
+    bound = max(t, key=t.get)
+    unit = {"hbm": "GB/s"}.get(bound, "TFLOP/s")
+    achieved = {"hbm": nbytes / t_launch / 1e9, "mfma": gemm / t_launch / 1e12,
+                "alu": pw / t_launch / 1e12}[bound]
+    peak = {"hbm": HBM_PEAK_GBS, "mfma": MFMA_PEAK_TFLOPS[mdt], "alu": VALU_PEAK_TFLOPS}[bound]
+    value = dofs * 5 * args.steps / t_steps
+    return {
+        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_steps * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.form in ("fp32-pert", "bf16-ops") else "f64", "data": "synthetic",
+        "config": config,
+        "vs_plain_fp64": {"value": dofs * 5 * args.steps / t64, "speedup": t64 / t_steps,
+                          "l2_rel_err": err,
+                          "l2_norm": "max over fields of ||U - U_fp64||_M / ||U_fp64 - U_inf||_M",
+                          "steps_compared": args.warmup + args.steps},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                     "avg_launch_us": t_launch * 1e6, "bytes_per_launch": nbytes,
+                     "frac_hbm": t["hbm"] / t_launch, "frac_valu": t["alu"] / t_launch},
+    }
 
 
 if __name__ == "__main__":

@@ -54,14 +54,21 @@ def term_scale(parts):
 
 
 def _check(got, want, tol=TOL, what="", terms=None):
+    """Per field: err <= tol max|R| (the relative bound), else <= 0.1 tol T_f
+    (the term-scale bound); prints err/max|R| and which bound held."""
+    report = []
     for f in range(4):
         scale = np.abs(want[f]).max()
         err = np.abs(got[f] - want[f]).max()
+        rel = err / scale if scale > 0 else (0.0 if err == 0 else np.inf)
+        branch = "rel" if err <= tol * scale else "terms"
         bound = tol * scale
         if terms is not None:
             bound = max(bound, 0.1 * tol * terms[f])
+        report.append("f%d %.2e(%s)" % (f, rel, branch))
         assert err <= bound, "%s field %d: err %.3e scale %.3e ratio %.3e" % (
             what, f, err, scale, err / scale)
+    print("[parity] %s err/max|R|: %s" % (what, " ".join(report)), flush=True)
 
 
 CASES = [

@@ -73,15 +73,20 @@ def pert_term_scale(dg, parts, vw):
 
 
 def _check(got, want, tol, terms, what):
+    """Per field: err <= tol max|R| (relative), else <= tol T'_f (term scale);
+    prints err/max|R| per field and which bound held."""
     worst = 0.0
+    report = []
     for f in range(4):
         scale = np.abs(want[f]).max()
         err = np.abs(got[f] - want[f]).max()
         bound = max(tol * scale, terms[f] * tol)
         worst = max(worst, err / bound)
+        report.append("f%d %.2e(%s)" % (f, err / scale if scale > 0 else 0.0,
+                                        "rel" if err <= tol * scale else "terms"))
         assert err <= bound, "%s field %d: err %.3e bound %.3e (max|R| %.3e, T' %.3e)" % (
             what, f, err, bound, scale, terms[f])
-    _say("%s: worst err/bound %.3f" % (what, worst))
+    _say("%s: worst err/bound %.3f; err/max|R| %s" % (what, worst, " ".join(report)))
 
 
 CASES = [
