@@ -176,6 +176,20 @@ int dg_rk_step(dg_ctx* ctx, double* U, double* K1, double dt, const double v_w[2
 int dg_rk_steps(dg_ctx* ctx, double* U, double* K1, int nsteps, double dt, const double v_w[2],
                 double* force_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dg_rk_steps
+ * with the same arguments and results (bitwise), whose stage ping-pong state
+ * and wall-force partials live in a static device array of 64 MiB per device
+ * instead of the context's set-up buffers.  It calls no hipMalloc, hipFree or
+ * allocating routine and no memset.  The state [K][4][Np] of doubles plus the
+ * force partials must fit the 64 MiB (K * Np up to about 2 million), else
+ * DG_EINVAL.  The context's device must be current.  Every call on a device
+ * shares that device's array (which keeps the last call's contents): calls
+ * that overlap on one device, on any streams, contexts or threads, race and
+ * must be serialised by the caller.  Asynchronous on `stream`. */
+int dg_rk_steps_noalloc(dg_ctx* ctx, double* U, double* K1, int nsteps, double dt,
+                        const double v_w[2], double* force_dev, void* stream);
+
 /* One RK stage: K1 <- a K1 + dt R(U_in); U_out <- U_in + b K1.  U_in and
  * U_out must not alias (neighbours read U_in).  Asynchronous. */
 int dg_rk_stage(dg_ctx* ctx, const double* U_in, double* U_out, double* K1,

@@ -44,6 +44,7 @@ SIGNATURES = {
     "dg_rhs": (_I, [_P, _P, _P, _DP, _P]),
     "dg_rk_step": (_I, [_P, _P, _P, _D, _DP, _P]),
     "dg_rk_steps": (_I, [_P, _P, _P, _I, _D, _DP, _P, _P]),
+    "dg_rk_steps_noalloc": (_I, [_P, _P, _P, _I, _D, _DP, _P, _P]),
     "dg_rk_stage": (_I, [_P, _P, _P, _P, _D, _D, _D, _DP, _P]),
     "dg_force": (_I, [_P, _P, _DP, _DP, _P]),
     "dg_force_device": (_I, [_P, _P, _DP, _P, _P]),
@@ -278,6 +279,14 @@ def dg_rk_steps(h, U, K1, nsteps, dt, v_w=(0.0, 0.0), force=None, stream=None):
     f = _dev(force, "f64", 3 * max(nsteps, 0), "force", optional=True)
     return _check(load().dg_rk_steps(h, _st(h, U, "U"), _st(h, K1, "K1"), nsteps, float(dt),
                                      _dp(vw), f, _stream(stream)), h)
+
+
+def dg_rk_steps_noalloc(h, U, K1, nsteps, dt, v_w=(0.0, 0.0), force=None, stream=None):
+    vw = _vw(v_w)
+    nsteps = int(nsteps)
+    f = _dev(force, "f64", 3 * max(nsteps, 0), "force", optional=True)
+    return _check(load().dg_rk_steps_noalloc(h, _st(h, U, "U"), _st(h, K1, "K1"), nsteps,
+                                             float(dt), _dp(vw), f, _stream(stream)), h)
 
 
 def dg_rk_stage(h, U_in, U_out, K1, a, b, dt, v_w=(0.0, 0.0), stream=None):

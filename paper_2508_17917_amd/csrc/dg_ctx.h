@@ -56,6 +56,7 @@ struct dg_ctx {
   unsigned* d_force_ticket = nullptr;
   double* d_cfl = nullptr;          // CFL work: 3K face maxima, 3K element maxima, result
   double* h_cfl = nullptr;          // pinned host word for the CFL result
+  double* noalloc_scratch = nullptr;  // this device's static scratch array (not owned)
   int force_blocks = 0;
   bool dev_ready = false;
   std::string err;
@@ -69,4 +70,8 @@ DeviceTables ctx_tables(const dg_ctx* c);
 // over-integrated FP64 stage)
 inline int ctx_form(const dg_ctx* c) { return c->overint ? kFormOverint : c->precision; }
 KernelPhysics ctx_phys(const dg_ctx* c, const double vw[2]);
+// noalloc.hip: device address of the static scratch array on the current
+// device (looked up once per device); its size in bytes
+int noalloc_scratch_address(double** out, std::string& err);
+size_t noalloc_scratch_bytes();
 }  // namespace dgmi

@@ -225,6 +225,13 @@ int dg_setup(dg_ctx* c) {
     return e == hipErrorOutOfMemory ? fail(c, DG_ENOMEM, "device allocation failed")
                                     : hip_fail(c, e, "hipMalloc");
   }
+  // the allocation-free entry point's static array on this device (a lookup,
+  // no allocation); left unset if the lookup fails, which that entry point
+  // then reports
+  {
+    std::string serr;
+    if (dgmi::noalloc_scratch_address(&c->noalloc_scratch, serr) != DG_OK) c->noalloc_scratch = nullptr;
+  }
   c->dev_ready = true;
   return DG_OK;
 }
