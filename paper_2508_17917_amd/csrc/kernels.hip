@@ -81,8 +81,7 @@ struct Order {
   static constexpr int H_SZ = 48 * HRS;          // face terms h | qr | qs
   static constexpr int X_SZ = N_SZ > H_SZ ? N_SZ : H_SZ;
   static constexpr int NORM_SZ = 4 * NF;
-  static constexpr int VN_SZ = 16 * NF;          // mean viscous normal flux per face node
-  static constexpr int WAVE_SZ = U_SZ + F_SZ + X_SZ + NORM_SZ + VN_SZ + 64 + 48;
+  static constexpr int WAVE_SZ = U_SZ + F_SZ + X_SZ + NORM_SZ + 64 + 48;
   // operator fragments (per workgroup)
   // one Dr-type / LIFT-type fragment set, in elements of T (bfloat16: four
   // values per lane, i.e. two floats' worth)
@@ -279,8 +278,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   T* sQr = sX + 16 * HRS;
   T* sQs = sX + 32 * HRS;
   T* sNorm = sX + O::X_SZ;
-  T* sVn = sNorm + O::NORM_SZ;      // [4 fields][4 NF]
-  T* sGeo = sVn + O::VN_SZ;         // [4][16]
+  T* sGeo = sNorm + O::NORM_SZ;     // [4][16]
   T* sNGeo = sGeo + 64;             // [4][3][4]
 
   Gas<T> gas;
@@ -448,14 +446,19 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     if (lane < nel * 12) sNGeo[lane] = (T)rng;
     wave_sync();
 
-    // ---- face nodes, pass 1: traces, ghosts, ||n^T G n||_2 on both sides and the
-    // mean viscous normal flux (one lane per face node)
-#pragma nounroll
-    for (int q = 0; q < FIT; ++q) {
-      const int it = lane + 64 * q;
-      int e = it / NF;
-      const int fn = it - e * NF;
-      const bool ok = (it < 4 * NF) && (e < nel);
+    // ---- face nodes, one lane each (the EPT elements' 3(p+1) face nodes fit
+    // the 64 lanes at every order built).  First half: traces, ghosts,
+    // ||n^T G n||_2 on both sides, the neighbour's gradient at the node and
+    // the mean viscous normal flux; the node's states and the viscous flux stay
+    // in registers across the one wave sync that G-bar_e (a maximum over the
+    // face's nodes) needs.  Second half: G-bar_e, sigma_e, Roe flux, penalty
+    // and theta term, written over the neighbour area (every read of it is
+    // done before the sync).
+    static_assert(FIT == 1, "the face nodes of a tile must fit one pass over the lanes");
+    {
+      int e = lane / NF;
+      const int fn = lane - e * NF;
+      const bool ok = (lane < EPT * NF) && (e < nel);
       e = e < 4 ? e : 3;
       const int f = fn / Nfp, j = fn - f * Nfp;
       const int n = face_node<N>(f, j);
@@ -473,12 +476,19 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           }
         }
       }
+      T up[4] = {T(0), T(0), T(0), T(0)}, uo[4] = {T(0), T(0), T(0), T(0)};
+      T vn[4] = {T(0), T(0), T(0), T(0)};
+      T nx = T(0), ny = T(0);
+      int tag = 0;
+      VState<T> sp = {}, so = {};
       if (ok) {
         const int conn = sConn[e * 3 + f];
-        const int tag = conn & 3, nf = (conn >> 2) & 3;
+        tag = conn & 3;
+        const int nf = (conn >> 2) & 3;
         const T* g = sGeo + e * kGeoStride;
-        const T nx = g[4 + 4 * f], ny = g[5 + 4 * f];
-        T up[4], uo[4], upf[4], uof[4];
+        nx = g[4 + 4 * f];
+        ny = g[5 + 4 * f];
+        T upf[4], uof[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) up[c] = sU[(ROWC * c + ROWE * e) * RS + n];
         full_state<T, PERT>(up, base, upf);
@@ -486,7 +496,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         const T* nbU = sX + (e * 3 + f) * S;
         ghost_state<T, PERT>(tag, up, upf, nbU + n2, Np, vwx, vwy, gas, base, uo);
         full_state<T, PERT>(uo, base, uof);
-        const VState<T> sp = vstate(gas, upf), so = vstate(gas, uof);
+        sp = vstate(gas, upf);
+        so = vstate(gas, uof);
         // one side at a time: the two evaluations need not be live together
         T nrm = T(0);
 #pragma nounroll
@@ -530,7 +541,6 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         // mean of G(U+) grad U+ and G(U-) grad U- inside; G(U^b) grad U+ on the
         // wall (grad U+ from the staged copy of the element itself); G(U+) grad U+
         // on the far field
-        T vn[4];
         if (tag == 1) {
           // adiabatic wall: stress and its work, no heat conduction
           viscous_normal_flux(gas_wall(gas), so, gxm, gym, nx, ny, vn);
@@ -543,47 +553,12 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
             for (int c = 0; c < 4; ++c) vn[c] = T(0.5) * (vn[c] + vm[c]);
           }
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) sVn[c * 4 * NF + e * NF + fn] = vn[c];  // field-major: consecutive lanes, consecutive banks
       }
-    }
-    wave_sync();
-    // ---- face nodes, pass 2: gather the other side's state (the only input
-    // that lives in the neighbour area), then, after every read of that area,
-    // the Roe flux, penalty and theta term, written over it as face terms
-    T fuo[FIT][4];
-#pragma unroll
-    for (int q = 0; q < FIT; ++q) {
-      const int it = lane + 64 * q;
-      const int e = it / NF;
-      const int fn = it - e * NF;
-      if ((it < 4 * NF) && (e < nel)) {
-        const int f = fn / Nfp, j = fn - f * Nfp;
-        const int n = face_node<N>(f, j);
-        const int conn = sConn[e * 3 + f];
-        const int tag = conn & 3, nf = (conn >> 2) & 3;
-        T up[4], upf[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) up[c] = sU[(ROWC * c + ROWE * e) * RS + n];
-        full_state<T, PERT>(up, base, upf);
-        const int n2 = face_node<N>(nf, Nfp - 1 - j);
-        ghost_state<T, PERT>(tag, up, upf, sX + (e * 3 + f) * S + n2, Np, vwx, vwy, gas, base,
-                             fuo[q]);
-      }
-    }
-    wave_sync();
-#pragma unroll
-    for (int q = 0; q < FIT; ++q) {
-      const int it = lane + 64 * q;
-      const int e = it / NF;
-      const int fn = it - e * NF;
-      if ((it < 4 * NF) && (e < nel)) {
-        const int f = fn / Nfp, j = fn - f * Nfp;
-        const int n = face_node<N>(f, j);
-        const int tag = sConn[e * 3 + f] & 3;
+      wave_sync();
+      if (ok) {
         const T* g = sGeo + e * kGeoStride;
-        const T nx = g[4 + 4 * f], ny = g[5 + 4 * f], fsc = g[6 + 4 * f];
-        // G-bar_e: largest norm over the face nodes of both sides (pass 1)
+        const T fsc = g[6 + 4 * f];
+        // G-bar_e: largest norm over the face nodes of both sides
         T gbar = T(0);
 #pragma unroll
         for (int jj = 0; jj < Nfp; ++jj) {
@@ -591,16 +566,10 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           gbar = v > gbar ? v : gbar;
         }
         const T sigma = g[7 + 4 * f] * gbar;
-        T up[4], vn[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          up[c] = sU[(ROWC * c + ROWE * e) * RS + n];
-          vn[c] = sVn[c * 4 * NF + e * NF + fn];
-        }
         const T vwn = vwx * nx + vwy * ny;
         T upf[4], uof[4];
         full_state<T, PERT>(up, base, upf);
-        full_state<T, PERT>(fuo[q], base, uof);
+        full_state<T, PERT>(uo, base, uof);
         const Prim<T> pp = prim_of<T, PERT>(upf, up, base, gas.gm1);
         T Fc[4];
         if (tag == 1) {
@@ -619,10 +588,10 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
             Fc[3] = pp.jp * vwn - (base.E + base.p) * q0n;
           }
         } else {
-          const Prim<T> po = prim_of<T, PERT>(uof, fuo[q], base, gas.gm1);
+          const Prim<T> po = prim_of<T, PERT>(uof, uo, base, gas.gm1);
           T FL[4], FR[4];
           normal_flux<T, PERT>(upf, up, pp, base, nx, ny, vwn, FL);
-          normal_flux<T, PERT>(uof, fuo[q], po, base, nx, ny, vwn, FR);
+          normal_flux<T, PERT>(uof, uo, po, base, nx, ny, vwn, FR);
           roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
         }
         T w[4];
@@ -632,11 +601,11 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
           const T fr = sFr[(ROWC * c + ROWE * e) * RS + n], fs = sFs[(ROWC * c + ROWE * e) * RS + n];
           const T own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
-          w[c] = up[c] - fuo[q][c];
+          w[c] = up[c] - uo[c];
           sH[(ROWC * c + ROWE * e) * HRS + fn] = own - fsc * (Fc[c] - vn[c] + sigma * w[c]);
         }
         T qx[4], qy[4];
-        viscous_transpose(tag == 1 ? gas_wall(gas) : gas, vstate(gas, tag == 1 ? uof : upf), nx, ny, w, qx, qy);
+        viscous_transpose(tag == 1 ? gas_wall(gas) : gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
         const T ce = theta * (tag == 0 ? T(0.5) : T(1)) * fsc;
         const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll
