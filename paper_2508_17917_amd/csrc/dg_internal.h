@@ -101,6 +101,10 @@ struct KernelPhysics {
   double gamma, Pr, mu, theta;
   double U_inf[4];
   double vw[2];
+  // derived once on the host (wave-uniform constants the kernels would
+  // otherwise divide out per lane): gamma - 1, 1/(gamma - 1), gamma/Pr, and
+  // the free stream's pressure and velocity
+  double gm1, igm1, k, p_inf, u_inf, v_inf;
 };
 
 // Launch shape of the stage kernel: waves (= elements / 4) per workgroup, 0

@@ -92,6 +92,13 @@ dgmi::KernelPhysics kphys(const dg_ctx* c, const double vw[2]) {
   for (int i = 0; i < 4; ++i) k.U_inf[i] = c->phys.U_inf[i];
   k.vw[0] = vw ? vw[0] : 0.0;
   k.vw[1] = vw ? vw[1] : 0.0;
+  k.gm1 = k.gamma - 1.0;
+  k.igm1 = 1.0 / (k.gamma - 1.0);
+  k.k = k.gamma / k.Pr;
+  k.u_inf = k.U_inf[1] / k.U_inf[0];
+  k.v_inf = k.U_inf[2] / k.U_inf[0];
+  const double ke = k.U_inf[1] * k.u_inf + k.U_inf[2] * k.v_inf;
+  k.p_inf = k.gm1 * (k.U_inf[3] - 0.5 * ke);
   return k;
 }
 

@@ -283,23 +283,20 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
 
   Gas<T> gas;
   gas.gamma = (T)ph.gamma;
-  gas.gm1 = (T)(ph.gamma - 1.0);
-  gas.igm1 = (T)(1.0 / (ph.gamma - 1.0));
+  gas.gm1 = (T)ph.gm1;
+  gas.igm1 = (T)ph.igm1;
   gas.mu = (T)ph.mu;
-  gas.k = (T)(ph.gamma / ph.Pr);
+  gas.k = (T)ph.k;
   const T theta = (T)ph.theta;
   const T vwx = (T)ph.vw[0], vwy = (T)ph.vw[1];
   Base<T> base;
-  {
-    const double r0 = ph.U_inf[0], ux0 = ph.U_inf[1] / r0, uy0 = ph.U_inf[2] / r0;
-    base.rho = (T)r0;
-    base.mx = (T)ph.U_inf[1];
-    base.my = (T)ph.U_inf[2];
-    base.E = (T)ph.U_inf[3];
-    base.p = (T)((ph.gamma - 1.0) * (ph.U_inf[3] - 0.5 * (ph.U_inf[1] * ux0 + ph.U_inf[2] * uy0)));
-    base.ux = (T)ux0;
-    base.uy = (T)uy0;
-  }
+  base.rho = (T)ph.U_inf[0];
+  base.mx = (T)ph.U_inf[1];
+  base.my = (T)ph.U_inf[2];
+  base.E = (T)ph.U_inf[3];
+  base.p = (T)ph.p_inf;
+  base.ux = (T)ph.u_inf;
+  base.uy = (T)ph.v_inf;
   const int64_t K = t.K;
 
   const int arow = lane & 15, acol = lane >> 4;  // A-operand row, k offset
@@ -322,22 +319,32 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
 
   // The global loads of a tile are software-pipelined: a tile's own states,
   // geometry and connectivity are issued at the end of the previous tile
-  // (before its final matrix-core phase), and its neighbour states before
-  // its volume phase, so that their latency overlaps computation.
+  // (after that tile's K1 / K0 loads, before its final matrix-core phase),
+  // and its neighbour states before its volume phase, so that their latency
+  // overlaps computation.  Every load is unconditional, its address clamped
+  // into the arrays (element K - 1, the block's last value, the tables' last
+  // entry) where the lane has nothing to load: with no control flow around
+  // the loads, the wait before each value's first use covers only the loads
+  // issued before it, not those issued ahead for later phases.  Values of
+  // clamped lanes are never stored.
   constexpr int NB1 = NQ == 1 ? 12 : 6;  // neighbour blocks issued before the volume phase
+  int vidx[NQ];                          // this lane's value within an element block
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) vidx[q] = lr_ok[q] ? lane + 64 * q : S - 1;
   double ru[4][NQ];
   double rg = 0.0;
   int rc = 0;
   auto load_own = [&](int64_t tl) {
     const int64_t b = tl * EPT;
-    const int ne = (int)((K - b) < EPT ? (K - b) : EPT);
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 4; ++e) {
+      const int64_t ke = (b + e) < K ? (b + e) : K - 1;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        ru[e][q] = (tl < tile_end && lr_ok[q] && e < ne) ? Uin[(b + e) * S + lane + 64 * q] : 0.0;
-    rg = (tl < tile_end && lane < ne * kGeoStride) ? t.geo[b * kGeoStride + lane] : 0.0;
-    rc = (tl < tile_end && lane < ne * 3) ? t.conn[b * 3 + lane] : 0;
+      for (int q = 0; q < NQ; ++q) ru[e][q] = Uin[ke * S + vidx[q]];
+    }
+    const int64_t gi = b * kGeoStride + lane, ci = b * 3 + lane;
+    rg = t.geo[gi < K * kGeoStride ? gi : K * kGeoStride - 1];
+    rc = t.conn[ci < K * 3 ? ci : K * 3 - 1];
   };
   load_own(tile0);
 
@@ -359,15 +366,18 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     // ---- neighbour states (a boundary face points at the element itself) and
     // metrics: the first NB1 blocks are issued now and stored after the volume
     // phase, the rest (high orders: bounded register use) after that
-    const double rng =
-        (lane < nel * 12) ? t.geo[(int64_t)(sConn[lane >> 2] >> 4) * kGeoStride + (lane & 3)] : 0.0;
+    // neighbour element of face slot i of the tile (slots beyond the tile's
+    // elements: its first element, a valid address whose data go unused)
+    auto nbr_elem = [&](int i) -> int64_t {
+      return i < 3 * nel ? (int64_t)(sConn[i < 12 ? i : 0] >> 4) : e0;
+    };
+    const double rng = t.geo[nbr_elem(lane >> 2) * kGeoStride + (lane & 3)];
     double rnb[NB1][NQ];
 #pragma unroll
     for (int bb = 0; bb < NB1; ++bb) {
-      const int64_t nb = (int64_t)(sConn[bb] >> 4) * S;  // bb uniform across the wave
+      const int64_t nb = nbr_elem(bb) * S;  // bb uniform across the wave
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        rnb[bb][q] = (lr_ok[q] && bb < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
+      for (int q = 0; q < NQ; ++q) rnb[bb][q] = Uin[nb + vidx[q]];
     }
 
     // ---- gradient on the matrix cores, then the volume flux per node
@@ -429,11 +439,9 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
       double rnb2[12 - NB1 > 0 ? 12 - NB1 : 1][NQ];
 #pragma unroll
       for (int bb = 0; bb < 12 - NB1; ++bb) {
-        const int ef = NB1 + bb;
-        const int64_t nb = (int64_t)(sConn[ef] >> 4) * S;
+        const int64_t nb = nbr_elem(NB1 + bb) * S;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          rnb2[bb][q] = (lr_ok[q] && ef < 3 * nel) ? Uin[nb + lane + 64 * q] : 0.0;
+        for (int q = 0; q < NQ; ++q) rnb2[bb][q] = Uin[nb + vidx[q]];
       }
 #pragma unroll
       for (int bb = 0; bb < 12 - NB1; ++bb) {
@@ -594,13 +602,20 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           normal_flux<T, PERT>(uof, uo, po, base, nx, ny, vwn, FR);
           roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
         }
+        // Fscale * own total normal flux from the contravariant flux:
+        // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
+        const T cfr = f == 0 ? T(0) : (f == 1 ? T(1) : T(-1));
+        const T cfs = f == 2 ? T(0) : (f == 1 ? T(1) : T(-1));
+        T fr[4], fs[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          fr[c] = sFr[(ROWC * c + ROWE * e) * RS + n];
+          fs[c] = sFs[(ROWC * c + ROWE * e) * RS + n];
+        }
         T w[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          // Fscale * own total normal flux from the contravariant flux:
-          // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
-          const T fr = sFr[(ROWC * c + ROWE * e) * RS + n], fs = sFs[(ROWC * c + ROWE * e) * RS + n];
-          const T own = (f == 0) ? -fs : (f == 1 ? fr + fs : -fr);
+          const T own = cfr * fr[c] + cfs * fs[c];
           w[c] = up[c] - uo[c];
           sH[(ROWC * c + ROWE * e) * HRS + fn] = own - fsc * (Fc[c] - vn[c] + sigma * w[c]);
         }
@@ -622,20 +637,26 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     wave_sync();
 
     // ---- divergence and lifts on the matrix cores, then the RK stage in FP64;
-    // the K1 (and, in the perturbation form, K0) loads, and those of the next
-    // tile's own data, are issued first so the matrix work covers their latency
-    load_own(tile + stride);
+    // the K1 (and, in the perturbation form, K0) loads, then those of the next
+    // tile's own data, are issued first so the matrix work covers their
+    // latency.  K1 is read only when the stage uses it (a != 0, not a bare
+    // right-hand side): otherwise the load reads the element's own state,
+    // which the tile has just brought into the cache, and is not used.
     double rk[NT][4], r0[NT][4];
+    {
+      const double* kp = (a != 0.0 && !rhs_only) ? (const double*)K1 : Uin;
+      const int64_t ke = (e0 + re) < K ? (e0 + re) : K - 1;
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      const int n = 16 * tt + rn;
-      const bool ok = !rhs_only && re < nel && n < Np;
+      for (int tt = 0; tt < NT; ++tt) {
+        const int n = 16 * tt + rn < Np ? 16 * tt + rn : Np - 1;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        rk[tt][c] = (ok && a != 0.0) ? K1[(e0 + re) * S + c * Np + n] : 0.0;
-        r0[tt][c] = (PERT && ok) ? Uin[(e0 + re) * S + c * Np + n] : 0.0;
+        for (int c = 0; c < 4; ++c) {
+          rk[tt][c] = kp[ke * S + c * Np + n];
+          r0[tt][c] = PERT ? Uin[ke * S + c * Np + n] : 0.0;
+        }
       }
     }
+    load_own(tile + stride);
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       V4 aD = {T(0), T(0), T(0), T(0)}, aL = {T(0), T(0), T(0), T(0)};
@@ -681,7 +702,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           if (rhs_only) {
             K1[idx] = R;
           } else {
-            const double k = (a == 0.0) ? dt * R : a * rk[tt][c] + dt * R;
+            const double k = (a != 0.0) ? a * rk[tt][c] + dt * R : dt * R;
             K1[idx] = k;
             const double u0 = PERT ? r0[tt][c] : (double)sU[(ROWC * c + ROWE * re) * RS + n];
             Uout[idx] = u0 + b * k;
@@ -692,16 +713,25 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   }
 }
 
-// Copy the operator fragments of order N into LDS and zero this workgroup's
-// wave areas (their pads are read as zeros by the matrix-core products).
+// Copy the operator fragments of order N into LDS and zero the pad columns
+// (nodes Np .. RS - 1) of the state and flux rows of this workgroup's wave
+// areas: the matrix-core products read them against zero operator entries,
+// so they must hold finite values, and no tile writes them.  (Rows of absent
+// elements only feed outputs that are never stored; the face-term pads are
+// zeroed per tile, since the neighbour states overwrite them.)
 template <int N, typename X, int W>
 __device__ __forceinline__ void stage_lds_init(const typename Real<X>::type* __restrict__ frag,
                                                typename Real<X>::type* sFrag,
                                                typename Real<X>::type* sWave) {
   typedef typename Real<X>::type T;
   using O = Order<N, X>;
+  constexpr int PAD = O::RS - O::Np;    // pad columns per row
+  constexpr int ROWS = 48;              // 16 state rows, then 32 flux rows
   for (int i = threadIdx.x; i < O::FRAG_SZ; i += 64 * W) sFrag[i] = frag[i];
-  for (int i = threadIdx.x; i < W * O::WAVE_SZ; i += 64 * W) sWave[i] = T(0);
+  for (int i = threadIdx.x; i < W * ROWS * PAD; i += 64 * W) {
+    const int w = i / (ROWS * PAD), r = (i / PAD) % ROWS, c = i % PAD;
+    sWave[w * O::WAVE_SZ + r * O::RS + O::Np + c] = T(0);
+  }
   __syncthreads();
 }
 
