@@ -65,6 +65,11 @@ struct Order {
   static constexpr int HRS = (BF && 16 * KF16 > 4 * KF ? 16 * KF16 : 4 * KF) + 1;
   static constexpr int EPT = elements_per_tile(N);  // elements per tile (4 slots)
   static constexpr int FIT = (EPT * NF + 63) / 64;  // face items per lane
+  // the volume flux in one pass over (element, node) pairs packed onto the
+  // lanes, where they fit 64 lanes but the matrix-core layout (16 node
+  // columns x 4 element slots per output tile) needs several tiles: p = 5
+  // (3 x 21 of 64 lanes in one pass instead of 63 of 128 in two)
+  static constexpr bool PACK = (EPT * Np <= 64) && (NT > 1);
   // default waves per workgroup (each wave owns its own tiles; the workgroup
   // shares the operator fragments)
   // (4 measured fastest for every order and form on MI355X: the fragments
@@ -267,6 +272,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   constexpr int Np = O::Np, Nfp = O::Nfp, NF = O::NF, S = O::S, NT = O::NT, KS = O::KS,
                 KF = O::KF, RS = O::RS, HRS = O::HRS, FIT = O::FIT, ROWC = O::ROWC,
                 ROWE = O::ROWE, EPT = O::EPT;
+  constexpr bool PACK = O::PACK;
   constexpr int OFF_DR = 0, OFF_DS = O::FD, OFF_L = 2 * O::FD, OFF_LR = 2 * O::FD + O::FL,
                 OFF_LS = 2 * O::FD + 2 * O::FL;
   const int lane = threadIdx.x & 63;
@@ -380,7 +386,28 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
       for (int q = 0; q < NQ; ++q) rnb[bb][q] = Uin[nb + vidx[q]];
     }
 
-    // ---- gradient on the matrix cores, then the volume flux per node
+    // ---- gradient on the matrix cores, then the volume flux per node:
+    // F = F_c - v_w (x) U - G grad U at node n of element slot e, stored as
+    // its contravariant components
+    auto volume_flux = [&](int e, int n, const T gx[4], const T gy[4], T rx, T ry, T sx, T sy) {
+      T u[4], uf[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) u[c] = sU[(ROWC * c + ROWE * e) * RS + n];
+      full_state<T, PERT>(u, base, uf);
+      T fvx[4], fvy[4];
+      const VState<T> st = vstate(gas, uf);
+      viscous_flux(gas, st, gx, gy, fvx, fvy);
+      const Prim<T> pr = prim_of<T, PERT>(uf, u, base, gas.gm1);
+      T Fx[4], Fy[4];
+      normal_flux<T, PERT>(uf, u, pr, base, T(1), T(0), vwx, Fx);
+      normal_flux<T, PERT>(uf, u, pr, base, T(0), T(1), vwy, Fy);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const T fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
+        sFr[(ROWC * c + ROWE * e) * RS + n] = rx * fx + ry * fy;
+        sFs[(ROWC * c + ROWE * e) * RS + n] = sx * fx + sy * fy;
+      }
+    };
     T gxk[NT][4], gyk[NT][4];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
@@ -410,24 +437,29 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         gxk[tt][c] = rx * aR[c] + sx * aS[c];
         gyk[tt][c] = ry * aR[c] + sy * aS[c];
       }
-      if (ok) {
-        T u[4], uf[4];
+      if (!PACK && ok) volume_flux(re, n, gxk[tt], gyk[tt], rx, ry, sx, sy);
+    }
+    if constexpr (PACK) {
+      // the tile's (element, node) pairs packed onto the lanes, one pass: the
+      // lane of pair (e, n) fetches that node's gradient from the lane of the
+      // matrix-core layout that holds it
+      const int e = lane / Np, n = lane - e * Np;
+      const int src = 16 * (e < 4 ? e : 3) + (n & 15);
+      T gx[4], gy[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) u[c] = sU[(ROWC * c + ROWE * re) * RS + n];
-        full_state<T, PERT>(u, base, uf);
-        T fvx[4], fvy[4];
-        const VState<T> st = vstate(gas, uf);
-        viscous_flux(gas, st, gxk[tt], gyk[tt], fvx, fvy);
-        const Prim<T> pr = prim_of<T, PERT>(uf, u, base, gas.gm1);
-        T Fx[4], Fy[4];
-        normal_flux<T, PERT>(uf, u, pr, base, T(1), T(0), vwx, Fx);
-        normal_flux<T, PERT>(uf, u, pr, base, T(0), T(1), vwy, Fy);
+      for (int tt = 0; tt < NT; ++tt) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const T fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
-          sFr[(ROWC * c + ROWE * re) * RS + n] = rx * fx + ry * fy;
-          sFs[(ROWC * c + ROWE * re) * RS + n] = sx * fx + sy * fy;
+          const T vx = lane_read(gxk[tt][c], src), vy = lane_read(gyk[tt][c], src);
+          if ((n >> 4) == tt) {
+            gx[c] = vx;
+            gy[c] = vy;
+          }
         }
+      }
+      if (e < nel) {
+        const T* g = sGeo + e * kGeoStride;
+        volume_flux(e, n, gx, gy, g[0], g[1], g[2], g[3]);
       }
     }
 #pragma unroll
