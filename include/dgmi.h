@@ -392,8 +392,9 @@ int dg_column_stats(const float* A, int64_t rows, int64_t ld, int cols, double* 
 int dg_closure_create(const dg_ctx* lo, const dg_ctx* hi, dg_closure** out);
 int dg_closure_sizes(const dg_closure* c, int* n_features, int* n_targets);
 /* Samples of every element into X (device FP32, row stride ldx >=
- * n_features) from an order-hi state (from_hi = 1, restricted) or an
- * order-lo state (from_hi = 0).  Asynchronous. */
+ * n_features) from an order-hi state (from_hi = 1, restricted), an order-lo
+ * state (from_hi = 0), or the free stream (from_hi = 2: the state columns
+ * zero, U unused and may be NULL).  Asynchronous. */
 int dg_closure_features(dg_closure* c, const double* U, int from_hi, float* X, int64_t ldx,
                         void* stream);
 /* Targets of every element from an order-hi state (T row stride >=
@@ -402,9 +403,28 @@ int dg_closure_targets(dg_closure* c, const double* U_hi, float* T, int64_t ldt,
 /* U_lo = Pi_lo U_hi, the order-lo state of an order-hi one (device
  * [K][4][Np_lo]).  Asynchronous. */
 int dg_closure_restrict(dg_closure* c, const double* U_hi, double* U_lo, void* stream);
-/* U_hi = I U_lo + Y (Y may be NULL: interpolation only).  Asynchronous. */
-int dg_closure_apply(dg_closure* c, const double* U_lo, const float* Y, int64_t ldy,
-                     double* U_hi, void* stream);
+/* U_hi = I U_lo + Y - Y0 (Y may be NULL: interpolation only; Y0, the
+ * network's output for the free-stream samples, may be NULL).  With Y0 the
+ * reconstruction of a free-stream element is exactly the interpolation.
+ * Asynchronous. */
+int dg_closure_apply(dg_closure* c, const double* U_lo, const float* Y, const float* Y0,
+                     int64_t ldy, double* U_hi, void* stream);
+/* The order-lo solve corrected toward the order-hi one (a learned m-step
+ * corrector, an extension not in the paper): every m steps of the order-lo
+ * solver, U_lo += net(x) - net(x0) with x the sample of U_lo and x0 the
+ * free stream's (so that a free-stream element is left alone, as both
+ * solvers leave it), the network trained on the
+ * drift of m order-lo steps from the restriction of an order-hi state,
+ * t = Pi_lo U_hi(t + m dt) - Phi_lo^m(Pi_lo U_hi(t)).  Rows of 4 Np_lo values
+ * (field-major, Np_lo nodes per field; n_features - 4 of dg_closure_sizes).
+ * dg_closure_drift_targets: T[k] = U_ref - U_lo per element (device order-lo
+ * states [K][4][Np_lo], FP64 difference rounded to FP32); dg_closure_correct:
+ * U_lo += Y - Y0 (device FP32 rows of one row stride ldy; Y0 may be NULL).
+ * Asynchronous. */
+int dg_closure_drift_targets(dg_closure* c, const double* U_ref, const double* U_lo, float* T,
+                             int64_t ldt, void* stream);
+int dg_closure_correct(dg_closure* c, const float* Y, const float* Y0, int64_t ldy, double* U_lo,
+                       void* stream);
 const char* dg_closure_last_error(const dg_closure* c);
 void dg_closure_destroy(dg_closure* c);
 

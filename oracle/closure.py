@@ -13,6 +13,12 @@ Closure protocol (a spec extension, not in the paper):
 * sample of element k: input x = [Pi_lo(U - U_inf) (Np_lo nodes x 4 fields,
   field-major), rx, ry, sx, sy], target t = U_hi - I Pi_lo U_hi
   (Np_hi x 4, field-major);
+* corrector of the order-lo solve: target t = Pi_lo U_hi(t + m dt) -
+  Phi_lo^m(Pi_lo U_hi(t)) (the drift of m order-lo steps from the restricted
+  state; Np_lo x 4, field-major), input the sample of the order-lo state
+  after those m steps; applied as U_lo + y(x) - y(x0) every m steps, x0 the
+  free stream's sample (state columns zero), and the reconstruction likewise
+  as I U_lo + y(x) - y(x0);
 * network: y = W3 g(W2 g(W1 x + b1) + b2) + b3 with the exact-erf GELU g,
   on normalised x and t (per-column mean and standard deviation), loss the
   mean of (y - t)^2 over samples and outputs, Adam with bias correction.
@@ -71,6 +77,26 @@ def apply_closure(U_lo, I, Y):
     K = U_lo.shape[2]
     Np_hi = I.shape[0]
     return np.einsum("mn,cnk->cmk", I, U_lo) + Y.reshape(K, 4, Np_hi).transpose(1, 2, 0)
+
+
+def drift_targets(U_ref, U):
+    """Corrector targets (K, 4 Np) field-major: U_ref - U per element (both
+    order-lo states (4, Np, K))."""
+    D = U_ref - U
+    return D.transpose(2, 0, 1).reshape(U.shape[2], -1)
+
+
+def free_features(geo, Np_lo):
+    """The free stream's samples (K x (4 Np_lo + 4)): no deviation, the
+    element's metrics."""
+    geo = np.asarray(geo)
+    return np.concatenate([np.zeros((geo.shape[0], 4 * Np_lo)), geo], axis=1)
+
+
+def apply_correction(U, Y):
+    """The order-lo state U + Y (Y: (K, 4 Np) field-major)."""
+    K, Np = U.shape[2], U.shape[1]
+    return U + Y.reshape(K, 4, Np).transpose(1, 2, 0)
 
 
 # ---------------------------------------------------------------- network

@@ -80,8 +80,10 @@ SIGNATURES = {
     "dg_closure_sizes": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "dg_closure_features": (_I, [_P, _P, _I, _P, _L, _P]),
     "dg_closure_targets": (_I, [_P, _P, _P, _L, _P]),
-    "dg_closure_apply": (_I, [_P, _P, _P, _L, _P, _P]),
+    "dg_closure_apply": (_I, [_P, _P, _P, _P, _L, _P, _P]),
     "dg_closure_restrict": (_I, [_P, _P, _P, _P]),
+    "dg_closure_drift_targets": (_I, [_P, _P, _P, _P, _L, _P]),
+    "dg_closure_correct": (_I, [_P, _P, _P, _L, _P, _P]),
     "dg_closure_last_error": (ctypes.c_char_p, [_P]),
     "dg_closure_destroy": (None, [_P]),
     "dg_last_error": (ctypes.c_char_p, [_P]),
@@ -586,10 +588,15 @@ def dg_closure_sizes(c):
 
 
 def dg_closure_features(c, U, X, from_hi, stream=None):
+    """from_hi: 1 an order-hi state (restricted), 0 an order-lo state, 2 the
+    free stream (U unused, may be None)."""
     K, s_lo, s_hi, nf, _ = _closure_sizes(c)
-    u = _dev(U, "f64", s_hi if from_hi else s_lo, "U")
+    mode = int(from_hi)
+    if mode not in (0, 1, 2):
+        raise ValueError("from_hi must be 0, 1 or 2")
+    u = None if mode == 2 else _dev(U, "f64", s_hi if mode == 1 else s_lo, "U")
     x, ldx = _rows(X, K, nf, "X")
-    return _ccheck(load().dg_closure_features(c, u, int(bool(from_hi)), x, ldx, _stream(stream)), c)
+    return _ccheck(load().dg_closure_features(c, u, mode, x, ldx, _stream(stream)), c)
 
 
 def dg_closure_targets(c, U_hi, T, stream=None):
@@ -605,11 +612,40 @@ def dg_closure_restrict(c, U_hi, U_lo, stream=None):
                                               _dev(U_lo, "f64", s_lo, "U_lo"), _stream(stream)), c)
 
 
-def dg_closure_apply(c, U_lo, Y, U_hi, stream=None):
+def _rows_like(Y0, ldy, K, n, what):
+    """Y0 with the same row stride as Y (or None)."""
+    if Y0 is None:
+        return None
+    y0, ld0 = _rows(Y0, K, n, what)
+    if ld0 != ldy:
+        raise ValueError("%s must have the row stride of Y" % what)
+    return y0
+
+
+def dg_closure_apply(c, U_lo, Y, U_hi, Y0=None, stream=None):
     K, s_lo, s_hi, _, nt = _closure_sizes(c)
     y, ldy = (None, 0) if Y is None else _rows(Y, K, nt, "Y")
-    return _ccheck(load().dg_closure_apply(c, _dev(U_lo, "f64", s_lo, "U_lo"), y, ldy,
+    if Y is None and Y0 is not None:
+        raise ValueError("Y0 needs Y")
+    y0 = _rows_like(Y0, ldy, K, nt, "Y0")
+    return _ccheck(load().dg_closure_apply(c, _dev(U_lo, "f64", s_lo, "U_lo"), y, y0, ldy,
                                            _dev(U_hi, "f64", s_hi, "U_hi"), _stream(stream)), c)
+
+
+def dg_closure_drift_targets(c, U_ref, U_lo, T, stream=None):
+    K, s_lo, _, nf, _ = _closure_sizes(c)
+    t, ldt = _rows(T, K, nf - 4, "T")
+    return _ccheck(load().dg_closure_drift_targets(c, _dev(U_ref, "f64", s_lo, "U_ref"),
+                                                   _dev(U_lo, "f64", s_lo, "U_lo"), t, ldt,
+                                                   _stream(stream)), c)
+
+
+def dg_closure_correct(c, Y, U_lo, Y0=None, stream=None):
+    K, s_lo, _, nf, _ = _closure_sizes(c)
+    y, ldy = _rows(Y, K, nf - 4, "Y")
+    y0 = _rows_like(Y0, ldy, K, nf - 4, "Y0")
+    return _ccheck(load().dg_closure_correct(c, y, y0, ldy, _dev(U_lo, "f64", s_lo, "U_lo"),
+                                             _stream(stream)), c)
 
 
 def dg_closure_last_error(c):

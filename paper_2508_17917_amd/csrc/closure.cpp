@@ -354,9 +354,11 @@ int dg_closure_sizes(const dg_closure* c, int* n_features, int* n_targets) {
 int dg_closure_features(dg_closure* c, const double* U, int from_hi, float* X, int64_t ldx,
                         void* stream) {
   if (!c) return DG_EINVAL;
-  if (!U || !X || ldx < c->n_features) return cfail(c, DG_EINVAL, "NULL array or stride too small");
+  if (from_hi < 0 || from_hi > 2) return cfail(c, DG_EINVAL, "from_hi must be 0, 1 or 2");
+  if ((!U && from_hi != 2) || !X || ldx < c->n_features)
+    return cfail(c, DG_EINVAL, "NULL array or stride too small");
   std::string err;
-  int rc = dgmi::closure_features(c->c, U, from_hi ? 1 : 0, X, ldx, stream, err);
+  int rc = dgmi::closure_features(c->c, U, from_hi, X, ldx, stream, err);
   return rc == 0 ? DG_OK : cfail(c, rc, err);
 }
 
@@ -376,13 +378,33 @@ int dg_closure_restrict(dg_closure* c, const double* U_hi, double* U_lo, void* s
   return rc == 0 ? DG_OK : cfail(c, rc, err);
 }
 
-int dg_closure_apply(dg_closure* c, const double* U_lo, const float* Y, int64_t ldy, double* U_hi,
-                     void* stream) {
+int dg_closure_apply(dg_closure* c, const double* U_lo, const float* Y, const float* Y0,
+                     int64_t ldy, double* U_hi, void* stream) {
   if (!c) return DG_EINVAL;
-  if (!U_lo || !U_hi || (Y && ldy < c->n_targets))
+  if (!U_lo || !U_hi || (Y && ldy < c->n_targets) || (Y0 && !Y))
     return cfail(c, DG_EINVAL, "NULL array or stride too small");
   std::string err;
-  int rc = dgmi::closure_apply(c->c, U_lo, Y, ldy, U_hi, stream, err);
+  int rc = dgmi::closure_apply(c->c, U_lo, Y, Y0, ldy, U_hi, stream, err);
+  return rc == 0 ? DG_OK : cfail(c, rc, err);
+}
+
+int dg_closure_drift_targets(dg_closure* c, const double* U_ref, const double* U_lo, float* T,
+                             int64_t ldt, void* stream) {
+  if (!c) return DG_EINVAL;
+  const int n = c->n_features - 4;
+  if (!U_ref || !U_lo || !T || ldt < n) return cfail(c, DG_EINVAL, "NULL array or stride too small");
+  std::string err;
+  int rc = dgmi::closure_drift(c->c, U_ref, U_lo, T, ldt, stream, err);
+  return rc == 0 ? DG_OK : cfail(c, rc, err);
+}
+
+int dg_closure_correct(dg_closure* c, const float* Y, const float* Y0, int64_t ldy, double* U_lo,
+                       void* stream) {
+  if (!c) return DG_EINVAL;
+  const int n = c->n_features - 4;
+  if (!Y || !U_lo || ldy < n) return cfail(c, DG_EINVAL, "NULL array or stride too small");
+  std::string err;
+  int rc = dgmi::closure_correct(c->c, Y, Y0, ldy, U_lo, stream, err);
   return rc == 0 ? DG_OK : cfail(c, rc, err);
 }
 

@@ -470,7 +470,10 @@ __global__ __launch_bounds__(kMapThreads) void closure_features_kernel(ClosureDe
   const int nl = c.np_lo, nh = c.np_hi;
   const double u0 = field_of(c.U_inf, f);
   float* x = X + k * ldx;
-  if (from_hi) {
+  if (from_hi == 2) {
+    // the free stream's sample: no deviation from U_inf
+    for (int m = 0; m < nl; ++m) x[f * nl + m] = 0.0f;
+  } else if (from_hi) {
     const double* u = U + (k * 4 + f) * nh;
     double* col = sv + threadIdx.x;
 #pragma unroll 8
@@ -532,7 +535,8 @@ __global__ __launch_bounds__(kMapThreads) void closure_restrict_kernel(ClosureDe
 }
 
 __global__ __launch_bounds__(kMapThreads) void closure_apply_kernel(ClosureDev c, const double* __restrict__ Ulo,
-                                                                    const float* __restrict__ Y, int64_t ldy,
+                                                                    const float* __restrict__ Y,
+                                                                    const float* __restrict__ Y0, int64_t ldy,
                                                                     double* __restrict__ Uhi) {
   __shared__ double sv[kMaxNodes * kMapThreads];
   const int64_t gid = (int64_t)blockIdx.x * kMapThreads + threadIdx.x;
@@ -547,7 +551,41 @@ __global__ __launch_bounds__(kMapThreads) void closure_apply_kernel(ClosureDev c
   for (int n = 0; n < nh; ++n) {
     double acc = 0.0;
     for (int m = 0; m < nl; ++m) acc += c.I[n * nl + m] * col[m * kMapThreads];
-    Uhi[(k * 4 + f) * nh + n] = acc + (Y ? (double)Y[k * ldy + f * nh + n] : 0.0);
+    const int64_t i = k * ldy + f * nh + n;
+    Uhi[(k * 4 + f) * nh + n] = acc + (Y ? (double)Y[i] - (Y0 ? (double)Y0[i] : 0.0) : 0.0);
+  }
+}
+
+// Drift samples of the order-lo corrector: T[k][f Np_lo + n] = U_ref - U at
+// node n of field f (one thread per element and field; FP64 difference,
+// rounded once to FP32).
+__global__ __launch_bounds__(kMapThreads) void closure_drift_kernel(ClosureDev c, const double* __restrict__ Uref,
+                                                                    const double* __restrict__ U,
+                                                                    float* __restrict__ T, int64_t ldt) {
+  const int64_t gid = (int64_t)blockIdx.x * kMapThreads + threadIdx.x;
+  const int64_t k = gid >> 2;
+  const int f = (int)(gid & 3);
+  if (k >= c.K) return;
+  const int nl = c.np_lo;
+  const double* a = Uref + (k * 4 + f) * nl;
+  const double* b = U + (k * 4 + f) * nl;
+  for (int n = 0; n < nl; ++n) T[k * ldt + f * nl + n] = (float)(a[n] - b[n]);
+}
+
+// The corrector's update of an order-lo state: U += Y - Y0 (rows as above;
+// Y0, the network's output for the free-stream sample, may be NULL).
+__global__ __launch_bounds__(kMapThreads) void closure_correct_kernel(ClosureDev c, const float* __restrict__ Y,
+                                                                      const float* __restrict__ Y0,
+                                                                      int64_t ldy, double* __restrict__ U) {
+  const int64_t gid = (int64_t)blockIdx.x * kMapThreads + threadIdx.x;
+  const int64_t k = gid >> 2;
+  const int f = (int)(gid & 3);
+  if (k >= c.K) return;
+  const int nl = c.np_lo;
+  double* u = U + (k * 4 + f) * nl;
+  for (int n = 0; n < nl; ++n) {
+    const int64_t i = k * ldy + f * nl + n;
+    u[n] += (double)Y[i] - (Y0 ? (double)Y0[i] : 0.0);
   }
 }
 
@@ -747,11 +785,25 @@ int closure_restrict(const ClosureDev& c, const double* Uhi, double* Ulo, void* 
   return lerr(err, "closure restrict kernel launch");
 }
 
-int closure_apply(const ClosureDev& c, const double* Ulo, const float* Y, int64_t ldy, double* Uhi,
-                  void* stream, std::string& err) {
+int closure_apply(const ClosureDev& c, const double* Ulo, const float* Y, const float* Y0,
+                  int64_t ldy, double* Uhi, void* stream, std::string& err) {
   hipLaunchKernelGGL(closure_apply_kernel, map_grid(c.K), dim3(kMapThreads), 0,
-                     (hipStream_t)stream, c, Ulo, Y, ldy, Uhi);
+                     (hipStream_t)stream, c, Ulo, Y, Y0, ldy, Uhi);
   return lerr(err, "closure apply kernel launch");
+}
+
+int closure_drift(const ClosureDev& c, const double* Uref, const double* U, float* T, int64_t ldt,
+                  void* stream, std::string& err) {
+  hipLaunchKernelGGL(closure_drift_kernel, map_grid(c.K), dim3(kMapThreads), 0,
+                     (hipStream_t)stream, c, Uref, U, T, ldt);
+  return lerr(err, "closure drift kernel launch");
+}
+
+int closure_correct(const ClosureDev& c, const float* Y, const float* Y0, int64_t ldy, double* U,
+                    void* stream, std::string& err) {
+  hipLaunchKernelGGL(closure_correct_kernel, map_grid(c.K), dim3(kMapThreads), 0,
+                     (hipStream_t)stream, c, Y, Y0, ldy, U);
+  return lerr(err, "closure correct kernel launch");
 }
 
 }  // namespace dgmi

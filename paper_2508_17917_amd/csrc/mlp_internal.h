@@ -69,7 +69,12 @@ int closure_targets(const ClosureDev& c, const double* U, float* T, int64_t ldt,
                     std::string& err);
 int closure_restrict(const ClosureDev& c, const double* Uhi, double* Ulo, void* stream,
                      std::string& err);
-int closure_apply(const ClosureDev& c, const double* Ulo, const float* Y, int64_t ldy, double* Uhi,
+int closure_apply(const ClosureDev& c, const double* Ulo, const float* Y, const float* Y0,
+                  int64_t ldy, double* Uhi, void* stream, std::string& err);
+// order-lo corrector: drift rows T = Uref - U, and U += Y - Y0
+int closure_drift(const ClosureDev& c, const double* Uref, const double* U, float* T, int64_t ldt,
                   void* stream, std::string& err);
+int closure_correct(const ClosureDev& c, const float* Y, const float* Y0, int64_t ldy, double* U,
+                    void* stream, std::string& err);
 
 }  // namespace dgmi

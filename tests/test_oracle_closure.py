@@ -122,3 +122,35 @@ def test_features_targets_apply_roundtrip():
     assert np.abs(C.apply_closure(Ulo, I, T) - U).max() < 1e-12
     assert np.abs(C.features(U, geo, Uinf, P) - C.features(Ulo, geo, Uinf)).max() < 1e-13
     assert C.features(Ulo, geo, Uinf).shape == (9, 28)
+
+
+def test_corrector_rows_round_trip_and_layout():
+    """The corrector's target rows and its update are inverse to each other,
+    and both use the samples' field-major layout (element k, field f, node n
+    at column f Np + n)."""
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((4, 6, 7))
+    U_ref = U + 1e-3 * rng.standard_normal(U.shape)
+    T = C.drift_targets(U_ref, U)
+    assert T.shape == (7, 24)
+    for k, f, n in ((0, 0, 0), (3, 2, 5), (6, 3, 1)):
+        assert T[k, f * 6 + n] == U_ref[f, n, k] - U[f, n, k]
+    assert np.abs(C.apply_correction(U, T) - U_ref).max() <= 1e-15
+    assert np.array_equal(C.drift_targets(U, U), np.zeros((7, 24)))
+    # the layout of the samples' state columns is the same
+    geo = rng.standard_normal((7, 4))
+    X = C.features(U + 1.0, geo, np.ones(4))
+    assert np.abs(X[:, :24] - C.drift_targets(U, np.zeros_like(U))).max() <= 1e-15
+
+
+def test_free_stream_sample_is_the_sample_of_the_free_stream():
+    """The free-stream sample equals the sample of a uniform U_inf state (order
+    lo directly, and order hi through the restriction, which keeps constants)."""
+    rng = np.random.default_rng(6)
+    U_inf = np.array([1.0, 0.2, 0.0, 1.8])
+    geo = rng.standard_normal((5, 4))
+    X0 = C.free_features(geo, 6)
+    lo_state = np.broadcast_to(U_inf[:, None, None], (4, 6, 5)).copy()
+    hi_state = np.broadcast_to(U_inf[:, None, None], (4, 15, 5)).copy()
+    assert np.abs(C.features(lo_state, geo, U_inf) - X0).max() == 0.0
+    assert np.abs(C.features(hi_state, geo, U_inf, C.restriction(4, 2)) - X0).max() < 1e-13
