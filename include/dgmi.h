@@ -79,6 +79,17 @@ typedef enum dg_penalty_mode {
   DG_PENALTY_STANDARD = 1
 } dg_penalty_mode;
 
+/* Viscous flux on the moving wall (Sec. 2.2.4).  The printed wall flux
+ * G(U^b) grad U+ (and G(U^b) in the wall's theta term) carries the
+ * interior's heat conduction through the wall, while the same section calls
+ * the wall adiabatic (Neumann conditions on pressure and temperature).
+ * DG_WALL_ADIABATIC (the default): the stress and its work, no conduction;
+ * DG_WALL_PRINTED: G(U^b) grad U+ as printed, with conduction. */
+typedef enum dg_wall_flux {
+  DG_WALL_ADIABATIC = 0,
+  DG_WALL_PRINTED = 1
+} dg_wall_flux;
+
 /* Create a context for polynomial order p (1 <= p <= 6) and a dg_precision mode.  *out receives the
  * context (owned by the caller, released with dg_destroy).  No GPU work. */
 int dg_create(int p, int precision, dg_ctx** out);
@@ -89,6 +100,12 @@ int dg_create(int p, int precision, dg_ctx** out);
  * ghost state on far-field faces).  Host only. */
 int dg_set_physics(dg_ctx* ctx, double gamma, double Pr, double mu, double theta,
                    int penalty_mode, double C_pen, const double U_inf[4]);
+
+/* The wall's viscous flux (a dg_wall_flux mode; default DG_WALL_ADIABATIC).
+ * Host only; any time after dg_create, taking effect at the next launch (a
+ * batch keeps the modes its contexts had at dg_batch_create); DG_EINVAL for
+ * another mode. */
+int dg_set_wall_flux(dg_ctx* ctx, int mode);
 
 /* Mesh T of straight-sided triangles (Sec. 2.2): Nv vertices (VX, VY host
  * arrays of length Nv), K triangles (EToV host array K*3, counter-clockwise

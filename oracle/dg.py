@@ -22,7 +22,8 @@ Readings (paper silent or garbled at these points):
   without its heat conduction, and the wall's theta term with G(U^b) likewise
   without conduction: the wall is adiabatic (Neumann conditions on pressure
   and temperature, Sec. 2.2.4), and the printed G(U^b) grad U+ would carry
-  the interior's conductive flux through it.
+  the interior's conductive flux through it.  The printed form, with
+  conduction, is kept as an option (Physics.wall_heat_flux).
 * grad U is the broken element gradient (no lifting operator).
 * G-bar_e = max over the face nodes of both sides (boundary: own trace and
   ghost) of ||N G N^T||_2; recomputed from the current state at every call.
@@ -59,8 +60,14 @@ LSERK_C = (0.0,
 
 
 class Physics:
+    """wall_heat_flux: False (default) the adiabatic wall reading -- the wall's
+    viscous flux and theta term without heat conduction; True the printed
+    wall flux G(U^b) grad U+ with the interior's conduction, and G(U^b) in
+    the theta term."""
+
     def __init__(self, gamma=1.4, Pr=0.72, mu=1e-3, theta=1.0, penalty_mode=PENALTY_PAPER,
-                 C_pen=0.01, U_inf=(1.0, 0.2, 0.0, 1.0 / (1.4 * 0.4) + 0.02)):
+                 C_pen=0.01, U_inf=(1.0, 0.2, 0.0, 1.0 / (1.4 * 0.4) + 0.02),
+                 wall_heat_flux=False):
         self.gamma = float(gamma)
         self.Pr = float(Pr)
         self.mu = float(mu)
@@ -68,6 +75,13 @@ class Physics:
         self.penalty_mode = int(penalty_mode)
         self.C_pen = float(C_pen)
         self.U_inf = np.asarray(U_inf, dtype=np.float64)
+        self.wall_heat_flux = bool(wall_heat_flux)
+
+    @property
+    def Pr_wall(self):
+        """The Prandtl number the wall faces' viscous terms use (infinite: no
+        conduction)."""
+        return self.Pr if self.wall_heat_flux else np.inf
 
 
 class DGOracle:
@@ -169,8 +183,9 @@ class DGOracle:
         # viscous normal flux (average of products inside, one-sided on the boundary)
         vxp, vyp = ph.viscous_flux(Up, fs['Uxp'], fs['Uyp'], p.mu, p.Pr, g)
         vxm, vym = ph.viscous_flux(Uo, fs['Uxm'], fs['Uym'], p.mu, p.Pr, g)
-        # adiabatic wall: the stress and its work, no heat conduction (Pr -> inf)
-        vxw, vyw = ph.viscous_flux(Uo, fs['Uxp'], fs['Uyp'], p.mu, np.inf, g)
+        # adiabatic wall: the stress and its work, no heat conduction (Pr -> inf);
+        # or the printed G(U^b) grad U+ with conduction
+        vxw, vyw = ph.viscous_flux(Uo, fs['Uxp'], fs['Uyp'], p.mu, p.Pr_wall, g)
         vn_int = 0.5 * ((vxp + vxm) * nx + (vyp + vym) * ny)
         vn_far = vxp * nx + vyp * ny
         vn_wall = vxw * nx + vyw * ny
@@ -186,7 +201,7 @@ class DGOracle:
         # theta term: c_e theta G(U*)^T (n (x) [U]), lifted with M^-1 D^T E
         Ustar = np.where(wall[None], Uo, Up)
         G = ph.g_matrix(Ustar, p.mu, p.Pr, g)                      # (3, Nfp, K, 8, 8)
-        G = np.where(wall[..., None, None], ph.g_matrix(Ustar, p.mu, np.inf, g), G)
+        G = np.where(wall[..., None, None], ph.g_matrix(Ustar, p.mu, p.Pr_wall, g), G)
         nvec = np.concatenate([np.moveaxis(jump, 0, -1) * m.nx[:, None, :, None],
                                np.moveaxis(jump, 0, -1) * m.ny[:, None, :, None]], axis=-1)
         q = np.einsum('...ji,...j->...i', G, nvec)                 # G^T (n (x) [U])

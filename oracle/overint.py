@@ -151,7 +151,7 @@ class DGOracleOI(DGOracle):
         # viscous normal flux
         vxp, vyp = ph.viscous_flux(Up, Uxp, Uyp, p.mu, p.Pr, g)
         vxm, vym = ph.viscous_flux(Uo, Uxm, Uym, p.mu, p.Pr, g)
-        vxw, vyw = ph.viscous_flux(Uo, Uxp, Uyp, p.mu, np.inf, g)    # adiabatic wall
+        vxw, vyw = ph.viscous_flux(Uo, Uxp, Uyp, p.mu, p.Pr_wall, g)    # wall (adiabatic by default)
         vn = np.where(interior[None], 0.5 * ((vxp + vxm) * nx + (vyp + vym) * ny),
                       np.where(wall[None], vxw * nx + vyw * ny, vxp * nx + vyp * ny))
         # penalty: G-bar_e over the face's quadrature points, both sides
@@ -170,7 +170,7 @@ class DGOracleOI(DGOracle):
         # theta term: c_e theta G(U*)^T (n (x) [U]) against grad l_i
         Ustar = np.where(wall[None], Uo, Up)
         G = ph.g_matrix(Ustar, p.mu, p.Pr, g)
-        G = np.where(wall[..., None, None], ph.g_matrix(Ustar, p.mu, np.inf, g), G)
+        G = np.where(wall[..., None, None], ph.g_matrix(Ustar, p.mu, p.Pr_wall, g), G)
         nvec = np.concatenate([np.moveaxis(jump, 0, -1) * m.nx[:, None, :, None],
                                np.moveaxis(jump, 0, -1) * m.ny[:, None, :, None]], axis=-1)
         qv = np.einsum("...ji,...j->...i", G, nvec)

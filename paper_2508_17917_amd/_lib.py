@@ -18,6 +18,7 @@ DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EMESH, DG_EUNSUPPORTED, DG_ENONFINITE, 
     0, -1, -2, -3, -4, -5, -6, -7
 DG_FP64, DG_FP64_PERT, DG_FP32_PERT, DG_FP32_PERT_BF16OPS = 0, 1, 2, 3
 DG_PENALTY_PAPER, DG_PENALTY_STANDARD = 0, 1
+DG_WALL_ADIABATIC, DG_WALL_PRINTED = 0, 1
 
 STATUS_NAMES = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_EMESH",
                 -5: "DG_EUNSUPPORTED", -6: "DG_ENONFINITE", -7: "DG_ESTATE"}
@@ -31,6 +32,7 @@ _DP = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "dg_create": (_I, [_I, _I, ctypes.POINTER(_P)]),
     "dg_set_physics": (_I, [_P, _D, _D, _D, _D, _I, _D, _DP]),
+    "dg_set_wall_flux": (_I, [_P, _I]),
     "dg_set_mesh": (_I, [_P, _L, _DP, _DP, _L, ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int8), _DP]),
     "dg_setup_host": (_I, [_P]),
@@ -217,6 +219,10 @@ def dg_create(p, precision=DG_FP64):
 def dg_set_physics(h, gamma, Pr, mu, theta, penalty_mode, C_pen, U_inf):
     u = np.ascontiguousarray(np.asarray(U_inf, dtype=np.float64))
     return _check(load().dg_set_physics(h, gamma, Pr, mu, theta, int(penalty_mode), C_pen, _dp(u)), h)
+
+
+def dg_set_wall_flux(h, mode):
+    return _check(load().dg_set_wall_flux(h, int(mode)), h)
 
 
 def dg_set_mesh(h, VX, VY, EToV, face_tag=None, period=(0.0, 0.0)):

@@ -50,6 +50,7 @@ struct Physics {
   int penalty_mode = 0;
   double C_pen = 0.01;
   double U_inf[4] = {1.0, 0.0, 0.0, 1.0};
+  int wall_flux = 0;  // dg_wall_flux
 };
 
 // Mesh tables built on the host.
@@ -105,6 +106,9 @@ struct KernelPhysics {
   // otherwise divide out per lane): gamma - 1, 1/(gamma - 1), gamma/Pr, and
   // the free stream's pressure and velocity
   double gm1, igm1, k, p_inf, u_inf, v_inf;
+  // conduction on wall faces: 0 (adiabatic wall, the default) or gamma/Pr
+  // (the printed wall flux)
+  double k_wall;
 };
 
 // Launch shape of the stage kernel: waves (= elements / 4) per workgroup, 0

@@ -26,14 +26,15 @@ struct Gas {
   T gamma, gm1, igm1, mu, k;  // igm1 = 1/(gamma-1), k = gamma / Pr
 };
 
-// The gas as seen by the viscous terms of an adiabatic wall face (Sec.
-// 2.2.4: Neumann conditions on pressure and temperature there): the same
-// stress, no heat conduction (k = gamma / Pr taken as 0), so that neither
-// the wall's viscous flux nor its theta term carries heat through the wall.
+// The gas as seen by the viscous terms of a wall face: the same stress, and
+// the conduction k_wall -- 0 for the adiabatic wall (Sec. 2.2.4: Neumann
+// conditions on pressure and temperature there), so that neither the wall's
+// viscous flux nor its theta term carries heat through the wall; gamma / Pr
+// for the printed wall flux G(U^b) grad U+.
 template <typename T>
-__device__ __forceinline__ Gas<T> gas_wall(const Gas<T>& g) {
+__device__ __forceinline__ Gas<T> gas_wall(const Gas<T>& g, T k_wall) {
   Gas<T> w = g;
-  w.k = T(0);
+  w.k = k_wall;
   return w;
 }
 

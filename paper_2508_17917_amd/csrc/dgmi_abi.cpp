@@ -99,6 +99,7 @@ dgmi::KernelPhysics kphys(const dg_ctx* c, const double vw[2]) {
   k.v_inf = k.U_inf[2] / k.U_inf[0];
   const double ke = k.U_inf[1] * k.u_inf + k.U_inf[2] * k.v_inf;
   k.p_inf = k.gm1 * (k.U_inf[3] - 0.5 * ke);
+  k.k_wall = c->phys.wall_flux == DG_WALL_PRINTED ? k.k : 0.0;
   return k;
 }
 
@@ -151,6 +152,14 @@ int dg_set_physics(dg_ctx* c, double gamma, double Pr, double mu, double theta, 
   for (int i = 0; i < 4; ++i) c->phys.U_inf[i] = U_inf[i];
   c->have_phys = true;
   c->host_ready = false;
+  return DG_OK;
+}
+
+int dg_set_wall_flux(dg_ctx* c, int mode) {
+  if (!c) return DG_EINVAL;
+  if (mode != DG_WALL_ADIABATIC && mode != DG_WALL_PRINTED)
+    return fail(c, DG_EINVAL, "wall flux mode must be DG_WALL_ADIABATIC or DG_WALL_PRINTED");
+  c->phys.wall_flux = mode;
   return DG_OK;
 }
 

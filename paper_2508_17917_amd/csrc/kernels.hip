@@ -294,6 +294,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   gas.mu = (T)ph.mu;
   gas.k = (T)ph.k;
   const T theta = (T)ph.theta;
+  const T k_wall = (T)ph.k_wall;
   const T vwx = (T)ph.vw[0], vwy = (T)ph.vw[1];
   Base<T> base;
   base.rho = (T)ph.U_inf[0];
@@ -583,7 +584,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         // on the far field
         if (tag == 1) {
           // adiabatic wall: stress and its work, no heat conduction
-          viscous_normal_flux(gas_wall(gas), so, gxm, gym, nx, ny, vn);
+          viscous_normal_flux(gas_wall(gas, k_wall), so, gxm, gym, nx, ny, vn);
         } else {
           viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
           if (tag == 0) {
@@ -652,7 +653,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           sH[(ROWC * c + ROWE * e) * HRS + fn] = own - fsc * (Fc[c] - vn[c] + sigma * w[c]);
         }
         T qx[4], qy[4];
-        viscous_transpose(tag == 1 ? gas_wall(gas) : gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
+        viscous_transpose(tag == 1 ? gas_wall(gas, k_wall) : gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
         const T ce = theta * (tag == 0 ? T(0.5) : T(1)) * fsc;
         const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll
@@ -872,6 +873,7 @@ __device__ __forceinline__ void oi_tiles(const DeviceTables& t, const KernelPhys
   gas.mu = ph.mu;
   gas.k = ph.gamma / ph.Pr;
   const T theta = ph.theta, vwx = ph.vw[0], vwy = ph.vw[1];
+  const T k_wall = ph.k_wall;
   Base<T> base;
   {
     const double r0 = ph.U_inf[0], ux0 = ph.U_inf[1] / r0, uy0 = ph.U_inf[2] / r0;
@@ -1053,7 +1055,7 @@ __device__ __forceinline__ void oi_tiles(const DeviceTables& t, const KernelPhys
       T vn[4];
       if (tag == 1) {
         // adiabatic wall: stress and its work, no heat conduction
-        viscous_normal_flux(gas_wall(gas), so, gxp, gyp, nx, ny, vn);
+        viscous_normal_flux(gas_wall(gas, k_wall), so, gxp, gyp, nx, ny, vn);
       } else {
         viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
         if (tag == 0) {
@@ -1099,7 +1101,7 @@ __device__ __forceinline__ void oi_tiles(const DeviceTables& t, const KernelPhys
         sH[(ROWC * c + ROWE * e) * GRS + fg] = -fsc * (Fc[c] - sVn[c * 4 * NG + e * NG + fg] + sigma * w[c]);
       }
       T qx[4], qy[4];
-      viscous_transpose(tag == 1 ? gas_wall(gas) : gas, vstate(gas, tag == 1 ? uo : up), nx, ny, w, qx, qy);
+      viscous_transpose(tag == 1 ? gas_wall(gas, k_wall) : gas, vstate(gas, tag == 1 ? uo : up), nx, ny, w, qx, qy);
       const T ce = theta * (tag == 0 ? 0.5 : 1.0) * fsc;
       const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
 #pragma unroll

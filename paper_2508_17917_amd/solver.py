@@ -11,7 +11,7 @@ from . import _lib as L
 class Solver:
     def __init__(self, p, mesh, gamma=1.4, Pr=0.72, mu=0.0, theta=1.0, penalty_mode=0, C_pen=0.01,
                  U_inf=(1.0, 0.0, 0.0, 1.0), device=True, precision=L.DG_FP64,
-                 overintegration=False):
+                 overintegration=False, wall_flux=L.DG_WALL_ADIABATIC):
         self.p = int(p)
         self.precision = int(precision)
         self.h = L.dg_create(self.p, self.precision)
@@ -19,6 +19,7 @@ class Solver:
             if overintegration:
                 L.dg_set_overintegration(self.h, True)
             L.dg_set_physics(self.h, gamma, Pr, mu, theta, penalty_mode, C_pen, U_inf)
+            L.dg_set_wall_flux(self.h, wall_flux)
             L.dg_set_mesh(self.h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh.get("face_tag"),
                           mesh.get("period", (0.0, 0.0)))
             if device:
@@ -56,6 +57,12 @@ class Solver:
     def set_overintegration(self, on):
         """Switch the quadrature-based (degree-3p) evaluation on or off."""
         L.dg_set_overintegration(self.h, on)
+
+    def set_wall_flux(self, mode):
+        """Wall viscous flux: DG_WALL_ADIABATIC (no conduction through the
+        wall) or DG_WALL_PRINTED (G(U^b) grad U+ with the interior's
+        conduction); takes effect at the next call."""
+        L.dg_set_wall_flux(self.h, mode)
 
     # -- device calls
     def empty_state(self):

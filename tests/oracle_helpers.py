@@ -16,14 +16,14 @@ def ref_element(p):
 
 
 def build(mesh, p, gamma=1.4, Pr=0.72, mu=2e-3, theta=1.0, penalty_mode=0, C_pen=0.01,
-          U_inf=None, face_tag=None):
+          U_inf=None, face_tag=None, wall_heat_flux=False):
     ref = ref_element(p)
     ft = mesh["face_tag"] if face_tag is None else face_tag
     m = Mesh(ref, mesh["VX"], mesh["VY"], mesh["EToV"], ft, mesh["period"])
     if U_inf is None:
         U_inf = mg.free_stream(0.2, gamma)
     phys = Physics(gamma=gamma, Pr=Pr, mu=mu, theta=theta, penalty_mode=penalty_mode,
-                   C_pen=C_pen, U_inf=U_inf)
+                   C_pen=C_pen, U_inf=U_inf, wall_heat_flux=wall_heat_flux)
     return DGOracle(m, phys)
 
 

@@ -118,6 +118,13 @@ def test_error_codes():
             L.dg_set_physics(h, 0.9, 0.72, 1e-3, 1.0, 0, 0.01, [1, 0, 0, 1])
         assert e.value.code == L.DG_EINVAL
         L.dg_set_physics(h, 1.4, 0.72, 1e-3, 1.0, 0, 0.01, [1, 0, 0, 1.8])
+        for bad in (-1, 2):
+            with pytest.raises(L.DGError) as e:
+                L.dg_set_wall_flux(h, bad)
+            assert e.value.code == L.DG_EINVAL and "wall flux" in str(e.value)
+        L.dg_set_wall_flux(h, L.DG_WALL_PRINTED)
+        L.dg_set_wall_flux(h, L.DG_WALL_ADIABATIC)
+        assert L.load().dg_set_wall_flux(None, 0) == L.DG_EINVAL
         mesh = mg.periodic_square(3, 3, 1.0, 1.0)
         # clockwise element
         E = mesh["EToV"].copy()
