@@ -109,9 +109,18 @@ class CylinderRun:
     force history (coefficients recorded every `record_every` steps)."""
 
     def __init__(self, mesh, p, phys, U0, precision=L.DG_FP32_PERT, C_cfl=8.0, C_grad=1.0,
-                 cfl_every=2000, record_every=10, overint=False):
+                 cfl_every=2000, record_every=10, overint=False, kick=None):
         import torch
         self.phys = phys
+        # everything a checkpoint must agree on to be resumed by this run
+        self.settings = dict(precision=int(precision), overint=bool(overint), C_cfl=float(C_cfl),
+                             C_grad=float(C_grad), cfl_every=int(cfl_every),
+                             record_every=int(record_every),
+                             kick=None if kick is None else float(kick),
+                             gamma=float(phys["gamma"]), Pr=float(phys["Pr"]),
+                             mu=float(phys["mu"]), theta=float(phys["theta"]),
+                             penalty_mode=int(phys["penalty_mode"]), C_pen=float(phys["C_pen"]),
+                             U_inf=[float(v) for v in phys["U_inf"]])
         self.s = Solver(p, mesh, gamma=phys["gamma"], Pr=phys["Pr"], mu=phys["mu"],
                         theta=phys["theta"], penalty_mode=phys["penalty_mode"], C_pen=phys["C_pen"],
                         U_inf=phys["U_inf"], precision=precision, overintegration=overint)
@@ -133,9 +142,8 @@ class CylinderRun:
         that many seconds of wall time have passed: see `done`); False if the
         state stopped being finite."""
         import torch
-        t_end = t_end_conv / self.vel
         t0 = time.time()
-        while self.t < t_end:
+        while not self.done(t_end_conv):
             if max_wall is not None and time.time() - t0 > max_wall:
                 break
             _, dt = self.s.cfl_time_step(self.U, C_cfl=self.C_cfl, C_grad=self.C_grad)
@@ -160,28 +168,40 @@ class CylinderRun:
         return True
 
     def done(self, t_end_conv):
-        return self.t * self.vel >= t_end_conv
+        """The stepping loop's own end condition."""
+        return not (self.t < t_end_conv / self.vel)
 
     def series(self):
         return np.concatenate(self.t_rec), np.concatenate(self.CD), np.concatenate(self.CL)
 
-    def save(self, path):
-        """Checkpoint: the state, the clock, the step count and the recorded
-        series (the CFL step is recomputed from the state, so a resumed run
-        takes the same steps as an uninterrupted one)."""
+    def save(self, path, wall_s=0.0):
+        """Checkpoint: the state, the clock, the step count, the recorded
+        series, the run's settings and the wall time spent so far (the CFL
+        step is recomputed from the state, so a resumed run takes the same
+        steps as an uninterrupted one)."""
+        import json
         t, cd, cl = self.series() if self.t_rec else (np.zeros(0), np.zeros(0), np.zeros(0))
         np.savez(path, U=self.U.cpu().numpy(), p=self.p, K=self.s.K, t=self.t, steps=self.steps,
-                 t_rec=t, CD=cd, CL=cl, dts=np.asarray(self.dts, dtype=np.float64))
+                 t_rec=t, CD=cd, CL=cl, dts=np.asarray(self.dts, dtype=np.float64),
+                 settings=json.dumps(self.settings, sort_keys=True), wall_s=float(wall_s))
 
     def load(self, path):
+        """Resume from a checkpoint of this order, mesh and settings (else
+        ValueError); returns the wall time the checkpointed segments took."""
+        import json
         import torch
         z = np.load(path)
         if int(z["p"]) != self.p or int(z["K"]) != self.s.K or z["U"].shape != tuple(self.U.shape):
             raise ValueError("checkpoint of another order or mesh")
+        if "settings" not in z.files or json.loads(str(z["settings"])) != json.loads(
+                json.dumps(self.settings, sort_keys=True)):
+            raise ValueError("checkpoint taken with other settings (form, physics, CFL or "
+                             "initial kick) than this run's")
         self.U.copy_(torch.from_numpy(z["U"]))
         self.t, self.steps = float(z["t"]), int(z["steps"])
         self.t_rec, self.CD, self.CL = [z["t_rec"]], [z["CD"]], [z["CL"]]
         self.dts = [float(d) for d in z["dts"]]
+        return float(z["wall_s"])
 
     def summary(self, t0, t1):
         t, cd, cl = self.series()
@@ -293,22 +313,27 @@ def cylinder_study(mesh, phys, ps, t_end, t0, t1, precision=L.DG_FP32_PERT, C_cf
         x, y = s0.nodes()
         s0.close()
         U0 = np.transpose(mg.wake_kick(x, y, phys["U_inf"], amp=kick, gamma=phys["gamma"]), (1, 0, 2))
-        run = CylinderRun(mesh, p, phys, U0, precision, C_cfl, C_grad, overint=overint)
+        run = CylinderRun(mesh, p, phys, U0, precision, C_cfl, C_grad, overint=overint, kick=kick)
         ck = None if checkpoint is None else "%s_p%d.npz" % (checkpoint, p)
+        wall_before = 0.0
         if ck is not None and os.path.exists(ck):
-            run.load(ck)
+            wall_before = run.load(ck)
             if log is not None:
                 log("p=%d resumed from %s at t*=%.2f" % (p, ck, run.t * run.vel))
         w0 = time.time()
         ok = run.advance(t_end, log, max_wall)
-        wall = time.time() - w0
+        # wall time of every segment of the run, so the rate covers all its steps
+        wall = wall_before + (time.time() - w0)
         if not ok:
             rows.append(dict(p=p, finite=False, steps=run.steps))
             run.close()
             continue
         if not run.done(t_end):
-            # wall-time limit reached: keep the checkpoint, report progress
-            run.save(ck)
+            # wall-time limit reached (the loop ends early only then): keep the
+            # checkpoint, report progress
+            if ck is None:
+                raise RuntimeError("run stopped before t* = %g without a checkpoint path" % t_end)
+            run.save(ck, wall)
             rows.append(dict(p=p, finite=True, complete=False, steps=run.steps,
                              t=run.t * run.vel, checkpoint=ck))
             run.close()

@@ -116,3 +116,57 @@ def test_edge_resampling_is_exact_for_the_edge_polynomials():
     assert np.allclose(got, want, rtol=1e-9, atol=1e-9)
     # and linear resampling would not be
     assert not np.allclose(np.interp(xs, x, w), want, rtol=1e-6, atol=1e-6)
+
+
+def _fake_run(p=3, K=12, Np=10, **over):
+    """A CylinderRun without a solver or GPU: the attributes that done(),
+    save() and load() use, on host tensors."""
+    import types
+
+    import torch
+    from paper_2508_17917_amd.studies import CylinderRun
+    run = object.__new__(CylinderRun)
+    run.p, run.vel = p, 0.1
+    run.s = types.SimpleNamespace(K=K, Np=Np)
+    run.U = torch.arange(K * 4 * Np, dtype=torch.float64).reshape(K, 4, Np)
+    run.t, run.steps = 0.0, 0
+    run.t_rec, run.CD, run.CL, run.dts = [], [], [], []
+    run.settings = dict(precision=2, overint=False, C_cfl=16.0, C_grad=1.0, cfl_every=2000,
+                        record_every=10, kick=0.1, gamma=1.4, Pr=0.72, mu=5e-4, theta=0.0,
+                        penalty_mode=0, C_pen=0.01, U_inf=[1.0, 0.1, 0.0, 1.8])
+    run.settings.update(over)
+    return run
+
+
+def test_done_is_the_stepping_loops_condition():
+    """done() is exactly the loop's `t < t_end / vel` test, also on a
+    rounding edge where t * vel and t_end disagree."""
+    run = _fake_run()
+    t_end = 0.3
+    run.t = t_end / run.vel
+    assert run.done(t_end)
+    run.t = np.nextafter(t_end / run.vel, 0.0)
+    assert not run.done(t_end)
+    # a clock where the product rounds up to t_end but the loop would go on
+    for x in np.linspace(0.1, 10.0, 997):
+        run.t = np.nextafter(x / run.vel, 0.0)
+        assert run.done(x) == (not (run.t < x / run.vel))
+
+
+def test_checkpoint_keeps_settings_and_wall_time(tmp_path):
+    run = _fake_run()
+    run.t, run.steps = 1.25, 4000
+    run.t_rec, run.CD, run.CL = [np.array([0.1, 0.2])], [np.array([1.3, 1.31])], [np.array([0.0, 0.1])]
+    run.dts = [1e-4, 1e-4]
+    path = str(tmp_path / "ck.npz")
+    run.save(path, wall_s=12.5)
+    other = _fake_run()
+    other.U.zero_()
+    assert other.load(path) == 12.5
+    assert other.steps == 4000 and other.t == 1.25 and float(other.U.sum()) == float(run.U.sum())
+    for key, val in (("precision", 0), ("overint", True), ("mu", 1e-3), ("C_cfl", 8.0),
+                     ("kick", 0.2), ("U_inf", [1.0, 0.2, 0.0, 1.8])):
+        with pytest.raises(ValueError, match="other settings"):
+            _fake_run(**{key: val}).load(path)
+    with pytest.raises(ValueError, match="another order"):
+        _fake_run(p=4).load(path)
