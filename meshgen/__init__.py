@@ -91,6 +91,62 @@ def ogrid(ntheta, nr, R0=0.5, R1=30.0, ratio=1.05):
                 face_tag=np.array(tags, dtype=np.int8), period=(0.0, 0.0))
 
 
+def curve_wall(mesh, x, y, center=(0.0, 0.0), tag=TAG_WALL):
+    """Node positions of isoparametric elements whose `tag` faces lie on
+    circles about `center` (the cylinder's wall): for every element with such
+    a face, the positions of all its nodes, so that the element's map is the
+    polynomial interpolant of those positions.
+
+    x, y: (Np, K) node coordinates of the straight-sided mesh (any node set;
+    only the positions are used).  For a face from vertex a to vertex b on the
+    circle through them, a node with barycentric coordinates (la, lb, lc) in
+    the straight triangle moves by (la + lb)^2 (A(xi) - C(xi)), xi = lb / (la +
+    lb): C is the chord point and A the circle point at the same fraction of
+    the angle from a to b.  Face nodes land on the circle; nodes on the two
+    other edges do not move (xi is 0 or 1 there), so those edges stay straight
+    and the mesh stays conforming.  Returns (elems, xy): element indices
+    (int32) and their node positions, shape (n, 2, Np).
+    """
+    VX = np.asarray(mesh["VX"], dtype=np.float64)
+    VY = np.asarray(mesh["VY"], dtype=np.float64)
+    EToV = np.asarray(mesh["EToV"])
+    ft = np.asarray(mesh["face_tag"])
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    cx, cy = float(center[0]), float(center[1])
+    elems, out = [], []
+    for k in range(EToV.shape[0]):
+        faces = [f for f in range(3) if ft[k, f] == tag]
+        if not faces:
+            continue
+        px, py = x[:, k].copy(), y[:, k].copy()
+        for f in faces:
+            a, b, c = EToV[k, f], EToV[k, (f + 1) % 3], EToV[k, (f + 2) % 3]
+            # barycentric coordinates of the straight-sided positions
+            det = (VX[b] - VX[a]) * (VY[c] - VY[a]) - (VX[c] - VX[a]) * (VY[b] - VY[a])
+            lb = ((x[:, k] - VX[a]) * (VY[c] - VY[a]) - (VX[c] - VX[a]) * (y[:, k] - VY[a])) / det
+            lc = ((VX[b] - VX[a]) * (y[:, k] - VY[a]) - (x[:, k] - VX[a]) * (VY[b] - VY[a])) / det
+            lab = 1.0 - lc
+            xi = np.where(lab > 1e-12, lb / np.where(lab > 1e-12, lab, 1.0), 0.0)
+            xi = np.clip(xi, 0.0, 1.0)
+            ra = math.hypot(VX[a] - cx, VY[a] - cy)
+            rb = math.hypot(VX[b] - cx, VY[b] - cy)
+            R = 0.5 * (ra + rb)
+            ta = math.atan2(VY[a] - cy, VX[a] - cx)
+            dth = math.atan2(VY[b] - cy, VX[b] - cx) - ta
+            dth = (dth + math.pi) % (2.0 * math.pi) - math.pi
+            th = ta + xi * dth
+            Ax, Ay = cx + R * np.cos(th), cy + R * np.sin(th)
+            Cx = (1.0 - xi) * VX[a] + xi * VX[b]
+            Cy = (1.0 - xi) * VY[a] + xi * VY[b]
+            w = lab * lab
+            px += w * (Ax - Cx)
+            py += w * (Ay - Cy)
+        elems.append(k)
+        out.append(np.stack([px, py]))
+    return np.array(elems, dtype=np.int32), np.array(out, dtype=np.float64).reshape(len(elems), 2, x.shape[0])
+
+
 def growth_ratio(R0, R1, nr, h_wall):
     """Geometric growth ratio q > 1 of nr radial cells from R0 to R1 whose
     first cell is h_wall thick: h_wall (q^nr - 1) / (q - 1) = R1 - R0, solved
