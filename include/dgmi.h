@@ -101,6 +101,24 @@ int dg_create(int p, int precision, dg_ctx** out);
 int dg_set_physics(dg_ctx* ctx, double gamma, double Pr, double mu, double theta,
                    int penalty_mode, double C_pen, const double U_inf[4]);
 
+/* Isoparametric (curved) elements (Sec. 2.2: T_K affine or isoparametric).
+ * elems: n element indices (host, int32, each once, in [0, K)); xy: host
+ * array n x 2 x Np, for element elems[i] the x then the y coordinates of its
+ * Np nodes in the library's node order (dg_get_nodes gives the straight
+ * positions).  The element's map is the degree-p interpolant of these
+ * positions; its faces shared with other elements must keep the other side's
+ * node positions (a conforming mesh; checked at set-up, DG_EMESH otherwise,
+ * also for a non-positive Jacobian).  Per-node metric terms, per-face-node
+ * normals and sJ, the mass matrix int l_i l_j J and the penalty's C_inv with
+ * the curved face length and area are built by the host set-up; the curved
+ * elements and their face neighbours are evaluated by a separate FP64 kernel
+ * in every precision mode (the wall force uses the same geometry).  n = 0
+ * removes them.  Host only; after dg_set_mesh (which clears them) and before
+ * dg_setup_host / dg_setup.  DG_EINVAL for bad indices or non-finite
+ * positions, DG_EUNSUPPORTED with over-integration; batches refuse such
+ * contexts. */
+int dg_set_curved_elements(dg_ctx* ctx, int64_t n, const int32_t* elems, const double* xy);
+
 /* The wall's viscous flux (a dg_wall_flux mode; default DG_WALL_ADIABATIC).
  * Host only; any time after dg_create, taking effect at the next launch (a
  * batch keeps the modes its contexts had at dg_batch_create); DG_EINVAL for

@@ -33,6 +33,7 @@ SIGNATURES = {
     "dg_create": (_I, [_I, _I, ctypes.POINTER(_P)]),
     "dg_set_physics": (_I, [_P, _D, _D, _D, _D, _I, _D, _DP]),
     "dg_set_wall_flux": (_I, [_P, _I]),
+    "dg_set_curved_elements": (_I, [_P, _L, ctypes.POINTER(ctypes.c_int32), _DP]),
     "dg_set_mesh": (_I, [_P, _L, _DP, _DP, _L, ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int8), _DP]),
     "dg_setup_host": (_I, [_P]),
@@ -235,6 +236,24 @@ def dg_set_mesh(h, VX, VY, EToV, face_tag=None, period=(0.0, 0.0)):
     return _check(load().dg_set_mesh(
         h, VX.size, _dp(VX), _dp(VY), K, E.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         None if ft is None else ft.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _dp(per)), h)
+
+
+def dg_set_curved_elements(h, elems, xy):
+    """Isoparametric elements: indices (n,) and node positions (n, 2, Np),
+    x then y per element in the library's node order (host arrays)."""
+    E = np.ascontiguousarray(np.asarray(elems, dtype=np.int32).ravel())
+    n = E.size
+    X = np.ascontiguousarray(np.asarray(xy, dtype=np.float64))
+    if n and X.ndim != 3:
+        raise ValueError("xy must have shape (n, 2, Np)")
+    if n and (X.shape[0] != n or X.shape[1] != 2):
+        raise ValueError("xy has shape %s for %d elements" % (X.shape, n))
+    if n and X.shape[2] != load().dg_num_nodes(h):
+        raise ValueError("xy has %d nodes per element, the context's order %d"
+                         % (X.shape[2], load().dg_num_nodes(h)))
+    return _check(load().dg_set_curved_elements(
+        h, n, E.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if n else None,
+        _dp(X) if n else None), h)
 
 
 def dg_setup_host(h):

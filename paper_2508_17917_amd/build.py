@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libdgmi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["host_setup.cpp", "dgmi_abi.cpp", "batch.cpp", "tune.cpp", "closure.cpp", "kernels.hip",
-           "mlp.hip", "cfl.hip", "noalloc.hip"]
+           "mlp.hip", "cfl.hip", "noalloc.hip", "curved_setup.cpp"]
 ARCH = os.environ.get("DGMI_OFFLOAD_ARCH", "gfx950")
 
 

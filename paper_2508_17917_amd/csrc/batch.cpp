@@ -269,6 +269,8 @@ static int batch_build(dg_batch* b, dg_ctx* const* ctxs, int n) {
       return bfail(b, DG_EINVAL, "contexts of a batch must share the precision mode");
     if (c->overint)
       return bfail(b, DG_EUNSUPPORTED, "over-integrated contexts are not batched");
+    if (!c->mesh.celem.empty())
+      return bfail(b, DG_EUNSUPPORTED, "contexts with curved elements are not batched");
   }
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);

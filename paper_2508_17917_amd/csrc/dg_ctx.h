@@ -57,6 +57,14 @@ struct dg_ctx {
   double* d_cfl = nullptr;          // CFL work: 3K face maxima, 3K element maxima, result
   double* h_cfl = nullptr;          // pinned host word for the CFL result
   double* noalloc_scratch = nullptr;  // this device's static scratch array (not owned)
+  // isoparametric elements given by dg_set_curved_elements, and their tables
+  std::vector<int32_t> curved_elems;
+  std::vector<double> curved_xy;
+  int32_t* d_cslot = nullptr;
+  int32_t* d_celem = nullptr;
+  double* d_cnode = nullptr;
+  double* d_cface = nullptr;
+  double* d_cP = nullptr;
   int force_blocks = 0;
   bool dev_ready = false;
   std::string err;

@@ -64,6 +64,15 @@ struct MeshTables {
   std::vector<double> x, y;       // K x Np node coordinates
   std::vector<int32_t> wall_faces;  // list of k*3+f with tag wall
   std::vector<double> wall_xy;      // (x, y) of each wall face node, face-major
+  // isoparametric elements (curved_setup.cpp): the set S of the curved
+  // elements and their face neighbours, evaluated by the curved kernel with
+  // per-node geometry; cslot[k] is k's slot in S or -1
+  std::vector<int32_t> cslot;       // K (empty: no curved element)
+  std::vector<int32_t> celem;       // |S|: element of each slot
+  std::vector<double> cnode;        // |S| x 5 x Np: rx, ry, sx, sy, J at the nodes
+  std::vector<double> cface;        // |S| x 3 x 3Nfp: nx, ny, sJ at the face nodes
+  std::vector<double> cP;           // |S| x Np x Np: (M^K)^-1 M, row-major
+  std::vector<double> carea;        // |S|: |K|
 };
 
 // host_setup.cpp
@@ -79,6 +88,19 @@ bool build_mesh_tables(const RefOps& ref, const Physics& phys, int64_t Nv, const
 bool build_order_maps(int lo, int hi, std::vector<double>& P, std::vector<double>& I,
                       std::string& err);
 
+// curved_setup.cpp: replace the node positions of n elements (xy: n x 2 x Np,
+// x then y per element) by those of their isoparametric maps and build the
+// curved tables, the curved elements' penalty factors and wall coordinates
+bool build_curved_tables(const RefOps& ref, const Physics& phys, int64_t n, const int32_t* elems,
+                         const double* xy, MeshTables& t, std::string& err);
+// host_setup.cpp helpers shared with it
+void gauss_jacobi_rule(int q, double a, double b, std::vector<double>& x, std::vector<double>& w);
+bool lagrange_at(const RefOps& ref, const std::vector<double>& r, const std::vector<double>& s,
+                 std::vector<double>& L, std::vector<double>& Lr, std::vector<double>& Ls);
+bool invert_matrix(std::vector<double>& A, int n);
+double legendre(double x, int n);   // orthonormal Legendre polynomial
+double dlegendre(double x, int n);
+
 // Device-side view handed to the kernels.
 struct DeviceTables {
   const double* geo = nullptr;     // K x 16
@@ -93,6 +115,13 @@ struct DeviceTables {
   const double* wall_xy = nullptr; // node coordinates of the wall faces, (x, y) per face node
   int64_t K = 0;
   int nwall = 0;
+  // isoparametric elements (see MeshTables): null / 0 without any
+  const int32_t* cslot = nullptr;
+  const int32_t* celem = nullptr;
+  const double* cnode = nullptr;
+  const double* cface = nullptr;
+  const double* cP = nullptr;
+  int ncurved = 0;                  // |S|
   double* force_part = nullptr;     // per-workgroup partials of the wall force
   unsigned* force_ticket = nullptr; // workgroups done (the last resets it to 0)
   int force_blocks = 0;             // capacity of force_part, in workgroups

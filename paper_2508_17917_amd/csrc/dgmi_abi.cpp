@@ -30,7 +30,8 @@ int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
 void free_device(dg_ctx* c) {
   void* ptrs[] = {c->d_geo,  c->d_conn,    c->d_ops,     c->d_frag,       c->d_frag32,
                   c->d_frag16, c->d_wall, c->d_wall_xy, c->d_scratch, c->d_force,
-                  c->d_force_part, c->d_force_ticket, c->d_oi, c->d_cfl};
+                  c->d_force_part, c->d_force_ticket, c->d_oi, c->d_cfl,
+                  c->d_cslot, c->d_celem, c->d_cnode, c->d_cface, c->d_cP};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_cfl) (void)hipHostFree(c->h_cfl);
@@ -49,6 +50,11 @@ void free_device(dg_ctx* c) {
   c->d_force_ticket = nullptr;
   c->d_oi = nullptr;
   c->d_cfl = nullptr;
+  c->d_cslot = nullptr;
+  c->d_celem = nullptr;
+  c->d_cnode = nullptr;
+  c->d_cface = nullptr;
+  c->d_cP = nullptr;
   c->force_blocks = 0;
   c->dev_ready = false;
 }
@@ -80,6 +86,14 @@ dgmi::DeviceTables tables(const dg_ctx* c) {
   t.force_part = c->d_force_part;
   t.force_ticket = c->d_force_ticket;
   t.force_blocks = c->force_blocks;
+  if (!c->mesh.celem.empty()) {
+    t.cslot = c->d_cslot;
+    t.celem = c->d_celem;
+    t.cnode = c->d_cnode;
+    t.cface = c->d_cface;
+    t.cP = c->d_cP;
+    t.ncurved = (int)c->mesh.celem.size();
+  }
   return t;
 }
 
@@ -180,6 +194,29 @@ int dg_set_mesh(dg_ctx* c, int64_t Nv, const double* VX, const double* VY, int64
   c->K = K;
   c->have_mesh = true;
   c->host_ready = false;
+  c->curved_elems.clear();
+  c->curved_xy.clear();
+  return DG_OK;
+}
+
+int dg_set_curved_elements(dg_ctx* c, int64_t n, const int32_t* elems, const double* xy) {
+  if (!c) return fail(c, DG_EINVAL, "null context");
+  if (!c->have_mesh) return fail(c, DG_ESTATE, "dg_set_mesh must precede dg_set_curved_elements");
+  if (n < 0 || (n > 0 && (!elems || !xy))) return fail(c, DG_EINVAL, "NULL or negative curved-element arrays");
+  if (n > 0 && c->overint)
+    return fail(c, DG_EUNSUPPORTED, "curved elements are not built for the over-integrated stage");
+  std::vector<char> seen(c->K, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (elems[i] < 0 || elems[i] >= c->K) return fail(c, DG_EINVAL, "curved element index out of range");
+    if (seen[elems[i]]) return fail(c, DG_EINVAL, "a curved element is listed twice");
+    seen[elems[i]] = 1;
+  }
+  const int Np = (c->N + 1) * (c->N + 2) / 2;
+  for (int64_t i = 0; i < n * 2 * Np; ++i)
+    if (!std::isfinite(xy[i])) return fail(c, DG_EINVAL, "non-finite curved node position");
+  c->curved_elems.assign(elems, elems + n);
+  c->curved_xy.assign(xy, xy + n * 2 * Np);
+  c->host_ready = false;
   return DG_OK;
 }
 
@@ -192,6 +229,9 @@ int dg_setup_host(dg_ctx* c) {
   if (!dgmi::build_oi_ops(c->ref, c->oi, err)) return fail(c, DG_EUNSUPPORTED, err);
   if (!dgmi::build_mesh_tables(c->ref, c->phys, c->Nv, c->VX.data(), c->VY.data(), c->K,
                                c->EToV.data(), c->tag.data(), c->period, c->mesh, err))
+    return fail(c, DG_EMESH, err);
+  if (!dgmi::build_curved_tables(c->ref, c->phys, (int64_t)c->curved_elems.size(),
+                                 c->curved_elems.data(), c->curved_xy.data(), c->mesh, err))
     return fail(c, DG_EMESH, err);
   c->host_ready = true;
   return DG_OK;
@@ -223,7 +263,13 @@ int dg_setup(dg_ctx* c) {
       (e = upload(&c->d_frag16, frag16)) != hipSuccess ||
       (e = upload(&c->d_oi, oi)) != hipSuccess ||
       (e = upload(&c->d_wall, c->mesh.wall_faces)) != hipSuccess ||
-      (e = upload(&c->d_wall_xy, c->mesh.wall_xy)) != hipSuccess) {
+      (e = upload(&c->d_wall_xy, c->mesh.wall_xy)) != hipSuccess ||
+      (!c->mesh.celem.empty() &&
+       ((e = upload(&c->d_cslot, c->mesh.cslot)) != hipSuccess ||
+        (e = upload(&c->d_celem, c->mesh.celem)) != hipSuccess ||
+        (e = upload(&c->d_cnode, c->mesh.cnode)) != hipSuccess ||
+        (e = upload(&c->d_cface, c->mesh.cface)) != hipSuccess ||
+        (e = upload(&c->d_cP, c->mesh.cP)) != hipSuccess))) {
     free_device(c);
     return hip_fail(c, e, "uploading set-up tables");
   }
@@ -257,6 +303,8 @@ int dg_set_overintegration(dg_ctx* c, int on) {
   if (on && c->precision != DG_FP64)
     return fail(c, DG_EUNSUPPORTED, "over-integration runs in the plain FP64 form only");
   if (on && (c->N < 1 || c->N > 6)) return fail(c, DG_EUNSUPPORTED, "over-integration is built for p = 1..6");
+  if (on && !c->curved_elems.empty())
+    return fail(c, DG_EUNSUPPORTED, "over-integration is not built for curved elements");
   c->overint = on != 0;
   return DG_OK;
 }
@@ -286,6 +334,15 @@ int dg_get_host_table(const dg_ctx* cc, const char* name, double* out, int64_t c
   else if (n == "geo") v = m.geo;
   else if (n == "nbr") v.assign(m.nbr.begin(), m.nbr.end());
   else if (n == "nbr_face") v.assign(m.nbr_face.begin(), m.nbr_face.end());
+  else if (n == "curved_slot") {
+    v.assign(m.cslot.begin(), m.cslot.end());
+    if (v.empty()) v.assign(c->K, -1.0);
+  }
+  else if (n == "curved_elem") v.assign(m.celem.begin(), m.celem.end());
+  else if (n == "curved_node") v = m.cnode;
+  else if (n == "curved_face") v = m.cface;
+  else if (n == "curved_P") v = m.cP;
+  else if (n == "curved_area") v = m.carea;
   else if (n == "oi_wq") v = c->oi.wq;
   else if (n == "oi_xg") v = c->oi.xg;
   else if (n == "oi_wg") v = c->oi.wg;

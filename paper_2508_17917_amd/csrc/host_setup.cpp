@@ -652,6 +652,31 @@ void pack_frags_bf16(const RefOps& ref, std::vector<uint16_t>& out) {
   emit(ref.LIFTs, NF, KF);
 }
 
+// Helpers for the curved-element set-up (curved_setup.cpp).
+void gauss_jacobi_rule(int q, double a, double b, std::vector<double>& x, std::vector<double>& w) {
+  gauss_jacobi(q, a, b, x, w);
+}
+
+bool lagrange_at(const RefOps& ref, const std::vector<double>& r, const std::vector<double>& s,
+                 std::vector<double>& L, std::vector<double>& Lr, std::vector<double>& Ls) {
+  const int N = ref.N, Np = ref.Np;
+  std::vector<double> V(Np * Np), vr(Np * Np), vs(Np * Np);
+  for (int n = 0; n < Np; ++n) {
+    int col = 0;
+    for (int i = 0; i <= N; ++i)
+      for (int j = 0; j <= N - i; ++j, ++col)
+        pkd(ref.r[n], ref.s[n], i, j, V[n * Np + col], vr[n * Np + col], vs[n * Np + col]);
+  }
+  if (!invert(V, Np)) return false;
+  basis_at(ref, V, r, s, L, Lr, Ls);
+  return true;
+}
+
+bool invert_matrix(std::vector<double>& A, int n) { return invert(A, n); }
+
+double legendre(double x, int n) { return jacobi(x, 0.0, 0.0, n); }
+double dlegendre(double x, int n) { return djacobi(x, 0.0, 0.0, n); }
+
 size_t ops_packed_size(int N) {
   size_t Np = (N + 1) * (N + 2) / 2, NF = 3 * (N + 1);
   return 2 * Np * Np + 3 * Np * NF + NF;

@@ -676,9 +676,11 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     // right-hand side): otherwise the load reads the element's own state,
     // which the tile has just brought into the cache, and is not used.
     double rk[NT][4], r0[NT][4];
+    bool mine;  // not an element of the curved set (which the curved kernel writes)
     {
       const double* kp = (a != 0.0 && !rhs_only) ? (const double*)K1 : Uin;
       const int64_t ke = (e0 + re) < K ? (e0 + re) : K - 1;
+      mine = t.cslot == nullptr || t.cslot[ke] < 0;
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt) {
         const int n = 16 * tt + rn < Np ? 16 * tt + rn : Np - 1;
@@ -726,7 +728,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         }
       }
       const int n = 16 * tt + rn;
-      if (re < nel && n < Np) {
+      if (re < nel && n < Np && mine) {
         const int64_t base_i = (e0 + re) * S + n;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -1286,6 +1288,23 @@ __device__ __forceinline__ void force_block(const DeviceTables& t, const KernelP
     const int n = face_node<N>(f, j);
     const double* Uk = U + k * S;
     const double* g = t.geo + k * kGeoStride;
+    // metric terms at the node, normal and sJ at the face node: per node on
+    // the elements of the curved set, the element's constants elsewhere
+    double rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+    double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
+    double sJ = g[6 + 4 * f] / (g[0] * g[3] - g[1] * g[2]);  // Fscale * J
+    const int cs = t.cslot ? t.cslot[k] : -1;
+    if (cs >= 0) {
+      const double* nd = t.cnode + (int64_t)cs * 5 * Np;
+      const double* fc = t.cface + (int64_t)cs * 9 * Nfp;
+      rx = nd[n];
+      ry = nd[Np + n];
+      sx = nd[2 * Np + n];
+      sy = nd[3 * Np + n];
+      nx = fc[f * Nfp + j];
+      ny = fc[3 * Nfp + f * Nfp + j];
+      sJ = fc[6 * Nfp + f * Nfp + j];
+    }
     double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < Np; ++m) {
@@ -1300,16 +1319,14 @@ __device__ __forceinline__ void force_block(const DeviceTables& t, const KernelP
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       Up[c] = Uk[c * Np + n];
-      dx[c] = g[0] * ur[c] + g[2] * us[c];
-      dy[c] = g[1] * ur[c] + g[3] * us[c];
+      dx[c] = rx * ur[c] + sx * us[c];
+      dy[c] = ry * ur[c] + sy * us[c];
     }
     const double p = gas.gm1 * (Up[3] - 0.5 * (Up[1] * Up[1] + Up[2] * Up[2]) / Up[0]);
     double Ub[4] = {Up[0], Up[0] * ph.vw[0], Up[0] * ph.vw[1],
                     p * gas.igm1 + 0.5 * Up[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1])};
     double vx[4], vy[4];
     viscous_flux(gas, vstate(gas, Ub), dx, dy, vx, vy);
-    const double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
-    const double sJ = g[6 + 4 * f] / (g[0] * g[3] - g[1] * g[2]);  // Fscale * J
     const double w = wface[f * Nfp + j] * sJ;
     const double tx = p * nx - (vx[1] * nx + vy[1] * ny);
     const double ty = p * ny - (vx[2] * nx + vy[2] * ny);
@@ -1359,6 +1376,228 @@ __global__ __launch_bounds__(kForceThreads) void batch_force_kernel(const ForceI
   while (i + 1 < count && (int)blockIdx.x >= items[i + 1].block_begin) ++i;
   const ForceItem& it = items[i];
   force_block<N>(it.t, it.ph, it.U, it.out, blockIdx.x - it.block_begin, it.nblocks);
+}
+
+// Isoparametric elements and their face neighbours (the curved set S), in
+// FP64 in every form: one element per 64-lane workgroup, per-node metric
+// terms, per-face-node normals and sJ, and the element's P = (M^K)^-1 M.
+// With J inside the contravariant flux and sJ in the face terms, the
+// strong-form residual X = -(D_r F~_r + D_s F~_s) + LIFT h + LIFT_r q_r +
+// LIFT_s q_s is M times the weak form's integrals, and R = P X (on an affine
+// element P = M / (J M), the stage kernel's arithmetic).  The stage kernel
+// leaves these elements unwritten; this kernel reads only the input state and
+// its own elements' K1, so the two launches do not depend on each other.
+template <int N>
+__global__ __launch_bounds__(64) void curved_stage_kernel(DeviceTables t, KernelPhysics ph,
+                                                          const double* __restrict__ Uin,
+                                                          double* __restrict__ Uout,
+                                                          double* __restrict__ K1, double a,
+                                                          double b, double dt, int rhs_only) {
+  constexpr int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1, NFN = 3 * Nfp, S = 4 * Np;
+  __shared__ double sU[S], sGx[S], sGy[S], sFr[S], sFs[S], sX[S], sNd[5 * Np];
+  __shared__ double sH[4 * NFN], sQr[4 * NFN], sQs[4 * NFN], sNorm[NFN];
+  const int lane = threadIdx.x;
+  const int slot = blockIdx.x;
+  const int64_t k = t.celem[slot];
+  const double* Dr = t.ops;
+  const double* Ds = t.ops + Np * Np;
+  const double* LIFT = t.ops + 2 * Np * Np;
+  const double* LIFTr = LIFT + Np * NFN;
+  const double* LIFTs = LIFTr + Np * NFN;
+  const double* nd = t.cnode + (int64_t)slot * 5 * Np;
+  const double* fc = t.cface + (int64_t)slot * 3 * NFN;
+  Gas<double> gas;
+  gas.gamma = ph.gamma;
+  gas.gm1 = ph.gm1;
+  gas.igm1 = ph.igm1;
+  gas.mu = ph.mu;
+  gas.k = ph.k;
+  Base<double> base;
+  base.rho = ph.U_inf[0];
+  base.mx = ph.U_inf[1];
+  base.my = ph.U_inf[2];
+  base.E = ph.U_inf[3];
+  base.p = ph.p_inf;
+  base.ux = ph.u_inf;
+  base.uy = ph.v_inf;
+  const double vwx = ph.vw[0], vwy = ph.vw[1];
+
+  for (int i = lane; i < S; i += 64) sU[i] = Uin[k * S + i];
+  for (int i = lane; i < 5 * Np; i += 64) sNd[i] = nd[i];
+  __syncthreads();
+  // gradient at the nodes with each node's metric terms
+  for (int i = lane; i < S; i += 64) {
+    const int c = i / Np, n = i - c * Np;
+    double ur = 0.0, us = 0.0;
+    for (int m = 0; m < Np; ++m) {
+      ur += Dr[n * Np + m] * sU[c * Np + m];
+      us += Ds[n * Np + m] * sU[c * Np + m];
+    }
+    sGx[i] = sNd[n] * ur + sNd[2 * Np + n] * us;
+    sGy[i] = sNd[Np + n] * ur + sNd[3 * Np + n] * us;
+  }
+  __syncthreads();
+  // total flux at the nodes, contravariant with J
+  for (int n = lane; n < Np; n += 64) {
+    double u[4], gx[4], gy[4];
+    for (int c = 0; c < 4; ++c) {
+      u[c] = sU[c * Np + n];
+      gx[c] = sGx[c * Np + n];
+      gy[c] = sGy[c * Np + n];
+    }
+    double fvx[4], fvy[4], Fx[4], Fy[4];
+    viscous_flux(gas, vstate(gas, u), gx, gy, fvx, fvy);
+    const Prim<double> pr = prim_plain(u, gas.gm1);
+    normal_flux_plain(u, pr, 1.0, 0.0, vwx, Fx);
+    normal_flux_plain(u, pr, 0.0, 1.0, vwy, Fy);
+    const double rx = sNd[n], ry = sNd[Np + n], sx = sNd[2 * Np + n], sy = sNd[3 * Np + n];
+    const double J = sNd[4 * Np + n];
+    for (int c = 0; c < 4; ++c) {
+      const double fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
+      sFr[c * Np + n] = J * (rx * fx + ry * fy);
+      sFs[c * Np + n] = J * (sx * fx + sy * fy);
+    }
+  }
+  __syncthreads();
+  // face nodes, one lane each: traces, ghosts, norms, the other side's
+  // gradient (with that element's metric terms at its node), viscous mean
+  const bool fl = lane < NFN;
+  const int l = fl ? lane : 0;
+  const int f = l / Nfp, j = l - f * Nfp;
+  const int n = face_node<N>(f, j);
+  const int conn = t.conn[k * 3 + f];
+  const int tag = conn & 3, nf = (conn >> 2) & 3;
+  const int64_t kn = conn >> 4;
+  const double nx = fc[l], ny = fc[NFN + l], sJ = fc[2 * NFN + l];
+  double up[4] = {0.0, 0.0, 0.0, 0.0}, uo[4] = {0.0, 0.0, 0.0, 0.0};
+  double vn[4] = {0.0, 0.0, 0.0, 0.0};
+  VState<double> sp = {}, so = {};
+  if (fl) {
+    double gxp[4], gyp[4], gxm[4], gym[4];
+    for (int c = 0; c < 4; ++c) {
+      up[c] = sU[c * Np + n];
+      gxp[c] = sGx[c * Np + n];
+      gyp[c] = sGy[c * Np + n];
+      gxm[c] = gxp[c];
+      gym[c] = gyp[c];
+    }
+    if (tag == 0) {
+      const int n2 = face_node<N>(nf, Nfp - 1 - j);
+      const double* Un = Uin + kn * S;
+      double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
+      for (int m = 0; m < Np; ++m) {
+        const double dr = Dr[n2 * Np + m], ds = Ds[n2 * Np + m];
+        for (int c = 0; c < 4; ++c) {
+          ur[c] += dr * Un[c * Np + m];
+          us[c] += ds * Un[c * Np + m];
+        }
+      }
+      const int cs = t.cslot[kn];
+      double rx, ry, sx, sy;
+      if (cs >= 0) {
+        const double* nd2 = t.cnode + (int64_t)cs * 5 * Np;
+        rx = nd2[n2];
+        ry = nd2[Np + n2];
+        sx = nd2[2 * Np + n2];
+        sy = nd2[3 * Np + n2];
+      } else {
+        const double* g2 = t.geo + kn * kGeoStride;
+        rx = g2[0];
+        ry = g2[1];
+        sx = g2[2];
+        sy = g2[3];
+      }
+      for (int c = 0; c < 4; ++c) {
+        uo[c] = Un[c * Np + n2];
+        gxm[c] = rx * ur[c] + sx * us[c];
+        gym[c] = ry * ur[c] + sy * us[c];
+      }
+    } else {
+      // wall or far field: the ghost (no neighbour value is read)
+      ghost_state<double, false>(tag, up, up, sU + n, Np, vwx, vwy, gas, base, uo);
+    }
+    sp = vstate(gas, up);
+    so = vstate(gas, uo);
+    const double a1 = normal_diffusion_norm(gas, sp, nx, ny);
+    const double a2 = normal_diffusion_norm(gas, so, nx, ny);
+    sNorm[l] = a1 > a2 ? a1 : a2;
+    if (tag == 1) {
+      // wall: G(U^b) grad U+ (conduction as the wall flux mode sets it)
+      viscous_normal_flux(gas_wall(gas, ph.k_wall), so, gxp, gyp, nx, ny, vn);
+    } else {
+      viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
+      if (tag == 0) {
+        double vm[4];
+        viscous_normal_flux(gas, so, gxm, gym, nx, ny, vm);
+        for (int c = 0; c < 4; ++c) vn[c] = 0.5 * (vn[c] + vm[c]);
+      }
+    }
+  }
+  __syncthreads();
+  if (fl) {
+    double gbar = 0.0;
+    for (int jj = 0; jj < Nfp; ++jj) gbar = sNorm[f * Nfp + jj] > gbar ? sNorm[f * Nfp + jj] : gbar;
+    const double sigma = t.geo[k * kGeoStride + 7 + 4 * f] * gbar;
+    const double vwn = vwx * nx + vwy * ny;
+    const Prim<double> pp = prim_plain(up, gas.gm1);
+    double Fc[4];
+    if (tag == 1) {
+      Fc[0] = 0.0;
+      Fc[1] = pp.p * nx;
+      Fc[2] = pp.p * ny;
+      Fc[3] = pp.p * vwn;
+    } else {
+      const Prim<double> po = prim_plain(uo, gas.gm1);
+      double FL[4], FR[4];
+      normal_flux_plain(up, pp, nx, ny, vwn, FL);
+      normal_flux_plain(uo, po, nx, ny, vwn, FR);
+      roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
+    }
+    // sJ times the own normal flux, from the contravariant flux (J inside):
+    // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
+    const double cfr = f == 0 ? 0.0 : (f == 1 ? 1.0 : -1.0);
+    const double cfs = f == 2 ? 0.0 : (f == 1 ? 1.0 : -1.0);
+    double w[4];
+    for (int c = 0; c < 4; ++c) {
+      w[c] = up[c] - uo[c];
+      const double own = cfr * sFr[c * Np + n] + cfs * sFs[c * Np + n];
+      sH[c * NFN + l] = own - sJ * (Fc[c] - vn[c] + sigma * w[c]);
+    }
+    double qx[4], qy[4];
+    viscous_transpose(tag == 1 ? gas_wall(gas, ph.k_wall) : gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
+    const double ce = ph.theta * (tag == 0 ? 0.5 : 1.0) * sJ;
+    const double rx = sNd[n], ry = sNd[Np + n], sx = sNd[2 * Np + n], sy = sNd[3 * Np + n];
+    for (int c = 0; c < 4; ++c) {
+      sQr[c * NFN + l] = ce * (rx * qx[c] + ry * qy[c]);
+      sQs[c * NFN + l] = ce * (sx * qx[c] + sy * qy[c]);
+    }
+  }
+  __syncthreads();
+  // strong-form residual, then R = P X and the stage
+  for (int i = lane; i < S; i += 64) {
+    const int c = i / Np, m0 = i - c * Np;
+    double x = 0.0;
+    for (int m = 0; m < Np; ++m) x -= Dr[m0 * Np + m] * sFr[c * Np + m] + Ds[m0 * Np + m] * sFs[c * Np + m];
+    for (int q = 0; q < NFN; ++q)
+      x += LIFT[m0 * NFN + q] * sH[c * NFN + q] + LIFTr[m0 * NFN + q] * sQr[c * NFN + q] +
+           LIFTs[m0 * NFN + q] * sQs[c * NFN + q];
+    sX[i] = x;
+  }
+  __syncthreads();
+  const double* P = t.cP + (int64_t)slot * Np * Np;
+  for (int i = lane; i < S; i += 64) {
+    const int c = i / Np, m0 = i - c * Np;
+    double R = 0.0;
+    for (int m = 0; m < Np; ++m) R += P[m0 * Np + m] * sX[c * Np + m];
+    const int64_t idx = k * S + i;
+    if (rhs_only) {
+      K1[idx] = R;
+    } else {
+      const double kk = (a != 0.0) ? a * K1[idx] + dt * R : dt * R;
+      K1[idx] = kk;
+      Uout[idx] = sU[i] + b * kk;
+    }
+  }
 }
 
 namespace {
@@ -1577,18 +1816,42 @@ int batch_resident_t() {
 }
 }  // namespace
 
+template <int N>
+int launch_curved_n(const DeviceTables& t, const KernelPhysics& ph, const double* Uin,
+                    double* Uout, double* K1, double a, double b, double dt, int rhs_only,
+                    hipStream_t s, std::string& err) {
+  hipLaunchKernelGGL(curved_stage_kernel<N>, dim3((unsigned)t.ncurved), dim3(64), 0, s, t, ph, Uin,
+                     Uout, K1, a, b, dt, rhs_only);
+  return launch_error(err, "curved stage kernel launch");
+}
+
 int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t,
                  const KernelPhysics& ph, const double* Uin, double* Uout, double* K1, double a,
                  double b, double dt, int rhs_only, void* stream, std::string& err) {
   hipStream_t s = (hipStream_t)stream;
+  int rc;
   switch (N) {
-    case 1: return launch_stage_n<1>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 2: return launch_stage_n<2>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 3: return launch_stage_n<3>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 4: return launch_stage_n<4>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 5: return launch_stage_n<5>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 6: return launch_stage_n<6>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 1: rc = launch_stage_n<1>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
+    case 2: rc = launch_stage_n<2>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
+    case 3: rc = launch_stage_n<3>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
+    case 4: rc = launch_stage_n<4>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
+    case 5: rc = launch_stage_n<5>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
+    case 6: rc = launch_stage_n<6>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
     default: err = "polynomial order not built"; return -5;
+  }
+  if (rc != 0 || t.ncurved == 0) return rc;
+  if (form == kFormOverint) {
+    err = "curved elements are not built for the over-integrated stage";
+    return -5;
+  }
+  // the curved set: its own launch, in stream order after the straight tiles
+  switch (N) {
+    case 1: return launch_curved_n<1>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 2: return launch_curved_n<2>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 3: return launch_curved_n<3>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 4: return launch_curved_n<4>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    case 5: return launch_curved_n<5>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
+    default: return launch_curved_n<6>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
   }
 }
 

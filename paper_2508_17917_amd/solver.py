@@ -11,7 +11,11 @@ from . import _lib as L
 class Solver:
     def __init__(self, p, mesh, gamma=1.4, Pr=0.72, mu=0.0, theta=1.0, penalty_mode=0, C_pen=0.01,
                  U_inf=(1.0, 0.0, 0.0, 1.0), device=True, precision=L.DG_FP64,
-                 overintegration=False, wall_flux=L.DG_WALL_ADIABATIC):
+                 overintegration=False, wall_flux=L.DG_WALL_ADIABATIC, curved=None):
+        """curved: isoparametric elements, as (elems, xy) with xy of shape
+        (n, 2, Np), or a function f(mesh, x, y) of the mesh and its straight
+        node coordinates x, y (each (Np, K)) returning that pair (e.g.
+        meshgen.curve_wall)."""
         self.p = int(p)
         self.precision = int(precision)
         self.h = L.dg_create(self.p, self.precision)
@@ -22,6 +26,13 @@ class Solver:
             L.dg_set_wall_flux(self.h, wall_flux)
             L.dg_set_mesh(self.h, mesh["VX"], mesh["VY"], mesh["EToV"], mesh.get("face_tag"),
                           mesh.get("period", (0.0, 0.0)))
+            if curved is not None:
+                if callable(curved):
+                    L.dg_setup_host(self.h)
+                    x, y = L.dg_get_nodes(self.h)
+                    Np = L.dg_num_nodes(self.h)
+                    curved = curved(mesh, x.reshape(-1, Np).T, y.reshape(-1, Np).T)
+                L.dg_set_curved_elements(self.h, curved[0], curved[1])
             if device:
                 L.dg_setup(self.h)
             else:
@@ -44,7 +55,13 @@ class Solver:
                  "M": self.Np ** 2,
                  "LIFT": self.Np * 3 * self.Nfp, "LIFTr": self.Np * 3 * self.Nfp,
                  "LIFTs": self.Np * 3 * self.Nfp, "Fmask": 3 * self.Nfp, "wface": 3 * self.Nfp,
-                 "geo": self.K * 16, "nbr": self.K * 3, "nbr_face": self.K * 3}
+                 "geo": self.K * 16, "nbr": self.K * 3, "nbr_face": self.K * 3,
+                 "curved_slot": self.K}
+        nc = int((self.table("curved_slot") >= 0).sum()) if name.startswith("curved_") and \
+            name != "curved_slot" else 0
+        sizes.update({"curved_elem": nc, "curved_node": nc * 5 * self.Np,
+                      "curved_face": nc * 9 * self.Nfp, "curved_P": nc * self.Np ** 2,
+                      "curved_area": nc})
         q = (3 * self.p + 2) // 2
         Nq, NG = q * q, 3 * q
         sizes.update({"oi_wq": Nq, "oi_xg": q, "oi_wg": q, "oi_Iq": Nq * self.Np,
