@@ -269,11 +269,19 @@ def mass_norms(solver, D):
     return np.sqrt(np.einsum("kcn,nm,kcm,k->c", d, M, d, J))
 
 
-def make_solver(w, p, mesh, precision, overint=False):
+def make_solver(w, p, mesh, precision, overint=False, curved=None):
     from paper_2508_17917_amd import Solver
     return Solver(p, mesh, gamma=w["gamma"], Pr=w["Pr"], mu=w["mu"], theta=w["theta"],
                   penalty_mode=w["penalty_mode"], C_pen=w["C_pen"], U_inf=w["U_inf"],
-                  precision=precision, overintegration=overint)
+                  precision=precision, overintegration=overint, curved=curved)
+
+
+def curved_bytes_per_element(Np, Nfp):
+    """Algorithmic HBM bytes per element of the curved set: the state read,
+    K1 read and written, the new state written (4 x 4 Np doubles), the node
+    table (rx, ry, sx, sy, J: 5 Np), the face table (nx, ny, sJ: 9 Nfp), P
+    (Np^2), the penalty factors and connectivity (16 doubles, 3 int32)."""
+    return 4 * 4 * Np * 8 + 5 * Np * 8 + 9 * Nfp * 8 + Np * Np * 8 + 16 * 8 + 3 * 4
 
 
 def stage_time(s, U, dt, stream, nl=100):
@@ -294,13 +302,13 @@ def stage_time(s, U, dt, stream, nl=100):
     return e0.elapsed_time(e1) / 1e3 / nl
 
 
-def run_single(w, U0, precision, steps, warmup, dt, overint=False):
+def run_single(w, U0, precision, steps, warmup, dt, overint=False, curved=None):
     """One mesh: warmup + steps LSERK steps, each followed by the wall-force
     integral into device memory (one library call per phase; the state
     alternates between two buffers, so no per-step copy).  Returns (final
     state, timed seconds, stage kernel seconds, solver)."""
     import torch
-    s = make_solver(w, w["p"], w["mesh"], precision, overint)
+    s = make_solver(w, w["p"], w["mesh"], precision, overint, curved)
     U = U0.clone()
     K1 = torch.zeros_like(U)
     F = torch.zeros((warmup + steps, 3), dtype=torch.float64, device=U.device)
@@ -600,6 +608,8 @@ def main():
     ap.add_argument("--overint", action="store_true",
                     help="single-mesh workloads: the over-integrated FP64 stage (degree-3p "
                          "quadrature), the nodal FP64 stage beside it")
+    ap.add_argument("--curved", action="store_true",
+                    help="single-mesh workloads: curve the wall layer (isoparametric elements)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -627,7 +637,8 @@ def main():
     else:
         orders = [args.p] if args.p is not None else [mg.workload(args.workload)["p"]]
         head = measure(args.workload, orders[0], args.form, args.steps, args.warmup,
-                       overint=args.overint, compare_forms=args.compare_forms, cfl=True)
+                       overint=args.overint, compare_forms=args.compare_forms, cfl=True,
+                       curved=args.curved)
         out = head.pop("line")
         # the rest of the metric: the other orders on the same mesh, and the
         # out-of-cache mesh at the headline order (same steps, same forms)
@@ -639,6 +650,23 @@ def main():
             out["orders"] = sub
             r = measure("cylinder327k", 4, args.form, args.steps, args.warmup)
             out["cylinder327k"] = r["summary"]
+            # the headline mesh with its wall layer curved (isoparametric):
+            # the curved kernel's cost is the stage time over the straight one
+            r = measure("cylinder20k", 4, args.form, args.steps, args.warmup, curved=True)
+            cw = r["summary"]
+            straight_us = out["roofline"]["avg_launch_us"]
+            over_us = cw["roofline"]["avg_launch_us"] - straight_us
+            cw["straight_stage_us"] = straight_us
+            cw["curved_overhead_us"] = over_us
+            if over_us > 0:
+                gbs = cw["curved_bytes_per_launch"] / (over_us * 1e-6) / 1e9
+                cw["curved_kernel_roofline"] = {
+                    "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS,
+                    "note": "curved set (the curved elements and their face neighbours, one "
+                            "element per wave in the stage launch's leading workgroups): its "
+                            "algorithmic bytes over the stage time it adds; latency-bound"}
+            out["curved_wall"] = cw
         if not args.no_cpu_baseline and args.workload == "cylinder20k":
             log("cpu baseline (oracle)")
             corders = [orders[0]] if (args.p is not None or args.quick or args.overint) else [4, 5, 6]
@@ -688,10 +716,13 @@ def describe(wname, K, p, form):
                "1.05" if wname == "cylinder20k" else "1.0125", K, p, Np, form))
 
 
-def measure(wname, p, form, steps, warmup, overint=False, compare_forms=False, cfl=False):
+def measure(wname, p, form, steps, warmup, overint=False, compare_forms=False, cfl=False,
+            curved=False):
     """One mesh and order: the chosen form and plain FP64 beside it from the
     same state (warmup + steps LSERK steps with the wall force after each), the
     stage kernel's launch time of each, the L2 difference, the roofline.
+    curved: the wall layer's elements isoparametric (meshgen.curve_wall); the
+    stage time then covers both launches of a stage.
     Returns {"line": the full bench record, "summary": its per-order digest}."""
     import numpy as np
     import torch
@@ -704,12 +735,15 @@ def measure(wname, p, form, steps, warmup, overint=False, compare_forms=False, c
     # SIPG with C1 = 1 on the 2.9e-3 wall layer at p = 4 is penalty-limited
     # near 3e-7; 1e-7 keeps the impulsively started state bounded
     dt = min(1e-7 if wname != "periodic51k" else 1.0, stable_dt(w["mesh"], p, w["mu"]) * 1.5)
-    log("%s p=%d form %s, warmup %d, steps %d" % (wname, p, form, warmup, steps))
-    U, t_steps, t_launch, s = run_single(w, U0, FORMS[form], steps, warmup, dt, overint=overint)
+    cv = mg.curve_wall if curved else None
+    log("%s p=%d form %s, warmup %d, steps %d%s" % (wname, p, form, warmup, steps,
+                                                    ", wall layer curved" if curved else ""))
+    U, t_steps, t_launch, s = run_single(w, U0, FORMS[form], steps, warmup, dt, overint=overint,
+                                         curved=cv)
     finite = bool(torch.isfinite(U).all().item())
     if form != "fp64" or overint:
         log("plain fp64 beside it")
-        U64, t64, tl64, s64 = run_single(w, U0, FORMS["fp64"], steps, warmup, dt)
+        U64, t64, tl64, s64 = run_single(w, U0, FORMS["fp64"], steps, warmup, dt, curved=cv)
     else:
         U64, t64, tl64, s64 = U, t_steps, t_launch, s
     err = rel_l2([s64], [U], [U64], w["U_inf"])
@@ -775,6 +809,14 @@ def measure(wname, p, form, steps, warmup, overint=False, compare_forms=False, c
                                                   "frac_valu")},
                "roofline_fp64": cmp["roofline"], "fp64_avg_launch_us": tl64 * 1e6,
                "launch_shape": config["launch_shape"]}
+    if curved:
+        slot = s.table("curved_slot")
+        ns = int((slot >= 0).sum())
+        nc = int((np.asarray(w["mesh"]["face_tag"]) == mg.TAG_WALL).any(axis=1).sum())
+        summary["workload"] += ", wall layer curved"
+        summary["curved_elements"] = nc
+        summary["curved_set"] = ns
+        summary["curved_bytes_per_launch"] = curved_bytes_per_element(Np, p + 1) * ns
     s.close()
     if s64 is not s:
         s64.close()

@@ -111,8 +111,9 @@ int dg_set_physics(dg_ctx* ctx, double gamma, double Pr, double mu, double theta
  * also for a non-positive Jacobian).  Per-node metric terms, per-face-node
  * normals and sJ, the mass matrix int l_i l_j J and the penalty's C_inv with
  * the curved face length and area are built by the host set-up; the curved
- * elements and their face neighbours are evaluated by a separate FP64 kernel
- * in every precision mode (the wall force uses the same geometry).  n = 0
+ * elements and their face neighbours are evaluated in FP64 in every precision
+ * mode, one element per wave in the stage launch's leading workgroups (the
+ * wall force uses the same geometry).  n = 0
  * removes them.  Host only; after dg_set_mesh (which clears them) and before
  * dg_setup_host / dg_setup.  DG_EINVAL for bad indices or non-finite
  * positions, DG_EUNSUPPORTED with over-integration; batches refuse such

@@ -65,7 +65,7 @@ struct MeshTables {
   std::vector<int32_t> wall_faces;  // list of k*3+f with tag wall
   std::vector<double> wall_xy;      // (x, y) of each wall face node, face-major
   // isoparametric elements (curved_setup.cpp): the set S of the curved
-  // elements and their face neighbours, evaluated by the curved kernel with
+  // elements and their face neighbours, evaluated by the curved body with
   // per-node geometry; cslot[k] is k's slot in S or -1
   std::vector<int32_t> cslot;       // K (empty: no curved element)
   std::vector<int32_t> celem;       // |S|: element of each slot

@@ -748,6 +748,260 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   }
 }
 
+// Isoparametric elements and their face neighbours (the curved set S), in
+// FP64 in every form: one element per wavefront, per-node metric terms,
+// per-face-node normals and sJ, and the element's P = (M^K)^-1 M.
+// With J inside the contravariant flux and sJ in the face terms, the
+// strong-form residual X = -(D_r F~_r + D_s F~_s) + LIFT h + LIFT_r q_r +
+// LIFT_s q_s is M times the weak form's integrals, and R = P X (on an affine
+// element P = M / (J M), the stage kernel's arithmetic).  The stage kernel's
+// straight tiles leave these elements unwritten, and this body reads only the
+// input state and its own element's K1, so both run in the same launch: the
+// stage kernel's leading workgroups take the curved set, one element per
+// wave, on the SIMDs beside the straight tiles.  lds: the wave's area,
+// curved_lds_doubles(N) doubles.
+constexpr int curved_lds_doubles(int N) {
+  return 29 * ((N + 1) * (N + 2) / 2) + 39 * (N + 1);
+}
+// workgroups of W waves that take the curved set, a multiple of 8 (so the
+// straight tiles' workgroups keep their XCD numbering)
+__host__ __device__ inline int curved_workgroups(int ncurved, int W) {
+  return ncurved > 0 ? ((ncurved + W - 1) / W + 7) / 8 * 8 : 0;
+}
+template <int N>
+__device__ __forceinline__ void curved_element(const DeviceTables& t, const KernelPhysics& ph,
+                                               const double* __restrict__ Uin,
+                                               double* __restrict__ Uout,
+                                               double* __restrict__ K1, double a, double b,
+                                               double dt, int rhs_only, int slot, double* lds) {
+  constexpr int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1, NFN = 3 * Nfp, S = 4 * Np;
+  double* sU = lds;
+  double* sGx = sU + S;
+  double* sGy = sGx + S;
+  double* sFr = sGy + S;
+  double* sFs = sFr + S;
+  double* sX = sFs + S;
+  double* sNd = sX + S;
+  double* sH = sNd + 5 * Np;
+  double* sQr = sH + 4 * NFN;
+  double* sQs = sQr + 4 * NFN;
+  double* sNorm = sQs + 4 * NFN;
+  static_assert(6 * S + 5 * Np + 13 * NFN == curved_lds_doubles(N), "curved LDS layout");
+  const int lane = threadIdx.x & 63;
+  const int64_t k = t.celem[slot];
+  const double* Dr = t.ops;
+  const double* Ds = t.ops + Np * Np;
+  const double* LIFT = t.ops + 2 * Np * Np;
+  const double* LIFTr = LIFT + Np * NFN;
+  const double* LIFTs = LIFTr + Np * NFN;
+  const double* nd = t.cnode + (int64_t)slot * 5 * Np;
+  const double* fc = t.cface + (int64_t)slot * 3 * NFN;
+  Gas<double> gas;
+  gas.gamma = ph.gamma;
+  gas.gm1 = ph.gm1;
+  gas.igm1 = ph.igm1;
+  gas.mu = ph.mu;
+  gas.k = ph.k;
+  Base<double> base;
+  base.rho = ph.U_inf[0];
+  base.mx = ph.U_inf[1];
+  base.my = ph.U_inf[2];
+  base.E = ph.U_inf[3];
+  base.p = ph.p_inf;
+  base.ux = ph.u_inf;
+  base.uy = ph.v_inf;
+  const double vwx = ph.vw[0], vwy = ph.vw[1];
+
+  #pragma unroll 1
+  for (int i = lane; i < S; i += 64) sU[i] = Uin[k * S + i];
+  #pragma unroll 1
+  for (int i = lane; i < 5 * Np; i += 64) sNd[i] = nd[i];
+  wave_sync();
+  // gradient at the nodes with each node's metric terms
+  #pragma unroll 1
+  for (int i = lane; i < S; i += 64) {
+    const int c = i / Np, n = i - c * Np;
+    double ur = 0.0, us = 0.0;
+    #pragma unroll 4
+    for (int m = 0; m < Np; ++m) {
+      ur += Dr[n * Np + m] * sU[c * Np + m];
+      us += Ds[n * Np + m] * sU[c * Np + m];
+    }
+    sGx[i] = sNd[n] * ur + sNd[2 * Np + n] * us;
+    sGy[i] = sNd[Np + n] * ur + sNd[3 * Np + n] * us;
+  }
+  wave_sync();
+  // total flux at the nodes, contravariant with J
+  #pragma unroll 1
+  for (int n = lane; n < Np; n += 64) {
+    double u[4], gx[4], gy[4];
+    for (int c = 0; c < 4; ++c) {
+      u[c] = sU[c * Np + n];
+      gx[c] = sGx[c * Np + n];
+      gy[c] = sGy[c * Np + n];
+    }
+    double fvx[4], fvy[4], Fx[4], Fy[4];
+    viscous_flux(gas, vstate(gas, u), gx, gy, fvx, fvy);
+    const Prim<double> pr = prim_plain(u, gas.gm1);
+    normal_flux_plain(u, pr, 1.0, 0.0, vwx, Fx);
+    normal_flux_plain(u, pr, 0.0, 1.0, vwy, Fy);
+    const double rx = sNd[n], ry = sNd[Np + n], sx = sNd[2 * Np + n], sy = sNd[3 * Np + n];
+    const double J = sNd[4 * Np + n];
+    for (int c = 0; c < 4; ++c) {
+      const double fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
+      sFr[c * Np + n] = J * (rx * fx + ry * fy);
+      sFs[c * Np + n] = J * (sx * fx + sy * fy);
+    }
+  }
+  wave_sync();
+  // face nodes, one lane each: traces, ghosts, norms, the other side's
+  // gradient (with that element's metric terms at its node), viscous mean
+  const bool fl = lane < NFN;
+  const int l = fl ? lane : 0;
+  const int f = l / Nfp, j = l - f * Nfp;
+  const int n = face_node<N>(f, j);
+  const int conn = t.conn[k * 3 + f];
+  const int tag = conn & 3, nf = (conn >> 2) & 3;
+  const int64_t kn = conn >> 4;
+  const double nx = fc[l], ny = fc[NFN + l], sJ = fc[2 * NFN + l];
+  double up[4] = {0.0, 0.0, 0.0, 0.0}, uo[4] = {0.0, 0.0, 0.0, 0.0};
+  double vn[4] = {0.0, 0.0, 0.0, 0.0};
+  VState<double> sp = {}, so = {};
+  if (fl) {
+    double gxp[4], gyp[4], gxm[4], gym[4];
+    for (int c = 0; c < 4; ++c) {
+      up[c] = sU[c * Np + n];
+      gxp[c] = sGx[c * Np + n];
+      gyp[c] = sGy[c * Np + n];
+      gxm[c] = gxp[c];
+      gym[c] = gyp[c];
+    }
+    if (tag == 0) {
+      const int n2 = face_node<N>(nf, Nfp - 1 - j);
+      const double* Un = Uin + kn * S;
+      double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
+      #pragma unroll 4
+      for (int m = 0; m < Np; ++m) {
+        const double dr = Dr[n2 * Np + m], ds = Ds[n2 * Np + m];
+        for (int c = 0; c < 4; ++c) {
+          ur[c] += dr * Un[c * Np + m];
+          us[c] += ds * Un[c * Np + m];
+        }
+      }
+      const int cs = t.cslot[kn];
+      double rx, ry, sx, sy;
+      if (cs >= 0) {
+        const double* nd2 = t.cnode + (int64_t)cs * 5 * Np;
+        rx = nd2[n2];
+        ry = nd2[Np + n2];
+        sx = nd2[2 * Np + n2];
+        sy = nd2[3 * Np + n2];
+      } else {
+        const double* g2 = t.geo + kn * kGeoStride;
+        rx = g2[0];
+        ry = g2[1];
+        sx = g2[2];
+        sy = g2[3];
+      }
+      for (int c = 0; c < 4; ++c) {
+        uo[c] = Un[c * Np + n2];
+        gxm[c] = rx * ur[c] + sx * us[c];
+        gym[c] = ry * ur[c] + sy * us[c];
+      }
+    } else {
+      // wall or far field: the ghost (no neighbour value is read)
+      ghost_state<double, false>(tag, up, up, sU + n, Np, vwx, vwy, gas, base, uo);
+    }
+    sp = vstate(gas, up);
+    so = vstate(gas, uo);
+    const double a1 = normal_diffusion_norm(gas, sp, nx, ny);
+    const double a2 = normal_diffusion_norm(gas, so, nx, ny);
+    sNorm[l] = a1 > a2 ? a1 : a2;
+    if (tag == 1) {
+      // wall: G(U^b) grad U+ (conduction as the wall flux mode sets it)
+      viscous_normal_flux(gas_wall(gas, ph.k_wall), so, gxp, gyp, nx, ny, vn);
+    } else {
+      viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
+      if (tag == 0) {
+        double vm[4];
+        viscous_normal_flux(gas, so, gxm, gym, nx, ny, vm);
+        for (int c = 0; c < 4; ++c) vn[c] = 0.5 * (vn[c] + vm[c]);
+      }
+    }
+  }
+  wave_sync();
+  if (fl) {
+    double gbar = 0.0;
+    #pragma unroll 1
+    for (int jj = 0; jj < Nfp; ++jj) gbar = sNorm[f * Nfp + jj] > gbar ? sNorm[f * Nfp + jj] : gbar;
+    const double sigma = t.geo[k * kGeoStride + 7 + 4 * f] * gbar;
+    const double vwn = vwx * nx + vwy * ny;
+    const Prim<double> pp = prim_plain(up, gas.gm1);
+    double Fc[4];
+    if (tag == 1) {
+      Fc[0] = 0.0;
+      Fc[1] = pp.p * nx;
+      Fc[2] = pp.p * ny;
+      Fc[3] = pp.p * vwn;
+    } else {
+      const Prim<double> po = prim_plain(uo, gas.gm1);
+      double FL[4], FR[4];
+      normal_flux_plain(up, pp, nx, ny, vwn, FL);
+      normal_flux_plain(uo, po, nx, ny, vwn, FR);
+      roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
+    }
+    // sJ times the own normal flux, from the contravariant flux (J inside):
+    // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
+    const double cfr = f == 0 ? 0.0 : (f == 1 ? 1.0 : -1.0);
+    const double cfs = f == 2 ? 0.0 : (f == 1 ? 1.0 : -1.0);
+    double w[4];
+    for (int c = 0; c < 4; ++c) {
+      w[c] = up[c] - uo[c];
+      const double own = cfr * sFr[c * Np + n] + cfs * sFs[c * Np + n];
+      sH[c * NFN + l] = own - sJ * (Fc[c] - vn[c] + sigma * w[c]);
+    }
+    double qx[4], qy[4];
+    viscous_transpose(tag == 1 ? gas_wall(gas, ph.k_wall) : gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
+    const double ce = ph.theta * (tag == 0 ? 0.5 : 1.0) * sJ;
+    const double rx = sNd[n], ry = sNd[Np + n], sx = sNd[2 * Np + n], sy = sNd[3 * Np + n];
+    for (int c = 0; c < 4; ++c) {
+      sQr[c * NFN + l] = ce * (rx * qx[c] + ry * qy[c]);
+      sQs[c * NFN + l] = ce * (sx * qx[c] + sy * qy[c]);
+    }
+  }
+  wave_sync();
+  // strong-form residual, then R = P X and the stage
+  #pragma unroll 1
+  for (int i = lane; i < S; i += 64) {
+    const int c = i / Np, m0 = i - c * Np;
+    double x = 0.0;
+    #pragma unroll 4
+    for (int m = 0; m < Np; ++m) x -= Dr[m0 * Np + m] * sFr[c * Np + m] + Ds[m0 * Np + m] * sFs[c * Np + m];
+    #pragma unroll 4
+    for (int q = 0; q < NFN; ++q)
+      x += LIFT[m0 * NFN + q] * sH[c * NFN + q] + LIFTr[m0 * NFN + q] * sQr[c * NFN + q] +
+           LIFTs[m0 * NFN + q] * sQs[c * NFN + q];
+    sX[i] = x;
+  }
+  wave_sync();
+  const double* P = t.cP + (int64_t)slot * Np * Np;
+  #pragma unroll 1
+  for (int i = lane; i < S; i += 64) {
+    const int c = i / Np, m0 = i - c * Np;
+    double R = 0.0;
+    #pragma unroll 4
+    for (int m = 0; m < Np; ++m) R += P[m0 * Np + m] * sX[c * Np + m];
+    const int64_t idx = k * S + i;
+    if (rhs_only) {
+      K1[idx] = R;
+    } else {
+      const double kk = (a != 0.0) ? a * K1[idx] + dt * R : dt * R;
+      K1[idx] = kk;
+      Uout[idx] = sU[i] + b * kk;
+    }
+  }
+}
+
 // Copy the operator fragments of order N into LDS and zero the pad columns
 // (nodes Np .. RS - 1) of the state and flux rows of this workgroup's wave
 // areas: the matrix-core products read them against zero operator entries,
@@ -782,15 +1036,29 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
   typedef typename Real<X>::type T;
   using O = Order<N, X>;
   __shared__ __attribute__((aligned(16))) T sFrag[O::FRAG_SZ];
-  __shared__ T sWave[W * O::WAVE_SZ];
+  __shared__ __attribute__((aligned(16))) T sWave[W * O::WAVE_SZ];
   __shared__ int sConnW[W * 12];
-  stage_lds_init<N, X, W>(frag_of<X>(t), sFrag, sWave);
   const int wid = threadIdx.x >> 6;
+  // the leading workgroups evaluate the curved set (one element per wave, in
+  // the wave's LDS area), the rest the straight tiles
+  const int ncw = curved_workgroups(t.ncurved, W);
+  static_assert((O::WAVE_SZ * sizeof(T)) / 8 >= curved_lds_doubles(N) + 1,
+                "the curved element's arrays must fit a wave's LDS area");
+  if ((int)blockIdx.x < ncw) {
+    const int slot = (int)blockIdx.x * W + wid;
+    if (slot < t.ncurved) {
+      const uintptr_t at = ((uintptr_t)(sWave + wid * O::WAVE_SZ) + 7) & ~(uintptr_t)7;
+      curved_element<N>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, slot, (double*)at);
+    }
+    return;
+  }
+  stage_lds_init<N, X, W>(frag_of<X>(t), sFrag, sWave);
+  const unsigned bx = blockIdx.x - ncw, gx = gridDim.x - ncw;
   const int64_t ntiles = (t.K + O::EPT - 1) / O::EPT;
-  const int xcd = blockIdx.x & 7;
+  const int xcd = bx & 7;
   const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
-  const int64_t w0 = (int64_t)(blockIdx.x >> 3) * W + wid;
-  const int64_t wstride = (int64_t)(gridDim.x >> 3) * W;
+  const int64_t w0 = (int64_t)(bx >> 3) * W + wid;
+  const int64_t wstride = (int64_t)(gx >> 3) * W;
   stage_tiles<N, X, PERT>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, sFrag, sWave + wid * O::WAVE_SZ,
                           sConnW + 12 * wid, tb + w0, te, wstride);
 }
@@ -1378,228 +1646,6 @@ __global__ __launch_bounds__(kForceThreads) void batch_force_kernel(const ForceI
   force_block<N>(it.t, it.ph, it.U, it.out, blockIdx.x - it.block_begin, it.nblocks);
 }
 
-// Isoparametric elements and their face neighbours (the curved set S), in
-// FP64 in every form: one element per 64-lane workgroup, per-node metric
-// terms, per-face-node normals and sJ, and the element's P = (M^K)^-1 M.
-// With J inside the contravariant flux and sJ in the face terms, the
-// strong-form residual X = -(D_r F~_r + D_s F~_s) + LIFT h + LIFT_r q_r +
-// LIFT_s q_s is M times the weak form's integrals, and R = P X (on an affine
-// element P = M / (J M), the stage kernel's arithmetic).  The stage kernel
-// leaves these elements unwritten; this kernel reads only the input state and
-// its own elements' K1, so the two launches do not depend on each other.
-template <int N>
-__global__ __launch_bounds__(64) void curved_stage_kernel(DeviceTables t, KernelPhysics ph,
-                                                          const double* __restrict__ Uin,
-                                                          double* __restrict__ Uout,
-                                                          double* __restrict__ K1, double a,
-                                                          double b, double dt, int rhs_only) {
-  constexpr int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1, NFN = 3 * Nfp, S = 4 * Np;
-  __shared__ double sU[S], sGx[S], sGy[S], sFr[S], sFs[S], sX[S], sNd[5 * Np];
-  __shared__ double sH[4 * NFN], sQr[4 * NFN], sQs[4 * NFN], sNorm[NFN];
-  const int lane = threadIdx.x;
-  const int slot = blockIdx.x;
-  const int64_t k = t.celem[slot];
-  const double* Dr = t.ops;
-  const double* Ds = t.ops + Np * Np;
-  const double* LIFT = t.ops + 2 * Np * Np;
-  const double* LIFTr = LIFT + Np * NFN;
-  const double* LIFTs = LIFTr + Np * NFN;
-  const double* nd = t.cnode + (int64_t)slot * 5 * Np;
-  const double* fc = t.cface + (int64_t)slot * 3 * NFN;
-  Gas<double> gas;
-  gas.gamma = ph.gamma;
-  gas.gm1 = ph.gm1;
-  gas.igm1 = ph.igm1;
-  gas.mu = ph.mu;
-  gas.k = ph.k;
-  Base<double> base;
-  base.rho = ph.U_inf[0];
-  base.mx = ph.U_inf[1];
-  base.my = ph.U_inf[2];
-  base.E = ph.U_inf[3];
-  base.p = ph.p_inf;
-  base.ux = ph.u_inf;
-  base.uy = ph.v_inf;
-  const double vwx = ph.vw[0], vwy = ph.vw[1];
-
-  for (int i = lane; i < S; i += 64) sU[i] = Uin[k * S + i];
-  for (int i = lane; i < 5 * Np; i += 64) sNd[i] = nd[i];
-  __syncthreads();
-  // gradient at the nodes with each node's metric terms
-  for (int i = lane; i < S; i += 64) {
-    const int c = i / Np, n = i - c * Np;
-    double ur = 0.0, us = 0.0;
-    for (int m = 0; m < Np; ++m) {
-      ur += Dr[n * Np + m] * sU[c * Np + m];
-      us += Ds[n * Np + m] * sU[c * Np + m];
-    }
-    sGx[i] = sNd[n] * ur + sNd[2 * Np + n] * us;
-    sGy[i] = sNd[Np + n] * ur + sNd[3 * Np + n] * us;
-  }
-  __syncthreads();
-  // total flux at the nodes, contravariant with J
-  for (int n = lane; n < Np; n += 64) {
-    double u[4], gx[4], gy[4];
-    for (int c = 0; c < 4; ++c) {
-      u[c] = sU[c * Np + n];
-      gx[c] = sGx[c * Np + n];
-      gy[c] = sGy[c * Np + n];
-    }
-    double fvx[4], fvy[4], Fx[4], Fy[4];
-    viscous_flux(gas, vstate(gas, u), gx, gy, fvx, fvy);
-    const Prim<double> pr = prim_plain(u, gas.gm1);
-    normal_flux_plain(u, pr, 1.0, 0.0, vwx, Fx);
-    normal_flux_plain(u, pr, 0.0, 1.0, vwy, Fy);
-    const double rx = sNd[n], ry = sNd[Np + n], sx = sNd[2 * Np + n], sy = sNd[3 * Np + n];
-    const double J = sNd[4 * Np + n];
-    for (int c = 0; c < 4; ++c) {
-      const double fx = Fx[c] - fvx[c], fy = Fy[c] - fvy[c];
-      sFr[c * Np + n] = J * (rx * fx + ry * fy);
-      sFs[c * Np + n] = J * (sx * fx + sy * fy);
-    }
-  }
-  __syncthreads();
-  // face nodes, one lane each: traces, ghosts, norms, the other side's
-  // gradient (with that element's metric terms at its node), viscous mean
-  const bool fl = lane < NFN;
-  const int l = fl ? lane : 0;
-  const int f = l / Nfp, j = l - f * Nfp;
-  const int n = face_node<N>(f, j);
-  const int conn = t.conn[k * 3 + f];
-  const int tag = conn & 3, nf = (conn >> 2) & 3;
-  const int64_t kn = conn >> 4;
-  const double nx = fc[l], ny = fc[NFN + l], sJ = fc[2 * NFN + l];
-  double up[4] = {0.0, 0.0, 0.0, 0.0}, uo[4] = {0.0, 0.0, 0.0, 0.0};
-  double vn[4] = {0.0, 0.0, 0.0, 0.0};
-  VState<double> sp = {}, so = {};
-  if (fl) {
-    double gxp[4], gyp[4], gxm[4], gym[4];
-    for (int c = 0; c < 4; ++c) {
-      up[c] = sU[c * Np + n];
-      gxp[c] = sGx[c * Np + n];
-      gyp[c] = sGy[c * Np + n];
-      gxm[c] = gxp[c];
-      gym[c] = gyp[c];
-    }
-    if (tag == 0) {
-      const int n2 = face_node<N>(nf, Nfp - 1 - j);
-      const double* Un = Uin + kn * S;
-      double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
-      for (int m = 0; m < Np; ++m) {
-        const double dr = Dr[n2 * Np + m], ds = Ds[n2 * Np + m];
-        for (int c = 0; c < 4; ++c) {
-          ur[c] += dr * Un[c * Np + m];
-          us[c] += ds * Un[c * Np + m];
-        }
-      }
-      const int cs = t.cslot[kn];
-      double rx, ry, sx, sy;
-      if (cs >= 0) {
-        const double* nd2 = t.cnode + (int64_t)cs * 5 * Np;
-        rx = nd2[n2];
-        ry = nd2[Np + n2];
-        sx = nd2[2 * Np + n2];
-        sy = nd2[3 * Np + n2];
-      } else {
-        const double* g2 = t.geo + kn * kGeoStride;
-        rx = g2[0];
-        ry = g2[1];
-        sx = g2[2];
-        sy = g2[3];
-      }
-      for (int c = 0; c < 4; ++c) {
-        uo[c] = Un[c * Np + n2];
-        gxm[c] = rx * ur[c] + sx * us[c];
-        gym[c] = ry * ur[c] + sy * us[c];
-      }
-    } else {
-      // wall or far field: the ghost (no neighbour value is read)
-      ghost_state<double, false>(tag, up, up, sU + n, Np, vwx, vwy, gas, base, uo);
-    }
-    sp = vstate(gas, up);
-    so = vstate(gas, uo);
-    const double a1 = normal_diffusion_norm(gas, sp, nx, ny);
-    const double a2 = normal_diffusion_norm(gas, so, nx, ny);
-    sNorm[l] = a1 > a2 ? a1 : a2;
-    if (tag == 1) {
-      // wall: G(U^b) grad U+ (conduction as the wall flux mode sets it)
-      viscous_normal_flux(gas_wall(gas, ph.k_wall), so, gxp, gyp, nx, ny, vn);
-    } else {
-      viscous_normal_flux(gas, sp, gxp, gyp, nx, ny, vn);
-      if (tag == 0) {
-        double vm[4];
-        viscous_normal_flux(gas, so, gxm, gym, nx, ny, vm);
-        for (int c = 0; c < 4; ++c) vn[c] = 0.5 * (vn[c] + vm[c]);
-      }
-    }
-  }
-  __syncthreads();
-  if (fl) {
-    double gbar = 0.0;
-    for (int jj = 0; jj < Nfp; ++jj) gbar = sNorm[f * Nfp + jj] > gbar ? sNorm[f * Nfp + jj] : gbar;
-    const double sigma = t.geo[k * kGeoStride + 7 + 4 * f] * gbar;
-    const double vwn = vwx * nx + vwy * ny;
-    const Prim<double> pp = prim_plain(up, gas.gm1);
-    double Fc[4];
-    if (tag == 1) {
-      Fc[0] = 0.0;
-      Fc[1] = pp.p * nx;
-      Fc[2] = pp.p * ny;
-      Fc[3] = pp.p * vwn;
-    } else {
-      const Prim<double> po = prim_plain(uo, gas.gm1);
-      double FL[4], FR[4];
-      normal_flux_plain(up, pp, nx, ny, vwn, FL);
-      normal_flux_plain(uo, po, nx, ny, vwn, FR);
-      roe_flux(pp, po, FL, FR, nx, ny, vwn, gas.gm1, Fc);
-    }
-    // sJ times the own normal flux, from the contravariant flux (J inside):
-    // face 0: -Fs, face 1: Fr + Fs, face 2: -Fr
-    const double cfr = f == 0 ? 0.0 : (f == 1 ? 1.0 : -1.0);
-    const double cfs = f == 2 ? 0.0 : (f == 1 ? 1.0 : -1.0);
-    double w[4];
-    for (int c = 0; c < 4; ++c) {
-      w[c] = up[c] - uo[c];
-      const double own = cfr * sFr[c * Np + n] + cfs * sFs[c * Np + n];
-      sH[c * NFN + l] = own - sJ * (Fc[c] - vn[c] + sigma * w[c]);
-    }
-    double qx[4], qy[4];
-    viscous_transpose(tag == 1 ? gas_wall(gas, ph.k_wall) : gas, tag == 1 ? so : sp, nx, ny, w, qx, qy);
-    const double ce = ph.theta * (tag == 0 ? 0.5 : 1.0) * sJ;
-    const double rx = sNd[n], ry = sNd[Np + n], sx = sNd[2 * Np + n], sy = sNd[3 * Np + n];
-    for (int c = 0; c < 4; ++c) {
-      sQr[c * NFN + l] = ce * (rx * qx[c] + ry * qy[c]);
-      sQs[c * NFN + l] = ce * (sx * qx[c] + sy * qy[c]);
-    }
-  }
-  __syncthreads();
-  // strong-form residual, then R = P X and the stage
-  for (int i = lane; i < S; i += 64) {
-    const int c = i / Np, m0 = i - c * Np;
-    double x = 0.0;
-    for (int m = 0; m < Np; ++m) x -= Dr[m0 * Np + m] * sFr[c * Np + m] + Ds[m0 * Np + m] * sFs[c * Np + m];
-    for (int q = 0; q < NFN; ++q)
-      x += LIFT[m0 * NFN + q] * sH[c * NFN + q] + LIFTr[m0 * NFN + q] * sQr[c * NFN + q] +
-           LIFTs[m0 * NFN + q] * sQs[c * NFN + q];
-    sX[i] = x;
-  }
-  __syncthreads();
-  const double* P = t.cP + (int64_t)slot * Np * Np;
-  for (int i = lane; i < S; i += 64) {
-    const int c = i / Np, m0 = i - c * Np;
-    double R = 0.0;
-    for (int m = 0; m < Np; ++m) R += P[m0 * Np + m] * sX[c * Np + m];
-    const int64_t idx = k * S + i;
-    if (rhs_only) {
-      K1[idx] = R;
-    } else {
-      const double kk = (a != 0.0) ? a * K1[idx] + dt * R : dt * R;
-      K1[idx] = kk;
-      Uout[idx] = sU[i] + b * kk;
-    }
-  }
-}
-
 namespace {
 constexpr int kMaxDev = 64;
 
@@ -1674,7 +1720,11 @@ int launch_stage_t(const StageTuning& tune, const DeviceTables& t, const KernelP
   static int cache[kMaxDev] = {0};
   const int resident = resident_blocks(stage_kernel<N, T, PERT, W>, 64 * W, cache);
   constexpr int EPT = elements_per_tile(N);
-  const int64_t grid = stage_grid((t.K + EPT - 1) / EPT, W, resident, tune.grid);
+  // the curved set's workgroups lead the grid; a persistent grid leaves them
+  // their resident slots
+  const int ncw = curved_workgroups(t.ncurved, W);
+  const int straight_resident = resident - ncw >= 8 ? resident - ncw : 8;
+  const int64_t grid = stage_grid((t.K + EPT - 1) / EPT, W, straight_resident, tune.grid) + ncw;
   hipLaunchKernelGGL((stage_kernel<N, T, PERT, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, t,
                      ph, Uin, Uout, K1, a, b, dt, rhs_only);
   return launch_error(err, "stage kernel launch");
@@ -1816,19 +1866,14 @@ int batch_resident_t() {
 }
 }  // namespace
 
-template <int N>
-int launch_curved_n(const DeviceTables& t, const KernelPhysics& ph, const double* Uin,
-                    double* Uout, double* K1, double a, double b, double dt, int rhs_only,
-                    hipStream_t s, std::string& err) {
-  hipLaunchKernelGGL(curved_stage_kernel<N>, dim3((unsigned)t.ncurved), dim3(64), 0, s, t, ph, Uin,
-                     Uout, K1, a, b, dt, rhs_only);
-  return launch_error(err, "curved stage kernel launch");
-}
-
 int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t,
                  const KernelPhysics& ph, const double* Uin, double* Uout, double* K1, double a,
                  double b, double dt, int rhs_only, void* stream, std::string& err) {
   hipStream_t s = (hipStream_t)stream;
+  if (t.ncurved > 0 && form == kFormOverint) {
+    err = "curved elements are not built for the over-integrated stage";
+    return -5;
+  }
   int rc;
   switch (N) {
     case 1: rc = launch_stage_n<1>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
@@ -1839,20 +1884,7 @@ int launch_stage(int N, int form, const StageTuning& tune, const DeviceTables& t
     case 6: rc = launch_stage_n<6>(form, tune, t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err); break;
     default: err = "polynomial order not built"; return -5;
   }
-  if (rc != 0 || t.ncurved == 0) return rc;
-  if (form == kFormOverint) {
-    err = "curved elements are not built for the over-integrated stage";
-    return -5;
-  }
-  // the curved set: its own launch, in stream order after the straight tiles
-  switch (N) {
-    case 1: return launch_curved_n<1>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 2: return launch_curved_n<2>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 3: return launch_curved_n<3>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 4: return launch_curved_n<4>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    case 5: return launch_curved_n<5>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-    default: return launch_curved_n<6>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, s, err);
-  }
+  return rc;
 }
 
 int default_waves(int, int) { return 4; }

@@ -2,8 +2,9 @@
 (oracle/curved.py), needs an MI355X.
 
 The wall layer of O-grids is curved onto the cylinder (meshgen.curve_wall);
-the library evaluates the curved elements and their face neighbours with the
-curved kernel (FP64 in every form) and the rest with the stage kernel.
+the library evaluates the curved elements and their face neighbours in FP64
+in every form (one element per wave in the stage launch's leading
+workgroups) and the rest as straight tiles of the same launch.
 Bounds: those of the nodal parity tests (plain FP64: per field
 max(1e-12 max|R|, 1e-13 T_f)), of the perturbation forms (1e-5 T'_f in
 FP32), and bitwise reproducibility across launch shapes and entry points.
