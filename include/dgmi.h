@@ -320,6 +320,21 @@ int dg_batch_get_state(dg_batch* b, int i, double* U, void* stream);
  * rewritten). */
 int dg_batch_rk_step(dg_batch* b, const double* dt, const double* v_w, void* stream);
 
+/* One LSERK step of every instance on caller-owned device arrays: U[i] and
+ * K1[i] (arrays of n device pointers, each [K_i][4][Np_i] FP64, distinct
+ * from each other and across instances), dt and v_w as dg_batch_rk_step.
+ * The same launches and graph as dg_batch_rk_step (the item table is
+ * rewritten on `stream` to point at these arrays; the batch's second state
+ * buffer of each instance is the stage ping-pong partner, and the result is
+ * copied back into U[i] at the end, as dg_rk_step does), so results equal
+ * dg_rk_step on each context bitwise.  The batch-owned states are not
+ * preserved by this call (load them again with dg_batch_set_state before
+ * dg_batch_rk_step, dg_batch_force or dg_batch_coupled_step).  Asynchronous
+ * on `stream`; DG_EINVAL for a NULL, shared or repeated array or a
+ * non-finite dt / v_w. */
+int dg_batch_rk_step_states(dg_batch* b, double* const* U, double* const* K1, const double* dt,
+                            const double* v_w, void* stream);
+
 /* Force and moment on each instance's wall faces (as dg_force), out a host
  * array of 3n doubles.  Synchronises `stream`. */
 int dg_batch_force(dg_batch* b, const double* v_w, double* out, void* stream);

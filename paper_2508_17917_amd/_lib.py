@@ -34,6 +34,7 @@ SIGNATURES = {
     "dg_set_physics": (_I, [_P, _D, _D, _D, _D, _I, _D, _DP]),
     "dg_set_wall_flux": (_I, [_P, _I]),
     "dg_set_curved_elements": (_I, [_P, _L, ctypes.POINTER(ctypes.c_int32), _DP]),
+    "dg_batch_rk_step_states": (_I, [_P, _P, _P, _DP, _DP, _P]),
     "dg_set_mesh": (_I, [_P, _L, _DP, _DP, _L, ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int8), _DP]),
     "dg_setup_host": (_I, [_P]),
@@ -419,6 +420,24 @@ def dg_batch_rk_step(b, dt, v_w, stream=None):
     dt = np.ascontiguousarray(np.asarray(dt, dtype=np.float64))
     vw = np.ascontiguousarray(np.asarray(v_w, dtype=np.float64).reshape(-1))
     return _bcheck(load().dg_batch_rk_step(b, _dp(dt), _dp(vw), _stream(stream)), b)
+
+
+def dg_batch_rk_step_states(b, U, K1, dt, v_w, stream=None):
+    """One step on caller-owned states: U, K1 lists of device arrays, one per
+    instance (the instance's [K][4][Np] FP64 size)."""
+    sizes = _BATCH_STATES.get(b.value)
+    if sizes is None:
+        raise ValueError("not a live batch")
+    n = len(sizes)
+    if len(U) != n or len(K1) != n:
+        raise ValueError("U and K1 need one array per instance (%d)" % n)
+    ua = (ctypes.c_void_p * n)(*[_dev(u, "f64", sizes[i], "U[%d]" % i).value for i, u in enumerate(U)])
+    ka = (ctypes.c_void_p * n)(*[_dev(k, "f64", sizes[i], "K1[%d]" % i).value for i, k in enumerate(K1)])
+    dt = np.ascontiguousarray(np.asarray(dt, dtype=np.float64))
+    vw = np.ascontiguousarray(np.asarray(v_w, dtype=np.float64).reshape(-1))
+    if dt.size != n or vw.size != 2 * n:
+        raise ValueError("dt needs %d values and v_w %d" % (n, 2 * n))
+    return _bcheck(load().dg_batch_rk_step_states(b, ua, ka, _dp(dt), _dp(vw), _stream(stream)), b)
 
 
 def dg_batch_force(b, n, v_w=None, stream=None):

@@ -27,6 +27,8 @@ struct dg_batch {
   double* h_force = nullptr;
   dgmi::ForceItem* d_fitems = nullptr;  // wall-force launch descriptors
   dgmi::ForceItem* h_fitems = nullptr;  // pinned staging
+  dgmi::BatchItem* h_items = nullptr;   // pinned staging of the item table
+  bool caller_items = false;            // d_items point at caller-owned states
   std::vector<int> inst_of;             // item -> instance
   hipEvent_t upload_ev = nullptr;
   bool upload_pending = false;
@@ -75,6 +77,7 @@ void release(dg_batch* b) {
     if (p) (void)hipFree(p);
   if (b->h_steps) (void)hipHostFree(b->h_steps);
   if (b->h_parity) (void)hipHostFree(b->h_parity);
+  if (b->h_items) (void)hipHostFree(b->h_items);
   if (b->h_force) (void)hipHostFree(b->h_force);
   if (b->h_fitems) (void)hipHostFree(b->h_fitems);
   if (b->upload_ev) (void)hipEventDestroy(b->upload_ev);
@@ -194,11 +197,29 @@ int capture(dg_batch* b) {
 // Stage the per-instance parameters and the parity, and copy them to the
 // device on `s` (the previous upload is waited for before the pinned area is
 // rewritten).
-int upload(dg_batch* b, const double* dt, const double* vw, hipStream_t s) {
+// With Uc / K1c (caller-owned states), the item table is rewritten to point
+// at them (state buffer 0 and K1; buffer 1 the batch's second buffer) and the
+// stages start from buffer 0; without, it points back at the batch's own
+// buffers if a caller-state step changed it.
+int upload(dg_batch* b, const double* dt, const double* vw, hipStream_t s,
+           double* const* Uc = nullptr, double* const* K1c = nullptr) {
   if (b->upload_pending) {
     hipError_t e = hipEventSynchronize(b->upload_ev);
     if (e != hipSuccess) return bhip(b, e, "hipEventSynchronize");
     b->upload_pending = false;
+  }
+  const bool want_caller = Uc != nullptr;
+  if (want_caller || b->caller_items) {
+    for (int i = 0; i < b->n; ++i) {
+      dgmi::BatchItem& it = b->h_items[b->item_of[i]];
+      it.buf[0] = want_caller ? Uc[i] : b->A[i];
+      it.buf[1] = b->B[i];
+      it.K1 = want_caller ? K1c[i] : b->K1[i];
+    }
+    hipError_t e = hipMemcpyAsync(b->d_items, b->h_items, b->n * sizeof(dgmi::BatchItem),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return bhip(b, e, "item upload");
+    b->caller_items = want_caller;
   }
   for (int i = 0; i < b->n; ++i) {
     dgmi::BatchStep& st = b->h_steps[b->item_of[i]];
@@ -207,7 +228,7 @@ int upload(dg_batch* b, const double* dt, const double* vw, hipStream_t s) {
     st.vw[1] = vw ? vw[2 * i + 1] : 0.0;
     st.pad = 0.0;
   }
-  *b->h_parity = b->parity;
+  *b->h_parity = want_caller ? 0 : b->parity;
   hipError_t e = hipMemcpyAsync(b->d_steps, b->h_steps, b->n * sizeof(dgmi::BatchStep),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -338,9 +359,11 @@ static int batch_build(dg_batch* b, dg_ctx* const* ctxs, int n) {
       (e = hipHostMalloc((void**)&b->h_force, 4 * n * sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void**)&b->d_fitems, n * sizeof(dgmi::ForceItem))) != hipSuccess ||
       (e = hipHostMalloc((void**)&b->h_fitems, n * sizeof(dgmi::ForceItem))) != hipSuccess ||
+      (e = hipHostMalloc((void**)&b->h_items, n * sizeof(dgmi::BatchItem))) != hipSuccess ||
       (e = hipEventCreateWithFlags(&b->upload_ev, hipEventDisableTiming)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
     return bhip(b, e, "allocating batch tables");
+  std::copy(items.begin(), items.end(), b->h_items);
   return plan(b);
 }
 
@@ -385,6 +408,41 @@ int dg_batch_rk_step(dg_batch* b, const double* dt, const double* v_w, void* str
     if (rc != DG_OK) return rc;
   }
   b->parity ^= 1;  // five stages: the state now sits in the other buffer
+  return DG_OK;
+}
+
+int dg_batch_rk_step_states(dg_batch* b, double* const* U, double* const* K1, const double* dt,
+                            const double* v_w, void* stream) {
+  if (!b) return DG_EINVAL;
+  if (!U || !K1 || !dt || !v_w) return bfail(b, DG_EINVAL, "U, K1, dt and v_w are required");
+  for (int i = 0; i < b->n; ++i) {
+    if (!U[i] || !K1[i] || U[i] == K1[i])
+      return bfail(b, DG_EINVAL, "each instance needs distinct U and K1 device arrays");
+    if (!std::isfinite(dt[i]) || !std::isfinite(v_w[2 * i]) || !std::isfinite(v_w[2 * i + 1]))
+      return bfail(b, DG_EINVAL, "dt or v_w not finite");
+    for (int j = 0; j < i; ++j)
+      if (U[j] == U[i] || K1[j] == K1[i] || U[j] == K1[i] || K1[j] == U[i])
+        return bfail(b, DG_EINVAL, "two instances share a state or K1 array");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = upload(b, dt, v_w, s, U, K1);
+  if (rc != DG_OK) return rc;
+  if (b->use_graph) {
+    if (!b->exec) {
+      rc = capture(b);
+      if (rc != DG_OK) return rc;
+    }
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return bhip(b, e, "hipGraphLaunch");
+  } else {
+    rc = launch_step(b, s);
+    if (rc != DG_OK) return rc;
+  }
+  // five stages from buffer 0 end in buffer 1: copy each state back
+  for (int i = 0; i < b->n; ++i) {
+    hipError_t e = hipMemcpyAsync(U[i], b->B[i], state_bytes(b->ctx[i]), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return bhip(b, e, "hipMemcpyAsync");
+  }
   return DG_OK;
 }
 

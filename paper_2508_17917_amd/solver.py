@@ -161,6 +161,11 @@ class Batch:
     def rk_step(self, dt, v_w, stream=None):
         L.dg_batch_rk_step(self.b, dt, v_w, stream)
 
+    def rk_step_states(self, U, K1, dt, v_w, stream=None):
+        """One step of every instance on caller-owned states (lists of device
+        tensors U[i], K1[i]); the batch-owned states are not preserved."""
+        L.dg_batch_rk_step_states(self.b, U, K1, dt, v_w, stream)
+
     def force(self, v_w=None, stream=None):
         return L.dg_batch_force(self.b, self.n, v_w, stream)
 

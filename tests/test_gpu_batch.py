@@ -112,6 +112,73 @@ def test_batch_steps_equal_single_instance_steps(precision):
         s.close()
 
 
+@pytest.mark.parametrize("precision", [0, 2], ids=["fp64", "fp32-pert"])
+def test_batch_steps_on_caller_owned_states(precision):
+    """dg_batch_rk_step_states: the same launches (and graph) on the caller's
+    U and K1 arrays give dg_rk_step's bits on each instance; batch-owned
+    steps still work afterwards once the states are loaded again."""
+    torch = _torch()
+    from paper_2508_17917_amd import Batch
+    inst = _make(precision)
+    n = len(inst)
+    for shape in ((1, 4, 0, True), (0, 2, 1, False)):
+        _say("batch caller states precision=%d shape=%s" % (precision, shape))
+        b = Batch([s for s, _ in inst])
+        b.configure(*shape[:3], use_graph=shape[3])
+        Us = [_to_dev(torch, U) for _, U in inst]
+        K1s = [torch.zeros_like(U) for U in Us]
+        ref = [U.clone() for U in Us]
+        Kref = [torch.zeros_like(U) for U in Us]
+        for step in range(3):
+            dt, vw = _params(step, n)
+            b.rk_step_states(Us, K1s, dt, vw)
+            for i, (s, _) in enumerate(inst):
+                s.rk_step(ref[i], Kref[i], dt[i], v_w=vw[i])
+            torch.cuda.synchronize()
+            for i in range(n):
+                assert torch.equal(Us[i], ref[i]), (shape, step, i)
+                assert torch.equal(K1s[i], Kref[i]), (shape, step, i)
+        # back to batch-owned states
+        for i in range(n):
+            b.set_state(i, Us[i])
+        dt, vw = _params(5, n)
+        b.rk_step(dt, vw)
+        for i, (s, _) in enumerate(inst):
+            s.rk_step(ref[i], torch.zeros_like(ref[i]), dt[i], v_w=vw[i])
+        torch.cuda.synchronize()
+        for i in range(n):
+            assert torch.equal(b.get_state(i), ref[i]), ("batch-owned after", shape, i)
+        b.close()
+    for s, _ in inst:
+        s.close()
+
+
+def test_batch_states_argument_checks():
+    torch = _torch()
+    from paper_2508_17917_amd import Batch, Solver, _lib as L
+    mesh = mg.ogrid(8, 3, 0.5, 4.0, 1.3)
+    sol = [Solver(3, mesh, mu=2e-3, C_pen=1.0, U_inf=mg.free_stream(0.2)) for _ in range(2)]
+    inst = [(s, mg.noisy_free_stream((4, s.Np, s.K), mg.free_stream(0.2), np.random.default_rng(7)))
+            for s in sol]
+    b = Batch([s for s, _ in inst])
+    Us = [_to_dev(torch, U) for _, U in inst]
+    K1s = [torch.zeros_like(U) for U in Us]
+    dt, vw = _params(0, 2)
+    with pytest.raises(ValueError):
+        b.rk_step_states(Us[:1], K1s, dt, vw)
+    with pytest.raises(ValueError):
+        b.rk_step_states([Us[0], Us[1][:1]], K1s, dt, vw)   # too small
+    with pytest.raises(L.DGError) as e:
+        b.rk_step_states([Us[0], Us[0]], K1s, dt, vw)       # shared array
+    assert e.value.code == L.DG_EINVAL
+    with pytest.raises(L.DGError) as e:
+        b.rk_step_states(Us, Us, dt, vw)                     # U is K1
+    assert e.value.code == L.DG_EINVAL
+    b.close()
+    for s, _ in inst:
+        s.close()
+
+
 def test_batch_autotune_keeps_results():
     torch = _torch()
     from paper_2508_17917_amd import Batch
