@@ -421,7 +421,17 @@ int dg_mlp_forward(dg_mlp* m, const float* X, int64_t ldx, int64_t B, float* Y, 
 /* Gradient of the mean squared error (over B x n_out normalised entries)
  * against raw targets T (device FP32, row stride ldt), kept for dg_mlp_adam
  * (partials per workgroup summed in a fixed order: reproducible).  With loss
- * non-NULL the loss is returned on the host (synchronises). */
+ * non-NULL the loss is returned on the host (synchronises).  For
+ * n_in <= 32, H = 128 and n_out <= 64 the step runs as one fused kernel
+ * (forward, loss, backward and weight gradients per 16-row tile, activations
+ * in registers and LDS; HBM traffic the inputs and targets) unless
+ * dg_mlp_set_schedule chose the layer-by-layer schedule. */
+/* Training schedule of dg_mlp_backward: 1 (the default) the fused kernel
+ * where it is built, 0 layer by layer (each layer's activations stored and
+ * re-read).  Both give the same gradient up to the order of the sums and the
+ * FP32 (fused) or bfloat16 (stored) GELU derivatives.  DG_EINVAL otherwise. */
+int dg_mlp_set_schedule(dg_mlp* m, int fused);
+
 int dg_mlp_backward(dg_mlp* m, const float* X, int64_t ldx, const float* T, int64_t ldt,
                     int64_t B, double* loss, void* stream);
 

@@ -35,6 +35,7 @@ SIGNATURES = {
     "dg_set_wall_flux": (_I, [_P, _I]),
     "dg_set_curved_elements": (_I, [_P, _L, ctypes.POINTER(ctypes.c_int32), _DP]),
     "dg_batch_rk_step_states": (_I, [_P, _P, _P, _DP, _DP, _P]),
+    "dg_mlp_set_schedule": (_I, [_P, _I]),
     "dg_set_mesh": (_I, [_P, _L, _DP, _DP, _L, ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int8), _DP]),
     "dg_setup_host": (_I, [_P]),
@@ -566,6 +567,11 @@ def dg_mlp_forward(m, X, Y, B=None, stream=None):
     x, ldx = _rows(X, B, n_in, "X")
     y, ldy = _rows(Y, B, n_out, "Y")
     return _mcheck(load().dg_mlp_forward(m, x, ldx, B, y, ldy, _stream(stream)), m)
+
+
+def dg_mlp_set_schedule(m, fused):
+    """1: the fused training kernel where built (default); 0: layer by layer."""
+    return _mcheck(load().dg_mlp_set_schedule(m, int(fused)), m)
 
 
 def dg_mlp_backward(m, X, T, B=None, want_loss=True, stream=None):

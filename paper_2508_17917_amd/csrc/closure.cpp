@@ -94,6 +94,7 @@ int mlp_build(dg_mlp* m, int n_in, int n_hidden, int n_out, int64_t max_batch) {
   const int wb_rows[3] = {n_hidden, n_hidden, d.out_pad};
   const int wt_rows[3] = {d.in_pad, n_hidden, n_hidden};
   d.nparts = 512;  // weight-gradient workgroups: two per CU at most batch sizes
+  d.fused = 1;
   const int64_t B = max_batch;
   const int64_t part_len = (int64_t)n_hidden * n_hidden + n_hidden;
   hipError_t e;
@@ -247,6 +248,13 @@ int dg_mlp_backward(dg_mlp* m, const float* X, int64_t ldx, const float* T, int6
     for (double x : h) s += x;
     *loss = s / ((double)B * m->d.n_out);
   }
+  return DG_OK;
+}
+
+int dg_mlp_set_schedule(dg_mlp* m, int fused) {
+  if (!m) return DG_EINVAL;
+  if (fused != 0 && fused != 1) return mfail(m, DG_EINVAL, "schedule must be 0 (layer by layer) or 1 (fused)");
+  m->d.fused = fused;
   return DG_OK;
 }
 

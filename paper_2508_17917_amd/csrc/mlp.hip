@@ -347,6 +347,325 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   if (threadIdx.x < g.nvalid) out[(int64_t)g.nvalid * g.kvalid + threadIdx.x] = bsum;
 }
 
+// ---------------------------------------------------------------- fused training step
+// One training step's forward pass, loss, backward pass and weight gradients
+// in one launch, for the shapes in_pad = 16 KIT, H = 16 HT, out_pad = 16 OT.
+// A workgroup of four waves takes 64 samples at a time, one 16-row tile per
+// wave.  A wave's tile goes through the three layers in registers: the
+// transposed products (weights as the row operand) leave lane l with sample
+// l%16 and four consecutive output columns, which are exactly its B operand
+// for the next layer, and the GELU derivatives stay in FP32 registers for the
+// backward pass.  What the weight gradients need -- the normalised inputs,
+// both hidden activations and the three output gradients -- is written to LDS
+// transposed ([column][sample], bfloat16), so that after a barrier every
+// wave reads its operands as 8-byte words: wave w accumulates the output
+// tiles of dW1, dW2 with row tiles w and w + 4, and of dW3 with row tile w,
+// over the block's 64 samples on the matrix cores.  The bias gradients are
+// per-thread sums over the same arrays (fixed order).  At the end each
+// workgroup writes its whole gradient (the parameter vector's layout) as one
+// partial; reduce_parts_kernel sums them in a fixed order.  HBM traffic per
+// sample: the inputs and targets only.
+struct TrainArgs {
+  const float* X;
+  int64_t ldx;
+  const float* T;
+  int64_t ldt;
+  int64_t B, chunk;          // samples; samples per workgroup (multiple of 64)
+  int n_in, n_out;
+  const float* in_mean;
+  const float* in_rstd;
+  const float* out_mean;
+  const float* out_std;
+  const unsigned short* W1;  // [H][ldw1]
+  const unsigned short* W2;  // [H][ldw2]
+  const unsigned short* W3;  // [out_pad][ldw3]
+  int ldw1, ldw2, ldw3;
+  const float* b1;
+  const float* b2;
+  const float* b3;
+  float loss_scale;          // 2 / (B n_out)
+  double* loss_part;         // one per workgroup
+  float* part;               // [gridDim][stride]: W1 b1 W2 b2 W3 b3
+  int64_t stride;
+  int64_t woff[3], boff[3];
+};
+
+__device__ __forceinline__ bf16x4 bf4(const float v[4]) {
+  return bf16x4{(short)f2bf(v[0]), (short)f2bf(v[1]), (short)f2bf(v[2]), (short)f2bf(v[3])};
+}
+__device__ __forceinline__ bf16x4 ld_bf4(const unsigned short* p) {
+  const uint2 w = *(const uint2*)p;
+  return bf16x4{(short)(w.x & 0xffff), (short)(w.x >> 16), (short)(w.y & 0xffff), (short)(w.y >> 16)};
+}
+__device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <int KIT, int HT, int OT>
+struct TrainShape {
+  static constexpr int KI = 16 * KIT, H = 16 * HT, NO = 16 * OT;
+  static constexpr int L1 = KI + 4, L2 = H + 4, L3 = H + 4;  // weight rows in LDS
+  static constexpr int LT = 64 + 4;                           // transposed rows (samples)
+  static constexpr int W_SZ = H * L1 + H * L2 + NO * L3;
+  static constexpr int T_SZ = LT * (KI + 4 * H + NO);
+};
+
+template <int KIT, int HT, int OT>
+__global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
+  using S = TrainShape<KIT, HT, OT>;
+  constexpr int KI = S::KI, H = S::H, NO = S::NO, L1 = S::L1, L2 = S::L2, L3 = S::L3, LT = S::LT;
+  static_assert(HT == 8 && OT <= 4, "shape not built: waves take row tiles wid and wid + 4");
+  __shared__ __attribute__((aligned(16))) unsigned short sW[S::W_SZ];
+  __shared__ __attribute__((aligned(16))) unsigned short sT[S::T_SZ];
+  __shared__ double sLoss[4];
+  unsigned short* sW1 = sW;
+  unsigned short* sW2 = sW1 + H * L1;
+  unsigned short* sW3 = sW2 + H * L2;
+  unsigned short* tX = sT;                 // [KI][LT]
+  unsigned short* tH1 = tX + KI * LT;      // [H][LT]
+  unsigned short* tH2 = tH1 + H * LT;
+  unsigned short* tZ1 = tH2 + H * LT;      // dZ1
+  unsigned short* tZ2 = tZ1 + H * LT;      // dZ2
+  unsigned short* tDY = tZ2 + H * LT;      // [NO][LT]
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int ar = lane & 15, ak = 4 * (lane >> 4);
+
+  // weights into LDS, 8-byte words
+  for (int i = threadIdx.x; i < H * (KI / 4); i += 256) {
+    const int n = i / (KI / 4), k = 4 * (i - n * (KI / 4));
+    *(uint2*)(sW1 + n * L1 + k) = *(const uint2*)(g.W1 + (int64_t)n * g.ldw1 + k);
+  }
+  for (int i = threadIdx.x; i < H * (H / 4); i += 256) {
+    const int n = i / (H / 4), k = 4 * (i - n * (H / 4));
+    *(uint2*)(sW2 + n * L2 + k) = *(const uint2*)(g.W2 + (int64_t)n * g.ldw2 + k);
+  }
+  for (int i = threadIdx.x; i < NO * (H / 4); i += 256) {
+    const int n = i / (H / 4), k = 4 * (i - n * (H / 4));
+    *(uint2*)(sW3 + n * L3 + k) = *(const uint2*)(g.W3 + (int64_t)n * g.ldw3 + k);
+  }
+
+  f32x4 acc1[2][KIT], acc2[2][HT], acc3[HT];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int t = 0; t < KIT; ++t) acc1[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < HT; ++t) acc2[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int t = 0; t < HT; ++t) acc3[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum[2] = {0.f, 0.f};  // bias entries threadIdx.x and threadIdx.x + 256
+  double loss = 0.0;
+
+  const int64_t s_begin = (int64_t)blockIdx.x * g.chunk;
+  const int64_t s_end = s_begin + g.chunk < g.B ? s_begin + g.chunk : g.B;
+  // a tile's inputs and targets (raw FP32), loaded one block ahead
+  float xr[KIT][4], tr[OT][4];
+  auto load = [&](int64_t s0) {
+    const int64_t row = s0 + 16 * wid + ar;
+    const bool rok = row < s_end;
+#pragma unroll
+    for (int ks = 0; ks < KIT; ++ks)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * ks + ak + j;
+        xr[ks][j] = (rok && k < g.n_in) ? g.X[row * g.ldx + k] : 0.f;
+      }
+#pragma unroll
+    for (int t = 0; t < OT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * t + ak + v;
+        tr[t][v] = (rok && c < g.n_out) ? g.T[row * g.ldt + c] : 0.f;
+      }
+  };
+  if (s_begin < s_end) load(s_begin);
+  __syncthreads();
+
+#pragma unroll 1
+  for (int64_t s0 = s_begin; s0 < s_end; s0 += 64) {
+    const int64_t row = s0 + 16 * wid + ar;
+    const bool rok = row < s_end;
+    const int col = 16 * wid + ar;  // this lane's sample column in the transposed arrays
+    // ---- forward: normalised inputs (zero beyond n_in and past the end)
+    bf16x4 a1[KIT];
+#pragma unroll
+    for (int ks = 0; ks < KIT; ++ks) {
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * ks + ak + j;
+        v[j] = (rok && k < g.n_in) ? (xr[ks][j] - g.in_mean[k]) * g.in_rstd[k] : 0.f;
+      }
+      a1[ks] = bf4(v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tX[(16 * ks + ak + j) * LT + col] = (unsigned short)a1[ks][j];
+    }
+    float d1[HT][4], d2[HT][4];  // GELU derivatives at the pre-activations
+    bf16x4 h1[HT], h2[HT];
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KIT; ++ks) acc = mma(ld_bf4(sW1 + (16 * t + ar) * L1 + 16 * ks + ak), a1[ks], acc);
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gelu_pair(acc[j] + g.b1[16 * t + ak + j], v[j], d1[t][j]);
+      h1[t] = bf4(v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tH1[(16 * t + ak + j) * LT + col] = (unsigned short)h1[t][j];
+    }
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < HT; ++ks) acc = mma(ld_bf4(sW2 + (16 * t + ar) * L2 + 16 * ks + ak), h1[ks], acc);
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gelu_pair(acc[j] + g.b2[16 * t + ak + j], v[j], d2[t][j]);
+      h2[t] = bf4(v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tH2[(16 * t + ak + j) * LT + col] = (unsigned short)h2[t][j];
+    }
+    // ---- output layer and loss: dY = 2 (y - t_n) / (B n_out), normalised units
+    bf16x4 dy[OT];
+#pragma unroll
+    for (int t = 0; t < OT; ++t) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < HT; ++ks) acc = mma(ld_bf4(sW3 + (16 * t + ar) * L3 + 16 * ks + ak), h2[ks], acc);
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = 16 * t + ak + j;
+        v[j] = 0.f;
+        if (rok && c < g.n_out) {
+          const float tn = (tr[t][j] - g.out_mean[c]) / g.out_std[c];
+          const float res = acc[j] + g.b3[c] - tn;
+          loss += (double)res * (double)res;
+          v[j] = g.loss_scale * res;
+        }
+      }
+      dy[t] = bf4(v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tDY[(16 * t + ak + j) * LT + col] = (unsigned short)dy[t][j];
+    }
+    // the next block's inputs, in flight during the backward pass
+    if (s0 + 64 < s_end) load(s0 + 64);
+    // ---- backward: dZ2 = (dY W3) gelu'(Z2), dZ1 = (dZ2 W2) gelu'(Z1); the
+    // transposed weights are read from the row-major copies, four rows apart
+    bf16x4 z2[HT];
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < OT; ++ks) {
+        const unsigned short* w = sW3 + (16 * ks + ak) * L3 + 16 * t + ar;
+        const bf16x4 wt{(short)w[0], (short)w[L3], (short)w[2 * L3], (short)w[3 * L3]};
+        acc = mma(wt, dy[ks], acc);
+      }
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = acc[j] * d2[t][j];
+      z2[t] = bf4(v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tZ2[(16 * t + ak + j) * LT + col] = (unsigned short)z2[t][j];
+    }
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < HT; ++ks) {
+        const unsigned short* w = sW2 + (16 * ks + ak) * L2 + 16 * t + ar;
+        const bf16x4 wt{(short)w[0], (short)w[L2], (short)w[2 * L2], (short)w[3 * L2]};
+        acc = mma(wt, z2[ks], acc);
+      }
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = acc[j] * d1[t][j];
+      const bf16x4 z1 = bf4(v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tZ1[(16 * t + ak + j) * LT + col] = (unsigned short)z1[j];
+    }
+    __syncthreads();
+    // ---- weight gradients of the block: dW[n][k] += sum_s dZ[s][n] A[s][k]
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int sb = 16 * ks + ak;  // samples sb .. sb + 3 of the block
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int nt = wid + 4 * i;
+        const bf16x4 az1 = ld_bf4(tZ1 + (16 * nt + ar) * LT + sb);
+        const bf16x4 az2 = ld_bf4(tZ2 + (16 * nt + ar) * LT + sb);
+#pragma unroll
+        for (int kt = 0; kt < KIT; ++kt) acc1[i][kt] = mma(az1, ld_bf4(tX + (16 * kt + ar) * LT + sb), acc1[i][kt]);
+#pragma unroll
+        for (int kt = 0; kt < HT; ++kt) acc2[i][kt] = mma(az2, ld_bf4(tH1 + (16 * kt + ar) * LT + sb), acc2[i][kt]);
+      }
+      if (wid < OT) {
+        const bf16x4 ady = ld_bf4(tDY + (16 * wid + ar) * LT + sb);
+#pragma unroll
+        for (int kt = 0; kt < HT; ++kt) acc3[kt] = mma(ady, ld_bf4(tH2 + (16 * kt + ar) * LT + sb), acc3[kt]);
+      }
+    }
+    // bias gradients: thread t sums its rows of dZ1 | dZ2 | dY over the block
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = threadIdx.x + 256 * r;
+      if (e < 2 * H + NO) {
+        const unsigned short* rowp = e < H ? tZ1 + e * LT : (e < 2 * H ? tZ2 + (e - H) * LT : tDY + (e - 2 * H) * LT);
+        float sum = 0.f;
+#pragma unroll
+        for (int s = 0; s < 64; s += 4) {
+          const bf16x4 q = ld_bf4(rowp + s);
+          sum += ((bf2f((unsigned short)q[0]) + bf2f((unsigned short)q[1])) + bf2f((unsigned short)q[2])) +
+                 bf2f((unsigned short)q[3]);
+        }
+        bsum[r] += sum;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- this workgroup's partial: the whole gradient vector
+  float* out = g.part + (int64_t)blockIdx.x * g.stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int nt = wid + 4 * i;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = 16 * nt + ak + v;
+#pragma unroll
+      for (int kt = 0; kt < KIT; ++kt) {
+        const int k = 16 * kt + ar;
+        if (k < g.n_in) out[g.woff[0] + (int64_t)n * g.n_in + k] = acc1[i][kt][v];
+      }
+#pragma unroll
+      for (int kt = 0; kt < HT; ++kt) out[g.woff[1] + (int64_t)n * H + 16 * kt + ar] = acc2[i][kt][v];
+    }
+  }
+  if (wid < OT) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = 16 * wid + ak + v;
+      if (n < g.n_out)
+#pragma unroll
+        for (int kt = 0; kt < HT; ++kt) out[g.woff[2] + (int64_t)n * H + 16 * kt + ar] = acc3[kt][v];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int e = threadIdx.x + 256 * r;
+    if (e < H) out[g.boff[0] + e] = bsum[r];
+    else if (e < 2 * H) out[g.boff[1] + (e - H)] = bsum[r];
+    else if (e < 2 * H + g.n_out) out[g.boff[2] + (e - 2 * H)] = bsum[r];
+  }
+  for (int o = 32; o > 0; o >>= 1) loss += __shfl_down(loss, o, 64);
+  if (lane == 0) sLoss[wid] = loss;
+  __syncthreads();
+  if (threadIdx.x == 0) g.loss_part[blockIdx.x] = ((sLoss[0] + sLoss[1]) + sLoss[2]) + sLoss[3];
+}
+
 // gradient = sum over the workgroup partials in a fixed order: wave w of a
 // workgroup sums the partials p = w mod 4 in increasing p for 64 consecutive
 // entries, then the four wave sums are added in wave order
@@ -686,9 +1005,58 @@ int mlp_forward(const MlpDev& d, const float* X, int64_t ldx, int64_t B, float* 
   return dense(NTO, EPI_OUT, false, a, blocks, s, err);
 }
 
+namespace {
+template <int KIT, int HT, int OT>
+int train_go(const TrainArgs& a, int blocks, hipStream_t s, std::string& err) {
+  hipLaunchKernelGGL((train_kernel<KIT, HT, OT>), dim3(blocks), dim3(256), 0, s, a);
+  return lerr(err, "training kernel launch");
+}
+
+// The fused training step for the shapes it is built for (in_pad 32,
+// H 128, out_pad 32 or 64); returns 1 (nothing launched) for others.
+int train_fused(const MlpDev& d, const float* X, int64_t ldx, const float* T, int64_t ldt,
+                int64_t B, int* loss_parts, hipStream_t s, std::string& err) {
+  const int KIT = d.in_pad / 16, HT = d.H / 16, OT = d.out_pad / 16;
+  if (KIT != 2 || HT != 8 || (OT != 2 && OT != 4)) return 1;
+  // workgroups: 256 (one per CU) at most, each a whole number of 64-sample
+  // blocks, and no more whole-gradient partials than the buffer holds
+  const int64_t cap = (int64_t)d.nparts * ((int64_t)d.H * d.H + d.H) / d.nparams;
+  const int64_t maxwg = cap < 256 ? cap : 256;
+  if (maxwg < 1) return 1;
+  const int64_t chunk = ((B + maxwg - 1) / maxwg + 63) / 64 * 64;
+  const int blocks = (int)((B + chunk - 1) / chunk);
+  if (blocks > 1024) return 1;  // the loss partial buffer
+  TrainArgs a{};
+  a.X = X; a.ldx = ldx; a.T = T; a.ldt = ldt; a.B = B; a.chunk = chunk;
+  a.n_in = d.n_in; a.n_out = d.n_out;
+  a.in_mean = d.in_mean; a.in_rstd = d.in_rstd; a.out_mean = d.out_mean; a.out_std = d.out_std;
+  a.W1 = d.wb[0]; a.W2 = d.wb[1]; a.W3 = d.wb[2];
+  a.ldw1 = d.ldw[0]; a.ldw2 = d.ldw[1]; a.ldw3 = d.ldw[2];
+  a.b1 = d.params + d.boff[0]; a.b2 = d.params + d.boff[1]; a.b3 = d.params + d.boff[2];
+  a.loss_scale = (float)(2.0 / ((double)B * d.n_out));
+  a.loss_part = d.loss_part;
+  a.part = d.part;
+  a.stride = d.nparams;
+  for (int l = 0; l < 3; ++l) {
+    a.woff[l] = d.woff[l];
+    a.boff[l] = d.boff[l];
+  }
+  int rc = OT == 4 ? train_go<2, 8, 4>(a, blocks, s, err) : train_go<2, 8, 2>(a, blocks, s, err);
+  if (rc) return rc;
+  if (loss_parts) *loss_parts = blocks;
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((d.nparams + 63) / 64)), dim3(256), 0, s,
+                     (const float*)d.part, blocks, (int64_t)d.nparams, (int64_t)d.nparams, d.grad);
+  return lerr(err, "reduce kernel launch");
+}
+}  // namespace
+
 int mlp_backward(const MlpDev& d, const float* X, int64_t ldx, const float* T, int64_t ldt,
                  int64_t B, int* loss_parts, void* stream, std::string& err) {
   hipStream_t s = (hipStream_t)stream;
+  if (d.fused) {
+    const int rc = train_fused(d, X, ldx, T, ldt, B, loss_parts, s, err);
+    if (rc != 1) return rc;
+  }
   const int blocks = dense_blocks(B);
   if (loss_parts) *loss_parts = blocks;  // the loss layer writes one partial per workgroup
   const int NTH = d.H / 16, NTO = d.out_pad / 16;

@@ -40,6 +40,7 @@ struct MlpDev {
   unsigned short* dZ1;
   float* part;                 // weight-gradient partials [nparts][...]
   int nparts;
+  int fused;                   // training step in one fused kernel where built (else layer by layer)
   double* loss_part;           // [1024]
 };
 

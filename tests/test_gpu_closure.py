@@ -87,15 +87,15 @@ def test_order_maps_and_samples_match_oracle():
     hi.close()
 
 
-def _net_case(seed, B=300):
+def _net_case(seed, B=300, n_out=60):
     rng = np.random.default_rng(seed)
-    params = mg.mlp_init(rng, 28, 128, 60)
+    params = mg.mlp_init(rng, 28, 128, n_out)
     X = (rng.standard_normal((B, 28)) * 0.3 + 0.1).astype(np.float32)
-    T = (rng.standard_normal((B, 60)) * 0.02 - 0.01).astype(np.float32)
+    T = (rng.standard_normal((B, n_out)) * 0.02 - 0.01).astype(np.float32)
     norm = [(0.1 + 0.05 * rng.standard_normal(28)).astype(np.float32),
             (0.3 * np.exp(0.2 * rng.standard_normal(28))).astype(np.float32),
-            (-0.01 + 0.005 * rng.standard_normal(60)).astype(np.float32),
-            (0.02 * np.exp(0.2 * rng.standard_normal(60))).astype(np.float32)]
+            (-0.01 + 0.005 * rng.standard_normal(n_out)).astype(np.float32),
+            (0.02 * np.exp(0.2 * rng.standard_normal(n_out))).astype(np.float32)]
     return params, X, T, norm
 
 
@@ -109,10 +109,10 @@ def _unpack(p, n_in=28, h=128, n_out=60):
     return out
 
 
-def _oracle_inputs(params, X, T, norm):
+def _oracle_inputs(params, X, T, norm, n_out=60):
     """Parameters with bfloat16 weights, bfloat16 normalised inputs, and
     normalised targets, as the GPU sees them."""
-    q = _unpack(params)
+    q = _unpack(params, n_out=n_out)
     for k in ("W1", "W2", "W3"):
         q[k] = OC.round_bf16(q[k].astype(np.float32)).astype(np.float64)
     rstd = (np.float32(1.0) / norm[1]).astype(np.float32)
@@ -174,6 +174,49 @@ def test_network_forward_backward_adam_match_oracle():
     L.dg_mlp_backward(m, Xd, Td, want_loss=False)
     assert np.array_equal(ga, L.dg_mlp_get_grad(m))
     L.dg_mlp_destroy(m)
+
+
+@pytest.mark.parametrize("n_out,B", [(60, 300), (24, 2049), (60, 5000)])
+def test_fused_and_layered_training_steps(n_out, B):
+    """The fused training kernel (forward, loss, backward and weight
+    gradients per 16-row tile) and the layer-by-layer schedule: both match
+    the FP64 oracle network at the gradient bound (3e-2 normwise), their
+    losses agree, and each is reproducible.  Ragged batches (the last 64-sample
+    block partly empty) and both output widths built (60 -> 64, 24 -> 32)."""
+    torch = _torch()
+    from paper_2508_17917_amd import _lib as L
+    params, X, T, norm = _net_case(3, B=B, n_out=n_out)
+    q, Xn, Tn = _oracle_inputs(params, X, T, norm, n_out=n_out)
+    lo, go = OC.loss_and_grads(q, Xn, Tn)
+    Xd = torch.from_numpy(X).cuda()
+    Td = torch.from_numpy(T).cuda()
+    grads, losses = {}, {}
+    for fused in (1, 0):
+        m = L.dg_mlp_create(28, 128, n_out, B)
+        L.dg_mlp_set_params(m, params)
+        L.dg_mlp_set_normalization(m, *norm)
+        L.dg_mlp_set_schedule(m, fused)
+        _say("mlp backward fused=%d n_out=%d B=%d" % (fused, n_out, B))
+        losses[fused] = L.dg_mlp_backward(m, Xd, Td)
+        g = L.dg_mlp_get_grad(m)
+        grads[fused] = _unpack(g, n_out=n_out)
+        L.dg_mlp_backward(m, Xd, Td, want_loss=False)
+        assert np.array_equal(g, L.dg_mlp_get_grad(m)), "not reproducible"
+        L.dg_mlp_destroy(m)
+        assert abs(losses[fused] - lo) <= 1.5e-2 * lo
+        for k in go:
+            e = _rel(grads[fused][k], go[k])
+            _say("fused=%d grad %s rel err %.3e" % (fused, k, e))
+            assert e <= 3e-2, (fused, k, e)
+    assert abs(losses[1] - losses[0]) <= 1e-3 * losses[0]
+    for k in go:
+        assert _rel(grads[1][k], grads[0][k]) <= 3e-2, k
+    with pytest.raises(L.DGError):
+        m = L.dg_mlp_create(28, 128, n_out, 64)
+        try:
+            L.dg_mlp_set_schedule(m, 2)
+        finally:
+            L.dg_mlp_destroy(m)
 
 
 def test_training_fits_a_smooth_map():
