@@ -146,6 +146,24 @@ def closure_bytes_per_sample(n_in, H, n_out):
     return fwd + bwd + wgr
 
 
+def closure_roofline(bytes_sample, flops_sample, samples, t):
+    """A training run against HBM (its algorithmic bytes) and the bfloat16
+    matrix cores (its flops), each a lower bound on the time; the larger
+    binds."""
+    tb = bytes_sample * samples / (HBM_PEAK_GBS * 1e9)
+    tf = flops_sample * samples / (MFMA_PEAK_TFLOPS["bf16"] * 1e12)
+    if tb >= tf:
+        bound, ach, peak, unit = "hbm", bytes_sample * samples / t / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        bound, ach, peak, unit = "mfma", flops_sample * samples / t / 1e12, MFMA_PEAK_TFLOPS["bf16"], "TFLOP/s"
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": None,
+            "kernel": "train_kernel (forward, loss, backward, weight gradients) + "
+                      "reduce_parts_kernel + adam_kernel (one training step)",
+            "bytes_per_sample": bytes_sample, "flops_per_sample": flops_sample,
+            "frac_hbm": tb / t, "frac_mfma_bf16": tf / t}
+
+
 def oi_flops_per_element(Np, Nfp):
     """(operator products, pointwise) FP64 flops of one over-integrated RHS +
     stage per element (q points per direction, q^2 element points, 3q face
@@ -507,7 +525,26 @@ def run_closure(args):
     steps = args.epochs * (Nc // args.batch)
     samples = steps * args.batch
     flops_sample = 2.0 * (28 * 128 + 128 * 128 + 128 * 24)
-    bytes_sample = closure_bytes_per_sample(28, 128, 24)
+    # the training step runs as one fused kernel: its algorithmic HBM bytes
+    # are the inputs and targets (FP32), its flops three passes of the network
+    bytes_sample = 4 * (28 + 24)
+    # both schedules on the same rows, 20 steps each (the trained network)
+    sched = {}
+    from paper_2508_17917_amd import _lib as L
+    Bt = min(args.batch, Xc.shape[0])
+    for fused in (1, 0):
+        L.dg_mlp_set_schedule(cl.mc, fused)
+        L.dg_mlp_backward(cl.mc, Xc[:Bt], Tc[:Bt], want_loss=False)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(20):
+            L.dg_mlp_backward(cl.mc, Xc[:Bt], Tc[:Bt], want_loss=False)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sched["fused" if fused else "layer_by_layer"] = {
+            "us_per_backward": ev0.elapsed_time(ev1) * 1e3 / 20,
+            "hbm_bytes_per_sample": bytes_sample if fused else closure_bytes_per_sample(28, 128, 24)}
+    L.dg_mlp_set_schedule(cl.mc, 1)
     # evaluation at Re = 120
     lo, hi, U_inf = pair(120.0)
     cl.rebind(lo, hi)
@@ -567,15 +604,8 @@ def run_closure(args):
                    "loss_last": losses[-1] if losses else None, "data_s": t_data,
                    "eval": evals, "inference_us_per_correction": t_inf * 1e6,
                    "inference_elements_per_s": K / t_inf},
-        "roofline": {"bound": "hbm", "achieved": bytes_sample * samples / t_train / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": bytes_sample * samples / t_train / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None,
-                     "kernel": "dense_kernel / wgrad_kernel / reduce_parts_kernel / adam_kernel "
-                               "(one training step)",
-                     "bytes_per_sample": bytes_sample,
-                     "mfma_tflops": 3 * flops_sample * samples / t_train / 1e12,
-                     "mfma_frac": 3 * flops_sample * samples / t_train / 1e12 / 2500.0},
+        "roofline": closure_roofline(bytes_sample, 3 * flops_sample, samples, t_train),
+        "schedules": sched,
     }
     cl.close()
     for a, b in keep:
