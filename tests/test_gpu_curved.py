@@ -232,3 +232,34 @@ def test_batches_refuse_curved_contexts():
         Batch([s])
     assert err.value.code == L.DG_EUNSUPPORTED
     s.close()
+
+
+def test_gpu_residual_of_an_exact_vortex_converges_with_curved_walls():
+    """The library's right-hand side of the exact potential vortex between
+    two walls (mu = 0: slip walls) on three nested annuli at p = 3: with the
+    walls curved its mass norm falls at order above 2.5, with straight walls
+    it stalls (below 1) -- the same rates as the oracle's."""
+    torch = _torch()
+    from tests.test_oracle_curved import _annulus_walls, _potential_vortex
+    res = []
+    for nt, nr in ((8, 2), (16, 4), (32, 8)):
+        mesh = _annulus_walls(nt, nr)
+        dg, dc, curved = _curved_oracle(mesh, 3, dict(mu=0.0, C_pen=1.0), mg.TAG_WALL)
+        row = []
+        for cv, geo in ((None, dg), (curved, dc)):
+            _say("vortex residual %dx%d curved=%s" % (nt, nr, cv is not None))
+            s = _solver(mesh, 3, dg.phys, cv)
+            x, y = s.nodes()
+            U = _potential_vortex(x.T, y.T)
+            R = _from_dev(s.rhs(_to_dev(torch, U)))
+            if cv is None:
+                row.append(geo.l2_norm(R).max())
+            else:
+                row.append(np.sqrt(np.einsum("fik,kij,fjk->f", R, geo.mesh.MK, R)).max())
+            s.close()
+        res.append(row)
+    r = np.array(res)
+    rate_s = np.log2(r[:-1, 0] / r[1:, 0])
+    rate_c = np.log2(r[:-1, 1] / r[1:, 1])
+    _say("rates straight %s curved %s" % (rate_s, rate_c))
+    assert np.all(rate_c > 2.5) and np.all(rate_s < 1.0)

@@ -2,9 +2,10 @@
 not depend on it: the affine oracle where nothing is curved, free-stream
 preservation and exact linear fields (the isoparametric property), areas by
 Green's theorem on the boundary curves, the exactness of the mass matrices,
-a state at rest whose momentum and mass tendencies vanish exactly, and the
+a state at rest whose momentum and mass tendencies vanish exactly, the
 wall force of a linear pressure field (the divergence theorem over the body
-the curved wall encloses)."""
+the curved wall encloses), and the order at which the residual of an exact
+steady vortex between curved slip walls falls."""
 import numpy as np
 import pytest
 from scipy.special import roots_legendre
@@ -202,3 +203,48 @@ def test_wall_force_of_a_linear_pressure(p):
     assert abs(body - np.pi * 0.25) < 5e-2 * np.pi * 0.25
     assert abs(F[0] + b * body) < 1e-13
     assert abs(F[1]) < 1e-13
+
+
+def _potential_vortex(x, y, gamma=1.4, circ=0.5):
+    """u_theta = circ / (2 pi r), homentropic (c_inf = 1 at infinity): an exact
+    steady solution of the Euler equations between circular slip walls."""
+    r2 = x * x + y * y
+    ut = circ / (2.0 * np.pi * np.sqrt(r2))
+    u, v = -ut * y / np.sqrt(r2), ut * x / np.sqrt(r2)
+    c2 = 1.0 - 0.5 * (gamma - 1.0) * ut * ut
+    rho = c2 ** (1.0 / (gamma - 1.0))
+    pr = rho ** gamma / gamma
+    return np.stack([rho, rho * u, rho * v, pr / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def _annulus_walls(nt, nr):
+    m = _retag(mg.ogrid(nt, nr, 0.5, 1.5, 1.0), mg.TAG_FAR, mg.TAG_WALL)
+    return m
+
+
+def vortex_residuals(p, levels=((8, 2), (16, 4), (32, 8))):
+    """Mass-norm residual of the exact state on straight and curved annuli."""
+    out = []
+    for nt, nr in levels:
+        m = _annulus_walls(nt, nr)
+        dg, dc, _ = _curved(m, p, mu=0.0, C_pen=1.0)
+        rs = dg.l2_norm(dg.rhs(_potential_vortex(dg.mesh.x, dg.mesh.y))).max()
+        R = dc.rhs(_potential_vortex(dc.mesh.x, dc.mesh.y))
+        rc = np.sqrt(np.einsum("fik,kij,fjk->f", R, dc.mesh.MK, R)).max()
+        out.append((rs, rc))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_curved_walls_converge_on_an_exact_vortex(p):
+    """With mu = 0 the wall flux is the slip wall's (pressure only) and the
+    potential vortex is steady: the discrete residual of the exact state
+    measures the consistency error.  Curved walls: it falls at order about p
+    (rates above p - 0.5 over two refinements); straight walls (polygons):
+    the wall normals are wrong by O(h) and it stalls (rates below 1)."""
+    r = vortex_residuals(p)
+    rate_s = np.log2(r[:-1, 0] / r[1:, 0])
+    rate_c = np.log2(r[:-1, 1] / r[1:, 1])
+    assert np.all(rate_c > p - 0.5), rate_c
+    assert np.all(rate_s < 1.0), rate_s
+    assert r[-1, 1] < 0.1 * r[-1, 0]
