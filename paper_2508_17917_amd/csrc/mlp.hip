@@ -503,26 +503,34 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
     }
     float d1[HT][4], d2[HT][4];  // GELU derivatives at the pre-activations
     bf16x4 h1[HT], h2[HT];
+    // the HT output tiles as independent accumulator chains (k-steps outer)
+    f32x4 acc[HT];
+#pragma unroll
+    for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KIT; ++ks)
+#pragma unroll
+      for (int t = 0; t < HT; ++t) acc[t] = mma(ld_bf4(sW1 + (16 * t + ar) * L1 + 16 * ks + ak), a1[ks], acc[t]);
 #pragma unroll
     for (int t = 0; t < HT; ++t) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < KIT; ++ks) acc = mma(ld_bf4(sW1 + (16 * t + ar) * L1 + 16 * ks + ak), a1[ks], acc);
       float v[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) gelu_pair(acc[j] + g.b1[16 * t + ak + j], v[j], d1[t][j]);
+      for (int j = 0; j < 4; ++j) gelu_pair(acc[t][j] + g.b1[16 * t + ak + j], v[j], d1[t][j]);
       h1[t] = bf4(v);
 #pragma unroll
       for (int j = 0; j < 4; ++j) tH1[(16 * t + ak + j) * LT + col] = (unsigned short)h1[t][j];
     }
 #pragma unroll
-    for (int t = 0; t < HT; ++t) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < HT; ++ks) acc = mma(ld_bf4(sW2 + (16 * t + ar) * L2 + 16 * ks + ak), h1[ks], acc);
+    for (int ks = 0; ks < HT; ++ks)
+#pragma unroll
+      for (int t = 0; t < HT; ++t) acc[t] = mma(ld_bf4(sW2 + (16 * t + ar) * L2 + 16 * ks + ak), h1[ks], acc[t]);
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
       float v[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) gelu_pair(acc[j] + g.b2[16 * t + ak + j], v[j], d2[t][j]);
+      for (int j = 0; j < 4; ++j) gelu_pair(acc[t][j] + g.b2[16 * t + ak + j], v[j], d2[t][j]);
       h2[t] = bf4(v);
 #pragma unroll
       for (int j = 0; j < 4; ++j) tH2[(16 * t + ak + j) * LT + col] = (unsigned short)h2[t][j];
@@ -530,10 +538,13 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
     // ---- output layer and loss: dY = 2 (y - t_n) / (B n_out), normalised units
     bf16x4 dy[OT];
 #pragma unroll
-    for (int t = 0; t < OT; ++t) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < OT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < HT; ++ks) acc = mma(ld_bf4(sW3 + (16 * t + ar) * L3 + 16 * ks + ak), h2[ks], acc);
+    for (int ks = 0; ks < HT; ++ks)
+#pragma unroll
+      for (int t = 0; t < OT; ++t) acc[t] = mma(ld_bf4(sW3 + (16 * t + ar) * L3 + 16 * ks + ak), h2[ks], acc[t]);
+#pragma unroll
+    for (int t = 0; t < OT; ++t) {
       float v[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -541,7 +552,7 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
         v[j] = 0.f;
         if (rok && c < g.n_out) {
           const float tn = (tr[t][j] - g.out_mean[c]) / g.out_std[c];
-          const float res = acc[j] + g.b3[c] - tn;
+          const float res = acc[t][j] + g.b3[c] - tn;
           loss += (double)res * (double)res;
           v[j] = g.loss_scale * res;
         }
@@ -556,33 +567,39 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
     // transposed weights are read from the row-major copies, four rows apart
     bf16x4 z2[HT];
 #pragma unroll
-    for (int t = 0; t < HT; ++t) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < OT; ++ks) {
+    for (int ks = 0; ks < OT; ++ks)
+#pragma unroll
+      for (int t = 0; t < HT; ++t) {
         const unsigned short* w = sW3 + (16 * ks + ak) * L3 + 16 * t + ar;
         const bf16x4 wt{(short)w[0], (short)w[L3], (short)w[2 * L3], (short)w[3 * L3]};
-        acc = mma(wt, dy[ks], acc);
+        acc[t] = mma(wt, dy[ks], acc[t]);
       }
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
       float v[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) v[j] = acc[j] * d2[t][j];
+      for (int j = 0; j < 4; ++j) v[j] = acc[t][j] * d2[t][j];
       z2[t] = bf4(v);
 #pragma unroll
       for (int j = 0; j < 4; ++j) tZ2[(16 * t + ak + j) * LT + col] = (unsigned short)z2[t][j];
     }
 #pragma unroll
-    for (int t = 0; t < HT; ++t) {
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < HT; ++ks) {
+    for (int ks = 0; ks < HT; ++ks)
+#pragma unroll
+      for (int t = 0; t < HT; ++t) {
         const unsigned short* w = sW2 + (16 * ks + ak) * L2 + 16 * t + ar;
         const bf16x4 wt{(short)w[0], (short)w[L2], (short)w[2 * L2], (short)w[3 * L2]};
-        acc = mma(wt, z2[ks], acc);
+        acc[t] = mma(wt, z2[ks], acc[t]);
       }
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
       float v[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) v[j] = acc[j] * d1[t][j];
+      for (int j = 0; j < 4; ++j) v[j] = acc[t][j] * d1[t][j];
       const bf16x4 z1 = bf4(v);
 #pragma unroll
       for (int j = 0; j < 4; ++j) tZ1[(16 * t + ak + j) * LT + col] = (unsigned short)z1[j];
