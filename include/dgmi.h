@@ -171,8 +171,13 @@ int dg_num_face_nodes(const dg_ctx* ctx);
  * "r", "s" (Np), "Dr", "Ds", "M" (Np*Np, row-major; M the reference mass
  * matrix (V V^T)^-1), "LIFT", "LIFTr", "LIFTs"
  * (Np*3Nfp), "Fmask" (3*Nfp, as doubles), "wface" (3*Nfp face quadrature
- * weights), "geo" (K*16: rx ry sx sy, then per face nx ny Fscale sigma_geo),
- * "nbr" (K*3 neighbour element, as doubles), "nbr_face" (K*3); the
+ * weights), "geo" (K*16: rx ry sx sy, then per face nx ny Fscale
+ * sigma_geo), "nbr" (K*3 neighbour element, as doubles), "nbr_face"
+ * (K*3); the curved set S (dg_set_curved_elements): "curved_slot" (K: the
+ * element's slot in S, or -1), "curved_elem" (|S|), "curved_node"
+ * (|S|*5*Np: rx ry sx sy J at the nodes), "curved_face" (|S|*3*3Nfp: nx, ny,
+ * sJ at the face nodes), "curved_P" (|S|*Np*Np: (M^K)^-1 M), "curved_area"
+ * (|S|); the
  * over-integration tables (q points per direction, Nq = q^2): "oi_wq" (Nq
  * element weights), "oi_xg", "oi_wg" (q face points and weights), "oi_Iq",
  * "oi_Drq", "oi_Dsq" (Nq*Np: l_j and its r/s derivatives at the element

@@ -79,6 +79,8 @@ struct Order {
   // waves per SIMD the register allocation must allow: 3 for FP32 at p <= 4
   // (a few spills, measured faster than 2 and than 4), else 2
   static constexpr int MIN_WAVES_EU = (sizeof(T) == 4 && N <= 4) ? 3 : 2;
+  // K1 / K0 of the tile issued before the face pass (registers to spare)
+  static constexpr bool EARLY_K = sizeof(T) == 4 && N <= 4;
   // per-wave LDS (elements of T)
   static constexpr int U_SZ = 16 * RS;           // own state
   static constexpr int F_SZ = 32 * RS;           // contravariant flux Fr rows | Fs rows
@@ -246,6 +248,33 @@ __device__ __forceinline__ const float* frag_of<float>(const DeviceTables& t) {
 template <>
 __device__ __forceinline__ const float* frag_of<bf16ops>(const DeviceTables& t) {
   return (const float*)t.frag16;
+}
+
+// K1 (and, in the perturbation form, K0) of output lane (element slot re,
+// nodes 16 tt + rn) of the tile at element e0, into registers; returns whether
+// the element is outside the curved set.  K1 is read only when the stage uses
+// it (a != 0, not a bare right-hand side): otherwise the load reads the
+// element's own state, which the tile has just brought into the cache, and is
+// not used.
+template <int N, typename X, bool PERT>
+__device__ __forceinline__ bool load_k(const DeviceTables& t, const double* __restrict__ Uin,
+                                       const double* __restrict__ K1, double a, int rhs_only,
+                                       int64_t e0, int re, int rn, double (&rk)[Order<N, X>::NT][4],
+                                       double (&r0)[Order<N, X>::NT][4]) {
+  using O = Order<N, X>;
+  constexpr int Np = O::Np, S = O::S;
+  const double* kp = (a != 0.0 && !rhs_only) ? K1 : Uin;
+  const int64_t ke = (e0 + re) < t.K ? (e0 + re) : t.K - 1;
+#pragma unroll
+  for (int tt = 0; tt < O::NT; ++tt) {
+    const int n = 16 * tt + rn < Np ? 16 * tt + rn : Np - 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      rk[tt][c] = kp[ke * S + c * Np + n];
+      r0[tt][c] = PERT ? Uin[ke * S + c * Np + n] : 0.0;
+    }
+  }
+  return t.cslot == nullptr || t.cslot[ke] < 0;
 }
 
 // The fused right-hand side + LSERK stage for the tiles tile0, tile0 + stride,
@@ -486,6 +515,15 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     }
     if (lane < nel * 12) sNGeo[lane] = (T)rng;
     wave_sync();
+    // K1 / K0 of the tile's outputs and the next tile's own data: at low orders
+    // in FP32 the registers allow issuing them here, so that the face pass
+    // covers their latency
+    double rk[NT][4], r0[NT][4];
+    bool mine;  // not an element of the curved set (which the curved kernel writes)
+    if constexpr (O::EARLY_K) {
+      mine = load_k<N, X, PERT>(t, Uin, K1, a, rhs_only, e0, re, rn, rk, r0);
+      load_own(tile + stride);
+    }
 
     // ---- face nodes, one lane each (the EPT elements' 3(p+1) face nodes fit
     // the 64 lanes at every order built).  First half: traces, ghosts,
@@ -670,14 +708,10 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     wave_sync();
 
     // ---- divergence and lifts on the matrix cores, then the RK stage in FP64;
-    // the K1 (and, in the perturbation form, K0) loads, then those of the next
-    // tile's own data, are issued first so the matrix work covers their
-    // latency.  K1 is read only when the stage uses it (a != 0, not a bare
-    // right-hand side): otherwise the load reads the element's own state,
-    // which the tile has just brought into the cache, and is not used.
-    double rk[NT][4], r0[NT][4];
-    bool mine;  // not an element of the curved set (which the curved kernel writes)
-    {
+    // the K1 / K0 loads (unless issued before the face pass), then those of
+    // the next tile's own data, are issued first so the matrix work covers
+    // their latency.
+    if constexpr (!O::EARLY_K) {
       const double* kp = (a != 0.0 && !rhs_only) ? (const double*)K1 : Uin;
       const int64_t ke = (e0 + re) < K ? (e0 + re) : K - 1;
       mine = t.cslot == nullptr || t.cslot[ke] < 0;
@@ -690,8 +724,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           r0[tt][c] = PERT ? Uin[ke * S + c * Np + n] : 0.0;
         }
       }
+      load_own(tile + stride);
     }
-    load_own(tile + stride);
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       V4 aD = {T(0), T(0), T(0), T(0)}, aL = {T(0), T(0), T(0), T(0)};
