@@ -401,11 +401,30 @@ __device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// gfx950's double-depth instruction (v_mfma_f32_16x16x32_bf16): lane l supplies
+// eight k-slots of A row l%16 and of B column l%16, and slot j of lane group
+// l/16 of A meets slot j of the same group of B, so any assignment of the 32
+// k values to (group, slot) that both operands share gives the product.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 mma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// slots 0-3 from lo, 4-7 from hi
+__device__ __forceinline__ bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
+  return __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+// eight consecutive bfloat16 values (16-byte aligned)
+__device__ __forceinline__ bf16x8 ld_bf8(const unsigned short* p) {
+  return __builtin_bit_cast(bf16x8, *(const u32x4*)p);
+}
+
 template <int KIT, int HT, int OT>
 struct TrainShape {
   static constexpr int KI = 16 * KIT, H = 16 * HT, NO = 16 * OT;
   static constexpr int L1 = KI + 4, L2 = H + 4, L3 = H + 4;  // weight rows in LDS
-  static constexpr int LT = 64 + 4;                           // transposed rows (samples)
+  static constexpr int LT = 64 + 8;  // transposed rows (samples; 16-byte aligned, no bank aliasing)
   static constexpr int W_SZ = H * L1 + H * L2 + NO * L3;
   static constexpr int T_SZ = LT * (KI + 4 * H + NO);
 };
@@ -415,6 +434,7 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
   using S = TrainShape<KIT, HT, OT>;
   constexpr int KI = S::KI, H = S::H, NO = S::NO, L1 = S::L1, L2 = S::L2, L3 = S::L3, LT = S::LT;
   static_assert(HT == 8 && OT <= 4, "shape not built: waves take row tiles wid and wid + 4");
+  static_assert(KIT % 2 == 0 && OT % 2 == 0, "the double-depth products pair k-tiles");
   __shared__ __attribute__((aligned(16))) unsigned short sW[S::W_SZ];
   __shared__ __attribute__((aligned(16))) unsigned short sT[S::T_SZ];
   __shared__ double sLoss[4];
@@ -507,10 +527,18 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
     f32x4 acc[HT];
 #pragma unroll
     for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the double-depth products take k-tiles 2q (slots 0-3) and 2q + 1 (slots
+    // 4-7): lane group g holds k = 16 (2q) + 4g + j and 16 (2q + 1) + 4g + j,
+    // exactly the values the previous product left in the lane
 #pragma unroll
-    for (int ks = 0; ks < KIT; ++ks)
+    for (int q = 0; q < KIT / 2; ++q) {
+      const bf16x8 b = cat8(a1[2 * q], a1[2 * q + 1]);
 #pragma unroll
-      for (int t = 0; t < HT; ++t) acc[t] = mma(ld_bf4(sW1 + (16 * t + ar) * L1 + 16 * ks + ak), a1[ks], acc[t]);
+      for (int t = 0; t < HT; ++t) {
+        const unsigned short* w = sW1 + (16 * t + ar) * L1 + 32 * q + ak;
+        acc[t] = mma32(cat8(ld_bf4(w), ld_bf4(w + 16)), b, acc[t]);
+      }
+    }
 #pragma unroll
     for (int t = 0; t < HT; ++t) {
       float v[4];
@@ -523,9 +551,14 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
 #pragma unroll
     for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < HT; ++ks)
+    for (int q = 0; q < HT / 2; ++q) {
+      const bf16x8 b = cat8(h1[2 * q], h1[2 * q + 1]);
 #pragma unroll
-      for (int t = 0; t < HT; ++t) acc[t] = mma(ld_bf4(sW2 + (16 * t + ar) * L2 + 16 * ks + ak), h1[ks], acc[t]);
+      for (int t = 0; t < HT; ++t) {
+        const unsigned short* w = sW2 + (16 * t + ar) * L2 + 32 * q + ak;
+        acc[t] = mma32(cat8(ld_bf4(w), ld_bf4(w + 16)), b, acc[t]);
+      }
+    }
 #pragma unroll
     for (int t = 0; t < HT; ++t) {
       float v[4];
@@ -540,9 +573,14 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
 #pragma unroll
     for (int t = 0; t < OT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < HT; ++ks)
+    for (int q = 0; q < HT / 2; ++q) {
+      const bf16x8 b = cat8(h2[2 * q], h2[2 * q + 1]);
 #pragma unroll
-      for (int t = 0; t < OT; ++t) acc[t] = mma(ld_bf4(sW3 + (16 * t + ar) * L3 + 16 * ks + ak), h2[ks], acc[t]);
+      for (int t = 0; t < OT; ++t) {
+        const unsigned short* w = sW3 + (16 * t + ar) * L3 + 32 * q + ak;
+        acc[t] = mma32(cat8(ld_bf4(w), ld_bf4(w + 16)), b, acc[t]);
+      }
+    }
 #pragma unroll
     for (int t = 0; t < OT; ++t) {
       float v[4];
@@ -569,13 +607,17 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
 #pragma unroll
     for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < OT; ++ks)
+    for (int q = 0; q < OT / 2; ++q) {
+      const bf16x8 b = cat8(dy[2 * q], dy[2 * q + 1]);
 #pragma unroll
       for (int t = 0; t < HT; ++t) {
-        const unsigned short* w = sW3 + (16 * ks + ak) * L3 + 16 * t + ar;
-        const bf16x4 wt{(short)w[0], (short)w[L3], (short)w[2 * L3], (short)w[3 * L3]};
-        acc[t] = mma(wt, dy[ks], acc[t]);
+        const unsigned short* w = sW3 + (32 * q + ak) * L3 + 16 * t + ar;
+        const unsigned short* v = w + 16 * L3;
+        const s16x8 wt{(short)w[0], (short)w[L3], (short)w[2 * L3], (short)w[3 * L3],
+                       (short)v[0], (short)v[L3], (short)v[2 * L3], (short)v[3 * L3]};
+        acc[t] = mma32(__builtin_bit_cast(bf16x8, wt), b, acc[t]);
       }
+    }
 #pragma unroll
     for (int t = 0; t < HT; ++t) {
       float v[4];
@@ -588,13 +630,17 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
 #pragma unroll
     for (int t = 0; t < HT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < HT; ++ks)
+    for (int q = 0; q < HT / 2; ++q) {
+      const bf16x8 b = cat8(z2[2 * q], z2[2 * q + 1]);
 #pragma unroll
       for (int t = 0; t < HT; ++t) {
-        const unsigned short* w = sW2 + (16 * ks + ak) * L2 + 16 * t + ar;
-        const bf16x4 wt{(short)w[0], (short)w[L2], (short)w[2 * L2], (short)w[3 * L2]};
-        acc[t] = mma(wt, z2[ks], acc[t]);
+        const unsigned short* w = sW2 + (32 * q + ak) * L2 + 16 * t + ar;
+        const unsigned short* v = w + 16 * L2;
+        const s16x8 wt{(short)w[0], (short)w[L2], (short)w[2 * L2], (short)w[3 * L2],
+                       (short)v[0], (short)v[L2], (short)v[2 * L2], (short)v[3 * L2]};
+        acc[t] = mma32(__builtin_bit_cast(bf16x8, wt), b, acc[t]);
       }
+    }
 #pragma unroll
     for (int t = 0; t < HT; ++t) {
       float v[4];
@@ -605,24 +651,26 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs g) {
       for (int j = 0; j < 4; ++j) tZ1[(16 * t + ak + j) * LT + col] = (unsigned short)z1[j];
     }
     __syncthreads();
-    // ---- weight gradients of the block: dW[n][k] += sum_s dZ[s][n] A[s][k]
+    // ---- weight gradients of the block: dW[n][k] += sum_s dZ[s][n] A[s][k],
+    // the samples as the double-depth k (lane group g: samples 32 ks + 8g ..
+    // 32 ks + 8g + 7, one 16-byte read per operand)
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int sb = 16 * ks + ak;  // samples sb .. sb + 3 of the block
+    for (int ks = 0; ks < 2; ++ks) {
+      const int sb = 32 * ks + 2 * ak;  // samples sb .. sb + 7 of the block
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int nt = wid + 4 * i;
-        const bf16x4 az1 = ld_bf4(tZ1 + (16 * nt + ar) * LT + sb);
-        const bf16x4 az2 = ld_bf4(tZ2 + (16 * nt + ar) * LT + sb);
+        const bf16x8 az1 = ld_bf8(tZ1 + (16 * nt + ar) * LT + sb);
+        const bf16x8 az2 = ld_bf8(tZ2 + (16 * nt + ar) * LT + sb);
 #pragma unroll
-        for (int kt = 0; kt < KIT; ++kt) acc1[i][kt] = mma(az1, ld_bf4(tX + (16 * kt + ar) * LT + sb), acc1[i][kt]);
+        for (int kt = 0; kt < KIT; ++kt) acc1[i][kt] = mma32(az1, ld_bf8(tX + (16 * kt + ar) * LT + sb), acc1[i][kt]);
 #pragma unroll
-        for (int kt = 0; kt < HT; ++kt) acc2[i][kt] = mma(az2, ld_bf4(tH1 + (16 * kt + ar) * LT + sb), acc2[i][kt]);
+        for (int kt = 0; kt < HT; ++kt) acc2[i][kt] = mma32(az2, ld_bf8(tH1 + (16 * kt + ar) * LT + sb), acc2[i][kt]);
       }
       if (wid < OT) {
-        const bf16x4 ady = ld_bf4(tDY + (16 * wid + ar) * LT + sb);
+        const bf16x8 ady = ld_bf8(tDY + (16 * wid + ar) * LT + sb);
 #pragma unroll
-        for (int kt = 0; kt < HT; ++kt) acc3[kt] = mma(ady, ld_bf4(tH2 + (16 * kt + ar) * LT + sb), acc3[kt]);
+        for (int kt = 0; kt < HT; ++kt) acc3[kt] = mma32(ady, ld_bf8(tH2 + (16 * kt + ar) * LT + sb), acc3[kt]);
       }
     }
     // bias gradients: thread t sums its rows of dZ1 | dZ2 | dY over the block
