@@ -79,8 +79,10 @@ struct Order {
   // waves per SIMD the register allocation must allow: 3 for FP32 at p <= 4
   // (a few spills, measured faster than 2 and than 4), else 2
   static constexpr int MIN_WAVES_EU = (sizeof(T) == 4 && N <= 4) ? 3 : 2;
-  // K1 / K0 of the tile issued before the face pass (registers to spare)
-  static constexpr bool EARLY_K = sizeof(T) == 4 && N <= 4;
+  // K1 / K0 of the tile, and the next tile's own data, issued before the
+  // face pass where the registers allow
+  static constexpr bool EARLY_K = true;
+  static constexpr bool EARLY_OWN = N <= 4;
   // per-wave LDS (elements of T)
   static constexpr int U_SZ = 16 * RS;           // own state
   static constexpr int F_SZ = 32 * RS;           // contravariant flux Fr rows | Fs rows
@@ -520,10 +522,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     // covers their latency
     double rk[NT][4], r0[NT][4];
     bool mine;  // not an element of the curved set (which the curved kernel writes)
-    if constexpr (O::EARLY_K) {
-      mine = load_k<N, X, PERT>(t, Uin, K1, a, rhs_only, e0, re, rn, rk, r0);
-      load_own(tile + stride);
-    }
+    if constexpr (O::EARLY_K) mine = load_k<N, X, PERT>(t, Uin, K1, a, rhs_only, e0, re, rn, rk, r0);
+    if constexpr (O::EARLY_OWN) load_own(tile + stride);
 
     // ---- face nodes, one lane each (the EPT elements' 3(p+1) face nodes fit
     // the 64 lanes at every order built).  First half: traces, ghosts,
@@ -724,8 +724,8 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           r0[tt][c] = PERT ? Uin[ke * S + c * Np + n] : 0.0;
         }
       }
-      load_own(tile + stride);
     }
+    if constexpr (!O::EARLY_OWN) load_own(tile + stride);
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       V4 aD = {T(0), T(0), T(0), T(0)}, aL = {T(0), T(0), T(0), T(0)};
