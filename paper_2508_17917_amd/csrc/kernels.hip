@@ -366,6 +366,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   // issued before it, not those issued ahead for later phases.  Values of
   // clamped lanes are never stored.
   constexpr int NB1 = NQ == 1 ? 12 : 6;  // neighbour blocks issued before the volume phase
+  constexpr bool SPLIT = NB1 < 12;
   int vidx[NQ];                          // this lane's value within an element block
 #pragma unroll
   for (int q = 0; q < NQ; ++q) vidx[q] = lr_ok[q] ? lane + 64 * q : S - 1;
@@ -469,7 +470,33 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         gxk[tt][c] = rx * aR[c] + sx * aS[c];
         gyk[tt][c] = ry * aR[c] + sy * aS[c];
       }
-      if (!PACK && ok) volume_flux(re, n, gxk[tt], gyk[tt], rx, ry, sx, sy);
+      if (!SPLIT && !PACK && ok) volume_flux(re, n, gxk[tt], gyk[tt], rx, ry, sx, sy);
+    }
+    // high orders: the first neighbour blocks go to LDS and the rest are issued
+    // between the matrix-core gradient and the volume flux, which covers them
+    double rnb2[12 - NB1 > 0 ? 12 - NB1 : 1][NQ];
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (lr_ok[q] && bb < 3 * nel) sX[bb * S + lane + 64 * q] = (T)(rnb[bb][q] - uinf_q[q]);
+#pragma unroll
+      for (int bb = 0; bb < 12 - NB1; ++bb) {
+        const int64_t nb = nbr_elem(NB1 + bb) * S;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) rnb2[bb][q] = Uin[nb + vidx[q]];
+      }
+      if constexpr (!PACK) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+          const int n = 16 * tt + rn;
+          if ((re < nel) && (n < Np)) {
+            const T* g = sGeo + re * kGeoStride;
+            volume_flux(re, n, gxk[tt], gyk[tt], g[0], g[1], g[2], g[3]);
+          }
+        }
+      }
     }
     if constexpr (PACK) {
       // the tile's (element, node) pairs packed onto the lanes, one pass: the
@@ -494,19 +521,13 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
         volume_flux(e, n, gx, gy, g[0], g[1], g[2], g[3]);
       }
     }
+    if constexpr (!SPLIT) {
 #pragma unroll
-    for (int bb = 0; bb < NB1; ++bb)
+      for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (lr_ok[q] && bb < 3 * nel) sX[bb * S + lane + 64 * q] = (T)(rnb[bb][q] - uinf_q[q]);
-    if (NB1 < 12) {
-      double rnb2[12 - NB1 > 0 ? 12 - NB1 : 1][NQ];
-#pragma unroll
-      for (int bb = 0; bb < 12 - NB1; ++bb) {
-        const int64_t nb = nbr_elem(NB1 + bb) * S;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) rnb2[bb][q] = Uin[nb + vidx[q]];
-      }
+        for (int q = 0; q < NQ; ++q)
+          if (lr_ok[q] && bb < 3 * nel) sX[bb * S + lane + 64 * q] = (T)(rnb[bb][q] - uinf_q[q]);
+    } else {
 #pragma unroll
       for (int bb = 0; bb < 12 - NB1; ++bb) {
         const int ef = NB1 + bb;
