@@ -1078,11 +1078,13 @@ int train_go(const TrainArgs& a, int blocks, hipStream_t s, std::string& err) {
 }
 
 // The fused training step for the shapes it is built for (in_pad 32,
-// H 128, out_pad 32 or 64); returns 1 (nothing launched) for others.
+// H 128, up to 64 outputs); returns 1 (nothing launched) for others.  The
+// output tiles cover n_out rounded up to 32 (two tiles at most 32 outputs,
+// else four), the rows of the stored output weights beyond that unread.
 int train_fused(const MlpDev& d, const float* X, int64_t ldx, const float* T, int64_t ldt,
                 int64_t B, int* loss_parts, hipStream_t s, std::string& err) {
-  const int KIT = d.in_pad / 16, HT = d.H / 16, OT = d.out_pad / 16;
-  if (KIT != 2 || HT != 8 || (OT != 2 && OT != 4)) return 1;
+  const int KIT = d.in_pad / 16, HT = d.H / 16, OT = d.n_out <= 32 ? 2 : 4;
+  if (KIT != 2 || HT != 8 || d.n_out > 64 || 16 * OT > d.out_pad) return 1;
   // workgroups: 256 (one per CU) at most, each a whole number of 64-sample
   // blocks, and no more whole-gradient partials than the buffer holds
   const int64_t cap = (int64_t)d.nparts * ((int64_t)d.H * d.H + d.H) / d.nparams;
