@@ -1,8 +1,9 @@
 // Learned-closure kernels for gfx950: a per-element MLP
 // (n_in -> H -> GELU -> H -> GELU -> n_out) trained and evaluated with
-// bfloat16 operands on the matrix cores (16x16x16, FP32 accumulation) and
-// FP32 master weights, plus the per-element order-change maps that make its
-// samples.
+// bfloat16 operands on the matrix cores (FP32 accumulation; 16x16x16 in the
+// layer-by-layer kernels, the double-depth 16x16x32 in the fused training
+// step) and FP32 master weights, plus the per-element order-change maps that
+// make its samples.
 //
 // Matrix-core operand layout (v_mfma_f32_16x16x16_bf16): lane l supplies
 // A[l%16][4(l/16) + j] and B[4(l/16) + j][l%16], j = 0..3, and receives
@@ -396,9 +397,6 @@ __device__ __forceinline__ bf16x4 bf4(const float v[4]) {
 __device__ __forceinline__ bf16x4 ld_bf4(const unsigned short* p) {
   const uint2 w = *(const uint2*)p;
   return bf16x4{(short)(w.x & 0xffff), (short)(w.x >> 16), (short)(w.y & 0xffff), (short)(w.y >> 16)};
-}
-__device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
 // gfx950's double-depth instruction (v_mfma_f32_16x16x32_bf16): lane l supplies
