@@ -125,6 +125,9 @@ struct DeviceTables {
   double* force_part = nullptr;     // per-workgroup partials of the wall force
   unsigned* force_ticket = nullptr; // workgroups done (the last resets it to 0)
   int force_blocks = 0;             // capacity of force_part, in workgroups
+  // where a stage launch writes the wall force of its input state (evaluated
+  // by leading workgroups of that launch), or null for none
+  double* force_in = nullptr;
 };
 
 struct KernelPhysics {

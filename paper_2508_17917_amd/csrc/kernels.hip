@@ -279,6 +279,122 @@ __device__ __forceinline__ bool load_k(const DeviceTables& t, const double* __re
   return t.cslot == nullptr || t.cslot[ke] < 0;
 }
 
+// The wall force (the traction of eq. force_integral: pressure minus the
+// viscous normal stress, and its moment about the origin) at wall face node i
+// (node i % Nfp of face t.wall[i / Nfp]) of the state U: the node's quadrature
+// weight times sJ times (tx, ty, x ty - y tx), in FP64 in every form.  UNR:
+// the unroll factor of the node's derivative loop (the same operations in the
+// same order whatever it is; a smaller one holds fewer registers where the
+// force runs inside the stage kernel).
+constexpr int kForceThreads = 64;
+template <int N, int UNR = (N + 1) * (N + 2) / 2>
+__device__ __forceinline__ void wall_node_force(const DeviceTables& t, const KernelPhysics& ph,
+                                                const double* __restrict__ U, int i, double& fx,
+                                                double& fy, double& mz) {
+  using O = Order<N, double>;
+  constexpr int Np = O::Np, Nfp = O::Nfp, S = 4 * Np;
+  Gas<double> gas;
+  gas.gamma = ph.gamma;
+  gas.gm1 = ph.gamma - 1.0;
+  gas.igm1 = 1.0 / (ph.gamma - 1.0);
+  gas.mu = ph.mu;
+  gas.k = ph.gamma / ph.Pr;
+  const double* Dr = t.ops;
+  const double* Ds = t.ops + Np * Np;
+  const double* wface = t.ops + 2 * Np * Np + 3 * Np * 3 * Nfp;
+  const int wf = t.wall[i / Nfp];
+  const int j = i % Nfp;
+  const int64_t k = wf / 3;
+  const int f = wf % 3;
+  const int n = face_node<N>(f, j);
+  const double* Uk = U + k * S;
+  const double* g = t.geo + k * kGeoStride;
+  // metric terms at the node, normal and sJ at the face node: per node on
+  // the elements of the curved set, the element's constants elsewhere
+  double rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+  double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
+  double sJ = g[6 + 4 * f] / (g[0] * g[3] - g[1] * g[2]);  // Fscale * J
+  const int cs = t.cslot ? t.cslot[k] : -1;
+  if (cs >= 0) {
+    const double* nd = t.cnode + (int64_t)cs * 5 * Np;
+    const double* fc = t.cface + (int64_t)cs * 9 * Nfp;
+    rx = nd[n];
+    ry = nd[Np + n];
+    sx = nd[2 * Np + n];
+    sy = nd[3 * Np + n];
+    nx = fc[f * Nfp + j];
+    ny = fc[3 * Nfp + f * Nfp + j];
+    sJ = fc[6 * Nfp + f * Nfp + j];
+  }
+  double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
+#pragma unroll UNR
+  for (int m = 0; m < Np; ++m) {
+    const double dr = Dr[n * Np + m], ds = Ds[n * Np + m];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ur[c] += dr * Uk[c * Np + m];
+      us[c] += ds * Uk[c * Np + m];
+    }
+  }
+  double Up[4], dx[4], dy[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    Up[c] = Uk[c * Np + n];
+    dx[c] = rx * ur[c] + sx * us[c];
+    dy[c] = ry * ur[c] + sy * us[c];
+  }
+  const double p = gas.gm1 * (Up[3] - 0.5 * (Up[1] * Up[1] + Up[2] * Up[2]) / Up[0]);
+  double Ub[4] = {Up[0], Up[0] * ph.vw[0], Up[0] * ph.vw[1],
+                  p * gas.igm1 + 0.5 * Up[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1])};
+  double vx[4], vy[4];
+  viscous_flux(gas, vstate(gas, Ub), dx, dy, vx, vy);
+  const double w = wface[f * Nfp + j] * sJ;
+  const double tx = p * nx - (vx[1] * nx + vy[1] * ny);
+  const double ty = p * ny - (vx[2] * nx + vy[2] * ny);
+  const double xw = t.wall_xy[2 * i], yw = t.wall_xy[2 * i + 1];
+  fx = w * tx;
+  fy = w * ty;
+  mz = w * (xw * ty - yw * tx);
+}
+
+// One wave's share of the wall force: nodes 64 blk .. 64 blk + 63 of the nblk
+// blocks of 64 that cover the wall face nodes, reduced by a fixed shuffle
+// tree into partial blk; the last wave to finish (an atomic ticket) sums the
+// partials in block order into out[0..2] and resets the ticket.  The order of
+// every sum is fixed by the wall face list alone, so the total does not depend
+// on which waves ran the blocks or in which launch.
+template <int N, int UNR = (N + 1) * (N + 2) / 2>
+__device__ __forceinline__ void force_wave(const DeviceTables& t, const KernelPhysics& ph,
+                                           const double* __restrict__ U, double* __restrict__ out,
+                                           unsigned blk, unsigned nblk) {
+  const int lane = threadIdx.x & 63;
+  double fx = 0.0, fy = 0.0, mz = 0.0;
+  const int i = (int)blk * kForceThreads + lane;
+  if (i < t.nwall * (N + 1)) wall_node_force<N, UNR>(t, ph, U, i, fx, fy, mz);
+  for (int o = 32; o > 0; o >>= 1) {
+    fx += __shfl_down(fx, o, 64);
+    fy += __shfl_down(fy, o, 64);
+    mz += __shfl_down(mz, o, 64);
+  }
+  unsigned last = 0;
+  if (lane == 0) {
+    t.force_part[3 * blk + 0] = fx;
+    t.force_part[3 * blk + 1] = fy;
+    t.force_part[3 * blk + 2] = mz;
+    __threadfence();
+    last = atomicAdd(t.force_ticket, 1u) == nblk - 1;
+  }
+  last = __shfl(last, 0, 64);
+  if (last && lane < 3) {
+    __threadfence();
+    const volatile double* part = t.force_part;
+    double sum = 0.0;
+    for (unsigned b = 0; b < nblk; ++b) sum += part[3 * b + lane];
+    out[lane] = sum;
+    if (lane == 0) atomicExch(t.force_ticket, 0u);
+  }
+}
+
 // The fused right-hand side + LSERK stage for the tiles tile0, tile0 + stride,
 // ... < tile_end of one mesh, run by one wavefront.  A tile has four element
 // slots (16 matrix-core rows = 4 fields x 4 elements) and holds EPT elements:
@@ -823,6 +939,12 @@ constexpr int curved_lds_doubles(int N) {
 __host__ __device__ inline int curved_workgroups(int ncurved, int W) {
   return ncurved > 0 ? ((ncurved + W - 1) / W + 7) / 8 * 8 : 0;
 }
+// workgroups of W waves that evaluate the wall force of the launch's input
+// state (one wave per 64 wall face nodes), a multiple of 8, or none
+__host__ __device__ inline int force_workgroups(const DeviceTables& t, int Nfp, int W) {
+  const int nblk = (t.nwall * Nfp + kForceThreads - 1) / kForceThreads;
+  return t.force_in != nullptr && nblk > 0 ? ((nblk + W - 1) / W + 7) / 8 * 8 : 0;
+}
 template <int N>
 __device__ __forceinline__ void curved_element(const DeviceTables& t, const KernelPhysics& ph,
                                                const double* __restrict__ Uin,
@@ -1107,8 +1229,18 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
     }
     return;
   }
+  // then, where the caller asks for it, the wall force of the input state
+  // (the previous step's output, which this launch only reads): one wave per
+  // 64 wall face nodes
+  const int nfw = force_workgroups(t, O::Nfp, W);
+  if ((int)blockIdx.x < ncw + nfw) {
+    const unsigned nblk = (unsigned)((t.nwall * O::Nfp + kForceThreads - 1) / kForceThreads);
+    const unsigned wv = (blockIdx.x - ncw) * W + wid;
+    if (wv < nblk) force_wave<N, 3>(t, ph, Uin, t.force_in, wv, nblk);
+    return;
+  }
   stage_lds_init<N, X, W>(frag_of<X>(t), sFrag, sWave);
-  const unsigned bx = blockIdx.x - ncw, gx = gridDim.x - ncw;
+  const unsigned bx = blockIdx.x - ncw - nfw, gx = gridDim.x - ncw - nfw;
   const int64_t ntiles = (t.K + O::EPT - 1) / O::EPT;
   const int xcd = bx & 7;
   const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
@@ -1582,104 +1714,12 @@ batch_order_kernel(const BatchItem* __restrict__ items, const BatchStep* __restr
 // partials, and the last workgroup to finish (an atomic ticket) sums the
 // partials in workgroup order and resets the ticket: deterministic, one
 // launch, no host synchronisation and no wait inside the kernel.
-constexpr int kForceThreads = 64;
 // Workgroup blk of the nblk that cover one mesh's wall face nodes.
 template <int N>
 __device__ __forceinline__ void force_block(const DeviceTables& t, const KernelPhysics& ph,
                                             const double* __restrict__ U, double* __restrict__ out,
                                             unsigned blk, unsigned nblk) {
-  using O = Order<N, double>;
-  constexpr int Np = O::Np, Nfp = O::Nfp, S = 4 * Np;
-  __shared__ int last;
-  Gas<double> gas;
-  gas.gamma = ph.gamma;
-  gas.gm1 = ph.gamma - 1.0;
-  gas.igm1 = 1.0 / (ph.gamma - 1.0);
-  gas.mu = ph.mu;
-  gas.k = ph.gamma / ph.Pr;
-  const double* Dr = t.ops;
-  const double* Ds = t.ops + Np * Np;
-  const double* wface = t.ops + 2 * Np * Np + 3 * Np * 3 * Nfp;
-  double fx = 0.0, fy = 0.0, mz = 0.0;
-  const int total = t.nwall * Nfp;
-  const int i = (int)blk * kForceThreads + threadIdx.x;
-  if (i < total) {
-    const int wf = t.wall[i / Nfp];
-    const int j = i % Nfp;
-    const int64_t k = wf / 3;
-    const int f = wf % 3;
-    const int n = face_node<N>(f, j);
-    const double* Uk = U + k * S;
-    const double* g = t.geo + k * kGeoStride;
-    // metric terms at the node, normal and sJ at the face node: per node on
-    // the elements of the curved set, the element's constants elsewhere
-    double rx = g[0], ry = g[1], sx = g[2], sy = g[3];
-    double nx = g[4 + 4 * f], ny = g[5 + 4 * f];
-    double sJ = g[6 + 4 * f] / (g[0] * g[3] - g[1] * g[2]);  // Fscale * J
-    const int cs = t.cslot ? t.cslot[k] : -1;
-    if (cs >= 0) {
-      const double* nd = t.cnode + (int64_t)cs * 5 * Np;
-      const double* fc = t.cface + (int64_t)cs * 9 * Nfp;
-      rx = nd[n];
-      ry = nd[Np + n];
-      sx = nd[2 * Np + n];
-      sy = nd[3 * Np + n];
-      nx = fc[f * Nfp + j];
-      ny = fc[3 * Nfp + f * Nfp + j];
-      sJ = fc[6 * Nfp + f * Nfp + j];
-    }
-    double ur[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int m = 0; m < Np; ++m) {
-      const double dr = Dr[n * Np + m], ds = Ds[n * Np + m];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        ur[c] += dr * Uk[c * Np + m];
-        us[c] += ds * Uk[c * Np + m];
-      }
-    }
-    double Up[4], dx[4], dy[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      Up[c] = Uk[c * Np + n];
-      dx[c] = rx * ur[c] + sx * us[c];
-      dy[c] = ry * ur[c] + sy * us[c];
-    }
-    const double p = gas.gm1 * (Up[3] - 0.5 * (Up[1] * Up[1] + Up[2] * Up[2]) / Up[0]);
-    double Ub[4] = {Up[0], Up[0] * ph.vw[0], Up[0] * ph.vw[1],
-                    p * gas.igm1 + 0.5 * Up[0] * (ph.vw[0] * ph.vw[0] + ph.vw[1] * ph.vw[1])};
-    double vx[4], vy[4];
-    viscous_flux(gas, vstate(gas, Ub), dx, dy, vx, vy);
-    const double w = wface[f * Nfp + j] * sJ;
-    const double tx = p * nx - (vx[1] * nx + vy[1] * ny);
-    const double ty = p * ny - (vx[2] * nx + vy[2] * ny);
-    const double xw = t.wall_xy[2 * i], yw = t.wall_xy[2 * i + 1];
-    fx = w * tx;
-    fy = w * ty;
-    mz = w * (xw * ty - yw * tx);
-  }
-  // fixed-shape reduction over the wave (one wave per workgroup)
-  for (int o = 32; o > 0; o >>= 1) {
-    fx += __shfl_down(fx, o, 64);
-    fy += __shfl_down(fy, o, 64);
-    mz += __shfl_down(mz, o, 64);
-  }
-  if (threadIdx.x == 0) {
-    t.force_part[3 * blk + 0] = fx;
-    t.force_part[3 * blk + 1] = fy;
-    t.force_part[3 * blk + 2] = mz;
-    __threadfence();
-    last = atomicAdd(t.force_ticket, 1u) == nblk - 1;
-  }
-  __syncthreads();
-  if (last && threadIdx.x < 3) {
-    __threadfence();
-    const volatile double* part = t.force_part;
-    double sum = 0.0;
-    for (unsigned b = 0; b < nblk; ++b) sum += part[3 * b + threadIdx.x];
-    out[threadIdx.x] = sum;
-    if (threadIdx.x == 0) atomicExch(t.force_ticket, 0u);
-  }
+  force_wave<N>(t, ph, U, out, blk, nblk);
 }
 
 template <int N>
@@ -1777,7 +1817,7 @@ int launch_stage_t(const StageTuning& tune, const DeviceTables& t, const KernelP
   constexpr int EPT = elements_per_tile(N);
   // the curved set's workgroups lead the grid; a persistent grid leaves them
   // their resident slots
-  const int ncw = curved_workgroups(t.ncurved, W);
+  const int ncw = curved_workgroups(t.ncurved, W) + force_workgroups(t, N + 1, W);
   const int straight_resident = resident - ncw >= 8 ? resident - ncw : 8;
   const int64_t grid = stage_grid((t.K + EPT - 1) / EPT, W, straight_resident, tune.grid) + ncw;
   hipLaunchKernelGGL((stage_kernel<N, T, PERT, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, t,
