@@ -104,6 +104,10 @@ struct Order {
   static constexpr int ROWE = sizeof(T) == 8 ? 1 : 4;
 };
 
+// Fourth word of a raw buffer descriptor on gfx9-family devices: 32-bit data
+// format (untyped loads need a valid one), no swizzle, no index stride.
+constexpr int kBufferWord3 = 0x00020000;
+
 // Node index of face node j (counter-clockwise) on face f; rows of the node
 // numbering start at i(N+1) - i(i-1)/2.
 template <int N>
@@ -526,13 +530,31 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     auto nbr_elem = [&](int i) -> int64_t {
       return i < 3 * nel ? (int64_t)(sConn[i < 12 ? i : 0] >> 4) : e0;
     };
+    // the same for a slot index uniform across the wave, as a scalar: lane i
+    // of the wave holds the connectivity of face slot i (loaded with the
+    // tile's own data), so the neighbour's address is formed on the scalar
+    // unit and each load is a scalar base plus the lane's fixed offset
+    const int nel_u = __builtin_amdgcn_readfirstlane(nel);
+    const int e0_u = __builtin_amdgcn_readfirstlane((int)e0);
+    auto nbr_elem_u = [&](int i) -> int {
+      const int conn = __builtin_amdgcn_readlane(rc, i < 12 ? i : 0);
+      return i < 3 * nel_u ? conn >> 4 : e0_u;
+    };
+    // value vidx[q] of element block ne (a scalar): a buffer load whose
+    // descriptor spans that block only (built on the scalar unit), the lane's
+    // fixed byte offset as the vector operand
+    auto load_block = [&](int ne, int q) -> double {
+      const __amdgpu_buffer_rsrc_t r =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(Uin + (int64_t)ne * S), (short)0, S * 8, kBufferWord3);
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vidx[q] * 8, 0, 0));
+    };
     const double rng = t.geo[nbr_elem(lane >> 2) * kGeoStride + (lane & 3)];
     double rnb[NB1][NQ];
 #pragma unroll
     for (int bb = 0; bb < NB1; ++bb) {
-      const int64_t nb = nbr_elem(bb) * S;  // bb uniform across the wave
+      const int nb = nbr_elem_u(bb);
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) rnb[bb][q] = Uin[nb + vidx[q]];
+      for (int q = 0; q < NQ; ++q) rnb[bb][q] = load_block(nb, q);
     }
 
     // ---- gradient on the matrix cores, then the volume flux per node:
@@ -599,9 +621,9 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
           if (lr_ok[q] && bb < 3 * nel) sX[bb * S + lane + 64 * q] = (T)(rnb[bb][q] - uinf_q[q]);
 #pragma unroll
       for (int bb = 0; bb < 12 - NB1; ++bb) {
-        const int64_t nb = nbr_elem(NB1 + bb) * S;
+        const int nb = nbr_elem_u(NB1 + bb);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) rnb2[bb][q] = Uin[nb + vidx[q]];
+        for (int q = 0; q < NQ; ++q) rnb2[bb][q] = load_block(nb, q);
       }
       if constexpr (!PACK) {
 #pragma unroll
