@@ -1237,7 +1237,7 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
   __shared__ __attribute__((aligned(16))) T sFrag[O::FRAG_SZ];
   __shared__ __attribute__((aligned(16))) T sWave[W * O::WAVE_SZ];
   __shared__ int sConnW[W * 12];
-  const int wid = threadIdx.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile indices stay scalar
   // the leading workgroups evaluate the curved set (one element per wave, in
   // the wave's LDS area), the rest the straight tiles
   const int ncw = curved_workgroups(t.ncurved, W);
@@ -1640,7 +1640,7 @@ oi_stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin
   for (int i = threadIdx.x; i < P::LDS_TAB; i += 64 * W) sTab[i] = t.oi[P::OFF_DRSF + i];
   for (int i = threadIdx.x; i < W * P::WAVE_SZ; i += 64 * W) sWave[i] = 0.0;
   __syncthreads();
-  const int wid = threadIdx.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile indices stay scalar
   const int64_t ntiles = (t.K + P::EPT - 1) / P::EPT;
   const int xcd = blockIdx.x & 7;
   const int64_t tb = ntiles * xcd / 8, te = ntiles * (xcd + 1) / 8;
@@ -1666,7 +1666,7 @@ __device__ __forceinline__ void batch_group(const BatchItem* __restrict__ items,
   T* sWave = sFrag + O::FRAG_SZ;
   int* sConnW = (int*)(sWave + W * O::WAVE_SZ);
   stage_lds_init<N, X, W>(frag_of<X>(items[g.first_item].t), sFrag, sWave);
-  const int wid = threadIdx.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile indices stay scalar
   const int local = blockIdx.x - g.block_begin;
   const int xcd = local & 7;
   const int64_t tb = g.ntiles * xcd / 8, te = g.ntiles * (xcd + 1) / 8;
