@@ -1258,7 +1258,9 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
   if ((int)blockIdx.x < ncw + nfw) {
     const unsigned nblk = (unsigned)((t.nwall * O::Nfp + kForceThreads - 1) / kForceThreads);
     const unsigned wv = (blockIdx.x - ncw) * W + wid;
-    if (wv < nblk) force_wave<N, 3>(t, ph, Uin, t.force_in, wv, nblk);
+    // the node's derivative loop unrolled by eight: two rounds of loads at
+    // p = 4, and no more registers than the stage kernel holds
+    if (wv < nblk) force_wave<N, 8>(t, ph, Uin, t.force_in, wv, nblk);
     return;
   }
   stage_lds_init<N, X, W>(frag_of<X>(t), sFrag, sWave);
