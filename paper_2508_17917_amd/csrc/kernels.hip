@@ -952,8 +952,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
 // input state and its own element's K1, so both run in the same launch: the
 // stage kernel's leading workgroups take the curved set, one element per
 // wave, on the SIMDs beside the straight tiles.  lds: the wave's area,
-// curved_lds_doubles(N) doubles; ops: the packed FP64 operators D_r, D_s,
-// LIFT, LIFT_r, LIFT_s (in the workgroup's LDS, or t.ops).
+// curved_lds_doubles(N) doubles.
 constexpr int curved_lds_doubles(int N) {
   return 29 * ((N + 1) * (N + 2) / 2) + 39 * (N + 1);
 }
@@ -973,8 +972,7 @@ __device__ __forceinline__ void curved_element(const DeviceTables& t, const Kern
                                                const double* __restrict__ Uin,
                                                double* __restrict__ Uout,
                                                double* __restrict__ K1, double a, double b,
-                                               double dt, int rhs_only, int slot, double* lds,
-                                               const double* ops) {
+                                               double dt, int rhs_only, int slot, double* lds) {
   constexpr int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1, NFN = 3 * Nfp, S = 4 * Np;
   double* sU = lds;
   double* sGx = sU + S;
@@ -990,7 +988,7 @@ __device__ __forceinline__ void curved_element(const DeviceTables& t, const Kern
   static_assert(6 * S + 5 * Np + 13 * NFN == curved_lds_doubles(N), "curved LDS layout");
   const int lane = threadIdx.x & 63;
   const int64_t k = t.celem[slot];
-  const double* Dr = ops;
+  const double* Dr = t.ops;
   const double* Ds = t.ops + Np * Np;
   const double* LIFT = t.ops + 2 * Np * Np;
   const double* LIFTr = LIFT + Np * NFN;
@@ -1236,33 +1234,20 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
              int rhs_only) {
   typedef typename Real<X>::type T;
   using O = Order<N, X>;
-  // one LDS block: the operator fragments, then the waves' areas
-  __shared__ __attribute__((aligned(16))) T sAll[O::FRAG_SZ + W * O::WAVE_SZ];
+  __shared__ __attribute__((aligned(16))) T sFrag[O::FRAG_SZ];
+  __shared__ __attribute__((aligned(16))) T sWave[W * O::WAVE_SZ];
   __shared__ int sConnW[W * 12];
-  T* sFrag = sAll;
-  T* sWave = sAll + O::FRAG_SZ;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile indices stay scalar
-  // the leading workgroups evaluate the curved set (one element per wave), the
-  // rest the straight tiles.  A curved workgroup lays its LDS out afresh: the
-  // FP64 operators D_r, D_s, LIFT, LIFT_r, LIFT_s shared by its waves where
-  // they fit beside the waves' arrays (every default shape), so the
-  // element's operator loops read LDS rather than the cache hierarchy
+  // the leading workgroups evaluate the curved set (one element per wave, in
+  // the wave's LDS area), the rest the straight tiles
   const int ncw = curved_workgroups(t.ncurved, W);
-  constexpr int OPS = 2 * O::Np * O::Np + 3 * O::Np * O::NF, CL = curved_lds_doubles(N);
-  constexpr bool OPS_LDS = (OPS + W * CL) * 8 <= (int)((O::FRAG_SZ + W * O::WAVE_SZ) * sizeof(T));
   static_assert((O::WAVE_SZ * sizeof(T)) / 8 >= curved_lds_doubles(N) + 1,
                 "the curved element's arrays must fit a wave's LDS area");
   if ((int)blockIdx.x < ncw) {
     const int slot = (int)blockIdx.x * W + wid;
-    if constexpr (OPS_LDS) {
-      double* ops = (double*)sAll;
-      for (int i = threadIdx.x; i < OPS; i += 64 * W) ops[i] = t.ops[i];
-      __syncthreads();
-      if (slot < t.ncurved)
-        curved_element<N>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, slot, ops + OPS + wid * CL, ops);
-    } else if (slot < t.ncurved) {
+    if (slot < t.ncurved) {
       const uintptr_t at = ((uintptr_t)(sWave + wid * O::WAVE_SZ) + 7) & ~(uintptr_t)7;
-      curved_element<N>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, slot, (double*)at, t.ops);
+      curved_element<N>(t, ph, Uin, Uout, K1, a, b, dt, rhs_only, slot, (double*)at);
     }
     return;
   }
