@@ -287,9 +287,10 @@ int dg_newmark_step(double state[3], double F_new, double dt, double M, double C
 int dg_set_tuning(dg_ctx* ctx, int waves, int grid);
 int dg_get_tuning(const dg_ctx* ctx, int* waves, int* grid);
 
-/* Time every launch shape on this context's mesh (reps stage launches each,
- * reading U, a device state [K][4][Np], writing only library scratch) and
- * keep the fastest.  With cache_path non-NULL, a matching entry of that
+/* Time every launch shape on this context's mesh (two sweeps over the
+ * shapes, reps launches of a K1-reading RK stage per shape and sweep, each
+ * shape's best kept; reading U, a device state [K][4][Np], writing only
+ * library scratch) and keep the fastest.  With cache_path non-NULL, a matching entry of that
  * JSON-lines file (same device architecture, order, precision and element
  * count within a factor 2) is used instead of timing, and a new measurement
  * is appended to it.  Allocates a temporary device register; synchronises
