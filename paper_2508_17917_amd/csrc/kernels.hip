@@ -79,9 +79,8 @@ struct Order {
   // waves per SIMD the register allocation must allow: 3 for FP32 at p <= 4
   // (a few spills, measured faster than 2 and than 4), else 2
   static constexpr int MIN_WAVES_EU = (sizeof(T) == 4 && N <= 4) ? 3 : 2;
-  // K1 / K0 of the tile, and the next tile's own data, issued before the
-  // face pass where the registers allow
-  static constexpr bool EARLY_K = true;
+  // the next tile's own data issued before the face pass where the
+  // registers allow (K1 / K0 of the tile always are)
   static constexpr bool EARLY_OWN = N <= 4;
   // per-wave LDS (elements of T)
   static constexpr int U_SZ = 16 * RS;           // own state
@@ -107,6 +106,20 @@ struct Order {
 // Fourth word of a raw buffer descriptor on gfx9-family devices: 32-bit data
 // format (untyped loads need a valid one), no swizzle, no index stride.
 constexpr int kBufferWord3 = 0x00020000;
+
+// A raw buffer descriptor over n consecutive records of `bytes_each` bytes
+// starting at record r0 of the array at p (built on the scalar unit when its
+// arguments are uniform).  Accesses past the n records read 0 and write
+// nothing (the hardware's range check), so n <= 0 gives an empty range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t records(const void* p, int64_t r0, int64_t n,
+                                                          int bytes_each) {
+  const int bytes = n > 0 ? (int)(n * bytes_each) : 0;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)p + r0 * bytes_each), (short)0, bytes,
+                                           kBufferWord3);
+}
+__device__ __forceinline__ double buf_load_f64(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
 
 // Node index of face node j (counter-clockwise) on face f; rows of the node
 // numbering start at i(N+1) - i(i-1)/2.
@@ -265,21 +278,25 @@ __device__ __forceinline__ const float* frag_of<bf16ops>(const DeviceTables& t) 
 template <int N, typename X, bool PERT>
 __device__ __forceinline__ bool load_k(const DeviceTables& t, const double* __restrict__ Uin,
                                        const double* __restrict__ K1, double a, int rhs_only,
-                                       int64_t e0, int re, int rn, double (&rk)[Order<N, X>::NT][4],
+                                       int64_t e0, int nel, int re, int rn,
+                                       double (&rk)[Order<N, X>::NT][4],
                                        double (&r0)[Order<N, X>::NT][4]) {
   using O = Order<N, X>;
   constexpr int Np = O::Np, S = O::S;
-  const double* kp = (a != 0.0 && !rhs_only) ? K1 : Uin;
-  const int64_t ke = (e0 + re) < t.K ? (e0 + re) : t.K - 1;
+  // descriptors over the tile's elements: the lane's offsets are constants
+  const __amdgpu_buffer_rsrc_t rk_d = records((a != 0.0 && !rhs_only) ? K1 : Uin, e0, nel, S * 8);
+  const __amdgpu_buffer_rsrc_t r0_d = records(Uin, e0, nel, S * 8);
 #pragma unroll
   for (int tt = 0; tt < O::NT; ++tt) {
     const int n = 16 * tt + rn < Np ? 16 * tt + rn : Np - 1;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      rk[tt][c] = kp[ke * S + c * Np + n];
-      r0[tt][c] = PERT ? Uin[ke * S + c * Np + n] : 0.0;
+      const int off = (re * S + c * Np + n) * 8;
+      rk[tt][c] = buf_load_f64(rk_d, off);
+      r0[tt][c] = PERT ? buf_load_f64(r0_d, off) : 0.0;
     }
   }
+  const int64_t ke = (e0 + re) < t.K ? (e0 + re) : t.K - 1;
   return t.cslot == nullptr || t.cslot[ke] < 0;
 }
 
@@ -490,20 +507,21 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
   int vidx[NQ];                          // this lane's value within an element block
 #pragma unroll
   for (int q = 0; q < NQ; ++q) vidx[q] = lr_ok[q] ? lane + 64 * q : S - 1;
-  double ru[4][NQ];
+  double ru[EPT][NQ];
   double rg = 0.0;
   int rc = 0;
+  // through descriptors over the tile's elements (past the last element a
+  // load reads 0, and such values are never stored)
   auto load_own = [&](int64_t tl) {
     const int64_t b = tl * EPT;
+    const int64_t nb = K - b < EPT ? K - b : EPT;
+    const __amdgpu_buffer_rsrc_t ud = records(Uin, b, nb, S * 8);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t ke = (b + e) < K ? (b + e) : K - 1;
+    for (int e = 0; e < EPT; ++e)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) ru[e][q] = Uin[ke * S + vidx[q]];
-    }
-    const int64_t gi = b * kGeoStride + lane, ci = b * 3 + lane;
-    rg = t.geo[gi < K * kGeoStride ? gi : K * kGeoStride - 1];
-    rc = t.conn[ci < K * 3 ? ci : K * 3 - 1];
+      for (int q = 0; q < NQ; ++q) ru[e][q] = buf_load_f64(ud, (e * S + vidx[q]) * 8);
+    rg = buf_load_f64(records(t.geo, b, nb, kGeoStride * 8), lane * 8);
+    rc = __builtin_amdgcn_raw_buffer_load_b32(records(t.conn, b, nb, 3 * 4), lane * 4, 0, 0);
   };
   load_own(tile0);
 
@@ -516,7 +534,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     // constant plus a wave-uniform base.
     if (lane < nel * 3) sConn[lane] = rc;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < EPT; ++e)
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
         if (lr_ok[q] && e < nel) sU[lds_u[q] + ROWE * e * RS] = (T)(ru[e][q] - uinf_q[q]);
@@ -681,7 +699,7 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     // covers their latency
     double rk[NT][4], r0[NT][4];
     bool mine;  // not an element of the curved set (which the curved kernel writes)
-    if constexpr (O::EARLY_K) mine = load_k<N, X, PERT>(t, Uin, K1, a, rhs_only, e0, re, rn, rk, r0);
+    mine = load_k<N, X, PERT>(t, Uin, K1, a, rhs_only, e0, nel, re, rn, rk, r0);
     if constexpr (O::EARLY_OWN) load_own(tile + stride);
 
     // ---- face nodes, one lane each (the EPT elements' 3(p+1) face nodes fit
@@ -870,20 +888,6 @@ __device__ __forceinline__ void stage_tiles(const DeviceTables& t, const KernelP
     // the K1 / K0 loads (unless issued before the face pass), then those of
     // the next tile's own data, are issued first so the matrix work covers
     // their latency.
-    if constexpr (!O::EARLY_K) {
-      const double* kp = (a != 0.0 && !rhs_only) ? (const double*)K1 : Uin;
-      const int64_t ke = (e0 + re) < K ? (e0 + re) : K - 1;
-      mine = t.cslot == nullptr || t.cslot[ke] < 0;
-#pragma unroll
-      for (int tt = 0; tt < NT; ++tt) {
-        const int n = 16 * tt + rn < Np ? 16 * tt + rn : Np - 1;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          rk[tt][c] = kp[ke * S + c * Np + n];
-          r0[tt][c] = PERT ? Uin[ke * S + c * Np + n] : 0.0;
-        }
-      }
-    }
     if constexpr (!O::EARLY_OWN) load_own(tile + stride);
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
