@@ -87,6 +87,12 @@ CASES = [
      dict(mu=1e-2, penalty_mode=1, C_pen=1.0), "fourier", (0.0, 0.0)),
     ("periodic-p1-nipg", lambda: mg.periodic_square(7, 3, 2.0, 1.0), 1,
      dict(mu=1e-2, penalty_mode=1, C_pen=2.0, theta=-1.0), "fourier", (0.05, 0.0)),
+    # 70 elements: a partly filled last tile at four elements per tile (p = 4)
+    # and at three (p = 5)
+    ("cylinder-ragged-p4", lambda: mg.ogrid(7, 5, 0.5, 5.0, 1.3), 4,
+     dict(mu=2e-3, penalty_mode=0, C_pen=1.0), "noise", (0.011, 0.017)),
+    ("cylinder-ragged-p5", lambda: mg.ogrid(7, 5, 0.5, 5.0, 1.3), 5,
+     dict(mu=2e-3, penalty_mode=0, C_pen=1.0), "noise", (0.0, 0.0)),
 ]
 
 
@@ -122,7 +128,10 @@ def test_rhs_parity(case):
     s.close()
 
 
-@pytest.mark.parametrize("case", CASES[:3], ids=[c[0] for c in CASES[:3]])
+RK_CASES = CASES[:3] + CASES[-2:]
+
+
+@pytest.mark.parametrize("case", RK_CASES, ids=[c[0] for c in RK_CASES])
 def test_rk_step_parity(case):
     torch = _torch()
     name, mk, p, over, recipe, vw = case

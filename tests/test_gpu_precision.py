@@ -103,6 +103,12 @@ CASES = [
      dict(mu=3e-3, penalty_mode=0, C_pen=1.0, U_inf=mg.free_stream(0.3)), "fourier", (0.0, 0.0)),
     ("periodic-p1-nipg", lambda: mg.periodic_square(7, 3, 2.0, 1.0), 1,
      dict(mu=1e-2, penalty_mode=1, C_pen=2.0, theta=-1.0), "fourier", (0.05, 0.0)),
+    # 70 elements: a partly filled last tile at four elements per tile (p = 4)
+    # and at three (p = 5)
+    ("cylinder-ragged-p4", lambda: mg.ogrid(7, 5, 0.5, 5.0, 1.3), 4,
+     dict(mu=2e-3, penalty_mode=0, C_pen=1.0), "noise", (0.011, 0.017)),
+    ("cylinder-ragged-p5", lambda: mg.ogrid(7, 5, 0.5, 5.0, 1.3), 5,
+     dict(mu=2e-3, penalty_mode=0, C_pen=1.0), "noise", (0.0, 0.0)),
 ]
 
 
@@ -151,7 +157,10 @@ def test_rhs_perturbation_forms(case):
     s.close()
 
 
-@pytest.mark.parametrize("case", CASES[:2], ids=[c[0] for c in CASES[:2]])
+RK_CASES = CASES[:2] + CASES[-2:]
+
+
+@pytest.mark.parametrize("case", RK_CASES, ids=[c[0] for c in RK_CASES])
 def test_rk_step_fp32_pert(case):
     """Five stages in the FP32 perturbation form: the increment U_new - U against
     the oracle's LSERK step, to the FP32 bound scaled by dt; the stage entry
