@@ -125,6 +125,13 @@ def test_rhs_parity(case):
     R2 = s.rhs(Ud, v_w=vw)
     torch.cuda.synchronize()
     assert torch.equal(R, R2)
+    if "ragged" in name:
+        # every launch shape (waves per workgroup, persistent or 1-3 tiles per
+        # wave) covers the partly filled last tile with the same bits
+        for waves in (2, 4):
+            for grid in (0, 1, 2, 3):
+                s.set_tuning(waves, grid)
+                assert torch.equal(s.rhs(Ud, v_w=vw), R), (waves, grid)
     s.close()
 
 
