@@ -211,10 +211,11 @@ int dg_rk_step(dg_ctx* ctx, double* U, double* K1, double dt, const double v_w[2
 /* nsteps RK steps (as dg_rk_step, v_w fixed), with the wall force (as
  * dg_force_device, the same bits) after each step written to
  * force_dev[3 n .. 3 n + 2] when force_dev (device, 3 nsteps doubles) is not
- * NULL.  The force after step n < nsteps - 1 is evaluated by leading
- * workgroups of step n + 1's first stage launch, whose input is that state;
- * the last step's by a launch of its own (the over-integrated stage: one
- * force launch per step).  The state alternates between U and the scratch
+ * NULL.  The force after step n < nsteps - 1 is evaluated inside step
+ * n + 1's stage launches: its partials by leading workgroups of the first,
+ * whose input is that state, and their sum, in the same order, by a leading
+ * wave of the second; the last step's by a launch of its own (the
+ * over-integrated stage: one force launch per step).  The state alternates between U and the scratch
  * buffer from step to step, so it is copied back into U only when nsteps is
  * odd (dg_rk_step copies every step).  Asynchronous on `stream`. */
 int dg_rk_steps(dg_ctx* ctx, double* U, double* K1, int nsteps, double dt, const double v_w[2],

@@ -125,9 +125,12 @@ struct DeviceTables {
   double* force_part = nullptr;     // per-workgroup partials of the wall force
   unsigned* force_ticket = nullptr; // workgroups done (the last resets it to 0)
   int force_blocks = 0;             // capacity of force_part, in workgroups
-  // where a stage launch writes the wall force of its input state (evaluated
-  // by leading workgroups of that launch), or null for none
-  double* force_in = nullptr;
+  // the wall force inside stage launches: with force_parts, leading waves of
+  // the launch write the force partials of its input state to force_part
+  // (plain stores: no ticket, no fence); with force_fin, one leading wave adds
+  // the partials a previous launch wrote, in block order, into force_fin[0..2]
+  bool force_parts = false;
+  double* force_fin = nullptr;
 };
 
 struct KernelPhysics {

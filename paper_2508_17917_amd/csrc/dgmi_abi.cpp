@@ -428,16 +428,18 @@ int dg_rk_steps(dg_ctx* c, double* U, double* K1, int nsteps, double dt, const d
   // the state alternates between U and the scratch buffer: five stages per
   // step, so it sits in the other buffer after every step
   double* bufs[2] = {U, c->d_scratch};
-  // the force after step n is evaluated by leading workgroups of step n + 1's
-  // first stage launch, whose input is that state (the nodal stage kernel;
-  // the over-integrated stage launches it apart), the last step's by a launch
-  // of its own
+  // the force after step n: its partials by leading waves of step n + 1's
+  // first stage launch, whose input is that state, their sum in block order
+  // by a leading wave of the second (the nodal stage kernel; the
+  // over-integrated stage launches it apart); the last step's by a launch of
+  // its own
   const bool fuse = force_dev && walls && !c->overint;
   int cur = 0;
   for (int n = 0; n < nsteps; ++n) {
     for (int i = 0; i < 5; ++i) {
       dgmi::DeviceTables ti = t;
-      if (fuse && i == 0 && n > 0) ti.force_in = force_dev + 3 * (int64_t)(n - 1);
+      if (fuse && n > 0 && i == 0) ti.force_parts = true;
+      if (fuse && n > 0 && i == 1) ti.force_fin = force_dev + 3 * (int64_t)(n - 1);
       rc = dgmi::launch_stage(c->N, dgmi::ctx_form(c), c->tune, ti, k, bufs[(cur + i) & 1],
                               bufs[(cur + i + 1) & 1], K1, dgmi::kRkA[i], dgmi::kRkB[i], dt, 0,
                               stream, err);

@@ -378,13 +378,36 @@ __device__ __forceinline__ void wall_node_force(const DeviceTables& t, const Ker
   mz = w * (xw * ty - yw * tx);
 }
 
+// The force from the nblk partials an earlier launch wrote, in block order:
+// lane c < 3 writes component c (eight loads in flight at a time, the sum
+// itself in block order, as the ticket's last wave adds them).
+__device__ __forceinline__ void force_sum(const double* __restrict__ part, double* out,
+                                          unsigned nblk) {
+  const int lane = threadIdx.x & 63;
+  if (lane < 3) {
+    double sum = 0.0;
+    for (unsigned b = 0; b < nblk; b += 8) {
+      double v[8];
+#pragma unroll
+      for (unsigned q = 0; q < 8; ++q) v[q] = b + q < nblk ? part[3 * (b + q) + lane] : 0.0;
+#pragma unroll
+      for (unsigned q = 0; q < 8; ++q)
+        if (b + q < nblk) sum += v[q];
+    }
+    out[lane] = sum;
+  }
+}
+
 // One wave's share of the wall force: nodes 64 blk .. 64 blk + 63 of the nblk
 // blocks of 64 that cover the wall face nodes, reduced by a fixed shuffle
-// tree into partial blk; the last wave to finish (an atomic ticket) sums the
-// partials in block order into out[0..2] and resets the ticket.  The order of
-// every sum is fixed by the wall face list alone, so the total does not depend
-// on which waves ran the blocks or in which launch.
-template <int N, int UNR = (N + 1) * (N + 2) / 2>
+// tree into partial blk.  With TICKET the last wave to finish (an atomic
+// ticket) sums the partials in block order into out[0..2] and resets the
+// ticket; without, the partials are left for a later launch to sum (the
+// ticket's device-scope fences write back and invalidate the L2 of the
+// wave's XCD, and its chain of round trips outlasts a stage launch's first
+// tiles).  The order of every sum is fixed by the wall face list alone, so
+// the total does not depend on which waves ran the blocks or in which launch.
+template <int N, int UNR = (N + 1) * (N + 2) / 2, bool TICKET = true>
 __device__ __forceinline__ void force_wave(const DeviceTables& t, const KernelPhysics& ph,
                                            const double* __restrict__ U, double* __restrict__ out,
                                            unsigned blk, unsigned nblk) {
@@ -397,11 +420,14 @@ __device__ __forceinline__ void force_wave(const DeviceTables& t, const KernelPh
     fy += __shfl_down(fy, o, 64);
     mz += __shfl_down(mz, o, 64);
   }
-  unsigned last = 0;
   if (lane == 0) {
     t.force_part[3 * blk + 0] = fx;
     t.force_part[3 * blk + 1] = fy;
     t.force_part[3 * blk + 2] = mz;
+  }
+  if constexpr (!TICKET) return;
+  unsigned last = 0;
+  if (lane == 0) {
     __threadfence();
     last = atomicAdd(t.force_ticket, 1u) == nblk - 1;
   }
@@ -965,11 +991,13 @@ constexpr int curved_lds_doubles(int N) {
 __host__ __device__ inline int curved_workgroups(int ncurved, int W) {
   return ncurved > 0 ? ((ncurved + W - 1) / W + 7) / 8 * 8 : 0;
 }
-// workgroups of W waves that evaluate the wall force of the launch's input
-// state (one wave per 64 wall face nodes), a multiple of 8, or none
+// workgroups of W waves for the wall force in a stage launch: one wave per 64
+// wall face nodes (the partials of the launch's input state), then the wave
+// that sums a previous launch's partials; a multiple of 8, or none
 __host__ __device__ inline int force_workgroups(const DeviceTables& t, int Nfp, int W) {
   const int nblk = (t.nwall * Nfp + kForceThreads - 1) / kForceThreads;
-  return t.force_in != nullptr && nblk > 0 ? ((nblk + W - 1) / W + 7) / 8 * 8 : 0;
+  if (nblk <= 0 || (!t.force_parts && t.force_fin == nullptr)) return 0;
+  return ((nblk + 1 + W - 1) / W + 7) / 8 * 8;
 }
 template <int N>
 __device__ __forceinline__ void curved_element(const DeviceTables& t, const KernelPhysics& ph,
@@ -1255,16 +1283,18 @@ stage_kernel(DeviceTables t, KernelPhysics ph, const double* __restrict__ Uin,
     }
     return;
   }
-  // then, where the caller asks for it, the wall force of the input state
-  // (the previous step's output, which this launch only reads): one wave per
-  // 64 wall face nodes
+  // then, where the caller asks for them, the wall force partials of the
+  // input state (the previous step's output, which this launch only reads):
+  // one wave per 64 wall face nodes; and the sum of the partials a previous
+  // launch left, by the wave after them
   const int nfw = force_workgroups(t, O::Nfp, W);
   if ((int)blockIdx.x < ncw + nfw) {
     const unsigned nblk = (unsigned)((t.nwall * O::Nfp + kForceThreads - 1) / kForceThreads);
     const unsigned wv = (blockIdx.x - ncw) * W + wid;
     // the node's derivative loop unrolled by eight: two rounds of loads at
     // p = 4, and no more registers than the stage kernel holds
-    if (wv < nblk) force_wave<N, 8>(t, ph, Uin, t.force_in, wv, nblk);
+    if (t.force_parts && wv < nblk) force_wave<N, 8, false>(t, ph, Uin, nullptr, wv, nblk);
+    if (t.force_fin != nullptr && wv == nblk) force_sum(t.force_part, t.force_fin, nblk);
     return;
   }
   stage_lds_init<N, X, W>(frag_of<X>(t), sFrag, sWave);
@@ -1843,11 +1873,17 @@ int launch_stage_t(const StageTuning& tune, const DeviceTables& t, const KernelP
   static int cache[kMaxDev] = {0};
   const int resident = resident_blocks(stage_kernel<N, T, PERT, W>, 64 * W, cache);
   constexpr int EPT = elements_per_tile(N);
-  // the curved set's workgroups lead the grid; a persistent grid leaves them
-  // their resident slots
-  const int ncw = curved_workgroups(t.ncurved, W) + force_workgroups(t, N + 1, W);
+  // the curved set's workgroups lead the grid, then the force's; a
+  // persistent grid leaves the curved set its resident slots, but not the
+  // force, which is done within a few microseconds: the tiles keep every
+  // slot, and the last tile workgroup of each XCD (the fewest tiles per wave)
+  // starts in the force workgroup's slot when that leaves, instead of one
+  // CU per XCD holding a workgroup fewer and its SIMDs a tile more each
+  const int ncw = curved_workgroups(t.ncurved, W);
+  const int nfw = force_workgroups(t, N + 1, W);
   const int straight_resident = resident - ncw >= 8 ? resident - ncw : 8;
-  const int64_t grid = stage_grid((t.K + EPT - 1) / EPT, W, straight_resident, tune.grid) + ncw;
+  const int64_t grid =
+      stage_grid((t.K + EPT - 1) / EPT, W, straight_resident, tune.grid) + ncw + nfw;
   hipLaunchKernelGGL((stage_kernel<N, T, PERT, W>), dim3((unsigned)grid), dim3(64 * W), 0, s, t,
                      ph, Uin, Uout, K1, a, b, dt, rhs_only);
   return launch_error(err, "stage kernel launch");
